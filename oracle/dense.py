@@ -1,0 +1,93 @@
+"""Brute-force assembled operators for tiny grids.
+
+The z operator is written here from its finite-volume definition -- the
+difference of the two face fluxes of a control volume divided by its width
+-- and not from ``grid.zop``, so that it checks that module rather than
+repeating it. Solutions come from numpy.linalg on the dense matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NEUMANN, DIRICHLET_CENTRE, DIRICHLET_FACE = 0, 1, 2
+
+
+def lz_dense(zf, bc):
+    """Dense matrix of the z second-derivative operator L_z."""
+    zf = np.asarray(zf, dtype=float)
+    nz = zf.size - 1
+    zc = 0.5 * (zf[1:] + zf[:-1])
+    if bc in (NEUMANN, DIRICHLET_CENTRE):
+        M = np.zeros((nz, nz))
+        for k in range(nz):
+            width = zf[k + 1] - zf[k]
+            # upper face flux (u[k+1]-u[k]) / (zc[k+1]-zc[k]); at the top wall:
+            # zero (Neumann) or (0 - u[k]) / (zf[nz] - zc[k]) (Dirichlet)
+            if k + 1 < nz:
+                h = zc[k + 1] - zc[k]
+                M[k, k + 1] += 1 / (h * width); M[k, k] -= 1 / (h * width)
+            elif bc == DIRICHLET_CENTRE:
+                M[k, k] -= 1 / ((zf[nz] - zc[k]) * width)
+            if k > 0:
+                h = zc[k] - zc[k - 1]
+                M[k, k - 1] += 1 / (h * width); M[k, k] -= 1 / (h * width)
+            elif bc == DIRICHLET_CENTRE:
+                M[k, k] -= 1 / ((zc[k] - zf[0]) * width)
+        return M
+    if bc == DIRICHLET_FACE:
+        n = nz - 1
+        M = np.zeros((n, n))
+        for u in range(n):
+            k = u + 1                           # face index
+            width = zc[k] - zc[k - 1]
+            up = 1 / ((zf[k + 1] - zf[k]) * width)
+            dn = 1 / ((zf[k] - zf[k - 1]) * width)
+            M[u, u] -= up + dn
+            if u + 1 < n:
+                M[u, u + 1] += up
+            if u > 0:
+                M[u, u - 1] += dn
+        return M
+    raise ValueError(bc)
+
+
+def periodic_d2(n, h):
+    """Dense periodic second difference on n points of spacing h."""
+    M = -2 * np.eye(n)
+    for i in range(n):
+        M[i, (i + 1) % n] += 1
+        M[i, (i - 1) % n] += 1
+    return M / (h * h)
+
+
+def l7_dense(nx, ny, zf, lx, ly):
+    """Dense 7-point operator for C-order (nz, ny, nx) flattening."""
+    nz = len(zf) - 1
+    Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
+    Dx = periodic_d2(nx, lx / nx)
+    Dy = periodic_d2(ny, ly / ny)
+    Dz = lz_dense(zf, NEUMANN)
+    return (np.kron(Iz, np.kron(Iy, Dx)) + np.kron(Iz, np.kron(Dy, Ix))
+            + np.kron(Dz, np.kron(Iy, Ix)))
+
+
+def poisson_dense(f, zf, lx, ly):
+    """Least-squares solution of L7 p = f with the row sum_ijk dzf[k] p = 0
+    appended (the solution of the projected problem when f is compatible)."""
+    nz, ny, nx = f.shape
+    L = l7_dense(nx, ny, zf, lx, ly)
+    w = np.repeat(np.diff(np.asarray(zf, float)), nx * ny)
+    # project f onto the range of L (orthogonal to the weights' null vector)
+    fv = f.reshape(-1)
+    fv = fv - np.dot(w, fv) / w.sum()
+    A = np.vstack([L, w[None, :]])
+    b = np.concatenate([fv, [0.0]])
+    p, *_ = np.linalg.lstsq(A, b, rcond=None)
+    return p.reshape(f.shape)
+
+
+def helmholtz_dense(r, zf, s, bc):
+    """Column-wise dense solve of (I - s L_z) u = r along axis 0."""
+    M = np.eye(lz_dense(zf, bc).shape[0]) - s * lz_dense(zf, bc)
+    shp = r.shape
+    return np.linalg.solve(M, r.reshape(shp[0], -1)).reshape(shp)

@@ -1,0 +1,108 @@
+"""Channel pressure-Poisson and wall-normal Helmholtz solves (paper Sec. 2.2.1,
+eq. fijk_eq; Sec. 2.1, eq. proj3_impl1d).
+
+Poisson: find p with L7 p = f, where L7 is the second-order 7-point operator
+of the staggered grid -- periodic uniform second differences in x and y plus
+the stretched three-point z operator with zero-gradient (Neumann) walls. L7
+is singular (constants), so f is first projected onto its range by removing
+its dzf-weighted mean, and p is pinned to zero dzf-weighted mean.
+
+Route (method of eigenfunction expansions): packed real transform along x,
+then along y (App. A layout); every slot pair (i, j) then decouples into one
+tridiagonal system in z whose diagonal is shifted by the modified wavenumbers
+sigma_x[i] + sigma_y[j]; the singular (0, 0) system is solved with the pin;
+inverse transforms bring p back.
+
+Helmholtz: u - s L_z u = r per column with Dirichlet walls (s = alpha nu dt;
+the paper writes gamma_k nu dt / 2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import grid, transforms, tridiag
+
+
+def project_rhs(f, zf):
+    """Remove the dzf-weighted mean of f (the part outside L7's range)."""
+    _, dzf, _ = grid.z_metrics(zf, f.dtype.type)
+    plane = f.reshape(f.shape[0], -1).sum(axis=1)
+    c = np.dot(dzf, plane) / (dzf.sum() * (f.shape[1] * f.shape[2]))
+    return f - c
+
+
+def zero_mode_solve(fhat00, zf):
+    """Solve L_z m = fhat00 for the singular Neumann column, pinned to
+    sum_k dzf[k] m[k] = 0. The right-hand side must be compatible
+    (sum_k dzf[k] fhat00[k] = 0). The last equation is dropped and replaced
+    by m[nz-1] = 0; a Thomas sweep solves the rest; the weighted mean is
+    then subtracted."""
+    dt = fhat00.dtype.type
+    alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
+    n = fhat00.size
+    _, dzf, _ = grid.z_metrics(zf, dt)
+    m = np.zeros(n, dtype=dt)
+    if n > 1:
+        al, ga, ep = alpha[:n - 1].copy(), gamma[:n - 1].copy(), eps[:n - 1].copy()
+        ep[-1] = ep[-1] + ga[-1]      # m[n-1] = 0: its coupling stays on the diagonal
+        ga[-1] = 0
+        m[:n - 1] = tridiag.thomas_gth(al, ga, ep, -fhat00[:n - 1])
+    return m - np.dot(dzf, m) / dzf.sum()
+
+
+def solve_poisson(f, zf, lx, ly):
+    """p with L7 p = f (projected), zero dzf-weighted mean. f is (nz, ny, nx),
+    float64 or longdouble; the result has f's dtype."""
+    dt = f.dtype.type
+    nz, ny, nx = f.shape
+    f = project_rhs(f, zf)
+    F = transforms.rfft_packed(transforms.rfft_packed(f, axis=2), axis=1)
+    sx = grid.modified_wavenumbers(nx, lx, dt)
+    sy = grid.modified_wavenumbers(ny, ly, dt)
+    alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
+    shift = sy[:, None] + sx[None, :]                  # (ny, nx) >= 0
+    shift[0, 0] = 1                                    # placeholder, redone below
+    eps3 = eps[:, None, None] + shift[None, :, :]
+    # -(L_z - shift) phi = -fhat in sign-normalised rows
+    P = tridiag.thomas_gth(alpha[:, None, None], gamma[:, None, None], eps3, -F)
+    P[:, 0, 0] = zero_mode_solve(F[:, 0, 0].copy(), zf)
+    return transforms.irfft_packed(transforms.irfft_packed(P, axis=1), axis=2)
+
+
+def apply_L7(p, zf, lx, ly):
+    """L7 p in the arithmetic of p's dtype (periodic x, y; Neumann z)."""
+    dt = p.dtype.type
+    nz, ny, nx = p.shape
+    dx, dy = dt(lx) / nx, dt(ly) / ny
+    out = (np.roll(p, -1, 2) - 2 * p + np.roll(p, 1, 2)) / (dx * dx)
+    out += (np.roll(p, -1, 1) - 2 * p + np.roll(p, 1, 1)) / (dy * dy)
+    alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
+    lz = -(alpha + gamma + eps)[:, None, None] * p
+    lz[1:] += alpha[1:, None, None] * p[:-1]
+    lz[:-1] += gamma[:-1, None, None] * p[1:]
+    return out + lz
+
+
+def residual7(p, f, zf, lx, ly):
+    """f - L7 p (f projected first)."""
+    return project_rhs(f, zf) - apply_L7(p, zf, lx, ly)
+
+
+def solve_helmholtz(r, zf, s, bc):
+    """u with u - s L_z u = r along z for every column; bc is DIRICHLET_CENTRE
+    (nz unknowns) or DIRICHLET_FACE (nz - 1 unknowns)."""
+    dt = r.dtype.type
+    alpha, gamma, eps = grid.zop(zf, bc, dt)
+    s = dt(s)
+    shp = (slice(None),) + (None,) * (r.ndim - 1)
+    return tridiag.thomas_gth((s * alpha)[shp], (s * gamma)[shp], (1 + s * eps)[shp], r)
+
+
+def rel_l2(x, ref):
+    """||x - ref||_2 / ||ref||_2 over all points, accumulated in float64
+    (longdouble if either operand is)."""
+    x = np.asarray(x); ref = np.asarray(ref)
+    dt = np.longdouble if np.longdouble in (x.dtype.type, ref.dtype.type) else np.float64
+    num = np.sqrt(np.sum((x.astype(dt) - ref.astype(dt)) ** 2))
+    den = np.sqrt(np.sum(ref.astype(dt) ** 2))
+    return float(num / den) if den != 0 else float(num)

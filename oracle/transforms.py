@@ -1,0 +1,71 @@
+"""Packed real Fourier transform (paper App. A).
+
+A real line of n values has floor(n/2)+1 complex Fourier coefficients X_q
+(forward sign e^{-2 pi i q t / n}, unnormalised). X_0 is real, and so is
+X_{n/2} for even n, so n reals carry the whole spectrum. The packed layout
+keeps the interleaved [X_0^r, X_0^i, X_1^r, X_1^i, ...] order and moves the
+one surplus value into the always-zero slot of X_0^i:
+
+  even n: [X_0^r, X_{n/2}^r, X_1^r, X_1^i, ..., X_{n/2-1}^r, X_{n/2-1}^i]
+  odd n:  [X_0^r, X_h^i,     X_1^r, X_1^i, ..., X_{h-1}^r, X_{h-1}^i, X_h^r]
+          with h = (n-1)/2.
+
+The inverse returns the real line, normalised by 1/n. numpy's FFT serves as
+the library transform; ``dft_direct`` is a direct summation used to pin it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _real_dtype(x):
+    return np.longdouble if x.dtype == np.longdouble else np.float64
+
+
+def rfft_packed(x: np.ndarray, axis: int) -> np.ndarray:
+    """Packed forward real transform of ``x`` along ``axis``."""
+    x = np.moveaxis(np.asarray(x), axis, -1)
+    n = x.shape[-1]
+    X = np.fft.rfft(x, axis=-1)
+    out = np.empty(x.shape, dtype=_real_dtype(x))
+    h = n // 2
+    out[..., 0] = X[..., 0].real
+    if n % 2 == 0:
+        out[..., 1] = X[..., h].real
+        out[..., 2::2] = X[..., 1:h].real
+        out[..., 3::2] = X[..., 1:h].imag
+    else:
+        if n > 1:
+            out[..., 1] = X[..., h].imag
+            out[..., 2::2] = X[..., 1:h + 1].real
+            out[..., 3::2] = X[..., 1:h].imag
+    return np.moveaxis(out, -1, axis)
+
+
+def irfft_packed(P: np.ndarray, axis: int) -> np.ndarray:
+    """Inverse of ``rfft_packed`` (normalised by 1/n)."""
+    P = np.moveaxis(np.asarray(P), axis, -1)
+    n = P.shape[-1]
+    h = n // 2
+    cdt = np.clongdouble if P.dtype == np.longdouble else np.complex128
+    X = np.zeros(P.shape[:-1] + (h + 1,), dtype=cdt)
+    X[..., 0] = P[..., 0]
+    if n % 2 == 0:
+        X[..., h] = P[..., 1]
+        X[..., 1:h] = P[..., 2::2] + 1j * P[..., 3::2]
+    elif n > 1:
+        X[..., 1:h] = P[..., 2:-1:2] + 1j * P[..., 3::2]
+        X[..., h] = P[..., -1] + 1j * P[..., 1]
+    x = np.fft.irfft(X, n=n, axis=-1)
+    return np.moveaxis(x, -1, axis)
+
+
+def dft_direct(x: np.ndarray) -> np.ndarray:
+    """Direct O(n^2) summation of the forward DFT of a 1-D sequence."""
+    x = np.asarray(x)
+    n = x.shape[0]
+    t = np.arange(n)
+    X = np.zeros(n, dtype=np.complex128)
+    for q in range(n):
+        X[q] = np.sum(x * np.exp(-2j * np.pi * ((q * t) % n) / n))
+    return X
