@@ -1,0 +1,184 @@
+/*
+ * pf_channel.h -- C ABI of the MI355X channel pressure-Poisson and
+ * wall-normal Helmholtz solvers (arXiv 2502.06296).
+ *
+ * Problem statement (paper Sec. 2.1 and 2.2.1):
+ *   Poisson    L7 p = f on a channel grid periodic in x and y, with uniform
+ *              spacing there, and non-uniform cell faces zf[0..nz] in z.
+ *              L7 is the second-order 7-point operator of the staggered
+ *              (MAC) grid, pressure at cell centres, zero normal gradient at
+ *              both walls. After packed real Fourier transforms in x and y
+ *              every wavenumber pair (i,j) leaves one tridiagonal system in
+ *              z whose diagonal is shifted by the modified wavenumbers
+ *              (eq. fijk_eq). L7 is singular: f is first projected by
+ *              removing its dzf-weighted mean, and p is returned with zero
+ *              dzf-weighted mean.
+ *   Helmholtz  (I - s L_z) u = r in every (x,y) column (eq. proj3_impl1d,
+ *              with s = alpha * nu * dt; the paper writes gamma_k nu dt / 2),
+ *              solved with the reworked cyclic reduction of Algorithm 2:
+ *              pcr_prepare computes the chunk coefficients once (Step 1),
+ *              pcr_apply runs the reduction, the reduced boundary solve and
+ *              the in-place reconstruction (Steps 2-4).
+ *
+ * Layout: every field is a dense C-order array of shape (nz, ny, nx), x
+ * fastest: element (i,j,k) at i + nx*(j + ny*k).
+ *
+ * Memory: field pointers are DEVICE pointers owned by the caller; plans own
+ * only small constant tables. Every call is asynchronous on the plan's HIP
+ * stream (passed as void*, a hipStream_t; NULL is the default stream); no
+ * call made after a plan exists allocates, synchronises or reads back, so a
+ * sequence of solves may be captured in a HIP graph.
+ *
+ * Errors: every function returns a pf_status; 0 is success. Arguments are
+ * validated on the host before anything is enqueued, so a failing call
+ * enqueues nothing. pf_last_error() returns a thread-local message for the
+ * last failure on the calling thread.
+ */
+#ifndef PF_CHANNEL_H
+#define PF_CHANNEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pf_status;
+#define PF_OK 0
+#define PF_ERR_ARG (-1)          /* NULL pointer, bad size, aliasing      */
+#define PF_ERR_UNSUPPORTED (-2)  /* length or option this build lacks     */
+#define PF_ERR_DEVICE (-3)       /* a HIP runtime call failed             */
+#define PF_ERR_WORKSPACE (-4)    /* workspace missing or too small        */
+
+/* Arithmetic of a solve.
+ * PF_FP64         float64 everywhere.
+ * PF_FP32         float32 transforms and storage; the z systems are
+ *                 eliminated in float64 registers; about 1e-7 relative.
+ * PF_FP32_REFINE  PF_FP32 followed by n_refine corrections, each solving
+ *                 for the float64 residual f - L7 p (Poisson) or r - (I -
+ *                 s L_z) u (Helmholtz, in registers); the singular zero
+ *                 mode is always solved in float64. */
+typedef enum { PF_FP64 = 0, PF_FP32 = 1, PF_FP32_REFINE = 2 } pf_precision;
+
+/* Wall-normal boundary families of the staggered grid.
+ * NEUMANN           cell centres (pressure), zero gradient at the walls.
+ * DIRICHLET_CENTRE  cell centres (u, v), value 0 at the walls through a
+ *                   ghost value mirrored about the wall.
+ * DIRICHLET_FACE    interior faces 1..nz-1 (w), w = 0 on the wall faces;
+ *                   nz-1 unknowns per column. */
+typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FACE = 2 } pf_zbc;
+
+/* Channel grid. nx, ny even, of the form 2^a 3^b, 64 <= n <= 2048 (the
+ * transform lengths this build instantiates); 4 <= nz <= 1024. zf: host array of
+ * nz+1 strictly increasing face coordinates, copied at plan time; if NULL
+ * the faces are zf[k] = lz/2 (1 + tanh(beta (2k/nz - 1)) / tanh(beta))
+ * (uniform when beta == 0). */
+typedef struct pf_grid {
+  int32_t nx, ny, nz;
+  double lx, ly, lz;
+  double beta;
+  const double *zf;
+} pf_grid;
+
+typedef struct pf_poisson_plan pf_poisson_plan;
+typedef struct pf_pcr_plan pf_pcr_plan;
+typedef struct pf_graph pf_graph;
+
+const char *pf_last_error(void);
+int32_t pf_abi_version(void);
+
+/* Host helper: the sign-normalised rows of -L_z for boundary family bc,
+ * row k = -alpha[k] x[k-1] + (alpha[k]+gamma[k]+excess[k]) x[k]
+ *         - gamma[k] x[k+1], all three >= 0, alpha[0] = gamma[n-1] = 0.
+ * n = nz (centres) or nz-1 (faces). Output arrays are host, length n. */
+pf_status pf_zop_rows(const pf_grid *g, int32_t bc, double *alpha, double *gamma,
+                      double *excess);
+
+/* Host helper: the face coordinates the plan uses (host array, nz+1). */
+pf_status pf_grid_faces(const pf_grid *g, double *zf_out);
+
+/* ------------------------------------------------------------ Poisson
+ * poisson_plan: validates the grid, builds the modified wavenumbers of the
+ * packed slots, the z rows, the twiddle tables and the kernel shapes, all
+ * on the device of the calling thread. n_refine: corrections for
+ * PF_FP32_REFINE, 0 or 1 (one correction reaches 1e-10 relative at
+ * nz <= 1024; 0 is PF_FP32), ignored otherwise. *workspace_bytes (may be NULL) receives the
+ * device workspace poisson_solve needs: 0 for PF_FP64 (p doubles as the
+ * spectral buffer), 4*N for PF_FP32, 8*N for PF_FP32_REFINE. */
+pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision,
+                       int32_t n_refine, void *stream, size_t *workspace_bytes);
+/* Caller-owned device workspace of at least *workspace_bytes, 256-byte
+ * aligned; kept by pointer until replaced or the plan is destroyed. */
+pf_status poisson_set_workspace(pf_poisson_plan *plan, void *workspace, size_t bytes);
+/* p <- L7^{-1} f. rhs: device (nz,ny,nx) float64, read only. p: device
+ * (nz,ny,nx) float64, must not overlap rhs or the workspace. */
+pf_status poisson_solve(pf_poisson_plan *plan, const double *rhs, double *p);
+/* The same solve for several plans, launched back to back on the first
+ * plan's stream. */
+pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans,
+                                const double *const *rhs, double *const *p);
+pf_status poisson_set_stream(pf_poisson_plan *plan, void *stream);
+pf_status poisson_destroy(pf_poisson_plan *plan);
+
+/* ---------------------------------------------------------- Helmholtz
+ * pcr_prepare (Algorithm 2, Step 1): host arrays alpha, gamma, excess of
+ * length n in the form of pf_zop_rows describe -L_z; the plan solves
+ * (I - s L_z) u = r, i.e. rows (s alpha, s gamma, 1 + s excess), s >= 0.
+ * Rows are split into P chunks; chunk_rows is the
+ * number of rows per chunk (0 picks it; otherwise 8, 16 or 32), at most 32
+ * chunks; the last chunk is padded with identity rows. The chunk
+ * coefficients, the reduced boundary system and its parallel cyclic
+ * reduction are computed here in float64, subtraction-free, and uploaded.
+ * precision: PF_FP64 (float64 field), PF_FP32 (float32 field), or
+ * PF_FP32_REFINE (float64 field, float32 solves plus one float64-residual
+ * correction in registers). n >= 4. */
+pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const double *gamma,
+                      const double *excess, double s, int32_t precision, int32_t chunk_rows,
+                      void *stream);
+/* Re-run Step 1 for a new s (per Runge-Kutta substep) on the host and
+ * enqueue the upload on the plan's stream. */
+pf_status pcr_update_coef(pf_pcr_plan *plan, double s);
+/* In place, every column of a device (n, ny, nx) field; float64 or float32
+ * per the plan's precision. nx must be a multiple of 64. */
+pf_status pcr_apply(pf_pcr_plan *plan, void *field, int32_t nx, int32_t ny);
+/* Several fields (for example the three velocity components) in one
+ * launch; all plans must share precision and stream. */
+pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *const *fields,
+                            const int32_t *nx, const int32_t *ny);
+pf_status pcr_set_stream(pf_pcr_plan *plan, void *stream);
+pf_status pcr_destroy(pf_pcr_plan *plan);
+
+/* ---------------------------------------------------------- HIP graphs
+ * Capture every call enqueued on `stream` between begin and end into a
+ * graph (stream must not be the default stream), replay it with
+ * pf_graph_launch. */
+pf_status pf_graph_begin(void *stream);
+pf_status pf_graph_end(void *stream, pf_graph **out);
+pf_status pf_graph_launch(pf_graph *graph, void *stream);
+pf_status pf_graph_destroy(pf_graph *graph);
+
+/* --------------------------------------------------------- measurement
+ * Stage timing in the style of the paper's per-operation GPU timers: when
+ * enabled, each kernel a plan launches is bracketed by HIP events on the
+ * plan's stream. pf_*_timing_read synchronises the stream and returns, per
+ * stage, the summed milliseconds and the launch count since the last read
+ * (arrays of PF_STAGE_COUNT). */
+enum {
+  PF_STAGE_XFWD = 0, PF_STAGE_YFWD = 1, PF_STAGE_ZSOLVE = 2, PF_STAGE_YINV = 3,
+  PF_STAGE_XINV = 4, PF_STAGE_ZERO_MODE = 5, PF_STAGE_XFWD_RESID = 6, PF_STAGE_XINV_FINAL = 7,
+  PF_STAGE_PCR_APPLY = 8, PF_STAGE_COUNT = 9
+};
+pf_status poisson_timing(pf_poisson_plan *plan, int32_t enable);
+pf_status poisson_timing_read(pf_poisson_plan *plan, double *ms, int32_t *count);
+pf_status pcr_timing(pf_pcr_plan *plan, int32_t enable);
+pf_status pcr_timing_read(pf_pcr_plan *plan, double *ms, int32_t *count);
+
+/* A plain device copy of `bytes` bytes (multiple of 16), the calibration
+ * kernel for hardware byte counters. */
+pf_status pf_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_CHANNEL_H */

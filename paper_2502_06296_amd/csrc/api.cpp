@@ -1,0 +1,748 @@
+// Host side of the C ABI: plans, grid and coefficient tables, validation,
+// launch sequences, stage timing and graph capture.
+//
+// Every table is built here in float64 from the grid definition (paper Sec.
+// 2.1: staggered grid, uniform in x and y, stretched in z) and uploaded once
+// per plan; the solves only enqueue kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pf_channel.h"
+#include "pf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+pf_status fail(pf_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define PF_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(PF_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+// ------------------------------------------------------------------ grid
+pf_status check_grid(const pf_grid *g, bool need_fft) {
+  if (!g) return fail(PF_ERR_ARG, "grid is NULL");
+  if (g->nz < 4) return fail(PF_ERR_ARG, "nz must be >= 4 (got %d)", g->nz);
+  if (!(g->lz > 0.0) && !g->zf) return fail(PF_ERR_ARG, "lz must be > 0");
+  if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
+  if (need_fft) {
+    if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
+    for (int n : {g->nx, g->ny})
+      if (!pf::fft_size_supported(n))
+        return fail(PF_ERR_UNSUPPORTED,
+                    "transform length %d not built (even 2^a 3^b in [64, 2048]: 64 96 128 192 256 "
+                    "384 512 768 1024 1536 2048)",
+                    n);
+  }
+  if (g->zf) {
+    for (int k = 0; k < g->nz; ++k)
+      if (!(g->zf[k + 1] > g->zf[k]) || !std::isfinite(g->zf[k + 1]))
+        return fail(PF_ERR_ARG, "zf must be finite and strictly increasing (k=%d)", k);
+  }
+  return PF_OK;
+}
+
+// faces: user array, or the tanh wall clustering
+std::vector<double> faces_of(const pf_grid *g) {
+  std::vector<double> zf(g->nz + 1);
+  if (g->zf) {
+    for (int k = 0; k <= g->nz; ++k) zf[k] = g->zf[k];
+  } else {
+    for (int k = 0; k <= g->nz; ++k) {
+      if (g->beta == 0.0) {
+        zf[k] = g->lz * (double)k / g->nz;
+      } else {
+        const long double t = std::tanh((long double)g->beta * (2.0L * k / g->nz - 1.0L)) /
+                              std::tanh((long double)g->beta);
+        zf[k] = (double)(0.5L * g->lz * (1.0L + t));
+      }
+    }
+  }
+  return zf;
+}
+
+// sign-normalised rows of -L_z: flux difference over the control volume
+void zrows(const std::vector<double> &zf, int bc, std::vector<double> &al, std::vector<double> &ga,
+           std::vector<double> &ex) {
+  const int nz = (int)zf.size() - 1;
+  std::vector<double> zc(nz), w(nz);
+  for (int k = 0; k < nz; ++k) {
+    zc[k] = 0.5 * (zf[k] + zf[k + 1]);
+    w[k] = zf[k + 1] - zf[k];
+  }
+  if (bc == PF_BC_NEUMANN || bc == PF_BC_DIRICHLET_CENTRE) {
+    al.assign(nz, 0.0); ga.assign(nz, 0.0); ex.assign(nz, 0.0);
+    for (int k = 0; k < nz; ++k) {
+      if (k > 0) al[k] = 1.0 / (w[k] * (zc[k] - zc[k - 1]));
+      if (k < nz - 1) ga[k] = 1.0 / (w[k] * (zc[k + 1] - zc[k]));
+    }
+    if (bc == PF_BC_DIRICHLET_CENTRE) {
+      // the wall value is reached over half a cell from the first centre
+      ex[0] = 1.0 / (w[0] * (zc[0] - zf[0]));
+      ex[nz - 1] = 1.0 / (w[nz - 1] * (zf[nz] - zc[nz - 1]));
+    }
+  } else {
+    const int n = nz - 1;
+    al.assign(n, 0.0); ga.assign(n, 0.0); ex.assign(n, 0.0);
+    for (int u = 0; u < n; ++u) {
+      const int k = u + 1;
+      const double cv = zc[k] - zc[k - 1];
+      const double dn = 1.0 / (cv * w[k - 1]), up = 1.0 / (cv * w[k]);
+      if (u > 0) al[u] = dn; else ex[u] += dn;
+      if (u < n - 1) ga[u] = up; else ex[u] += up;
+    }
+  }
+}
+
+// modified wavenumbers 4 sin^2(pi q / n) / dx^2 in packed slot order
+std::vector<double> sigma_slots(int n, double len) {
+  std::vector<double> s(n);
+  const double dx = len / n;
+  for (int sl = 0; sl < n; ++sl) {
+    const int q = sl == 0 ? 0 : (sl == 1 ? n / 2 : sl / 2);
+    const long double v = std::sin((long double)M_PI * q / n);
+    s[sl] = (double)(4.0L * v * v / ((long double)dx * dx));
+  }
+  return s;
+}
+
+// exp(-2 pi i t / n), t = 0..n-1
+template <typename T>
+std::vector<T> twiddles(int n) {
+  std::vector<T> tw(n);
+  for (int t = 0; t < n; ++t) {
+    const long double a = 2.0L * (long double)M_PI * t / n;
+    tw[t].x = (decltype(tw[t].x))std::cos(a);
+    tw[t].y = (decltype(tw[t].y))(-std::sin(a));
+  }
+  return tw;
+}
+
+// one device block holding all small tables of a plan
+struct DevArena {
+  char *base = nullptr;
+  size_t used = 0, cap = 0;
+  std::vector<char> host;
+  template <typename T>
+  size_t add(const T *src, size_t n) {
+    const size_t off = (used + 255) & ~size_t(255);
+    used = off + n * sizeof(T);
+    if (host.size() < used) host.resize(used);
+    if (src) std::memcpy(host.data() + off, src, n * sizeof(T));
+    return off;
+  }
+  template <typename T>
+  T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+};
+
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[PF_STAGE_COUNT] = {};
+  int n[PF_STAGE_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void destroy() {
+    for (auto &p : pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
+    for (auto e : pool) hipEventDestroy(e);
+    pending.clear(); pool.clear();
+  }
+};
+
+// launches a stage, bracketed by events when timing is on
+template <typename F>
+pf_status run_stage(Timing &tm, hipStream_t st, int stage, F &&f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm.on) {
+    a = tm.get(); b = tm.get();
+    if (!a || !b) return fail(PF_ERR_DEVICE, "hipEventCreate failed");
+    PF_HIP(hipEventRecord(a, st));
+  }
+  hipError_t e = f();
+  if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stage %d launch failed: %s", stage, hipGetErrorString(e));
+  if (tm.on) {
+    PF_HIP(hipEventRecord(b, st));
+    tm.pending.push_back({stage, {a, b}});
+  }
+  return PF_OK;
+}
+
+pf_status timing_read(Timing &tm, hipStream_t st, double *ms, int32_t *count) {
+  if (!ms || !count) return fail(PF_ERR_ARG, "NULL output array");
+  PF_HIP(hipStreamSynchronize(st));
+  for (auto &p : tm.pending) {
+    float v = 0.f;
+    PF_HIP(hipEventElapsedTime(&v, p.second.first, p.second.second));
+    tm.ms[p.first] += v;
+    tm.n[p.first] += 1;
+    tm.pool.push_back(p.second.first);
+    tm.pool.push_back(p.second.second);
+  }
+  tm.pending.clear();
+  for (int s = 0; s < PF_STAGE_COUNT; ++s) {
+    ms[s] = tm.ms[s];
+    count[s] = tm.n[s];
+    tm.ms[s] = 0.0;
+    tm.n[s] = 0;
+  }
+  return PF_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+// ====================================================================== plans
+struct pf_poisson_plan {
+  int nx, ny, nz;
+  double lx, ly;
+  int prec, nref;
+  hipStream_t st;
+  int zchunk;
+  DevArena ar;
+  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_twx_f, o_twy_f, o_sums, o_sump, o_zm;
+  void *ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  Timing tm;
+  size_t npts() const { return (size_t)nx * ny * nz; }
+};
+
+struct pf_pcr_plan {
+  int n, prec, M, P, steps;
+  double s;
+  hipStream_t st;
+  std::vector<double> al, ga, ex;
+  DevArena ar;
+  size_t o_d[8], o_f[8], o_m[3];  // double tables, float tables, M-matrix rows
+  Timing tm;
+};
+
+struct pf_graph {
+  hipGraph_t g;
+  hipGraphExec_t ex;
+};
+
+namespace {
+
+// Algorithm 2, Step 1 (subtraction-free) for every chunk, then the
+// cyclic-reduction multipliers of the reduced system. Fills 8 tables:
+// fa, bg, ib, ra, rc (n each), k1, k2 (steps*2P), invd (2P).
+void pcr_tables(const pf_pcr_plan &pl, std::vector<std::vector<double>> &T) {
+  const int n = pl.n, P = pl.P, M = pl.M, np = P * M;
+  // rows past n are identity rows: they decouple because gamma[n-1] = 0
+  std::vector<double> A(np, 0.0), G(np, 0.0), E(np, 1.0);
+  for (int r = 0; r < n; ++r) {
+    A[r] = pl.s * pl.al[r];
+    G[r] = pl.s * pl.ga[r];
+    E[r] = 1.0 + pl.s * pl.ex[r];
+  }
+  T.assign(8, {});
+  for (int t = 0; t < 5; ++t) T[t].assign(np, 0.0);
+  std::vector<double> RA(2 * P), RG(2 * P), RE(2 * P);
+  for (int p = 0; p < P; ++p) {
+    const int r0 = p * M, m = M;
+    const double *al = &A[r0], *ga = &G[r0], *ep = &E[r0];
+    std::vector<double> b(m), a(m), c(m), ef(m), eta(m);
+    a[1] = al[1]; ef[1] = ep[1]; b[1] = ga[1] + al[1] + ep[1];
+    for (int i = 2; i < m; ++i) {
+      const double t = al[i] / b[i - 1];
+      a[i] = t * a[i - 1];
+      ef[i] = ep[i] + t * ef[i - 1];
+      b[i] = ga[i] + a[i] + ef[i];
+    }
+    c[m - 2] = ga[m - 2];
+    eta[m - 2] = ef[m - 2];
+    for (int i = m - 3; i >= 1; --i) {
+      const double t = ga[i] / b[i + 1];
+      a[i] = a[i] + t * a[i + 1];
+      c[i] = t * c[i + 1];
+      eta[i] = ef[i] + t * eta[i + 1];
+    }
+    const double t0 = ga[0] / b[1];
+    RA[2 * p] = al[0]; RG[2 * p] = t0 * c[1]; RE[2 * p] = ep[0] + t0 * eta[1];
+    RA[2 * p + 1] = a[m - 1]; RG[2 * p + 1] = ga[m - 1]; RE[2 * p + 1] = ef[m - 1];
+    for (int i = 2; i < m; ++i) T[0][r0 + i] = al[i] / b[i - 1];
+    for (int i = 0; i <= m - 3; ++i) T[1][r0 + i] = ga[i] / b[i + 1];
+    for (int i = 1; i <= m - 2; ++i) {
+      T[2][r0 + i] = 1.0 / b[i];
+      T[3][r0 + i] = a[i];
+      T[4][r0 + i] = c[i];
+    }
+  }
+  const int nr = 2 * P;
+  T[5].assign((size_t)pl.steps * nr, 0.0);
+  T[6].assign((size_t)pl.steps * nr, 0.0);
+  for (int st = 0; st < pl.steps; ++st) {
+    const int s = 1 << st;
+    std::vector<double> nA(nr), nG(nr), nE(nr);
+    for (int r = 0; r < nr; ++r) {
+      double k1 = 0.0, k2 = 0.0, em = 0.0, ep2 = 0.0, am = 0.0, gp = 0.0;
+      if (r - s >= 0) { k1 = RA[r] / (RA[r - s] + RG[r - s] + RE[r - s]); am = RA[r - s]; em = RE[r - s]; }
+      if (r + s < nr) { k2 = RG[r] / (RA[r + s] + RG[r + s] + RE[r + s]); gp = RG[r + s]; ep2 = RE[r + s]; }
+      T[5][(size_t)st * nr + r] = k1;
+      T[6][(size_t)st * nr + r] = k2;
+      nA[r] = k1 * am;
+      nG[r] = k2 * gp;
+      nE[r] = RE[r] + k1 * em + k2 * ep2;
+    }
+    RA = nA; RG = nG; RE = nE;
+  }
+  T[7].assign(nr, 0.0);
+  for (int r = 0; r < nr; ++r) T[7][r] = 1.0 / (RA[r] + RG[r] + RE[r]);
+}
+
+pf_status pcr_upload(pf_pcr_plan *pl, bool first) {
+  std::vector<std::vector<double>> T;
+  pcr_tables(*pl, T);
+  if (first) {
+    for (int t = 0; t < 8; ++t) pl->o_d[t] = pl->ar.add(T[t].data(), T[t].size());
+    for (int t = 0; t < 8; ++t) pl->o_f[t] = pl->ar.add<float>(nullptr, T[t].size());
+    for (int t = 0; t < 3; ++t) pl->o_m[t] = pl->ar.add<double>(nullptr, (size_t)pl->P * pl->M);
+  } else {
+    for (int t = 0; t < 8; ++t) std::memcpy(pl->ar.host.data() + pl->o_d[t], T[t].data(), T[t].size() * 8);
+  }
+  for (int t = 0; t < 8; ++t) {
+    float *f = reinterpret_cast<float *>(pl->ar.host.data() + pl->o_f[t]);
+    for (size_t i = 0; i < T[t].size(); ++i) f[i] = (float)T[t][i];
+  }
+  double *mA = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[0]);
+  double *mG = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[1]);
+  double *mE = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[2]);
+  for (int r = 0; r < pl->P * pl->M; ++r) {
+    const bool real = r < pl->n;
+    mA[r] = real ? pl->s * pl->al[r] : 0.0;
+    mG[r] = real ? pl->s * pl->ga[r] : 0.0;
+    mE[r] = real ? 1.0 + pl->s * pl->ex[r] : 1.0;
+  }
+  if (first) {
+    pl->ar.cap = pl->ar.used;
+    PF_HIP(hipMalloc((void **)&pl->ar.base, pl->ar.cap));
+    PF_HIP(hipMemcpy(pl->ar.base, pl->ar.host.data(), pl->ar.used, hipMemcpyHostToDevice));
+  } else {
+    PF_HIP(hipMemcpyAsync(pl->ar.base, pl->ar.host.data(), pl->ar.used, hipMemcpyHostToDevice, pl->st));
+  }
+  return PF_OK;
+}
+
+pf::HelmCoef helm_coef(const pf_pcr_plan *pl) {
+  pf::HelmCoef c;
+  const size_t *o = pl->prec == PF_FP64 ? pl->o_d : pl->o_f;
+  c.fa = pl->ar.base + o[0];
+  c.bg = pl->ar.base + o[1];
+  c.ib = pl->ar.base + o[2];
+  c.ra = pl->ar.base + o[3];
+  c.rc = pl->ar.base + o[4];
+  c.k1 = pl->ar.base + o[5];
+  c.k2 = pl->ar.base + o[6];
+  c.invd = pl->ar.base + o[7];
+  c.al = pl->ar.at<double>(pl->o_m[0]);
+  c.ga = pl->ar.at<double>(pl->o_m[1]);
+  c.ep = pl->ar.at<double>(pl->o_m[2]);
+  c.n = pl->n;
+  c.P = pl->P;
+  c.steps = pl->steps;
+  return c;
+}
+
+// rows per thread of the Poisson z solve; a column of up to 64 chunks of
+// 16 rows fits a 512-thread workgroup of 8 columns
+constexpr int kZChunk = 16;
+int zpad(int nz) { return (nz + kZChunk - 1) / kZChunk * kZChunk; }
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *pf_last_error(void) { return g_err.c_str(); }
+int32_t pf_abi_version(void) { return 1; }
+
+pf_status pf_grid_faces(const pf_grid *g, double *zf_out) {
+  pf_status s = check_grid(g, false);
+  if (s) return s;
+  if (!zf_out) return fail(PF_ERR_ARG, "zf_out is NULL");
+  std::vector<double> zf = faces_of(g);
+  std::memcpy(zf_out, zf.data(), zf.size() * sizeof(double));
+  return PF_OK;
+}
+
+pf_status pf_zop_rows(const pf_grid *g, int32_t bc, double *alpha, double *gamma, double *excess) {
+  pf_status s = check_grid(g, false);
+  if (s) return s;
+  if (bc < 0 || bc > 2) return fail(PF_ERR_ARG, "unknown boundary family %d", bc);
+  if (!alpha || !gamma || !excess) return fail(PF_ERR_ARG, "NULL output array");
+  std::vector<double> al, ga, ex;
+  zrows(faces_of(g), bc, al, ga, ex);
+  std::memcpy(alpha, al.data(), al.size() * 8);
+  std::memcpy(gamma, ga.data(), ga.size() * 8);
+  std::memcpy(excess, ex.data(), ex.size() * 8);
+  return PF_OK;
+}
+
+pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision, int32_t n_refine,
+                       void *stream, size_t *workspace_bytes) {
+  if (!out) return fail(PF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  pf_status s = check_grid(g, true);
+  if (s) return s;
+  if (precision < PF_FP64 || precision > PF_FP32_REFINE) return fail(PF_ERR_ARG, "unknown precision %d", precision);
+  if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
+    return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
+  if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
+  const int zc = kZChunk;
+  auto *pl = new pf_poisson_plan();
+  pl->nx = g->nx; pl->ny = g->ny; pl->nz = g->nz;
+  pl->lx = g->lx; pl->ly = g->ly;
+  pl->prec = precision;
+  pl->nref = precision == PF_FP32_REFINE ? n_refine : 0;
+  if (precision == PF_FP32_REFINE && n_refine == 0) pl->prec = PF_FP32;
+  pl->st = (hipStream_t)stream;
+  pl->zchunk = zc;
+  std::vector<double> zf = faces_of(g), al, ga, ex;
+  zrows(zf, PF_BC_NEUMANN, al, ga, ex);
+  // identity rows pad the z tables to whole chunks
+  al.resize(zpad(g->nz), 0.0);
+  ga.resize(zpad(g->nz), 0.0);
+  ex.resize(zpad(g->nz), 1.0);
+  std::vector<double> dzf(g->nz);
+  for (int k = 0; k < g->nz; ++k) dzf[k] = zf[k + 1] - zf[k];
+  auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
+  auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
+  auto twxf = twiddles<float2>(g->nx), twyf = twiddles<float2>(g->ny);
+  DevArena &A = pl->ar;
+  pl->o_zal = A.add(al.data(), al.size());
+  pl->o_zga = A.add(ga.data(), ga.size());
+  pl->o_zex = A.add(ex.data(), ex.size());
+  pl->o_dzf = A.add(dzf.data(), dzf.size());
+  pl->o_sx = A.add(sx.data(), sx.size());
+  pl->o_sy = A.add(sy.data(), sy.size());
+  pl->o_twx_d = A.add(twxd.data(), twxd.size());
+  pl->o_twy_d = A.add(twyd.data(), twyd.size());
+  pl->o_twx_f = A.add(twxf.data(), twxf.size());
+  pl->o_twy_f = A.add(twyf.data(), twyf.size());
+  pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * g->nz);
+  pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * g->nz);
+  pl->o_zm = A.add<double>(nullptr, (size_t)g->nz);
+  A.cap = A.used;
+  hipError_t e = hipMalloc((void **)&A.base, A.cap);
+  if (e == hipSuccess) e = hipMemcpy(A.base, A.host.data(), A.used, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (A.base) (void)hipFree(A.base);
+    delete pl;
+    return fail(PF_ERR_DEVICE, "plan tables: %s", hipGetErrorString(e));
+  }
+  const size_t N = pl->npts();
+  pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * N : 8 * N);
+  if (workspace_bytes) *workspace_bytes = pl->ws_need;
+  *out = pl;
+  return PF_OK;
+}
+
+pf_status poisson_set_workspace(pf_poisson_plan *pl, void *ws, size_t bytes) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (bytes < pl->ws_need) return fail(PF_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, pl->ws_need);
+  if (pl->ws_need && !ws) return fail(PF_ERR_WORKSPACE, "workspace is NULL");
+  if (ws && ((uintptr_t)ws & 255)) return fail(PF_ERR_ARG, "workspace must be 256-byte aligned");
+  pl->ws = ws;
+  pl->ws_bytes = bytes;
+  return PF_OK;
+}
+
+pf_status poisson_set_stream(pf_poisson_plan *pl, void *stream) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  pl->st = (hipStream_t)stream;
+  return PF_OK;
+}
+
+static pf_status poisson_check_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (!rhs || !p) return fail(PF_ERR_ARG, "rhs and p must be device pointers");
+  const size_t nb = pl->npts() * sizeof(double);
+  if (overlaps(rhs, nb, p, nb)) return fail(PF_ERR_ARG, "p must not overlap rhs");
+  if (pl->ws_need) {
+    if (!pl->ws || pl->ws_bytes < pl->ws_need)
+      return fail(PF_ERR_WORKSPACE, "workspace of %zu bytes required (poisson_set_workspace)", pl->ws_need);
+    if (overlaps(pl->ws, pl->ws_need, p, nb) || overlaps(pl->ws, pl->ws_need, rhs, nb))
+      return fail(PF_ERR_ARG, "workspace overlaps rhs or p");
+  }
+  if (((uintptr_t)rhs & 15) || ((uintptr_t)p & 15)) return fail(PF_ERR_ARG, "rhs and p must be 16-byte aligned");
+  return PF_OK;
+}
+
+static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p) {
+  const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
+  const long lines = (long)ny * nz;
+  const double scale = 1.0 / ((double)nx * ny);
+  hipStream_t st = pl->st;
+  const DevArena &A = pl->ar;
+  const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
+  const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
+  double *sums = A.at<double>(pl->o_sums), *sump = A.at<double>(pl->o_sump), *zm = A.at<double>(pl->o_zm);
+  Timing &tm = pl->tm;
+  pf_status s;
+#define STAGE(id, expr)                                      \
+  if ((s = run_stage(tm, st, id, [&]() { return (expr); }))) \
+    return s;
+  if (pl->prec == PF_FP64) {
+    const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<double>(nx, rhs, p, twx, sums, lines, st));
+    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, nullptr, dzf, zal, zga, zm, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, twy, st));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, zal, zga, zex, sx, sy, pl->zchunk, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, twy, st));
+    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, p, twx, zm, nullptr, scale, lines, st)));
+    return PF_OK;
+  }
+  const float2 *twx = A.at<float2>(pl->o_twx_f), *twy = A.at<float2>(pl->o_twy_f);
+  float *W0 = (float *)pl->ws;
+  if (pl->prec == PF_FP32) {
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W0, twx, sums, lines, st));
+    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, nullptr, dzf, zal, zga, zm, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, twy, st));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, zal, zga, zex, sx, sy, pl->zchunk, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, twy, st));
+    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, p, twx, zm, nullptr, scale, lines, st)));
+    return PF_OK;
+  }
+  // float32 solve, then one correction for the float64 residual
+  float *W1 = W0 + pl->npts();
+  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W1, twx, nullptr, lines, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
+  STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, W0, twx, nullptr, nullptr, scale, lines, st)));
+  const double idx2 = (double)nx * nx / (pl->lx * pl->lx), idy2 = (double)ny * ny / (pl->ly * pl->ly);
+  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, W0, W1, twx, sums, sump, zal, zga, idx2, idy2, st));
+  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, sump, dzf, zal, zga, zm, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
+  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W1, p, twx, zm, W0, scale, lines, st)));
+#undef STAGE
+  return PF_OK;
+}
+
+pf_status poisson_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
+  pf_status s = poisson_check_solve(pl, rhs, p);
+  if (s) return s;
+  return poisson_enqueue(pl, rhs, p);
+}
+
+pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans, const double *const *rhs,
+                                double *const *p) {
+  if (count < 0 || (count > 0 && (!plans || !rhs || !p))) return fail(PF_ERR_ARG, "bad batch arguments");
+  for (int t = 0; t < count; ++t) {
+    pf_status s = poisson_check_solve(plans[t], rhs[t], p[t]);
+    if (s) return s;
+  }
+  for (int t = 0; t < count; ++t) {
+    hipStream_t keep = plans[t]->st;
+    plans[t]->st = plans[0]->st;
+    pf_status s = poisson_enqueue(plans[t], rhs[t], p[t]);
+    plans[t]->st = keep;
+    if (s) return s;
+  }
+  return PF_OK;
+}
+
+pf_status poisson_destroy(pf_poisson_plan *pl) {
+  if (!pl) return PF_OK;
+  pl->tm.destroy();
+  if (pl->ar.base) (void)hipFree(pl->ar.base);
+  delete pl;
+  return PF_OK;
+}
+
+pf_status poisson_timing(pf_poisson_plan *pl, int32_t enable) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  pl->tm.on = enable != 0;
+  return PF_OK;
+}
+
+pf_status poisson_timing_read(pf_poisson_plan *pl, double *ms, int32_t *count) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  return timing_read(pl->tm, pl->st, ms, count);
+}
+
+// ------------------------------------------------------------ Helmholtz
+pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const double *gamma,
+                      const double *excess, double s, int32_t precision, int32_t chunk_rows, void *stream) {
+  if (!out) return fail(PF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 4) return fail(PF_ERR_ARG, "n must be >= 4 (got %d)", n);
+  if (!alpha || !gamma || !excess) return fail(PF_ERR_ARG, "coefficient arrays must be host pointers");
+  if (!(s >= 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and >= 0");
+  if (precision < PF_FP64 || precision > PF_FP32_REFINE) return fail(PF_ERR_ARG, "unknown precision %d", precision);
+  if (alpha[0] != 0.0 || gamma[n - 1] != 0.0) return fail(PF_ERR_ARG, "alpha[0] and gamma[n-1] must be 0");
+  for (int r = 0; r < n; ++r)
+    if (!(alpha[r] >= 0.0) || !(gamma[r] >= 0.0) || !(excess[r] >= 0.0) || !std::isfinite(alpha[r] + gamma[r] + excess[r]))
+      return fail(PF_ERR_ARG, "row %d: alpha, gamma, excess must be finite and >= 0", r);
+  int M = chunk_rows;
+  if (M == 0) {
+    M = 32;
+    for (int c : {8, 16, 32})
+      if ((n + c - 1) / c <= 16) { M = c; break; }
+  }
+  if (M != 8 && M != 16 && M != 32) return fail(PF_ERR_UNSUPPORTED, "chunk_rows must be 8, 16 or 32");
+  const int P = (n + M - 1) / M;  // rows past n are identity padding
+  if (P > 32) return fail(PF_ERR_UNSUPPORTED, "n=%d needs %d chunks of %d rows (max 32)", n, P, M);
+  auto *pl = new pf_pcr_plan();
+  pl->n = n; pl->prec = precision; pl->M = M; pl->P = P; pl->s = s;
+  pl->steps = 0;
+  while ((1 << pl->steps) < 2 * P) ++pl->steps;
+  pl->st = (hipStream_t)stream;
+  pl->al.assign(alpha, alpha + n);
+  pl->ga.assign(gamma, gamma + n);
+  pl->ex.assign(excess, excess + n);
+  pf_status st = pcr_upload(pl, true);
+  if (st) {
+    if (pl->ar.base) (void)hipFree(pl->ar.base);
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return PF_OK;
+}
+
+pf_status pcr_update_coef(pf_pcr_plan *pl, double s) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (!(s >= 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and >= 0");
+  PF_HIP(hipStreamSynchronize(pl->st));  // the host staging copy is reused
+  pl->s = s;
+  return pcr_upload(pl, false);
+}
+
+pf_status pcr_set_stream(pf_pcr_plan *pl, void *stream) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  pl->st = (hipStream_t)stream;
+  return PF_OK;
+}
+
+pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *const *fields, const int32_t *nx,
+                            const int32_t *ny) {
+  if (count < 1 || count > pf::kMaxHelmJobs) return fail(PF_ERR_ARG, "count must be 1..%d", pf::kMaxHelmJobs);
+  if (!plans || !fields || !nx || !ny) return fail(PF_ERR_ARG, "NULL argument array");
+  pf::HelmJob jobs[pf::kMaxHelmJobs];
+  int M = 0;
+  for (int t = 0; t < count; ++t) {
+    const pf_pcr_plan *pl = plans[t];
+    if (!pl || !fields[t]) return fail(PF_ERR_ARG, "plan or field %d is NULL", t);
+    if (nx[t] < 64 || nx[t] % 64 || ny[t] < 1) return fail(PF_ERR_ARG, "nx must be a positive multiple of 64, ny >= 1");
+    if (pl->M != plans[0]->M) return fail(PF_ERR_ARG, "batched plans must share chunk_rows");
+    if (pl->prec != plans[0]->prec) return fail(PF_ERR_ARG, "batched plans must share precision");
+    const size_t esz = pl->prec == PF_FP32 ? 4 : 8;
+    if ((uintptr_t)fields[t] % esz) return fail(PF_ERR_ARG, "field %d misaligned", t);
+    M = M > pl->M ? M : pl->M;
+    jobs[t].field = fields[t];
+    jobs[t].nx = nx[t];
+    jobs[t].ny = ny[t];
+    jobs[t].c = helm_coef(pl);
+  }
+  for (int t = 0; t < count; ++t)
+    for (int u = t + 1; u < count; ++u) {
+      const size_t a = (size_t)plans[t]->n * nx[t] * ny[t] * (plans[t]->prec == PF_FP32 ? 4 : 8);
+      const size_t b = (size_t)plans[u]->n * nx[u] * ny[u] * (plans[u]->prec == PF_FP32 ? 4 : 8);
+      if (overlaps(fields[t], a, fields[u], b)) return fail(PF_ERR_ARG, "fields %d and %d overlap", t, u);
+    }
+  const int prec = plans[0]->prec == PF_FP64 ? 0 : (plans[0]->prec == PF_FP32 ? 1 : 2);
+  pf_pcr_plan *p0 = plans[0];
+  return run_stage(p0->tm, p0->st, PF_STAGE_PCR_APPLY,
+                   [&]() { return pf::launch_helm(prec, M, count, jobs, p0->st); });
+}
+
+pf_status pcr_apply(pf_pcr_plan *pl, void *field, int32_t nx, int32_t ny) {
+  pf_pcr_plan *pls[1] = {pl};
+  void *f[1] = {field};
+  int32_t a[1] = {nx}, b[1] = {ny};
+  return pcr_apply_batched(1, pls, f, a, b);
+}
+
+pf_status pcr_destroy(pf_pcr_plan *pl) {
+  if (!pl) return PF_OK;
+  pl->tm.destroy();
+  if (pl->ar.base) (void)hipFree(pl->ar.base);
+  delete pl;
+  return PF_OK;
+}
+
+pf_status pcr_timing(pf_pcr_plan *pl, int32_t enable) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  pl->tm.on = enable != 0;
+  return PF_OK;
+}
+
+pf_status pcr_timing_read(pf_pcr_plan *pl, double *ms, int32_t *count) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  return timing_read(pl->tm, pl->st, ms, count);
+}
+
+// ---------------------------------------------------------------- graphs
+pf_status pf_graph_begin(void *stream) {
+  if (!stream) return fail(PF_ERR_ARG, "capture needs a non-default stream");
+  PF_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  return PF_OK;
+}
+
+pf_status pf_graph_end(void *stream, pf_graph **out) {
+  if (!stream || !out) return fail(PF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  PF_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(PF_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = new pf_graph{g, ex};
+  return PF_OK;
+}
+
+pf_status pf_graph_launch(pf_graph *gr, void *stream) {
+  if (!gr) return fail(PF_ERR_ARG, "graph is NULL");
+  PF_HIP(hipGraphLaunch(gr->ex, (hipStream_t)stream));
+  return PF_OK;
+}
+
+pf_status pf_graph_destroy(pf_graph *gr) {
+  if (!gr) return PF_OK;
+  (void)hipGraphExecDestroy(gr->ex);
+  (void)hipGraphDestroy(gr->g);
+  delete gr;
+  return PF_OK;
+}
+
+pf_status pf_copy_kernel(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || bytes % 16) return fail(PF_ERR_ARG, "copy needs device pointers and a multiple of 16 bytes");
+  if (overlaps(dst, bytes, src, bytes)) return fail(PF_ERR_ARG, "copy ranges overlap");
+  PF_HIP(pf::launch_copy(dst, src, bytes, (hipStream_t)stream));
+  return PF_OK;
+}
+
+}  // extern "C"

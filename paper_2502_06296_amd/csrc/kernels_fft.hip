@@ -1,0 +1,415 @@
+// Line transforms of the Poisson solve (paper Sec. 2.2.3 steps 2, 3, 7, 8;
+// packed real layout of App. A).
+//
+// x direction: a workgroup takes LPW consecutive pairs of real x lines, so
+// every global access is a run of contiguous values. y direction: a
+// workgroup takes one z plane and 2*LPW adjacent x slots and transforms the
+// LPW complex columns formed by pairing neighbouring slots; each row access
+// is 2*LPW contiguous values (128 bytes by default). The x<->y permutation of
+// the pencil method is therefore never materialised: the y kernel gathers
+// its columns straight from the x-packed array and writes them back in place.
+#include "pf_internal.hpp"
+
+namespace pf {
+
+bool fft_size_supported(int n) {
+  switch (n) {
+#define PF_CASE(N) case N:
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+// ----------------------------------------------------------- x forward
+template <typename T, int N, int TPL, int LPW, bool SUMS>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
+                                                   const cplx<T> *__restrict__ tw,
+                                                   double *__restrict__ sums, long ncl) {
+  __shared__ cplx<T> lds[LPW * lds_len(N)];
+  __shared__ double red[SUMS ? 2 * LPW * TPL : 2];
+  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
+  const long c = (long)blockIdx.x * LPW + l;
+  const bool ok = c < ncl;
+  cplx<T> *buf = lds + l * lds_len(N);
+  double sa = 0.0, sb = 0.0;
+  if (ok) {
+    const double *a = in + (size_t)(2 * c) * N;
+    const double *b = a + N;
+#pragma unroll
+    for (int s = 0; s < N / TPL; ++s) {
+      const int pos = t + s * TPL;
+      const double va = a[pos], vb = b[pos];
+      if (SUMS) { sa += va; sb += vb; }
+      buf[lds_idx(pos)] = mkc<T>((T)va, (T)vb);
+    }
+  }
+  if (SUMS) { red[2 * tid] = sa; red[2 * tid + 1] = sb; }
+  __syncthreads();
+  fft_line<T, N, TPL, false>(buf, tw, t);
+  if (!ok) return;
+  if (SUMS && t == 0) {
+    double A = 0.0, B = 0.0;
+    for (int u = 0; u < TPL; ++u) { A += red[2 * (l * TPL + u)]; B += red[2 * (l * TPL + u) + 1]; }
+    sums[2 * c] = A;
+    sums[2 * c + 1] = B;
+  }
+  T *oa = out + (size_t)(2 * c) * N;
+  T *ob = oa + N;
+  for (int q = t; q < N / 2; q += TPL) {
+    cplx<T> A, B;
+    if (q == 0) {
+      const cplx<T> z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
+      A = mkc<T>(z0.x, zh.x);
+      B = mkc<T>(z0.y, zh.y);
+    } else {
+      split_pair<T>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+    }
+    *reinterpret_cast<cplx<T> *>(oa + 2 * q) = A;
+    *reinterpret_cast<cplx<T> *>(ob + 2 * q) = B;
+  }
+}
+
+// -------------------------------------- x forward of the 7-point residual
+// r = f - L7 p0 in float64 from the float32 iterate p0 (Neumann z rows:
+// alpha_0 = 0, gamma_{nz-1} = 0, no excess), then the float32 transform of r.
+// The two real lines of a pair are (j, k) and (j+1, k).
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
+    const double *__restrict__ f, const float *__restrict__ p0, float *__restrict__ out,
+    const cplx<float> *__restrict__ tw, double *__restrict__ sums_r, double *__restrict__ sums_p,
+    const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
+    double idy2, long ncl) {
+  __shared__ cplx<float> lds[LPW * lds_len(N)];
+  __shared__ double red[4 * LPW * TPL];
+  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
+  const long c = (long)blockIdx.x * LPW + l;
+  const bool ok = c < ncl;
+  cplx<float> *buf = lds + l * lds_len(N);
+  double sr[2] = {0.0, 0.0}, sp[2] = {0.0, 0.0};
+  if (ok) {
+    const long line0 = 2 * c;
+    const int k = (int)(line0 / ny);
+    const int j0 = (int)(line0 % ny);
+    const double ak = zal[k], gk = zga[k];
+    const double dk = ak + gk;
+    float rv[2][N / TPL];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = j0 + h;
+      const size_t row = ((size_t)k * ny + j) * N;
+      const size_t rym = ((size_t)k * ny + (j == 0 ? ny - 1 : j - 1)) * N;
+      const size_t ryp = ((size_t)k * ny + (j == ny - 1 ? 0 : j + 1)) * N;
+      const size_t plane = (size_t)ny * N;
+#pragma unroll
+      for (int s = 0; s < N / TPL; ++s) {
+        const int i = t + s * TPL;
+        const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+        const double pc = p0[row + i];
+        const double lx = ((double)p0[row + ip] - 2.0 * pc + (double)p0[row + im]) * idx2;
+        const double ly = ((double)p0[ryp + i] - 2.0 * pc + (double)p0[rym + i]) * idy2;
+        double lzv = -dk * pc;
+        if (k > 0) lzv += ak * (double)p0[row - plane + i];
+        if (k < nz - 1) lzv += gk * (double)p0[row + plane + i];
+        const double r = f[row + i] - (lx + ly + lzv);
+        sr[h] += r;
+        sp[h] += pc;
+        rv[h][s] = (float)r;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < N / TPL; ++s) buf[lds_idx(t + s * TPL)] = mkc<float>(rv[0][s], rv[1][s]);
+  }
+  red[4 * tid + 0] = sr[0];
+  red[4 * tid + 1] = sr[1];
+  red[4 * tid + 2] = sp[0];
+  red[4 * tid + 3] = sp[1];
+  __syncthreads();
+  fft_line<float, N, TPL, false>(buf, tw, t);
+  if (!ok) return;
+  if (t == 0) {
+    double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    for (int u = 0; u < TPL; ++u) {
+      const double *rr = red + 4 * (l * TPL + u);
+      a0 += rr[0]; a1 += rr[1]; b0 += rr[2]; b1 += rr[3];
+    }
+    sums_r[2 * c] = a0; sums_r[2 * c + 1] = a1;
+    sums_p[2 * c] = b0; sums_p[2 * c + 1] = b1;
+  }
+  float *oa = out + (size_t)(2 * c) * N;
+  float *ob = oa + N;
+  for (int q = t; q < N / 2; q += TPL) {
+    cplx<float> A, B;
+    if (q == 0) {
+      const cplx<float> z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
+      A = mkc<float>(z0.x, zh.x);
+      B = mkc<float>(z0.y, zh.y);
+    } else {
+      split_pair<float>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+    }
+    *reinterpret_cast<cplx<float> *>(oa + 2 * q) = A;
+    *reinterpret_cast<cplx<float> *>(ob + 2 * q) = B;
+  }
+}
+
+// ------------------------------------------------------------- y forward
+template <typename T, int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data, const cplx<T> *__restrict__ tw,
+                                                   int nx, int nib) {
+  __shared__ cplx<T> lds[LPW * lds_len(N)];
+  constexpr int NT = TPL * LPW;
+  const int tid = threadIdx.x;
+  const int ib = blockIdx.x % nib;
+  const long k = blockIdx.x / nib;
+  T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
+#pragma unroll
+  for (int s = 0; s < N / TPL; ++s) {
+    const int e = tid + s * NT;
+    const int l = e % LPW, y = e / LPW;
+    lds[l * lds_len(N) + lds_idx(y)] = *reinterpret_cast<const cplx<T> *>(base + (size_t)y * nx + 2 * l);
+  }
+  __syncthreads();
+  const int l = tid / TPL, t = tid % TPL;
+  fft_line<T, N, TPL, false>(lds + l * lds_len(N), tw, t);
+#pragma unroll
+  for (int s = 0; s < N / (2 * TPL); ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, q = e / LPW;
+    const cplx<T> *buf = lds + l2 * lds_len(N);
+    cplx<T> r0, r1;
+    if (q == 0) {
+      r0 = buf[lds_idx(0)];
+      r1 = buf[lds_idx(N / 2)];
+    } else {
+      cplx<T> A, B;
+      split_pair<T>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+      r0 = mkc<T>(A.x, B.x);
+      r1 = mkc<T>(A.y, B.y);
+    }
+    *reinterpret_cast<cplx<T> *>(base + (size_t)(2 * q) * nx + 2 * l2) = r0;
+    *reinterpret_cast<cplx<T> *>(base + (size_t)(2 * q + 1) * nx + 2 * l2) = r1;
+  }
+}
+
+// ------------------------------------------------------------- y inverse
+template <typename T, int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data, const cplx<T> *__restrict__ tw,
+                                                   int nx, int nib) {
+  __shared__ cplx<T> lds[LPW * lds_len(N)];
+  constexpr int NT = TPL * LPW;
+  const int tid = threadIdx.x;
+  const int ib = blockIdx.x % nib;
+  const long k = blockIdx.x / nib;
+  T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
+#pragma unroll
+  for (int s = 0; s < N / (2 * TPL); ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, q = e / LPW;
+    cplx<T> *buf = lds + l2 * lds_len(N);
+    const cplx<T> r0 = *reinterpret_cast<const cplx<T> *>(base + (size_t)(2 * q) * nx + 2 * l2);
+    const cplx<T> r1 = *reinterpret_cast<const cplx<T> *>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
+    if (q == 0) {
+      buf[lds_idx(0)] = r0;
+      buf[lds_idx(N / 2)] = r1;
+    } else {
+      cplx<T> zq, zn;
+      join_pair<T>(mkc<T>(r0.x, r1.x), mkc<T>(r0.y, r1.y), zq, zn);
+      buf[lds_idx(q)] = zq;
+      buf[lds_idx(N - q)] = zn;
+    }
+  }
+  __syncthreads();
+  const int l = tid / TPL, t = tid % TPL;
+  fft_line<T, N, TPL, true>(lds + l * lds_len(N), tw, t);
+#pragma unroll
+  for (int s = 0; s < N / TPL; ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, y = e / LPW;
+    *reinterpret_cast<cplx<T> *>(base + (size_t)y * nx + 2 * l2) = lds[l2 * lds_len(N) + lds_idx(y)];
+  }
+}
+
+// ------------------------------------------------------------- x inverse
+template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool ADDP0>
+// in and out may be the same array (each workgroup reads its line pair into
+// LDS before writing it), so they are not marked restrict.
+__global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
+                                                   const cplx<TS> *__restrict__ tw,
+                                                   const double *__restrict__ zm,
+                                                   const float *__restrict__ p0, double scale,
+                                                   int ny, long ncl) {
+  __shared__ cplx<TS> lds[LPW * lds_len(N)];
+  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
+  const long c = (long)blockIdx.x * LPW + l;
+  const bool ok = c < ncl;
+  cplx<TS> *buf = lds + l * lds_len(N);
+  if (ok) {
+    const TS *a = in + (size_t)(2 * c) * N;
+    const TS *b = a + N;
+    for (int q = t; q < N / 2; q += TPL) {
+      const cplx<TS> A = *reinterpret_cast<const cplx<TS> *>(a + 2 * q);
+      const cplx<TS> B = *reinterpret_cast<const cplx<TS> *>(b + 2 * q);
+      if (q == 0) {
+        buf[lds_idx(0)] = mkc<TS>(A.x, B.x);
+        buf[lds_idx(N / 2)] = mkc<TS>(A.y, B.y);
+      } else {
+        cplx<TS> zq, zn;
+        join_pair<TS>(A, B, zq, zn);
+        buf[lds_idx(q)] = zq;
+        buf[lds_idx(N - q)] = zn;
+      }
+    }
+  }
+  __syncthreads();
+  fft_line<TS, N, TPL, true>(buf, tw, t);
+  if (!ok) return;
+  double add = 0.0;
+  if (ADDZ) add = zm[(2 * c) / ny];
+  TO *oa = out + (size_t)(2 * c) * N;
+  TO *ob = oa + N;
+  const float *pa = ADDP0 ? p0 + (size_t)(2 * c) * N : nullptr;
+  const float *pb = ADDP0 ? pa + N : nullptr;
+#pragma unroll
+  for (int s = 0; s < N / TPL; ++s) {
+    const int pos = t + s * TPL;
+    const cplx<TS> z = buf[lds_idx(pos)];
+    double va = (double)z.x * scale + add;
+    double vb = (double)z.y * scale + add;
+    if (ADDP0) { va += (double)pa[pos]; vb += (double)pb[pos]; }
+    oa[pos] = (TO)va;
+    ob[pos] = (TO)vb;
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, double *sums, long lines,
+                       hipStream_t st) {
+  const long ncl = lines / 2;
+  switch (nx) {
+#define PF_CASE(N)                                                                              \
+  case N: {                                                                                     \
+    constexpr int TPL = x_tpl<T>(N), LPW = x_lpw<T>(N);                                         \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
+    if (sums)                                                                                   \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, in, out, tw, \
+                         sums, ncl);                                                            \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, false>), g, dim3(TPL * LPW), 0, st, in, out,    \
+                         tw, sums, ncl);                                                        \
+    return hipGetLastError();                                                                   \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const float *p0, float *out,
+                             const cplx<float> *tw, double *sums_r, double *sums_p0,
+                             const double *zal, const double *zga, double idx2, double idy2,
+                             hipStream_t st) {
+  const long ncl = (long)ny * nz / 2;
+  switch (nx) {
+#define PF_CASE(N)                                                                               \
+  case N: {                                                                                      \
+    constexpr int TPL = x_tpl<float>(N), LPW = x_lpw<float>(N) > 2 ? 2 : x_lpw<float>(N);        \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
+    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), g, dim3(TPL * LPW), 0, st, f, p0, out, tw,   \
+                       sums_r, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                      \
+    return hipGetLastError();                                                                    \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st) {
+  switch (ny) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = y_tpl<T>(N), LPW = y_lpw<T>(N);                                       \
+    if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
+    const int nib = nx / (2 * LPW);                                                           \
+    hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
+                       dim3(TPL * LPW), 0, st, data, tw, nx, nib);                            \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st) {
+  switch (ny) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = y_tpl<T>(N), LPW = y_lpw<T>(N);                                       \
+    if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
+    const int nib = nx / (2 * LPW);                                                           \
+    hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
+                       dim3(TPL * LPW), 0, st, data, tw, nx, nib);                            \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename TS, typename TO>
+hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<TS> *tw, const double *zm,
+                       const float *p0, double scale, long lines, hipStream_t st) {
+  const long ncl = lines / 2;
+  switch (nx) {
+#define PF_CASE(N)                                                                              \
+  case N: {                                                                                     \
+    constexpr int TPL = x_tpl<TS>(N), LPW = x_lpw<TS>(N);                                       \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
+    if (zm && p0)                                                                               \
+      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
+                         zm, p0, scale, ny, ncl);                                               \
+    else if (zm)                                                                                \
+      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, false>), g, b, 0, st, in, out, tw, \
+                         zm, p0, scale, ny, ncl);                                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, false, false>), g, b, 0, st, in, out,    \
+                         tw, zm, p0, scale, ny, ncl);                                           \
+    return hipGetLastError();                                                                   \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_xfwd<double>(int, const double *, double *, const cplx<double> *,
+                                        double *, long, hipStream_t);
+template hipError_t launch_xfwd<float>(int, const double *, float *, const cplx<float> *, double *,
+                                       long, hipStream_t);
+template hipError_t launch_yfwd<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
+template hipError_t launch_yfwd<float>(int, int, int, float *, const cplx<float> *, hipStream_t);
+template hipError_t launch_yinv<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
+template hipError_t launch_yinv<float>(int, int, int, float *, const cplx<float> *, hipStream_t);
+template hipError_t launch_xinv<double, double>(int, int, const double *, double *,
+                                                const cplx<double> *, const double *,
+                                                const float *, double, long, hipStream_t);
+template hipError_t launch_xinv<float, float>(int, int, const float *, float *, const cplx<float> *,
+                                              const double *, const float *, double, long,
+                                              hipStream_t);
+template hipError_t launch_xinv<float, double>(int, int, const float *, double *,
+                                               const cplx<float> *, const double *, const float *,
+                                               double, long, hipStream_t);
+
+}  // namespace pf

@@ -1,0 +1,437 @@
+// Wall-normal solves (paper Sec. 2.2.3 steps 4-6, Sec. 2.2.4, Algorithm 2).
+//
+// Both the Poisson z solve and the Helmholtz apply use the partition method
+// of the paper inside one workgroup: each column of N_z unknowns is cut into
+// P chunks, one thread per chunk holds its m = N_z/P values in registers,
+// reduces them to the two boundary rows of the chunk, the 2P boundary rows of
+// every column form a tridiagonal system that is solved by parallel cyclic
+// reduction in LDS, and each thread rebuilds its interior. Where the paper
+// exchanges the boundary rows between GPUs with an all-to-all, here they only
+// cross the LDS of one compute unit.
+//
+// All rows are sign-normalised M-matrix rows
+//   -alpha x[k-1] + (alpha + gamma + eps) x[k] - gamma x[k+1] = d,
+// alpha, gamma, eps >= 0, and every elimination keeps each diagonal as a sum
+// of non-negative parts (a forward excess, a backward excess), so no pivot is
+// ever formed by subtraction.
+#include "pf_internal.hpp"
+
+namespace pf {
+
+// ------------------------------------------------------- Poisson z solve
+// Thread (col, ch): column i = ib*TI + col of plane j, rows [ch*M, ch*M+M)
+// of the column. Columns are padded to P*M rows with identity rows (alpha =
+// gamma = 0, excess = 1), which decouple exactly because the last real row
+// has gamma = 0; the padding keeps every loop and register index a compile-
+// time constant. The chunk's Step 1 coefficients depend on the column's
+// shift lambda = sx[i] + sy[j] (the modified wavenumbers), so they are
+// rebuilt in registers: an upward sweep gives the reduced first row, a
+// downward sweep (Algorithm 2, Step 1 and the forward half of Step 2, fused)
+// gives the reduced last row and leaves the forward-reduced d and the pivots
+// 1/b. After the reduced solve the interior follows from one forward and one
+// backward substitution with the chunk's end values as Dirichlet data.
+template <typename TS, int M, int TI>
+__global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, int ny, int nz, int P,
+                                                 const double *__restrict__ zal,
+                                                 const double *__restrict__ zga,
+                                                 const double *__restrict__ zex,
+                                                 const double *__restrict__ sx,
+                                                 const double *__restrict__ sy) {
+  extern __shared__ double red[];  // [4][2P][TI]: alpha, gamma, eps, d of the reduced rows
+  const int nr = 2 * P;
+  double *RA = red, *RG = red + nr * TI, *RE = red + 2 * nr * TI, *RD = red + 3 * nr * TI;
+  const int nib = nx / TI;
+  const int ib = blockIdx.x % nib;
+  const int j = blockIdx.x / nib;
+  const int col = threadIdx.x % TI;
+  const int ch = threadIdx.x / TI;
+  const int i = ib * TI + col;
+  const int r0 = ch * M;
+  const size_t plane = (size_t)nx * ny;
+  TS *cp = data + (size_t)j * nx + i + (size_t)r0 * plane;
+  const bool zero_col = (i == 0 && j == 0);
+  const double lam = zero_col ? 1.0 : sx[i] + sy[j];
+  const double *al = zal + r0, *ga = zga + r0, *ex = zex + r0;
+
+  double d[M], ib_[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    d[q] = (r0 + q < nz) ? -(double)cp[(size_t)q * plane] : 0.0;
+    ib_[q] = 0.0;
+  }
+
+  // upward sweep: the first row reduced to couple x_{-1}, x_0, x_{M-1}
+  double uc = ga[M - 2];
+  double ue = ex[M - 2] + lam;
+  double ud = d[M - 2];
+  double ub = al[M - 2] + uc + ue;
+#pragma unroll
+  for (int q = M - 3; q >= 0; --q) {
+    const double tq = ga[q] / ub;
+    uc = tq * uc;
+    ue = (ex[q] + lam) + tq * ue;
+    ud = d[q] + tq * ud;
+    ub = al[q] + uc + ue;
+  }
+  // downward sweep: pivots b_q = gamma_q + |a_q| + e'_q, forward-reduced d
+  double fa = al[1];
+  double fe = ex[1] + lam;
+  ib_[1] = 1.0 / (ga[1] + fa + fe);
+#pragma unroll
+  for (int q = 2; q < M; ++q) {
+    const double tq = al[q] * ib_[q - 1];
+    fa = tq * fa;
+    fe = (ex[q] + lam) + tq * fe;
+    d[q] = d[q] + tq * d[q - 1];
+    ib_[q] = 1.0 / (ga[q] + fa + fe);
+  }
+
+  // reduced rows 2ch (first) and 2ch+1 (last) of this column
+  double ra0 = al[0], rg0 = uc, re0 = ue, rd0 = ud;
+  double ra1 = fa, rg1 = ga[M - 1], re1 = fe, rd1 = d[M - 1];
+  const int w0 = (2 * ch) * TI + col, w1 = (2 * ch + 1) * TI + col;
+  // parallel cyclic reduction over the 2P rows: after the step of stride s
+  // every row couples only to rows 2s away; the sums stay subtraction-free
+  for (int s = 1; s < nr; s *= 2) {
+    RA[w0] = ra0; RG[w0] = rg0; RE[w0] = re0; RD[w0] = rd0;
+    RA[w1] = ra1; RG[w1] = rg1; RE[w1] = re1; RD[w1] = rd1;
+    __syncthreads();
+    double na[2], ng[2], ne[2], nd[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = 2 * ch + h;
+      const double a = h ? ra1 : ra0, g = h ? rg1 : rg0, e = h ? re1 : re0, dd = h ? rd1 : rd0;
+      double k1 = 0.0, k2 = 0.0, am = 0.0, em = 0.0, dm = 0.0, gp = 0.0, ep = 0.0, dp = 0.0;
+      if (r - s >= 0) {
+        const int o = (r - s) * TI + col;
+        am = RA[o]; em = RE[o]; dm = RD[o];
+        k1 = a / (am + RG[o] + em);
+      }
+      if (r + s < nr) {
+        const int o = (r + s) * TI + col;
+        gp = RG[o]; ep = RE[o]; dp = RD[o];
+        k2 = g / (RA[o] + gp + ep);
+      }
+      na[h] = k1 * am;
+      ng[h] = k2 * gp;
+      ne[h] = e + k1 * em + k2 * ep;
+      nd[h] = dd + k1 * dm + k2 * dp;
+    }
+    __syncthreads();
+    ra0 = na[0]; rg0 = ng[0]; re0 = ne[0]; rd0 = nd[0];
+    ra1 = na[1]; rg1 = ng[1]; re1 = ne[1]; rd1 = nd[1];
+  }
+  const double x0 = rd0 / (ra0 + rg0 + re0);
+  const double xl = rd1 / (ra1 + rg1 + re1);
+
+  // interior: y_q = (d_q + |a_q| x0) / b_q forward, x_q = y_q + gamma_q x_{q+1} / b_q backward
+  double a = al[1];
+#pragma unroll
+  for (int q = 1; q < M - 1; ++q) {
+    if (q >= 2) a = al[q] * ib_[q - 1] * a;
+    d[q] = (d[q] + a * x0) * ib_[q];
+  }
+  d[M - 1] = xl;
+#pragma unroll
+  for (int q = M - 2; q >= 1; --q) d[q] = d[q] + ga[q] * ib_[q] * d[q + 1];
+  d[0] = x0;
+#pragma unroll
+  for (int q = 0; q < M; ++q)
+    if (r0 + q < nz) cp[(size_t)q * plane] = (TS)(zero_col ? 0.0 : d[q]);
+}
+
+template <typename TS>
+hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
+                         const double *zex, const double *sx, const double *sy, int chunk_rows,
+                         hipStream_t st) {
+  // the z tables hold P*M rows (identity padding past nz)
+  if (chunk_rows != 16) return hipErrorInvalidValue;
+  constexpr int M = 16;
+  const int P = (nz + M - 1) / M;
+  const int TI = P * 16 <= 512 ? 16 : 8;
+  if (P * TI > 512 || nx % TI) return hipErrorInvalidValue;
+  const size_t shm = (size_t)4 * 2 * P * TI * sizeof(double);
+  dim3 g((unsigned)((long)(nx / TI) * ny)), b(P * TI);
+  if (TI == 16)
+    hipLaunchKernelGGL((k_zsolve<TS, M, 16>), g, b, shm, st, data, nx, ny, nz, P, zal, zga, zex, sx, sy);
+  else
+    hipLaunchKernelGGL((k_zsolve<TS, M, 8>), g, b, shm, st, data, nx, ny, nz, P, zal, zga, zex, sx, sy);
+  return hipGetLastError();
+}
+template hipError_t launch_zsolve<double>(int, int, int, double *, const double *, const double *,
+                                          const double *, const double *, const double *, int,
+                                          hipStream_t);
+template hipError_t launch_zsolve<float>(int, int, int, float *, const double *, const double *,
+                                         const double *, const double *, const double *, int,
+                                         hipStream_t);
+
+// ----------------------------------------------------------- zero mode
+// One workgroup. Plane means of the right-hand side (and of the iterate,
+// for a correction) from the float64 line sums; the right-hand side is
+// projected onto the range of L_z (zero dzf-weighted mean); the singular
+// Neumann system is solved with its last equation replaced by x[nz-1] = 0,
+// then shifted so that the total field has zero dzf-weighted mean.
+__global__ __launch_bounds__(256) void k_zero_mode(const double *__restrict__ sums,
+                                                   const double *__restrict__ sums_p0,
+                                                   const double *__restrict__ dzf,
+                                                   const double *__restrict__ zal,
+                                                   const double *__restrict__ zga,
+                                                   double *__restrict__ zm, int ny, int nz,
+                                                   double inv_nxny) {
+  extern __shared__ double sh[];  // R[nz], Pm[nz], Y[nz], RT[nz]
+  double *R = sh, *Pm = sh + nz, *Y = sh + 2 * nz, *RT = sh + 3 * nz;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < nz; k += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    const double *s = sums + (size_t)k * ny;
+    for (int j = 0; j < ny; ++j) a += s[j];
+    if (sums_p0) {
+      const double *sp = sums_p0 + (size_t)k * ny;
+      for (int j = 0; j < ny; ++j) b += sp[j];
+    }
+    R[k] = a * inv_nxny;
+    Pm[k] = b * inv_nxny;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double wr = 0.0, w = 0.0;
+  for (int k = 0; k < nz; ++k) { wr += dzf[k] * R[k]; w += dzf[k]; }
+  const double c = wr / w;
+  // rows 0..nz-2 of -L_z x = -(R - c), with x[nz-1] = 0 (row nz-2 keeps its
+  // gamma on the diagonal). No row has an excess, so the pivot of row k is
+  // gamma_k + g_k with g_0 = 0 and g_k = alpha_k g_{k-1} / pivot_{k-1}.
+  double g = 0.0, piv = 1.0, y = 0.0;
+  for (int k = 0; k < nz - 1; ++k) {
+    g = (k == 0) ? 0.0 : zal[k] * g / piv;
+    piv = zga[k] + g;
+    y = (-(R[k] - c) + zal[k] * y) / piv;
+    Y[k] = y;
+    RT[k] = zga[k] / piv;
+  }
+  double x = 0.0;
+  R[nz - 1] = 0.0;
+  for (int k = nz - 2; k >= 0; --k) {
+    x = Y[k] + (k == nz - 2 ? 0.0 : RT[k] * x);
+    R[k] = x;
+  }
+  double wm = 0.0;
+  for (int k = 0; k < nz; ++k) wm += dzf[k] * (R[k] + Pm[k]);
+  const double shift = wm / w;
+  for (int k = 0; k < nz; ++k) zm[k] = R[k] - shift;
+}
+
+hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *sums_p0,
+                            const double *dzf, const double *zal, const double *zga, double *zm,
+                            hipStream_t st) {
+  const size_t shm = (size_t)4 * nz * sizeof(double);
+  hipLaunchKernelGGL(k_zero_mode, dim3(1), dim3(256), shm, st, sums, sums_p0, dzf, zal, zga, zm, ny,
+                     nz, 1.0 / ((double)nx * (double)ny));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- Helmholtz apply
+// Algorithm 2, Steps 2-4, with the Step 1 coefficients of pcr_prepare. One
+// wave (64 consecutive columns) per chunk of M rows, so every coefficient
+// address is uniform across the wave. Columns are padded to P*M rows with
+// identity rows (see the Poisson z solve). The reduced 2P-row system is the
+// same for all columns; its cyclic-reduction multipliers are precomputed,
+// and only the right-hand sides cross LDS.
+template <typename TC, int M>
+__device__ __forceinline__ void helm_solve_regs(TC (&d)[M], TC &x0, TC &xl, int r0,
+                                                const TC *__restrict__ fa, const TC *__restrict__ bg,
+                                                const TC *__restrict__ ib, const TC *__restrict__ ra,
+                                                const TC *__restrict__ rc, const TC *__restrict__ k1,
+                                                const TC *__restrict__ k2, const TC *__restrict__ invd,
+                                                int P, int steps, TC *RD, int w, int lane, bool active,
+                                                int CW) {
+  // Step 2: forward and backward reduction of d
+  if (active) {
+#pragma unroll
+    for (int q = 2; q < M; ++q) d[q] = d[q] + fa[r0 + q] * d[q - 1];
+#pragma unroll
+    for (int q = M - 3; q >= 0; --q) d[q] = d[q] + bg[r0 + q] * d[q + 1];
+  }
+  // Step 3: the reduced system; rows 2w and 2w+1 belong to this wave
+  const int nr = 2 * P;
+  x0 = d[0];
+  xl = d[M - 1];
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    if (active) {
+      RD[(2 * w) * CW + lane] = x0;
+      RD[(2 * w + 1) * CW + lane] = xl;
+    }
+    __syncthreads();
+    if (active) {
+      const int ra0 = 2 * w, ra1 = 2 * w + 1;
+      TC n0 = x0, n1 = xl;
+      if (ra0 - s >= 0) n0 += k1[st * nr + ra0] * RD[(ra0 - s) * CW + lane];
+      if (ra0 + s < nr) n0 += k2[st * nr + ra0] * RD[(ra0 + s) * CW + lane];
+      if (ra1 - s >= 0) n1 += k1[st * nr + ra1] * RD[(ra1 - s) * CW + lane];
+      if (ra1 + s < nr) n1 += k2[st * nr + ra1] * RD[(ra1 + s) * CW + lane];
+      x0 = n0;
+      xl = n1;
+    }
+    __syncthreads();
+  }
+  if (active) {
+    x0 = x0 * invd[2 * w];
+    xl = xl * invd[2 * w + 1];
+    // Step 4: rebuild the interior in place
+#pragma unroll
+    for (int q = 1; q < M - 1; ++q) d[q] = (d[q] + ra[r0 + q] * x0 + rc[r0 + q] * xl) * ib[r0 + q];
+    d[0] = x0;
+    d[M - 1] = xl;
+  }
+}
+
+struct HelmArgs {
+  HelmJob job[kMaxHelmJobs];
+  int count;
+};
+
+// TS = TC = double (float64), TS = TC = float (float32 storage), or TS =
+// double, TC = float with REFINE: a float32 solve, the float64 residual
+// r - (I - s L_z) u in registers, a float32 solve for the correction.
+// CW columns per chunk: 64 (one wave per chunk, wave-uniform coefficient
+// addresses) or 32 (two chunks per wave, for columns of up to 32 chunks).
+template <typename TS, typename TC, int M, int CW, bool REFINE>
+__global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
+  extern __shared__ unsigned char shraw[];
+  const HelmJob &J = args.job[blockIdx.y];
+  const HelmCoef &C = J.c;
+  const int nib = J.nx / CW;
+  const long nblk = (long)nib * J.ny;
+  if ((long)blockIdx.x >= nblk) return;  // uniform per block
+  TC *RD = reinterpret_cast<TC *>(shraw);
+  const int w = CW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / CW;
+  const int lane = threadIdx.x % CW;
+  const bool active = w < C.P;
+  const int ib = blockIdx.x % nib;
+  const int j = blockIdx.x / nib;
+  const int n = C.n;
+  const int r0 = active ? w * M : 0;
+  const size_t plane = (size_t)J.nx * J.ny;
+  TS *cp = reinterpret_cast<TS *>(J.field) + (size_t)j * J.nx + ib * CW + lane + (size_t)r0 * plane;
+  const TC *fa = (const TC *)C.fa, *bg = (const TC *)C.bg, *ibv = (const TC *)C.ib;
+  const TC *ra = (const TC *)C.ra, *rc = (const TC *)C.rc;
+  const TC *k1 = (const TC *)C.k1, *k2 = (const TC *)C.k2, *invd = (const TC *)C.invd;
+  TC x0, xl;
+
+  if constexpr (!REFINE) {
+    TC d[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) d[q] = (active && r0 + q < n) ? (TC)cp[(size_t)q * plane] : TC(0);
+    helm_solve_regs<TC, M>(d, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
+                           lane, active, CW);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (r0 + q < n) cp[(size_t)q * plane] = (TS)d[q];
+    }
+  } else {
+    double r[M];
+    TC u[M], dd[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
+      u[q] = (TC)r[q];
+    }
+    helm_solve_regs<TC, M>(u, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
+                           lane, active, CW);
+    // the neighbours across chunk ends, for the residual
+    double *NB = reinterpret_cast<double *>(shraw);
+    if (active) {
+      NB[(2 * w) * CW + lane] = (double)u[0];
+      NB[(2 * w + 1) * CW + lane] = (double)u[M - 1];
+    }
+    __syncthreads();
+    double below = 0.0, above = 0.0;
+    if (active) {
+      if (w > 0) below = NB[(2 * w - 1) * CW + lane];
+      if (w < C.P - 1) above = NB[(2 * w + 2) * CW + lane];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const double al = C.al[r0 + q], ga = C.ga[r0 + q], ep = C.ep[r0 + q];
+        const double um = q == 0 ? below : (double)u[q == 0 ? 0 : q - 1];
+        const double up = q == M - 1 ? above : (double)u[q == M - 1 ? q : q + 1];
+        const double uc = (double)u[q];
+        dd[q] = (TC)(r[q] - ((al + ga + ep) * uc - al * um - ga * up));
+      }
+    }
+    helm_solve_regs<TC, M>(dd, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
+                           lane, active, CW);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (r0 + q < n) cp[(size_t)q * plane] = (TS)((double)u[q] + (double)dd[q]);
+    }
+  }
+}
+
+hipError_t launch_helm(int precision, int chunk_rows, int count, const HelmJob *jobs,
+                       hipStream_t st) {
+  if (count < 1 || count > kMaxHelmJobs) return hipErrorInvalidValue;
+  HelmArgs a;
+  a.count = count;
+  int maxP = 0;
+  for (int t = 0; t < count; ++t) maxP = jobs[t].c.P > maxP ? jobs[t].c.P : maxP;
+  const int CW = maxP <= 16 ? 64 : 32;
+  if (maxP < 1 || maxP * CW > 1024) return hipErrorInvalidValue;
+  long maxblk = 0;
+  for (int t = 0; t < count; ++t) {
+    a.job[t] = jobs[t];
+    if (jobs[t].nx % CW) return hipErrorInvalidValue;
+    const long nb = (long)(jobs[t].nx / CW) * jobs[t].ny;
+    if (nb > maxblk) maxblk = nb;
+  }
+  dim3 g((unsigned)maxblk, (unsigned)count), b(CW * maxP);
+  const size_t shm = (size_t)2 * maxP * CW * sizeof(double);
+#define PF_HELM_CW(M, CWV)                                                                      \
+  if (precision == 0)                                                                           \
+    hipLaunchKernelGGL((k_helm<double, double, M, CWV, false>), g, b, shm, st, a);              \
+  else if (precision == 1)                                                                      \
+    hipLaunchKernelGGL((k_helm<float, float, M, CWV, false>), g, b, shm, st, a);                \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_helm<double, float, M, CWV, true>), g, b, shm, st, a);
+#define PF_HELM(M)                    \
+  case M:                             \
+    if (CW == 64) {                   \
+      PF_HELM_CW(M, 64)               \
+    } else {                          \
+      PF_HELM_CW(M, 32)               \
+    }                                 \
+    break;
+  switch (chunk_rows) {
+    PF_HELM(8)
+    PF_HELM(16)
+    PF_HELM(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PF_HELM
+#undef PF_HELM_CW
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ plain copy
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                              size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4 *)src,
+                     (uint4 *)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace pf

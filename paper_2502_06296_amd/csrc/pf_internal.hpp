@@ -1,0 +1,100 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_lds.hpp"
+
+namespace pf {
+
+// Transform lengths instantiated for the x and y directions.
+#define PF_FOR_FFT_SIZES(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+bool fft_size_supported(int n);
+
+// Kernel shapes of the line transforms: TPL threads per complex line, LPW
+// complex lines per workgroup. x lines are contiguous; y lines are columns
+// gathered as LPW pairs of adjacent x slots (2*LPW contiguous values per
+// row, for coalescing).
+template <typename T>
+constexpr int x_tpl(int n) { return n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16); }
+template <typename T>
+constexpr int x_lpw(int n) {
+  int by_threads = 256 / x_tpl<T>(n);
+  int by_lds = 32768 / (n * (int)sizeof(cplx<T>));
+  int v = by_threads < by_lds ? by_threads : by_lds;
+  return v < 1 ? 1 : v;
+}
+template <typename T>
+constexpr int y_tpl(int n) { return n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16); }
+template <typename T>
+constexpr int y_lpw(int n) {
+  int want = sizeof(T) == 8 ? 8 : 16;  // 128-byte rows
+  int by_lds = 65536 / (n * (int)sizeof(cplx<T>));
+  int v = want < by_lds ? want : by_lds;
+  return v < 2 ? 2 : v;
+}
+
+// --------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error. Lengths are runtime checked by
+// the caller against fft_size_supported.
+
+// x forward: rhs (float64 lines of nx) -> packed spectrum (T). Optional
+// float64 sums of every input line (sums may be null).
+template <typename T>
+hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, double *sums,
+                       long lines, hipStream_t st);
+// x forward of the float64 7-point residual r = f - L7 p0 (p0 float32), with
+// float64 sums of r and p0 per line; the spectrum is float32.
+hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const float *p0, float *out,
+                             const cplx<float> *tw, double *sums_r, double *sums_p0,
+                             const double *zal, const double *zga, double idx2, double idy2,
+                             hipStream_t st);
+// y forward / inverse, in place on the packed (T) data.
+template <typename T>
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st);
+template <typename T>
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st);
+// x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
+// per-plane float64 profile zm[k] and float32 base field p0 added.
+template <typename TS, typename TO>
+hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<TS> *tw, const double *zm,
+                       const float *p0, double scale, long lines, hipStream_t st);
+
+// Poisson z solve on the doubly packed spectrum (in place), float64
+// elimination in registers; the (0,0) slot column is set to zero.
+template <typename TS>
+hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
+                         const double *zex, const double *sx, const double *sy, int chunk_rows,
+                         hipStream_t st);
+// Singular (0,0) mode: plane means from the line sums, projection, pinned
+// Neumann solve; writes the float64 plane profile zm[nz].
+hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *sums_p0,
+                            const double *dzf, const double *zal, const double *zga, double *zm,
+                            hipStream_t st);
+
+// Helmholtz apply (Algorithm 2, Steps 2-4).
+struct HelmCoef {
+  // per row r (n): forward multiplier alpha_r/b_{r-1}, backward multiplier
+  // gamma_r/b_{r+1}, 1/b_r, |a_r|, |c_r|; M-matrix rows for the residual
+  const void *fa, *bg, *ib, *ra, *rc;  // float or double per plan precision
+  const double *al, *ga, *ep;          // float64 rows (s alpha, s gamma, 1 + s excess)
+  const void *k1, *k2, *invd;          // reduced-system PCR multipliers [steps][2P], [2P]
+  int n, P, steps;
+};
+struct HelmJob {
+  void *field;
+  int nx, ny;
+  HelmCoef c;
+};
+constexpr int kMaxHelmJobs = 4;
+// precision: 0 float64, 1 float32 storage, 2 float64 I/O with a float32
+// solve and one float64-residual correction.
+hipError_t launch_helm(int precision, int chunk_rows, int count, const HelmJob *jobs,
+                       hipStream_t st);
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+}  // namespace pf

@@ -1,0 +1,233 @@
+"""Python face of the C ABI, with the same names (include/pf_channel.h).
+
+Fields are torch tensors on a HIP device, C-order (nz, ny, nx). Plans hold a
+handle to the library's plan; workspaces are torch allocations the plan keeps
+alive. Nothing here computes: every call goes to libpf_channel.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _native as N
+
+PRECISIONS = {"fp64": N.PF_FP64, "fp32": N.PF_FP32, "fp32_refine": N.PF_FP32_REFINE}
+BCS = {"neumann": N.PF_BC_NEUMANN, "dirichlet_centre": N.PF_BC_DIRICHLET_CENTRE,
+       "dirichlet_face": N.PF_BC_DIRICHLET_FACE}
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def grid_faces(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5, zf=None):
+    """Face coordinates the library uses for this grid (numpy, nz+1)."""
+    import numpy as np
+    g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf)
+    out = np.empty(nz + 1, dtype=np.float64)
+    N.check(N.lib().pf_grid_faces(C.byref(g), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def zop_rows(nz, bc, lz=2.0, beta=1.5, zf=None):
+    """(alpha, gamma, excess) of -L_z for a boundary family (numpy arrays)."""
+    import numpy as np
+    bc = BCS[bc] if isinstance(bc, str) else int(bc)
+    n = nz - 1 if bc == N.PF_BC_DIRICHLET_FACE else nz
+    g, keep = N.make_grid(64, 64, nz, 1.0, 1.0, lz, beta, zf)
+    a, b, c = (np.empty(n, dtype=np.float64) for _ in range(3))
+    pd = C.POINTER(C.c_double)
+    N.check(N.lib().pf_zop_rows(C.byref(g), bc, a.ctypes.data_as(pd), b.ctypes.data_as(pd),
+                                c.ctypes.data_as(pd)))
+    return a, b, c
+
+
+class PoissonPlan:
+    def __init__(self, handle, shape, precision, stream, workspace):
+        self.handle = handle
+        self.shape = shape
+        self.precision = precision
+        self.stream = stream
+        self.workspace = workspace
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and N._lib is not None:
+            N._lib.poisson_destroy(h)
+            self.handle = None
+
+
+def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
+                 zf=None, precision="fp64", n_refine=1, stream=None, device=None):
+    """Plan the channel Poisson solve; allocates the workspace as a torch tensor."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf)
+        h = C.c_void_p()
+        ws = C.c_size_t(0)
+        s = N.stream_handle(stream)
+        N.check(N.lib().poisson_plan(C.byref(h), C.byref(g), _prec(precision), int(n_refine), s,
+                                     C.byref(ws)))
+        plan = PoissonPlan(h, (nz, ny, nx), _prec(precision), stream, None)
+        if ws.value:
+            plan.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
+            N.check(N.lib().poisson_set_workspace(h, _ptr(plan.workspace), ws.value))
+    return plan
+
+
+def _check_field(t, shape, dtype):
+    import torch
+    if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor of shape {shape}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return torch
+
+
+def poisson_solve(plan, rhs, p):
+    """p <- L7^{-1} rhs (float64 device tensors of the plan's shape)."""
+    import torch
+    _check_field(rhs, plan.shape, torch.float64)
+    _check_field(p, plan.shape, torch.float64)
+    N.check(N.lib().poisson_solve(plan.handle, _ptr(rhs), _ptr(p)))
+    return p
+
+
+def poisson_solve_batched(plans, rhs, p):
+    import torch
+    n = len(plans)
+    for pl, r, q in zip(plans, rhs, p):
+        _check_field(r, pl.shape, torch.float64)
+        _check_field(q, pl.shape, torch.float64)
+    arr = C.c_void_p * n
+    N.check(N.lib().poisson_solve_batched(n, arr(*[pl.handle for pl in plans]),
+                                          arr(*[r.data_ptr() for r in rhs]),
+                                          arr(*[q.data_ptr() for q in p])))
+
+
+def poisson_set_stream(plan, stream):
+    N.check(N.lib().poisson_set_stream(plan.handle, N.stream_handle(stream)))
+    plan.stream = stream
+
+
+class PcrPlan:
+    def __init__(self, handle, n, precision, stream):
+        self.handle = handle
+        self.n = n
+        self.precision = precision
+        self.stream = stream
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and N._lib is not None:
+            N._lib.pcr_destroy(h)
+            self.handle = None
+
+
+def pcr_prepare(alpha, gamma, excess, s, precision="fp64", chunk_rows=0, stream=None):
+    """Algorithm 2, Step 1 for (I - s L_z); alpha, gamma, excess: host rows of -L_z."""
+    import numpy as np
+    a, b, c = (np.ascontiguousarray(v, dtype=np.float64) for v in (alpha, gamma, excess))
+    n = a.size
+    pd = C.POINTER(C.c_double)
+    h = C.c_void_p()
+    N.check(N.lib().pcr_prepare(C.byref(h), n, a.ctypes.data_as(pd), b.ctypes.data_as(pd),
+                                c.ctypes.data_as(pd), float(s), _prec(precision), int(chunk_rows),
+                                N.stream_handle(stream)))
+    return PcrPlan(h, n, _prec(precision), stream)
+
+
+def pcr_update_coef(plan, s):
+    N.check(N.lib().pcr_update_coef(plan.handle, float(s)))
+
+
+def _pcr_dtype(plan):
+    import torch
+    return torch.float32 if plan.precision == N.PF_FP32 else torch.float64
+
+
+def pcr_apply(plan, field):
+    """In-place Helmholtz solve of every column of field (n, ny, nx)."""
+    n, ny, nx = field.shape
+    if n != plan.n:
+        raise ValueError(f"field has {n} rows, plan has {plan.n}")
+    _check_field(field, field.shape, _pcr_dtype(plan))
+    N.check(N.lib().pcr_apply(plan.handle, _ptr(field), nx, ny))
+    return field
+
+
+def pcr_apply_batched(plans, fields):
+    n = len(plans)
+    for pl, f in zip(plans, fields):
+        if f.shape[0] != pl.n:
+            raise ValueError("field rows do not match plan")
+        _check_field(f, f.shape, _pcr_dtype(pl))
+    vp = C.c_void_p * n
+    i32 = C.c_int32 * n
+    N.check(N.lib().pcr_apply_batched(n, vp(*[p.handle for p in plans]),
+                                      vp(*[f.data_ptr() for f in fields]),
+                                      i32(*[f.shape[2] for f in fields]),
+                                      i32(*[f.shape[1] for f in fields])))
+
+
+def pcr_set_stream(plan, stream):
+    N.check(N.lib().pcr_set_stream(plan.handle, N.stream_handle(stream)))
+    plan.stream = stream
+
+
+# ------------------------------------------------------------------ graphs
+class Graph:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream):
+        N.check(N.lib().pf_graph_launch(self.handle, N.stream_handle(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and N._lib is not None:
+            N._lib.pf_graph_destroy(h)
+            self.handle = None
+
+
+def pf_graph_begin(stream):
+    N.check(N.lib().pf_graph_begin(N.stream_handle(stream)))
+
+
+def pf_graph_end(stream):
+    h = C.c_void_p()
+    N.check(N.lib().pf_graph_end(N.stream_handle(stream), C.byref(h)))
+    return Graph(h)
+
+
+# ------------------------------------------------------------- measurement
+def poisson_timing(plan, enable=True):
+    N.check(N.lib().poisson_timing(plan.handle, 1 if enable else 0))
+
+
+def _read(fn, handle):
+    ms = (C.c_double * N.PF_STAGE_COUNT)()
+    cnt = (C.c_int32 * N.PF_STAGE_COUNT)()
+    N.check(fn(handle, ms, cnt))
+    return {N.STAGES[i]: (ms[i], cnt[i]) for i in range(N.PF_STAGE_COUNT) if cnt[i]}
+
+
+def poisson_timing_read(plan):
+    """{stage: (summed ms, launches)} since the last read (synchronises)."""
+    return _read(N.lib().poisson_timing_read, plan.handle)
+
+
+def pcr_timing(plan, enable=True):
+    N.check(N.lib().pcr_timing(plan.handle, 1 if enable else 0))
+
+
+def pcr_timing_read(plan):
+    return _read(N.lib().pcr_timing_read, plan.handle)
+
+
+def pf_copy_kernel(dst, src, stream=None):
+    nbytes = src.numel() * src.element_size()
+    N.check(N.lib().pf_copy_kernel(_ptr(dst), _ptr(src), nbytes, N.stream_handle(stream)))
