@@ -1,0 +1,299 @@
+"""Benchmark of the pressure-projection hot path on one MI355X.
+
+One step = the z-implicit Helmholtz solves of the three velocity components
+(u, v at cell centres, w at interior faces; one batched launch) followed by
+the pressure Poisson solve, on the 1024 x 512 x 512 channel grid (Lx = 2 pi,
+Ly = pi, Lz = 2, tanh stretching 1.5), inputs resident in HBM. The headline
+path computes in float32 with one float64-residual correction (relative
+error <= 1e-10); the plain float64 path is timed beside it.
+
+Prints one JSON line. Per-kernel times come from HIP events recorded on the
+solver's stream around every kernel of the timed steps; the roofline entry
+prices the kernel with the largest share of the step against 8 TB/s.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --copy-calibration 4294967296   (byte-counter calibration)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NX, NY, NZ, BETA = 1024, 512, 512, 1.5
+LX, LY, LZ = 2 * math.pi, math.pi, 2.0
+S_HELM = 0.5 * (1.0 / 5200.0) * 1e-4     # alpha * nu * dt, Re_tau = 5200
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SOURCES = ["paper_2502_06296_amd/csrc/kernels_fft.hip", "paper_2502_06296_amd/csrc/kernels_z.hip",
+                  "paper_2502_06296_amd/csrc/fft_lds.hpp", "paper_2502_06296_amd/csrc/pf_internal.hpp"]
+
+# algorithmic HBM bytes per grid point of one launch of each stage (one read
+# and one write of what the stage must touch; stencil neighbours not counted)
+BYTES_PER_POINT = {
+    "fp32_refine": {"xfwd": 8 + 4, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8,
+                    "xfwd_resid": 8 + 4 + 4, "xinv_final": 4 + 4 + 8, "zero_mode": 0,
+                    "pcr_apply": 16},
+    "fp64": {"xfwd": 16, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "zero_mode": 0,
+             "pcr_apply": 16},
+}
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Step:
+    """Plans and fields of one projection step at one precision."""
+
+    def __init__(self, pf, torch, dev, prec, f, r3):
+        self.pf, self.torch, self.prec = pf, torch, prec
+        self.stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(self.stream):
+            self.poisson = pf.poisson_plan(NX, NY, NZ, LX, LY, LZ, BETA, precision=prec, n_refine=1,
+                                           stream=self.stream, device=dev)
+            self.pcr = []
+            for bc in ("dirichlet_centre", "dirichlet_centre", "dirichlet_face"):
+                al, ga, ex = pf.zop_rows(NZ, bc, LZ, BETA)
+                self.pcr.append(pf.pcr_prepare(al, ga, ex, S_HELM, precision=prec, stream=self.stream))
+            self.rhs = f
+            self.p = torch.empty_like(f)
+            self.u = [r.clone() for r in r3]
+
+    def run(self):
+        self.pf.pcr_apply_batched(self.pcr, self.u)
+        self.pf.poisson_solve(self.poisson, self.rhs, self.p)
+
+    def timing(self, on):
+        self.pf.poisson_timing(self.poisson, on)
+        self.pf.pcr_timing(self.pcr[0], on)
+
+    def read_timing(self):
+        t = self.pf.poisson_timing_read(self.poisson)
+        t.update(self.pf.pcr_timing_read(self.pcr[0]))
+        return t
+
+
+def time_steps(step, steps, warmup):
+    torch = step.torch
+    for _ in range(warmup):
+        step.run()
+    step.stream.synchronize()
+    step.read_timing()                       # discard anything recorded so far
+    step.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(step.stream)
+    for _ in range(steps):
+        step.run()
+    end.record(step.stream)
+    step.stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = step.read_timing()
+    step.timing(False)
+    ms = start.elapsed_time(end) / steps
+    return ms, wall, stages
+
+
+def graph_ms(step, reps):
+    """Mean ms of the step replayed from one captured HIP graph."""
+    pf, torch = step.pf, step.torch
+    step.stream.synchronize()
+    pf.pf_graph_begin(step.stream)
+    step.run()
+    g = pf.pf_graph_end(step.stream)
+    g.launch(step.stream)
+    step.stream.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(step.stream)
+    for _ in range(reps):
+        g.launch(step.stream)
+    b.record(step.stream)
+    step.stream.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def stage_points(stage):
+    # pcr_apply covers u, v (nz rows) and w (nz-1 rows) in one launch
+    if stage == "pcr_apply":
+        return NX * NY * (2 * NZ + NZ - 1)
+    return NX * NY * NZ
+
+
+def roofline(prec, stages, traffic):
+    per = BYTES_PER_POINT[prec]
+    best = max((s for s in stages if per.get(s, 0) > 0), key=lambda s: stages[s][0])
+    ms, n = stages[best]
+    avg_ms = ms / n
+    algo = per[best] * stage_points(best)
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    tr = None
+    if traffic and traffic.get("sources") == sources_hash():
+        entry = traffic.get("kernels", {}).get(f"{prec}:{best}")
+        if entry:
+            tr = entry["bytes_per_launch"]
+    return {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+            "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(avg_ms, 4)}
+
+
+def cpu_baseline():
+    """The float64 oracle on a bounded sample of the workload: the same z
+    grid (512 rows, stretching 1.5) with a 256 x 128 plane, Poisson plus the
+    three Helmholtz solves, timed on the host."""
+    import numpy as np
+    import synth
+    from oracle import grid as og
+    from oracle import poisson as op
+    nx, ny = 256, 128
+    f, zf = synth.channel_rhs(0, nx, ny, NZ, beta=BETA)
+    r = [synth.normal01(1 + c, (NZ if c < 2 else NZ - 1, ny, nx)) for c in range(3)]
+    t0 = time.perf_counter()
+    op.solve_poisson(f, zf, LX, LY)
+    for c in range(3):
+        op.solve_helmholtz(r[c], zf, S_HELM, og.DIRICHLET_CENTRE if c < 2 else og.DIRICHLET_FACE)
+    dt = time.perf_counter() - t0
+    pts = nx * ny * NZ
+    return {"value": round(pts / dt / 1e9, 6), "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"float64 numpy oracle, Poisson + 3 Helmholtz on {nx}x{ny}x{NZ} "
+                      f"(same z grid), {dt:.1f} s", "seconds": round(dt, 2),
+            "host_cpus": os.cpu_count()}
+
+
+def copy_calibration(nbytes):
+    import torch
+    import paper_2502_06296_amd as pf
+    dev = torch.device("cuda", 0)
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        pf.pf_copy_kernel(b, a)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(10):
+        pf.pf_copy_kernel(b, a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 10
+    print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
+              "supported (the solver is single-device).", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import numpy as np
+    import torch
+    import paper_2502_06296_amd as pf
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("bench: generating inputs")
+    f_host, zf = synth.channel_rhs(0, NX, NY, NZ, beta=BETA)
+    f = torch.from_numpy(f_host).to(dev)
+    del f_host
+    r3 = [torch.from_numpy(synth.normal01(1 + c, (NZ if c < 2 else NZ - 1, NY, NX))).to(dev)
+          for c in range(3)]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            traffic = json.load(fh)
+
+    results = {}
+    for prec in (["fp32_refine"] if args.no_fp64 else ["fp32_refine", "fp64"]):
+        log(f"bench: {prec} plans")
+        st = Step(pf, torch, dev, prec, f, r3)
+        ms, wall, stages = time_steps(st, args.steps, args.warmup)
+        log(f"bench: {prec} {ms:.3f} ms/step")
+        gms = graph_ms(st, max(3, args.steps // 2))
+        results[prec] = dict(ms=ms, wall=wall, stages=stages, graph_ms=gms, step=st)
+
+    # accuracy of the timed configuration: one fresh step at each precision
+    log("bench: accuracy check")
+    acc = {}
+    outs = {}
+    for prec in results:
+        st = results[prec]["step"]
+        for i in range(3):
+            st.u[i].copy_(r3[i])
+        st.run()
+        st.stream.synchronize()
+        outs[prec] = (st.p, st.u)
+    if "fp64" in outs:
+        p32, u32 = outs["fp32_refine"]
+        p64, u64 = outs["fp64"]
+        acc["poisson_rel_l2_vs_fp64_gpu"] = float(torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64))
+        acc["helmholtz_rel_l2_vs_fp64_gpu"] = max(
+            float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(u32, u64))
+
+    main = results["fp32_refine"]
+    npts = NX * NY * NZ
+    value = npts / (main["ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "Poisson+Helmholtz Gpoints/s, FP32+refine vs FP64 on 1 GPU at rel.err<=1e-10",
+        "value": round(value, 3), "unit": "Gpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(main["ms"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-residual", "data": "synthetic",
+        "config": {"workload": "projection step: 3 z-Helmholtz (u,v centres; w faces; one batched "
+                               "launch) + pressure Poisson, 1024x512x512 channel, tanh 1.5, "
+                               "float32 with one float64-residual correction",
+                   "nx": NX, "ny": NY, "nz": NZ, "beta": BETA, "s": S_HELM,
+                   "precision": "fp32_refine", "parallelism": "1 GPU"},
+        "roofline": roofline("fp32_refine", main["stages"], traffic),
+        "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in main["stages"].items()},
+        "graph_ms_per_step": round(main["graph_ms"], 4),
+        "accuracy": acc,
+    }
+    if "fp64" in results:
+        r64 = results["fp64"]
+        line["fp64"] = {"value": round(npts / (r64["ms"] * 1e-3) / 1e9, 3),
+                        "ms_per_step": round(r64["ms"], 4),
+                        "graph_ms_per_step": round(r64["graph_ms"], 4),
+                        "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in r64["stages"].items()},
+                        "roofline": roofline("fp64", r64["stages"], traffic)}
+        line["speedup_fp32_refine_vs_fp64"] = round(r64["ms"] / main["ms"], 4)
+    if not args.no_cpu_baseline:
+        log("bench: oracle cpu baseline")
+        line["cpu_baseline"] = cpu_baseline()
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

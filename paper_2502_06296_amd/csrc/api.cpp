@@ -226,7 +226,8 @@ struct pf_poisson_plan {
   hipStream_t st;
   int zchunk;
   DevArena ar;
-  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_twx_f, o_twy_f, o_sums, o_sump, o_zm;
+  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_twx_f, o_twy_f, o_sums, o_sump,
+      o_fbar, o_m, o_zm;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   Timing tm;
@@ -448,6 +449,8 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->o_twy_f = A.add(twyf.data(), twyf.size());
   pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * g->nz);
   pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * g->nz);
+  pl->o_fbar = A.add<double>(nullptr, (size_t)g->nz);
+  pl->o_m = A.add<double>(nullptr, (size_t)g->nz);
   pl->o_zm = A.add<double>(nullptr, (size_t)g->nz);
   A.cap = A.used;
   hipError_t e = hipMalloc((void **)&A.base, A.cap);
@@ -503,7 +506,8 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   const DevArena &A = pl->ar;
   const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
   const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
-  double *sums = A.at<double>(pl->o_sums), *sump = A.at<double>(pl->o_sump), *zm = A.at<double>(pl->o_zm);
+  double *sums = A.at<double>(pl->o_sums), *sump = A.at<double>(pl->o_sump);
+  double *fbar = A.at<double>(pl->o_fbar), *mm = A.at<double>(pl->o_m), *zm = A.at<double>(pl->o_zm);
   Timing &tm = pl->tm;
   pf_status s;
 #define STAGE(id, expr)                                      \
@@ -512,34 +516,37 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<double>(nx, rhs, p, twx, sums, lines, st));
-    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, nullptr, dzf, zal, zga, zm, st));
+    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, zal, zga, zex, sx, sy, pl->zchunk, st));
     STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, twy, st));
-    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, p, twx, zm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
   const float2 *twx = A.at<float2>(pl->o_twx_f), *twy = A.at<float2>(pl->o_twy_f);
   float *W0 = (float *)pl->ws;
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W0, twx, sums, lines, st));
-    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, nullptr, dzf, zal, zga, zm, st));
+    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, zal, zga, zex, sx, sy, pl->zchunk, st));
     STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, twy, st));
-    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, p, twx, zm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
-  // float32 solve, then one correction for the float64 residual
+  // float32 solve without the zero mode, then one correction for the
+  // float64 residual of the plane-mean-free problem; the zero mode is solved
+  // once, in float64, from the plane means of f
   float *W1 = W0 + pl->npts();
-  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W1, twx, nullptr, lines, st));
+  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W1, twx, sums, lines, st));
+  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
   STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, W0, twx, nullptr, nullptr, scale, lines, st)));
   const double idx2 = (double)nx * nx / (pl->lx * pl->lx), idy2 = (double)ny * ny / (pl->ly * pl->ly);
-  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, W0, W1, twx, sums, sump, zal, zga, idx2, idy2, st));
-  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, sump, dzf, zal, zga, zm, st));
+  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, fbar, W0, W1, twx, sump, zal, zga, idx2, idy2, st));
+  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, zm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));

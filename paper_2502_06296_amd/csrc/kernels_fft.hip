@@ -73,70 +73,75 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 }
 
 // -------------------------------------- x forward of the 7-point residual
-// r = f - L7 p0 in float64 from the float32 iterate p0 (Neumann z rows:
-// alpha_0 = 0, gamma_{nz-1} = 0, no excess), then the float32 transform of r.
-// The two real lines of a pair are (j, k) and (j+1, k).
+// r = (f - fbar[k]) - L7 p0 in float64 from the float32 iterate p0 (Neumann
+// z rows: alpha_0 = 0, gamma_{nz-1} = 0, no excess), then the float32
+// transform of r. The iterate carries no plane means (its (0,0) slot was
+// zeroed), so removing the plane means of f keeps the large constant-per-
+// plane part out of the float32 spectrum, where its rounding would spread
+// into the weakly damped (0,j) and (i,0) modes. The two real lines of a
+// pair are (j, k) and (j+1, k).
 template <int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
-    const double *__restrict__ f, const float *__restrict__ p0, float *__restrict__ out,
-    const cplx<float> *__restrict__ tw, double *__restrict__ sums_r, double *__restrict__ sums_p,
+    const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
+    float *__restrict__ out, const cplx<float> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
     double idy2, long ncl) {
   __shared__ cplx<float> lds[LPW * lds_len(N)];
-  __shared__ double red[4 * LPW * TPL];
+  __shared__ double red[2 * LPW * TPL];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
   cplx<float> *buf = lds + l * lds_len(N);
-  double sr[2] = {0.0, 0.0}, sp[2] = {0.0, 0.0};
+  double sp[2] = {0.0, 0.0};
   if (ok) {
     const long line0 = 2 * c;
     const int k = (int)(line0 / ny);
     const int j0 = (int)(line0 % ny);
     const double ak = zal[k], gk = zga[k];
     const double dk = ak + gk;
-    float rv[2][N / TPL];
+    const double fb = fbar[k];
+    const size_t plane = (size_t)ny * N;
+    size_t row[2], rym[2], ryp[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int j = j0 + h;
-      const size_t row = ((size_t)k * ny + j) * N;
-      const size_t rym = ((size_t)k * ny + (j == 0 ? ny - 1 : j - 1)) * N;
-      const size_t ryp = ((size_t)k * ny + (j == ny - 1 ? 0 : j + 1)) * N;
-      const size_t plane = (size_t)ny * N;
-#pragma unroll
-      for (int s = 0; s < N / TPL; ++s) {
-        const int i = t + s * TPL;
-        const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-        const double pc = p0[row + i];
-        const double lx = ((double)p0[row + ip] - 2.0 * pc + (double)p0[row + im]) * idx2;
-        const double ly = ((double)p0[ryp + i] - 2.0 * pc + (double)p0[rym + i]) * idy2;
-        double lzv = -dk * pc;
-        if (k > 0) lzv += ak * (double)p0[row - plane + i];
-        if (k < nz - 1) lzv += gk * (double)p0[row + plane + i];
-        const double r = f[row + i] - (lx + ly + lzv);
-        sr[h] += r;
-        sp[h] += pc;
-        rv[h][s] = (float)r;
-      }
+      row[h] = ((size_t)k * ny + j) * N;
+      rym[h] = ((size_t)k * ny + (j == 0 ? ny - 1 : j - 1)) * N;
+      ryp[h] = ((size_t)k * ny + (j == ny - 1 ? 0 : j + 1)) * N;
     }
+#pragma unroll 2
+    for (int s = 0; s < N / TPL; ++s) {
+      const int i = t + s * TPL;
+      const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+      float rv[2];
 #pragma unroll
-    for (int s = 0; s < N / TPL; ++s) buf[lds_idx(t + s * TPL)] = mkc<float>(rv[0][s], rv[1][s]);
+      for (int h = 0; h < 2; ++h) {
+        const double pc = p0[row[h] + i];
+        const double lx = ((double)p0[row[h] + ip] - 2.0 * pc + (double)p0[row[h] + im]) * idx2;
+        const double ly = ((double)p0[ryp[h] + i] - 2.0 * pc + (double)p0[rym[h] + i]) * idy2;
+        double lzv = -dk * pc;
+        if (k > 0) lzv += ak * (double)p0[row[h] - plane + i];
+        if (k < nz - 1) lzv += gk * (double)p0[row[h] + plane + i];
+        const double r = (f[row[h] + i] - fb) - (lx + ly + lzv);
+        sp[h] += pc;
+        rv[h] = (float)r;
+      }
+      buf[lds_idx(i)] = mkc<float>(rv[0], rv[1]);
+    }
   }
-  red[4 * tid + 0] = sr[0];
-  red[4 * tid + 1] = sr[1];
-  red[4 * tid + 2] = sp[0];
-  red[4 * tid + 3] = sp[1];
+  red[2 * tid + 0] = sp[0];
+  red[2 * tid + 1] = sp[1];
   __syncthreads();
   fft_line<float, N, TPL, false>(buf, tw, t);
   if (!ok) return;
   if (t == 0) {
-    double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    double b0 = 0, b1 = 0;
     for (int u = 0; u < TPL; ++u) {
-      const double *rr = red + 4 * (l * TPL + u);
-      a0 += rr[0]; a1 += rr[1]; b0 += rr[2]; b1 += rr[3];
+      const double *rr = red + 2 * (l * TPL + u);
+      b0 += rr[0]; b1 += rr[1];
     }
-    sums_r[2 * c] = a0; sums_r[2 * c + 1] = a1;
-    sums_p[2 * c] = b0; sums_p[2 * c + 1] = b1;
+    sums_p[2 * c] = b0;
+    sums_p[2 * c + 1] = b1;
   }
   float *oa = out + (size_t)(2 * c) * N;
   float *ob = oa + N;
@@ -308,8 +313,8 @@ hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, doub
   }
 }
 
-hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const float *p0, float *out,
-                             const cplx<float> *tw, double *sums_r, double *sums_p0,
+hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
+                             const float *p0, float *out, const cplx<float> *tw, double *sums_p0,
                              const double *zal, const double *zga, double idx2, double idy2,
                              hipStream_t st) {
   const long ncl = (long)ny * nz / 2;
@@ -318,8 +323,8 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const floa
   case N: {                                                                                      \
     constexpr int TPL = x_tpl<float>(N), LPW = x_lpw<float>(N) > 2 ? 2 : x_lpw<float>(N);        \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
-    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), g, dim3(TPL * LPW), 0, st, f, p0, out, tw,   \
-                       sums_r, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                      \
+    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), g, dim3(TPL * LPW), 0, st, f, fbar, p0, out, \
+                       tw, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                          \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)

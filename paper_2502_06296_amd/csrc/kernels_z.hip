@@ -166,31 +166,26 @@ template hipError_t launch_zsolve<float>(int, int, int, float *, const double *,
                                          hipStream_t);
 
 // ----------------------------------------------------------- zero mode
-// One workgroup. Plane means of the right-hand side (and of the iterate,
-// for a correction) from the float64 line sums; the right-hand side is
-// projected onto the range of L_z (zero dzf-weighted mean); the singular
-// Neumann system is solved with its last equation replaced by x[nz-1] = 0,
-// then shifted so that the total field has zero dzf-weighted mean.
+// The (0,0) slot of the transformed problem is the plane-mean profile of p.
+// One workgroup: plane means fbar[k] of the right-hand side from its float64
+// line sums; projection onto the range of L_z (zero dzf-weighted mean); the
+// singular Neumann system solved with its last equation replaced by
+// m[nz-1] = 0, then shifted to zero dzf-weighted mean.
 __global__ __launch_bounds__(256) void k_zero_mode(const double *__restrict__ sums,
-                                                   const double *__restrict__ sums_p0,
                                                    const double *__restrict__ dzf,
                                                    const double *__restrict__ zal,
                                                    const double *__restrict__ zga,
-                                                   double *__restrict__ zm, int ny, int nz,
-                                                   double inv_nxny) {
-  extern __shared__ double sh[];  // R[nz], Pm[nz], Y[nz], RT[nz]
-  double *R = sh, *Pm = sh + nz, *Y = sh + 2 * nz, *RT = sh + 3 * nz;
+                                                   double *__restrict__ fbar, double *__restrict__ m,
+                                                   int ny, int nz, double inv_nxny) {
+  extern __shared__ double sh[];  // R[nz], Y[nz], RT[nz]
+  double *R = sh, *Y = sh + nz, *RT = sh + 2 * nz;
   const int tid = threadIdx.x;
   for (int k = tid; k < nz; k += blockDim.x) {
-    double a = 0.0, b = 0.0;
+    double a = 0.0;
     const double *s = sums + (size_t)k * ny;
     for (int j = 0; j < ny; ++j) a += s[j];
-    if (sums_p0) {
-      const double *sp = sums_p0 + (size_t)k * ny;
-      for (int j = 0; j < ny; ++j) b += sp[j];
-    }
     R[k] = a * inv_nxny;
-    Pm[k] = b * inv_nxny;
+    fbar[k] = R[k];
   }
   __syncthreads();
   if (tid != 0) return;
@@ -215,17 +210,38 @@ __global__ __launch_bounds__(256) void k_zero_mode(const double *__restrict__ su
     R[k] = x;
   }
   double wm = 0.0;
-  for (int k = 0; k < nz; ++k) wm += dzf[k] * (R[k] + Pm[k]);
+  for (int k = 0; k < nz; ++k) wm += dzf[k] * R[k];
   const double shift = wm / w;
-  for (int k = 0; k < nz; ++k) zm[k] = R[k] - shift;
+  for (int k = 0; k < nz; ++k) m[k] = R[k] - shift;
 }
 
-hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *sums_p0,
-                            const double *dzf, const double *zal, const double *zga, double *zm,
+// zm[k] = m[k] - (plane mean of the iterate p0): the profile that gives the
+// corrected field the plane means m.
+__global__ __launch_bounds__(256) void k_zero_shift(const double *__restrict__ sums_p0,
+                                                    const double *__restrict__ m,
+                                                    double *__restrict__ zm, int ny, int nz,
+                                                    double inv_nxny) {
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    double a = 0.0;
+    const double *s = sums_p0 + (size_t)k * ny;
+    for (int j = 0; j < ny; ++j) a += s[j];
+    zm[k] = m[k] - a * inv_nxny;
+  }
+}
+
+hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *dzf,
+                            const double *zal, const double *zga, double *fbar, double *m,
                             hipStream_t st) {
-  const size_t shm = (size_t)4 * nz * sizeof(double);
-  hipLaunchKernelGGL(k_zero_mode, dim3(1), dim3(256), shm, st, sums, sums_p0, dzf, zal, zga, zm, ny,
-                     nz, 1.0 / ((double)nx * (double)ny));
+  const size_t shm = (size_t)3 * nz * sizeof(double);
+  hipLaunchKernelGGL(k_zero_mode, dim3(1), dim3(256), shm, st, sums, dzf, zal, zga, fbar, m, ny, nz,
+                     1.0 / ((double)nx * (double)ny));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_shift(int nx, int ny, int nz, const double *sums_p0, const double *m,
+                             double *zm, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_shift, dim3(1), dim3(256), 0, st, sums_p0, m, zm, ny, nz,
+                     1.0 / ((double)nx * (double)ny));
   return hipGetLastError();
 }
 

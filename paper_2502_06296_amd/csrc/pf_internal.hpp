@@ -46,10 +46,11 @@ constexpr int y_lpw(int n) {
 template <typename T>
 hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, double *sums,
                        long lines, hipStream_t st);
-// x forward of the float64 7-point residual r = f - L7 p0 (p0 float32), with
-// float64 sums of r and p0 per line; the spectrum is float32.
-hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const float *p0, float *out,
-                             const cplx<float> *tw, double *sums_r, double *sums_p0,
+// x forward of the float64 7-point residual r = (f - fbar[k]) - L7 p0 (p0
+// float32, fbar the float64 plane means of f), with the float64 sums of p0
+// per line; the spectrum is float32.
+hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
+                             const float *p0, float *out, const cplx<float> *tw, double *sums_p0,
                              const double *zal, const double *zga, double idx2, double idy2,
                              hipStream_t st);
 // y forward / inverse, in place on the packed (T) data.
@@ -69,11 +70,15 @@ template <typename TS>
 hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
                          const double *zex, const double *sx, const double *sy, int chunk_rows,
                          hipStream_t st);
-// Singular (0,0) mode: plane means from the line sums, projection, pinned
-// Neumann solve; writes the float64 plane profile zm[nz].
-hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *sums_p0,
-                            const double *dzf, const double *zal, const double *zga, double *zm,
+// Singular (0,0) mode: plane means fbar[nz] of the right-hand side from its
+// line sums, projection, pinned Neumann solve for the plane-mean profile
+// m[nz] of p.
+hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *dzf,
+                            const double *zal, const double *zga, double *fbar, double *m,
                             hipStream_t st);
+// zm = m - plane means of an iterate (from its float64 line sums).
+hipError_t launch_zero_shift(int nx, int ny, int nz, const double *sums_p0, const double *m,
+                             double *zm, hipStream_t st);
 
 // Helmholtz apply (Algorithm 2, Steps 2-4).
 struct HelmCoef {
