@@ -249,8 +249,9 @@ def main():
     outs = {}
     for prec in results:
         st = results[prec]["step"]
-        for i in range(3):
-            st.u[i].copy_(r3[i])
+        with torch.cuda.stream(st.stream):       # same stream as the solver
+            for i in range(3):
+                st.u[i].copy_(r3[i])
         st.run()
         st.stream.synchronize()
         outs[prec] = (st.p, st.u)

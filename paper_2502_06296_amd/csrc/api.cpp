@@ -226,7 +226,7 @@ struct pf_poisson_plan {
   hipStream_t st;
   int zchunk;
   DevArena ar;
-  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_twx_f, o_twy_f, o_sums, o_sump,
+  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
       o_fbar, o_m, o_zm;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
@@ -435,7 +435,6 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   for (int k = 0; k < g->nz; ++k) dzf[k] = zf[k + 1] - zf[k];
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
   auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
-  auto twxf = twiddles<float2>(g->nx), twyf = twiddles<float2>(g->ny);
   DevArena &A = pl->ar;
   pl->o_zal = A.add(al.data(), al.size());
   pl->o_zga = A.add(ga.data(), ga.size());
@@ -445,8 +444,6 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->o_sy = A.add(sy.data(), sy.size());
   pl->o_twx_d = A.add(twxd.data(), twxd.size());
   pl->o_twy_d = A.add(twyd.data(), twyd.size());
-  pl->o_twx_f = A.add(twxf.data(), twxf.size());
-  pl->o_twy_f = A.add(twyf.data(), twyf.size());
   pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * g->nz);
   pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * g->nz);
   pl->o_fbar = A.add<double>(nullptr, (size_t)g->nz);
@@ -523,7 +520,7 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
     STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
-  const float2 *twx = A.at<float2>(pl->o_twx_f), *twy = A.at<float2>(pl->o_twy_f);
+  const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   float *W0 = (float *)pl->ws;
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W0, twx, sums, lines, st));

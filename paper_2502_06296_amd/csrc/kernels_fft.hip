@@ -8,6 +8,13 @@
 // is 2*LPW contiguous values (128 bytes by default). The x<->y permutation of
 // the pencil method is therefore never materialised: the y kernel gathers
 // its columns straight from the x-packed array and writes them back in place.
+//
+// Storage (HBM) is float64 or float32 (TS); the transforms themselves always
+// run in float64 in LDS and registers. A float32 butterfly network leaves
+// errors of about eps32 * max|X| in every mode, and the refinement residual is
+// dominated by high wavenumbers, so its weakly damped low modes would lose
+// all their digits; rounding only at the stores keeps the per-mode error
+// relative to each stored value.
 #include "pf_internal.hpp"
 
 namespace pf {
@@ -26,14 +33,15 @@ bool fft_size_supported(int n) {
 // ----------------------------------------------------------- x forward
 template <typename T, int N, int TPL, int LPW, bool SUMS>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
-                                                   const cplx<T> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ tw,
                                                    double *__restrict__ sums, long ncl) {
-  __shared__ cplx<T> lds[LPW * lds_len(N)];
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
   __shared__ double red[SUMS ? 2 * LPW * TPL : 2];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
-  cplx<T> *buf = lds + l * lds_len(N);
+  C *buf = lds + l * lds_len(N);
   double sa = 0.0, sb = 0.0;
   if (ok) {
     const double *a = in + (size_t)(2 * c) * N;
@@ -43,12 +51,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
       const int pos = t + s * TPL;
       const double va = a[pos], vb = b[pos];
       if (SUMS) { sa += va; sb += vb; }
-      buf[lds_idx(pos)] = mkc<T>((T)va, (T)vb);
+      buf[lds_idx(pos)] = mkc<double>(va, vb);
     }
   }
   if (SUMS) { red[2 * tid] = sa; red[2 * tid + 1] = sb; }
   __syncthreads();
-  fft_line<T, N, TPL, false>(buf, tw, t);
+  fft_line<double, N, TPL, false>(buf, tw, t);
   if (!ok) return;
   if (SUMS && t == 0) {
     double A = 0.0, B = 0.0;
@@ -59,16 +67,16 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   T *oa = out + (size_t)(2 * c) * N;
   T *ob = oa + N;
   for (int q = t; q < N / 2; q += TPL) {
-    cplx<T> A, B;
+    C A, B;
     if (q == 0) {
-      const cplx<T> z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
-      A = mkc<T>(z0.x, zh.x);
-      B = mkc<T>(z0.y, zh.y);
+      const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
+      A = mkc<double>(z0.x, zh.x);
+      B = mkc<double>(z0.y, zh.y);
     } else {
-      split_pair<T>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+      split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
     }
-    *reinterpret_cast<cplx<T> *>(oa + 2 * q) = A;
-    *reinterpret_cast<cplx<T> *>(ob + 2 * q) = B;
+    *reinterpret_cast<cplx<T> *>(oa + 2 * q) = mkc<T>((T)A.x, (T)A.y);
+    *reinterpret_cast<cplx<T> *>(ob + 2 * q) = mkc<T>((T)B.x, (T)B.y);
   }
 }
 
@@ -83,15 +91,16 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 template <int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
-    float *__restrict__ out, const cplx<float> *__restrict__ tw, double *__restrict__ sums_p,
+    float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
     double idy2, long ncl) {
-  __shared__ cplx<float> lds[LPW * lds_len(N)];
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
   __shared__ double red[2 * LPW * TPL];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
-  cplx<float> *buf = lds + l * lds_len(N);
+  C *buf = lds + l * lds_len(N);
   double sp[2] = {0.0, 0.0};
   if (ok) {
     const long line0 = 2 * c;
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
     for (int s = 0; s < N / TPL; ++s) {
       const int i = t + s * TPL;
       const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-      float rv[2];
+      double rv[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const double pc = p0[row[h] + i];
@@ -124,15 +133,15 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
         if (k < nz - 1) lzv += gk * (double)p0[row[h] + plane + i];
         const double r = (f[row[h] + i] - fb) - (lx + ly + lzv);
         sp[h] += pc;
-        rv[h] = (float)r;
+        rv[h] = r;
       }
-      buf[lds_idx(i)] = mkc<float>(rv[0], rv[1]);
+      buf[lds_idx(i)] = mkc<double>(rv[0], rv[1]);
     }
   }
   red[2 * tid + 0] = sp[0];
   red[2 * tid + 1] = sp[1];
   __syncthreads();
-  fft_line<float, N, TPL, false>(buf, tw, t);
+  fft_line<double, N, TPL, false>(buf, tw, t);
   if (!ok) return;
   if (t == 0) {
     double b0 = 0, b1 = 0;
@@ -146,129 +155,147 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
   float *oa = out + (size_t)(2 * c) * N;
   float *ob = oa + N;
   for (int q = t; q < N / 2; q += TPL) {
-    cplx<float> A, B;
+    C A, B;
     if (q == 0) {
-      const cplx<float> z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
-      A = mkc<float>(z0.x, zh.x);
-      B = mkc<float>(z0.y, zh.y);
+      const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
+      A = mkc<double>(z0.x, zh.x);
+      B = mkc<double>(z0.y, zh.y);
     } else {
-      split_pair<float>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+      split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
     }
-    *reinterpret_cast<cplx<float> *>(oa + 2 * q) = A;
-    *reinterpret_cast<cplx<float> *>(ob + 2 * q) = B;
+    *reinterpret_cast<cplx<float> *>(oa + 2 * q) = mkc<float>((float)A.x, (float)A.y);
+    *reinterpret_cast<cplx<float> *>(ob + 2 * q) = mkc<float>((float)B.x, (float)B.y);
   }
 }
 
 // ------------------------------------------------------------- y forward
+template <typename T>
+__device__ __forceinline__ cplx<double> ld2(const T *p) {
+  const cplx<T> v = *reinterpret_cast<const cplx<T> *>(p);
+  return mkc<double>((double)v.x, (double)v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *p, double x, double y) {
+  *reinterpret_cast<cplx<T> *>(p) = mkc<T>((T)x, (T)y);
+}
+
 template <typename T, int N, int TPL, int LPW>
-__global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data, const cplx<T> *__restrict__ tw,
-                                                   int nx, int nib) {
-  __shared__ cplx<T> lds[LPW * lds_len(N)];
+__global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
+                                                   const cplx<double> *__restrict__ tw, int nx,
+                                                   int nib) {
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
-  const int ib = blockIdx.x % nib;
-  const long k = blockIdx.x / nib;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int ib = blk % nib;
+  const long k = blk / nib;
   T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
     const int l = e % LPW, y = e / LPW;
-    lds[l * lds_len(N) + lds_idx(y)] = *reinterpret_cast<const cplx<T> *>(base + (size_t)y * nx + 2 * l);
+    lds[l * lds_len(N) + lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l);
   }
   __syncthreads();
   const int l = tid / TPL, t = tid % TPL;
-  fft_line<T, N, TPL, false>(lds + l * lds_len(N), tw, t);
+  fft_line<double, N, TPL, false>(lds + l * lds_len(N), tw, t);
 #pragma unroll
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, q = e / LPW;
-    const cplx<T> *buf = lds + l2 * lds_len(N);
-    cplx<T> r0, r1;
+    const C *buf = lds + l2 * lds_len(N);
+    C r0, r1;
     if (q == 0) {
       r0 = buf[lds_idx(0)];
       r1 = buf[lds_idx(N / 2)];
     } else {
-      cplx<T> A, B;
-      split_pair<T>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
-      r0 = mkc<T>(A.x, B.x);
-      r1 = mkc<T>(A.y, B.y);
+      C A, B;
+      split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+      r0 = mkc<double>(A.x, B.x);
+      r1 = mkc<double>(A.y, B.y);
     }
-    *reinterpret_cast<cplx<T> *>(base + (size_t)(2 * q) * nx + 2 * l2) = r0;
-    *reinterpret_cast<cplx<T> *>(base + (size_t)(2 * q + 1) * nx + 2 * l2) = r1;
+    st2<T>(base + (size_t)(2 * q) * nx + 2 * l2, r0.x, r0.y);
+    st2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2, r1.x, r1.y);
   }
 }
 
 // ------------------------------------------------------------- y inverse
 template <typename T, int N, int TPL, int LPW>
-__global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data, const cplx<T> *__restrict__ tw,
-                                                   int nx, int nib) {
-  __shared__ cplx<T> lds[LPW * lds_len(N)];
+__global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
+                                                   const cplx<double> *__restrict__ tw, int nx,
+                                                   int nib) {
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
-  const int ib = blockIdx.x % nib;
-  const long k = blockIdx.x / nib;
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int ib = blk % nib;
+  const long k = blk / nib;
   T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
 #pragma unroll
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, q = e / LPW;
-    cplx<T> *buf = lds + l2 * lds_len(N);
-    const cplx<T> r0 = *reinterpret_cast<const cplx<T> *>(base + (size_t)(2 * q) * nx + 2 * l2);
-    const cplx<T> r1 = *reinterpret_cast<const cplx<T> *>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
+    C *buf = lds + l2 * lds_len(N);
+    const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
+    const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
     if (q == 0) {
       buf[lds_idx(0)] = r0;
       buf[lds_idx(N / 2)] = r1;
     } else {
-      cplx<T> zq, zn;
-      join_pair<T>(mkc<T>(r0.x, r1.x), mkc<T>(r0.y, r1.y), zq, zn);
+      C zq, zn;
+      join_pair<double>(mkc<double>(r0.x, r1.x), mkc<double>(r0.y, r1.y), zq, zn);
       buf[lds_idx(q)] = zq;
       buf[lds_idx(N - q)] = zn;
     }
   }
   __syncthreads();
   const int l = tid / TPL, t = tid % TPL;
-  fft_line<T, N, TPL, true>(lds + l * lds_len(N), tw, t);
+  fft_line<double, N, TPL, true>(lds + l * lds_len(N), tw, t);
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, y = e / LPW;
-    *reinterpret_cast<cplx<T> *>(base + (size_t)y * nx + 2 * l2) = lds[l2 * lds_len(N) + lds_idx(y)];
+    const C v = lds[l2 * lds_len(N) + lds_idx(y)];
+    st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
   }
 }
 
 // ------------------------------------------------------------- x inverse
-template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool ADDP0>
 // in and out may be the same array (each workgroup reads its line pair into
 // LDS before writing it), so they are not marked restrict.
+template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool ADDP0>
 __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
-                                                   const cplx<TS> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ tw,
                                                    const double *__restrict__ zm,
                                                    const float *__restrict__ p0, double scale,
                                                    int ny, long ncl) {
-  __shared__ cplx<TS> lds[LPW * lds_len(N)];
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
-  cplx<TS> *buf = lds + l * lds_len(N);
+  C *buf = lds + l * lds_len(N);
   if (ok) {
     const TS *a = in + (size_t)(2 * c) * N;
     const TS *b = a + N;
     for (int q = t; q < N / 2; q += TPL) {
-      const cplx<TS> A = *reinterpret_cast<const cplx<TS> *>(a + 2 * q);
-      const cplx<TS> B = *reinterpret_cast<const cplx<TS> *>(b + 2 * q);
+      const C A = ld2<TS>(a + 2 * q);
+      const C B = ld2<TS>(b + 2 * q);
       if (q == 0) {
-        buf[lds_idx(0)] = mkc<TS>(A.x, B.x);
-        buf[lds_idx(N / 2)] = mkc<TS>(A.y, B.y);
+        buf[lds_idx(0)] = mkc<double>(A.x, B.x);
+        buf[lds_idx(N / 2)] = mkc<double>(A.y, B.y);
       } else {
-        cplx<TS> zq, zn;
-        join_pair<TS>(A, B, zq, zn);
+        C zq, zn;
+        join_pair<double>(A, B, zq, zn);
         buf[lds_idx(q)] = zq;
         buf[lds_idx(N - q)] = zn;
       }
     }
   }
   __syncthreads();
-  fft_line<TS, N, TPL, true>(buf, tw, t);
+  fft_line<double, N, TPL, true>(buf, tw, t);
   if (!ok) return;
   double add = 0.0;
   if (ADDZ) add = zm[(2 * c) / ny];
@@ -279,9 +306,9 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int pos = t + s * TPL;
-    const cplx<TS> z = buf[lds_idx(pos)];
-    double va = (double)z.x * scale + add;
-    double vb = (double)z.y * scale + add;
+    const C z = buf[lds_idx(pos)];
+    double va = z.x * scale + add;
+    double vb = z.y * scale + add;
     if (ADDP0) { va += (double)pa[pos]; vb += (double)pb[pos]; }
     oa[pos] = (TO)va;
     ob[pos] = (TO)vb;
@@ -290,13 +317,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
 
 // ------------------------------------------------------------- launchers
 template <typename T>
-hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, double *sums, long lines,
-                       hipStream_t st) {
+hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw, double *sums,
+                       long lines, hipStream_t st) {
   const long ncl = lines / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
-    constexpr int TPL = x_tpl<T>(N), LPW = x_lpw<T>(N);                                         \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
     if (sums)                                                                                   \
       hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, in, out, tw, \
@@ -314,14 +341,14 @@ hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, doub
 }
 
 hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, const cplx<float> *tw, double *sums_p0,
+                             const float *p0, float *out, const cplx<double> *tw, double *sums_p0,
                              const double *zal, const double *zga, double idx2, double idy2,
                              hipStream_t st) {
   const long ncl = (long)ny * nz / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
-    constexpr int TPL = x_tpl<float>(N), LPW = x_lpw<float>(N) > 2 ? 2 : x_lpw<float>(N);        \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N) > 2 ? 2 : x_lpw(N);                             \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
     hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), g, dim3(TPL * LPW), 0, st, f, fbar, p0, out, \
                        tw, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                          \
@@ -335,11 +362,11 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const doub
 }
 
 template <typename T>
-hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st) {
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
-    constexpr int TPL = y_tpl<T>(N), LPW = y_lpw<T>(N);                                       \
+    constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
@@ -354,11 +381,11 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipSt
 }
 
 template <typename T>
-hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st) {
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
-    constexpr int TPL = y_tpl<T>(N), LPW = y_lpw<T>(N);                                       \
+    constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
@@ -373,13 +400,14 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipSt
 }
 
 template <typename TS, typename TO>
-hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<TS> *tw, const double *zm,
-                       const float *p0, double scale, long lines, hipStream_t st) {
+hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double> *tw,
+                       const double *zm, const float *p0, double scale, long lines,
+                       hipStream_t st) {
   const long ncl = lines / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
-    constexpr int TPL = x_tpl<TS>(N), LPW = x_lpw<TS>(N);                                       \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
     if (zm && p0)                                                                               \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
@@ -401,20 +429,20 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<TS> *tw
 
 template hipError_t launch_xfwd<double>(int, const double *, double *, const cplx<double> *,
                                         double *, long, hipStream_t);
-template hipError_t launch_xfwd<float>(int, const double *, float *, const cplx<float> *, double *,
-                                       long, hipStream_t);
+template hipError_t launch_xfwd<float>(int, const double *, float *, const cplx<double> *,
+                                       double *, long, hipStream_t);
 template hipError_t launch_yfwd<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
-template hipError_t launch_yfwd<float>(int, int, int, float *, const cplx<float> *, hipStream_t);
+template hipError_t launch_yfwd<float>(int, int, int, float *, const cplx<double> *, hipStream_t);
 template hipError_t launch_yinv<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
-template hipError_t launch_yinv<float>(int, int, int, float *, const cplx<float> *, hipStream_t);
+template hipError_t launch_yinv<float>(int, int, int, float *, const cplx<double> *, hipStream_t);
 template hipError_t launch_xinv<double, double>(int, int, const double *, double *,
                                                 const cplx<double> *, const double *,
                                                 const float *, double, long, hipStream_t);
-template hipError_t launch_xinv<float, float>(int, int, const float *, float *, const cplx<float> *,
-                                              const double *, const float *, double, long,
-                                              hipStream_t);
+template hipError_t launch_xinv<float, float>(int, int, const float *, float *,
+                                              const cplx<double> *, const double *, const float *,
+                                              double, long, hipStream_t);
 template hipError_t launch_xinv<float, double>(int, int, const float *, double *,
-                                               const cplx<float> *, const double *, const float *,
+                                               const cplx<double> *, const double *, const float *,
                                                double, long, hipStream_t);
 
 }  // namespace pf

@@ -41,8 +41,9 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
   const int nr = 2 * P;
   double *RA = red, *RG = red + nr * TI, *RE = red + 2 * nr * TI, *RD = red + 3 * nr * TI;
   const int nib = nx / TI;
-  const int ib = blockIdx.x % nib;
-  const int j = blockIdx.x / nib;
+  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int ib = blk % nib;
+  const int j = blk / nib;
   const int col = threadIdx.x % TI;
   const int ch = threadIdx.x / TI;
   const int i = ib * TI + col;

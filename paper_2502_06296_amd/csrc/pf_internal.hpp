@@ -9,60 +9,73 @@
 
 namespace pf {
 
+// Workgroup b is dispatched to XCD b % 8, and each XCD has its own L2. This
+// renumbers blocks so that every XCD walks one contiguous range of the
+// logical block order: neighbouring blocks that read the two halves of the
+// same 128-byte lines then share an L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  constexpr unsigned kXcd = 8;
+  if (nb % kXcd) return b;
+  return (b % kXcd) * (nb / kXcd) + b / kXcd;
+}
+
 // Transform lengths instantiated for the x and y directions.
 #define PF_FOR_FFT_SIZES(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 bool fft_size_supported(int n);
 
 // Kernel shapes of the line transforms: TPL threads per complex line, LPW
-// complex lines per workgroup. x lines are contiguous; y lines are columns
-// gathered as LPW pairs of adjacent x slots (2*LPW contiguous values per
-// row, for coalescing).
-template <typename T>
+// complex lines per workgroup. The LDS holds float64 complex lines whatever
+// the storage type. x lines are contiguous; y lines are columns gathered as
+// LPW pairs of adjacent x slots, 2*LPW contiguous values per row (128 bytes
+// when the LDS budget allows). LPW is a power of two, so 2*LPW (at most 32)
+// divides every supported nx.
 constexpr int x_tpl(int n) { return n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16); }
-template <typename T>
 constexpr int x_lpw(int n) {
-  int by_threads = 256 / x_tpl<T>(n);
-  int by_lds = 32768 / (n * (int)sizeof(cplx<T>));
-  int v = by_threads < by_lds ? by_threads : by_lds;
-  return v < 1 ? 1 : v;
+  const int by_threads = 256 / x_tpl(n);
+  const int by_lds = 32768 / (n * 16);
+  int v = 1;
+  while (v * 2 <= by_threads && v * 2 <= by_lds) v *= 2;
+  return v;
 }
-template <typename T>
 constexpr int y_tpl(int n) { return n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16); }
 template <typename T>
 constexpr int y_lpw(int n) {
-  int want = sizeof(T) == 8 ? 8 : 16;  // 128-byte rows
-  int by_lds = 65536 / (n * (int)sizeof(cplx<T>));
-  int v = want < by_lds ? want : by_lds;
-  return v < 2 ? 2 : v;
+  const int want = sizeof(T) == 8 ? 8 : 16;
+  const int by_lds = 65536 / (n * 16);
+  int v = 2;
+  while (v * 2 <= want && v * 2 <= by_lds) v *= 2;
+  return v;
 }
 
 // --------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error. Lengths are runtime checked by
 // the caller against fft_size_supported.
 
+// Every transform runs in float64; T, TS and TO are storage types.
 // x forward: rhs (float64 lines of nx) -> packed spectrum (T). Optional
 // float64 sums of every input line (sums may be null).
 template <typename T>
-hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<T> *tw, double *sums,
+hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw, double *sums,
                        long lines, hipStream_t st);
 // x forward of the float64 7-point residual r = (f - fbar[k]) - L7 p0 (p0
 // float32, fbar the float64 plane means of f), with the float64 sums of p0
 // per line; the spectrum is float32.
 hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, const cplx<float> *tw, double *sums_p0,
+                             const float *p0, float *out, const cplx<double> *tw, double *sums_p0,
                              const double *zal, const double *zga, double idx2, double idy2,
                              hipStream_t st);
 // y forward / inverse, in place on the packed (T) data.
 template <typename T>
-hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st);
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st);
 template <typename T>
-hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<T> *tw, hipStream_t st);
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k] and float32 base field p0 added.
 template <typename TS, typename TO>
-hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<TS> *tw, const double *zm,
-                       const float *p0, double scale, long lines, hipStream_t st);
+hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double> *tw,
+                       const double *zm, const float *p0, double scale, long lines,
+                       hipStream_t st);
 
 // Poisson z solve on the doubly packed spectrum (in place), float64
 // elimination in registers; the (0,0) slot column is set to zero.
