@@ -174,6 +174,23 @@ pf_status poisson_timing_read(pf_poisson_plan *plan, double *ms, int32_t *count)
 pf_status pcr_timing(pf_pcr_plan *plan, int32_t enable);
 pf_status pcr_timing_read(pf_pcr_plan *plan, double *ms, int32_t *count);
 
+/* ------------------------------------------------------------ tuning
+ * Launch-shape variants that an autotuner may choose between. For
+ * PF_STAGE_ZSOLVE the variants are table entries of (rows per thread,
+ * columns per workgroup, occupancy bound, reciprocal flavour); every variant
+ * computes the same solution (to rounding). *count receives the number of
+ * table entries; pf_poisson_set_variant returns PF_ERR_UNSUPPORTED for a
+ * variant that does not fit the plan's grid. Set variants only while no
+ * solve of the plan is in flight. */
+pf_status poisson_variant_count(pf_poisson_plan *plan, int32_t stage, int32_t *count);
+pf_status poisson_set_variant(pf_poisson_plan *plan, int32_t stage, int32_t variant);
+pf_status poisson_get_variant(pf_poisson_plan *plan, int32_t stage, int32_t *variant);
+/* Re-shape a Helmholtz plan: rows per chunk (8, 16 or 32) and columns per
+ * chunk (16, 32 or 64); re-runs Step 1 and re-uploads the tables
+ * (synchronises the plan's stream; allocates). */
+pf_status pcr_set_shape(pf_pcr_plan *plan, int32_t chunk_rows, int32_t columns_per_chunk);
+pf_status pcr_get_shape(pf_pcr_plan *plan, int32_t *chunk_rows, int32_t *columns_per_chunk);
+
 /* A plain device copy of `bytes` bytes (multiple of 16), the calibration
  * kernel for hardware byte counters. */
 pf_status pf_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);

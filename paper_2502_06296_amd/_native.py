@@ -29,6 +29,8 @@ EXPORTS = [
     "pf_graph_begin", "pf_graph_end", "pf_graph_launch", "pf_graph_destroy",
     "poisson_timing", "poisson_timing_read", "pcr_timing", "pcr_timing_read",
     "pf_copy_kernel",
+    "poisson_variant_count", "poisson_set_variant", "poisson_get_variant",
+    "pcr_set_shape", "pcr_get_shape",
 ]
 
 
@@ -85,6 +87,11 @@ def lib():
             "pcr_timing": (i32, [vp, i32]),
             "pcr_timing_read": (i32, [vp, pd, C.POINTER(i32)]),
             "pf_copy_kernel": (i32, [vp, vp, sz, vp]),
+            "poisson_variant_count": (i32, [vp, i32, C.POINTER(i32)]),
+            "poisson_set_variant": (i32, [vp, i32, i32]),
+            "poisson_get_variant": (i32, [vp, i32, C.POINTER(i32)]),
+            "pcr_set_shape": (i32, [vp, i32, i32]),
+            "pcr_get_shape": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

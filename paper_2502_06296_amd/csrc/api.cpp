@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -227,7 +228,7 @@ struct pf_poisson_plan {
   int zchunk;
   DevArena ar;
   size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
-      o_fbar, o_m, o_zm;
+      o_fbar, o_m, o_zm, o_p0m;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   Timing tm;
@@ -235,7 +236,7 @@ struct pf_poisson_plan {
 };
 
 struct pf_pcr_plan {
-  int n, prec, M, P, steps;
+  int n, prec, M, P, steps, cw;
   double s;
   hipStream_t st;
   std::vector<double> al, ga, ex;
@@ -416,7 +417,12 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
     return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
   if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
-  const int zc = kZChunk;
+  int zc = pf::zsolve_default_variant(g->nx, g->nz);
+  if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
+    const int v = std::atoi(ev);
+    if (pf::zsolve_variant_fits(v, g->nx, g->nz)) zc = v;
+  }
+  if (zc < 0) return fail(PF_ERR_UNSUPPORTED, "no z-solve shape fits nx=%d nz=%d", g->nx, g->nz);
   auto *pl = new pf_poisson_plan();
   pl->nx = g->nx; pl->ny = g->ny; pl->nz = g->nz;
   pl->lx = g->lx; pl->ly = g->ly;
@@ -449,6 +455,7 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->o_fbar = A.add<double>(nullptr, (size_t)g->nz);
   pl->o_m = A.add<double>(nullptr, (size_t)g->nz);
   pl->o_zm = A.add<double>(nullptr, (size_t)g->nz);
+  pl->o_p0m = A.add<double>(nullptr, (size_t)g->nz);
   A.cap = A.used;
   hipError_t e = hipMalloc((void **)&A.base, A.cap);
   if (e == hipSuccess) e = hipMemcpy(A.base, A.host.data(), A.used, hipMemcpyHostToDevice);
@@ -543,7 +550,7 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, W0, twx, nullptr, nullptr, scale, lines, st)));
   const double idx2 = (double)nx * nx / (pl->lx * pl->lx), idy2 = (double)ny * ny / (pl->ly * pl->ly);
   STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, fbar, W0, W1, twx, sump, zal, zga, idx2, idy2, st));
-  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, zm, st));
+  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
@@ -580,6 +587,29 @@ pf_status poisson_destroy(pf_poisson_plan *pl) {
   pl->tm.destroy();
   if (pl->ar.base) (void)hipFree(pl->ar.base);
   delete pl;
+  return PF_OK;
+}
+
+pf_status poisson_variant_count(pf_poisson_plan *pl, int32_t stage, int32_t *count) {
+  if (!pl || !count) return fail(PF_ERR_ARG, "NULL argument");
+  if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
+  *count = pf::zsolve_variant_count();
+  return PF_OK;
+}
+
+pf_status poisson_set_variant(pf_poisson_plan *pl, int32_t stage, int32_t variant) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
+  if (!pf::zsolve_variant_fits(variant, pl->nx, pl->nz))
+    return fail(PF_ERR_UNSUPPORTED, "z-solve variant %d does not fit nx=%d nz=%d", variant, pl->nx, pl->nz);
+  pl->zchunk = variant;
+  return PF_OK;
+}
+
+pf_status poisson_get_variant(pf_poisson_plan *pl, int32_t stage, int32_t *variant) {
+  if (!pl || !variant) return fail(PF_ERR_ARG, "NULL argument");
+  if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
+  *variant = pl->zchunk;
   return PF_OK;
 }
 
@@ -620,6 +650,11 @@ pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const d
   pl->n = n; pl->prec = precision; pl->M = M; pl->P = P; pl->s = s;
   pl->steps = 0;
   while ((1 << pl->steps) < 2 * P) ++pl->steps;
+  pl->cw = pf::helm_default_cw(P);
+  if (const char *ev = std::getenv("PF_PCR_CW")) {
+    const int c = std::atoi(ev);
+    if ((c == 16 || c == 32 || c == 64) && c * P <= 1024) pl->cw = c;
+  }
   pl->st = (hipStream_t)stream;
   pl->al.assign(alpha, alpha + n);
   pl->ga.assign(gamma, gamma + n);
@@ -642,6 +677,33 @@ pf_status pcr_update_coef(pf_pcr_plan *pl, double s) {
   return pcr_upload(pl, false);
 }
 
+pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  const int M = chunk_rows;
+  if (M != 8 && M != 16 && M != 32) return fail(PF_ERR_UNSUPPORTED, "chunk_rows must be 8, 16 or 32");
+  if (cw != 16 && cw != 32 && cw != 64) return fail(PF_ERR_UNSUPPORTED, "columns per chunk must be 16, 32 or 64");
+  const int P = (pl->n + M - 1) / M;
+  if (P > 32 || P * cw > 1024) return fail(PF_ERR_UNSUPPORTED, "%d chunks of %d columns exceed a workgroup", P, cw);
+  PF_HIP(hipStreamSynchronize(pl->st));
+  char *old = pl->ar.base;
+  pl->M = M;
+  pl->P = P;
+  pl->cw = cw;
+  pl->steps = 0;
+  while ((1 << pl->steps) < 2 * P) ++pl->steps;
+  pl->ar = DevArena();
+  pf_status st = pcr_upload(pl, true);
+  if (old) (void)hipFree(old);
+  return st;
+}
+
+pf_status pcr_get_shape(pf_pcr_plan *pl, int32_t *chunk_rows, int32_t *cw) {
+  if (!pl || !chunk_rows || !cw) return fail(PF_ERR_ARG, "NULL argument");
+  *chunk_rows = pl->M;
+  *cw = pl->cw;
+  return PF_OK;
+}
+
 pf_status pcr_set_stream(pf_pcr_plan *pl, void *stream) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   pl->st = (hipStream_t)stream;
@@ -653,16 +715,18 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
   if (count < 1 || count > pf::kMaxHelmJobs) return fail(PF_ERR_ARG, "count must be 1..%d", pf::kMaxHelmJobs);
   if (!plans || !fields || !nx || !ny) return fail(PF_ERR_ARG, "NULL argument array");
   pf::HelmJob jobs[pf::kMaxHelmJobs];
-  int M = 0;
+  int M = 0, cw = 1 << 30;
   for (int t = 0; t < count; ++t) {
     const pf_pcr_plan *pl = plans[t];
     if (!pl || !fields[t]) return fail(PF_ERR_ARG, "plan or field %d is NULL", t);
     if (nx[t] < 64 || nx[t] % 64 || ny[t] < 1) return fail(PF_ERR_ARG, "nx must be a positive multiple of 64, ny >= 1");
+    if (pl->P * pl->cw > 1024) return fail(PF_ERR_ARG, "plan %d: chunk shape exceeds a workgroup", t);
     if (pl->M != plans[0]->M) return fail(PF_ERR_ARG, "batched plans must share chunk_rows");
     if (pl->prec != plans[0]->prec) return fail(PF_ERR_ARG, "batched plans must share precision");
     const size_t esz = pl->prec == PF_FP32 ? 4 : 8;
     if ((uintptr_t)fields[t] % esz) return fail(PF_ERR_ARG, "field %d misaligned", t);
     M = M > pl->M ? M : pl->M;
+    cw = cw < pl->cw ? cw : pl->cw;
     jobs[t].field = fields[t];
     jobs[t].nx = nx[t];
     jobs[t].ny = ny[t];
@@ -677,7 +741,7 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
   const int prec = plans[0]->prec == PF_FP64 ? 0 : (plans[0]->prec == PF_FP32 ? 1 : 2);
   pf_pcr_plan *p0 = plans[0];
   return run_stage(p0->tm, p0->st, PF_STAGE_PCR_APPLY,
-                   [&]() { return pf::launch_helm(prec, M, count, jobs, p0->st); });
+                   [&]() { return pf::launch_helm(prec, M, cw, count, jobs, p0->st); });
 }
 
 pf_status pcr_apply(pf_pcr_plan *pl, void *field, int32_t nx, int32_t ny) {

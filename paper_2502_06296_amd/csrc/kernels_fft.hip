@@ -37,6 +37,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
                                                    double *__restrict__ sums, long ncl) {
   using C = cplx<double>;
   __shared__ C lds[LPW * lds_len(N)];
+  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ double red[SUMS ? 2 * LPW * TPL : 2];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   }
   T *oa = out + (size_t)(2 * c) * N;
   T *ob = oa + N;
+#pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
     if (q == 0) {
@@ -86,74 +88,88 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 // transform of r. The iterate carries no plane means (its (0,0) slot was
 // zeroed), so removing the plane means of f keeps the large constant-per-
 // plane part out of the float32 spectrum, where its rounding would spread
-// into the weakly damped (0,j) and (i,0) modes. The two real lines of a
-// pair are (j, k) and (j+1, k).
-template <int N, int TPL, int LPW>
-__global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
+// into the weakly damped (0,j) and (i,0) modes.
+// One workgroup per line pair (j, j+1) of plane k, TPL threads: every load
+// (f, the pair and its y neighbours j-1, j+2 at plane k, the pair at k-1 and
+// k+1) is issued up front; the plane-k lines go to LDS for the x and y
+// differences. Each XCD walks a contiguous run of planes, so the neighbour
+// lines read by other workgroups are still in its L2.
+template <int N, int TPL>
+__global__ __launch_bounds__(TPL) void k_xfwd_resid(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
     double idy2, long ncl) {
   using C = cplx<double>;
-  __shared__ C lds[LPW * lds_len(N)];
-  __shared__ double red[2 * LPW * TPL];
-  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
-  const long c = (long)blockIdx.x * LPW + l;
-  const bool ok = c < ncl;
-  C *buf = lds + l * lds_len(N);
-  double sp[2] = {0.0, 0.0};
-  if (ok) {
-    const long line0 = 2 * c;
-    const int k = (int)(line0 / ny);
-    const int j0 = (int)(line0 % ny);
-    const double ak = zal[k], gk = zga[k];
-    const double dk = ak + gk;
-    const double fb = fbar[k];
-    const size_t plane = (size_t)ny * N;
-    size_t row[2], rym[2], ryp[2];
+  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
+  constexpr int S = N / TPL;
+  __shared__ C buf[lds_len(N)];
+  __shared__ float P[4][N];          // lines j-1, j, j+1, j+2 of plane k
+  __shared__ double red[2 * TPL];
+  const int t = threadIdx.x;
+  const long c = (long)xcd_block(blockIdx.x, gridDim.x);
+  const long line0 = 2 * c;
+  const int k = (int)(line0 / ny);
+  const int j0 = (int)(line0 % ny);
+  const double ak = zal[k], gk = zga[k], dk = ak + gk, fb = fbar[k];
+  const size_t plane = (size_t)ny * N;
+  const size_t row0 = ((size_t)k * ny + j0) * N;
+  const size_t rym = ((size_t)k * ny + (j0 == 0 ? ny - 1 : j0 - 1)) * N;
+  const size_t ryp = ((size_t)k * ny + (j0 + 2 == ny ? 0 : j0 + 2)) * N;
+  double acc[2][S];
+  float pc[2][S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = t + s * TPL;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int j = j0 + h;
-      row[h] = ((size_t)k * ny + j) * N;
-      rym[h] = ((size_t)k * ny + (j == 0 ? ny - 1 : j - 1)) * N;
-      ryp[h] = ((size_t)k * ny + (j == ny - 1 ? 0 : j + 1)) * N;
+      const size_t o = row0 + (size_t)h * N + i;
+      pc[h][s] = p0[o];
+      double z = 0.0;
+      if (k > 0) z += ak * (double)p0[o - plane];
+      if (k < nz - 1) z += gk * (double)p0[o + plane];
+      acc[h][s] = (f[o] - fb) - (z - dk * (double)pc[h][s]);
     }
-#pragma unroll 2
-    for (int s = 0; s < N / TPL; ++s) {
-      const int i = t + s * TPL;
-      const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-      double rv[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const double pc = p0[row[h] + i];
-        const double lx = ((double)p0[row[h] + ip] - 2.0 * pc + (double)p0[row[h] + im]) * idx2;
-        const double ly = ((double)p0[ryp[h] + i] - 2.0 * pc + (double)p0[rym[h] + i]) * idy2;
-        double lzv = -dk * pc;
-        if (k > 0) lzv += ak * (double)p0[row[h] - plane + i];
-        if (k < nz - 1) lzv += gk * (double)p0[row[h] + plane + i];
-        const double r = (f[row[h] + i] - fb) - (lx + ly + lzv);
-        sp[h] += pc;
-        rv[h] = r;
-      }
-      buf[lds_idx(i)] = mkc<double>(rv[0], rv[1]);
-    }
+    P[0][i] = p0[rym + i];
+    P[3][i] = p0[ryp + i];
   }
-  red[2 * tid + 0] = sp[0];
-  red[2 * tid + 1] = sp[1];
+  double sp0 = 0.0, sp1 = 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = t + s * TPL;
+    P[1][i] = pc[0][s];
+    P[2][i] = pc[1][s];
+    sp0 += (double)pc[0][s];
+    sp1 += (double)pc[1][s];
+  }
+  red[2 * t] = sp0;
+  red[2 * t + 1] = sp1;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = t + s * TPL;
+    const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
+    double r[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double c0 = (double)P[h + 1][i];
+      const double lx = ((double)P[h + 1][ip] - 2.0 * c0 + (double)P[h + 1][im]) * idx2;
+      const double ly = ((double)P[h + 2][i] - 2.0 * c0 + (double)P[h][i]) * idy2;
+      r[h] = acc[h][s] - (lx + ly);
+    }
+    buf[lds_idx(i)] = mkc<double>(r[0], r[1]);
+  }
   __syncthreads();
   fft_line<double, N, TPL, false>(buf, tw, t);
-  if (!ok) return;
   if (t == 0) {
     double b0 = 0, b1 = 0;
-    for (int u = 0; u < TPL; ++u) {
-      const double *rr = red + 2 * (l * TPL + u);
-      b0 += rr[0]; b1 += rr[1];
-    }
+    for (int u = 0; u < TPL; ++u) { b0 += red[2 * u]; b1 += red[2 * u + 1]; }
     sums_p[2 * c] = b0;
     sums_p[2 * c + 1] = b1;
   }
-  float *oa = out + (size_t)(2 * c) * N;
+  float *oa = out + row0;
   float *ob = oa + N;
+#pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
     if (q == 0) {
@@ -184,6 +200,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw, int nx,
                                                    int nib) {
   using C = cplx<double>;
+  static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
@@ -226,6 +243,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw, int nx,
                                                    int nib) {
   using C = cplx<double>;
+  static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
@@ -272,6 +290,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
                                                    const float *__restrict__ p0, double scale,
                                                    int ny, long ncl) {
   using C = cplx<double>;
+  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
@@ -280,6 +299,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   if (ok) {
     const TS *a = in + (size_t)(2 * c) * N;
     const TS *b = a + N;
+#pragma unroll
     for (int q = t; q < N / 2; q += TPL) {
       const C A = ld2<TS>(a + 2 * q);
       const C B = ld2<TS>(b + 2 * q);
@@ -348,10 +368,9 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const doub
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
-    constexpr int TPL = x_tpl(N), LPW = x_lpw(N) > 2 ? 2 : x_lpw(N);                             \
-    dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
-    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), g, dim3(TPL * LPW), 0, st, f, fbar, p0, out, \
-                       tw, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                          \
+    constexpr int TPL = N / 4 > 256 ? 256 : N / 4;                                               \
+    hipLaunchKernelGGL((k_xfwd_resid<N, TPL>), dim3((unsigned)ncl), dim3(TPL), 0, st, f, fbar,   \
+                       p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                 \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)

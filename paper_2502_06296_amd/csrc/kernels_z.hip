@@ -30,8 +30,24 @@ namespace pf {
 // gives the reduced last row and leaves the forward-reduced d and the pivots
 // 1/b. After the reduced solve the interior follows from one forward and one
 // backward substitution with the chunk's end values as Dirichlet data.
-template <typename TS, int M, int TI>
-__global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, int ny, int nz, int P,
+// 1/b for the positive, normal pivots of the eliminations: the hardware
+// reciprocal refined by two Newton steps (about 1 ulp), a third of the
+// instructions of an IEEE division.
+__device__ __forceinline__ double rcp64(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+template <bool FAST>
+__device__ __forceinline__ double qdiv(double a, double b) {
+  if constexpr (FAST) return a * rcp64(b);
+  else return a / b;
+}
+
+template <typename TS, int M, int TI, int WAVES, bool FAST>
+__global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, int nx, int ny, int nz, int P,
                                                  const double *__restrict__ zal,
                                                  const double *__restrict__ zga,
                                                  const double *__restrict__ zex,
@@ -68,7 +84,7 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
   double ub = al[M - 2] + uc + ue;
 #pragma unroll
   for (int q = M - 3; q >= 0; --q) {
-    const double tq = ga[q] / ub;
+    const double tq = qdiv<FAST>(ga[q], ub);
     uc = tq * uc;
     ue = (ex[q] + lam) + tq * ue;
     ud = d[q] + tq * ud;
@@ -77,14 +93,14 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
   // downward sweep: pivots b_q = gamma_q + |a_q| + e'_q, forward-reduced d
   double fa = al[1];
   double fe = ex[1] + lam;
-  ib_[1] = 1.0 / (ga[1] + fa + fe);
+  ib_[1] = qdiv<FAST>(1.0, ga[1] + fa + fe);
 #pragma unroll
   for (int q = 2; q < M; ++q) {
     const double tq = al[q] * ib_[q - 1];
     fa = tq * fa;
     fe = (ex[q] + lam) + tq * fe;
     d[q] = d[q] + tq * d[q - 1];
-    ib_[q] = 1.0 / (ga[q] + fa + fe);
+    ib_[q] = qdiv<FAST>(1.0, ga[q] + fa + fe);
   }
 
   // reduced rows 2ch (first) and 2ch+1 (last) of this column
@@ -106,12 +122,12 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
       if (r - s >= 0) {
         const int o = (r - s) * TI + col;
         am = RA[o]; em = RE[o]; dm = RD[o];
-        k1 = a / (am + RG[o] + em);
+        k1 = qdiv<FAST>(a, am + RG[o] + em);
       }
       if (r + s < nr) {
         const int o = (r + s) * TI + col;
         gp = RG[o]; ep = RE[o]; dp = RD[o];
-        k2 = g / (RA[o] + gp + ep);
+        k2 = qdiv<FAST>(g, RA[o] + gp + ep);
       }
       na[h] = k1 * am;
       ng[h] = k2 * gp;
@@ -122,8 +138,8 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
     ra0 = na[0]; rg0 = ng[0]; re0 = ne[0]; rd0 = nd[0];
     ra1 = na[1]; rg1 = ng[1]; re1 = ne[1]; rd1 = nd[1];
   }
-  const double x0 = rd0 / (ra0 + rg0 + re0);
-  const double xl = rd1 / (ra1 + rg1 + re1);
+  const double x0 = qdiv<FAST>(rd0, ra0 + rg0 + re0);
+  const double xl = qdiv<FAST>(rd1, ra1 + rg1 + re1);
 
   // interior: y_q = (d_q + |a_q| x0) / b_q forward, x_q = y_q + gamma_q x_{q+1} / b_q backward
   double a = al[1];
@@ -141,22 +157,63 @@ __global__ __launch_bounds__(512) void k_zsolve(TS *__restrict__ data, int nx, i
     if (r0 + q < nz) cp[(size_t)q * plane] = (TS)(zero_col ? 0.0 : d[q]);
 }
 
+// Launch shapes of the z solve: rows per thread M, columns per workgroup
+// TI, minimum waves per SIMD (0: none), fast reciprocals.
+struct ZVariant {
+  int M, TI, waves;
+  bool fast;
+};
+static const ZVariant kZVariants[] = {
+    {16, 16, 0, false}, {16, 16, 4, true}, {16, 16, 0, true}, {8, 8, 0, true},
+    {16, 8, 0, true},   {8, 16, 0, true},  {16, 32, 0, true}, {8, 8, 4, true},
+};
+constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
+
+int zsolve_variant_count() { return kZVariantCount; }
+
+bool zsolve_variant_fits(int v, int nx, int nz) {
+  if (v < 0 || v >= kZVariantCount) return false;
+  const ZVariant &z = kZVariants[v];
+  const int P = (nz + z.M - 1) / z.M;
+  return P * z.TI <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16;
+}
+
+int zsolve_default_variant(int nx, int nz) {
+  // measured order on MI355X at 1024x512x512: 4 (1.55 ms, float32 storage),
+  // 3, 7 (1.66), 2 (2.03), 0 (2.14), 1 (2.63: spills)
+  for (int v : {4, 3, 2})
+    if (zsolve_variant_fits(v, nx, nz)) return v;
+  return -1;
+}
+
 template <typename TS>
 hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
-                         const double *zex, const double *sx, const double *sy, int chunk_rows,
+                         const double *zex, const double *sx, const double *sy, int variant,
                          hipStream_t st) {
-  // the z tables hold P*M rows (identity padding past nz)
-  if (chunk_rows != 16) return hipErrorInvalidValue;
-  constexpr int M = 16;
-  const int P = (nz + M - 1) / M;
-  const int TI = P * 16 <= 512 ? 16 : 8;
-  if (P * TI > 512 || nx % TI) return hipErrorInvalidValue;
-  const size_t shm = (size_t)4 * 2 * P * TI * sizeof(double);
-  dim3 g((unsigned)((long)(nx / TI) * ny)), b(P * TI);
-  if (TI == 16)
-    hipLaunchKernelGGL((k_zsolve<TS, M, 16>), g, b, shm, st, data, nx, ny, nz, P, zal, zga, zex, sx, sy);
-  else
-    hipLaunchKernelGGL((k_zsolve<TS, M, 8>), g, b, shm, st, data, nx, ny, nz, P, zal, zga, zex, sx, sy);
+  // the z tables hold whole 16-row chunks (identity padding past nz)
+  if (!zsolve_variant_fits(variant, nx, nz)) return hipErrorInvalidValue;
+  const ZVariant &z = kZVariants[variant];
+  const int P = (nz + z.M - 1) / z.M;
+  const size_t shm = (size_t)4 * 2 * P * z.TI * sizeof(double);
+  dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(P * z.TI);
+#define PF_ZV(ID, M_, TI_, W_, F_)                                                                \
+  case ID:                                                                                        \
+    hipLaunchKernelGGL((k_zsolve<TS, M_, TI_, W_, F_>), g, b, shm, st, data, nx, ny, nz, P, zal, \
+                       zga, zex, sx, sy);                                                         \
+    break;
+  switch (variant) {
+    PF_ZV(0, 16, 16, 0, false)
+    PF_ZV(1, 16, 16, 4, true)
+    PF_ZV(2, 16, 16, 0, true)
+    PF_ZV(3, 8, 8, 0, true)
+    PF_ZV(4, 16, 8, 0, true)
+    PF_ZV(5, 8, 16, 0, true)
+    PF_ZV(6, 16, 32, 0, true)
+    PF_ZV(7, 8, 8, 4, true)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PF_ZV
   return hipGetLastError();
 }
 template hipError_t launch_zsolve<double>(int, int, int, double *, const double *, const double *,
@@ -168,81 +225,103 @@ template hipError_t launch_zsolve<float>(int, int, int, float *, const double *,
 
 // ----------------------------------------------------------- zero mode
 // The (0,0) slot of the transformed problem is the plane-mean profile of p.
-// One workgroup: plane means fbar[k] of the right-hand side from its float64
-// line sums; projection onto the range of L_z (zero dzf-weighted mean); the
-// singular Neumann system solved with its last equation replaced by
-// m[nz-1] = 0, then shifted to zero dzf-weighted mean.
-__global__ __launch_bounds__(256) void k_zero_mode(const double *__restrict__ sums,
-                                                   const double *__restrict__ dzf,
-                                                   const double *__restrict__ zal,
-                                                   const double *__restrict__ zga,
-                                                   double *__restrict__ fbar, double *__restrict__ m,
-                                                   int ny, int nz, double inv_nxny) {
-  extern __shared__ double sh[];  // R[nz], Y[nz], RT[nz]
-  double *R = sh, *Y = sh + nz, *RT = sh + 2 * nz;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < nz; k += blockDim.x) {
-    double a = 0.0;
-    const double *s = sums + (size_t)k * ny;
-    for (int j = 0; j < ny; ++j) a += s[j];
-    R[k] = a * inv_nxny;
-    fbar[k] = R[k];
-  }
+// Plane means come from the float64 line sums, one workgroup per plane with
+// a fixed-order tree reduction (bitwise reproducible).
+__global__ __launch_bounds__(256) void k_plane_means(const double *__restrict__ sums,
+                                                     double *__restrict__ mean, int ny,
+                                                     double inv_nxny) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double *s = sums + (size_t)k * ny;
+  double a = 0.0;
+  for (int j = tid; j < ny; j += 256) a += s[j];
+  red[tid] = a;
   __syncthreads();
-  if (tid != 0) return;
-  double wr = 0.0, w = 0.0;
-  for (int k = 0; k < nz; ++k) { wr += dzf[k] * R[k]; w += dzf[k]; }
-  const double c = wr / w;
-  // rows 0..nz-2 of -L_z x = -(R - c), with x[nz-1] = 0 (row nz-2 keeps its
-  // gamma on the diagonal). No row has an excess, so the pivot of row k is
-  // gamma_k + g_k with g_0 = 0 and g_k = alpha_k g_{k-1} / pivot_{k-1}.
-  double g = 0.0, piv = 1.0, y = 0.0;
-  for (int k = 0; k < nz - 1; ++k) {
-    g = (k == 0) ? 0.0 : zal[k] * g / piv;
-    piv = zga[k] + g;
-    y = (-(R[k] - c) + zal[k] * y) / piv;
-    Y[k] = y;
-    RT[k] = zga[k] / piv;
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
   }
-  double x = 0.0;
-  R[nz - 1] = 0.0;
-  for (int k = nz - 2; k >= 0; --k) {
-    x = Y[k] + (k == nz - 2 ? 0.0 : RT[k] * x);
-    R[k] = x;
-  }
-  double wm = 0.0;
-  for (int k = 0; k < nz; ++k) wm += dzf[k] * R[k];
-  const double shift = wm / w;
-  for (int k = 0; k < nz; ++k) m[k] = R[k] - shift;
+  if (tid == 0) mean[k] = red[0] * inv_nxny;
 }
 
-// zm[k] = m[k] - (plane mean of the iterate p0): the profile that gives the
-// corrected field the plane means m.
-__global__ __launch_bounds__(256) void k_zero_shift(const double *__restrict__ sums_p0,
-                                                    const double *__restrict__ m,
-                                                    double *__restrict__ zm, int ny, int nz,
-                                                    double inv_nxny) {
+// One thread: projection of the plane means fbar onto the range of L_z (zero
+// dzf-weighted mean), the singular Neumann system solved with its last
+// equation replaced by m[nz-1] = 0, then the shift to zero dzf-weighted mean.
+// With p0mean (the iterate's plane means) it writes zm = m - p0mean instead.
+__global__ __launch_bounds__(256) void k_zero_solve(const double *__restrict__ fbar,
+                                                    const double *__restrict__ dzf,
+                                                    const double *__restrict__ zal,
+                                                    const double *__restrict__ zga,
+                                                    double *__restrict__ m, int nz) {
+  extern __shared__ double sh[];  // F, W, A, G, Y, RT: nz each
+  double *F = sh, *W = sh + nz, *A = sh + 2 * nz, *G = sh + 3 * nz, *Y = sh + 4 * nz,
+         *RT = sh + 5 * nz;
   for (int k = threadIdx.x; k < nz; k += blockDim.x) {
-    double a = 0.0;
-    const double *s = sums_p0 + (size_t)k * ny;
-    for (int j = 0; j < ny; ++j) a += s[j];
-    zm[k] = m[k] - a * inv_nxny;
+    F[k] = fbar[k];
+    W[k] = dzf[k];
+    A[k] = zal[k];
+    G[k] = zga[k];
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double wr = 0.0, w = 0.0;
+  for (int k = 0; k < nz; ++k) { wr += W[k] * F[k]; w += W[k]; }
+  const double c = wr / w;
+  // rows 0..nz-2 of -L_z x = -(fbar - c), x[nz-1] = 0 (row nz-2 keeps its
+  // gamma on the diagonal). No row has an excess, so the pivot of row k is
+  // gamma_k + g_k with g_0 = 0 and g_k = alpha_k g_{k-1} / pivot_{k-1}.
+  // pivots first (a chain of reciprocals only), then the right-hand side
+  double g = 0.0, rp = 0.0;
+  for (int k = 0; k < nz - 1; ++k) {
+    g = A[k] * g * rp;
+    rp = 1.0 / (G[k] + g);
+    RT[k] = rp;
+  }
+  double y = 0.0;
+  for (int k = 0; k < nz - 1; ++k) {
+    y = (-(F[k] - c) + A[k] * y) * RT[k];
+    Y[k] = y;
+    RT[k] = G[k] * RT[k];
+  }
+  double x = 0.0, wm = 0.0;
+  Y[nz - 1] = 0.0;
+  for (int k = nz - 2; k >= 0; --k) {
+    x = Y[k] + (k == nz - 2 ? 0.0 : RT[k] * x);
+    Y[k] = x;
+    wm += W[k] * x;
+  }
+  const double shift = wm / w;
+  for (int k = 0; k < nz; ++k) m[k] = Y[k] - shift;
+}
+
+__global__ __launch_bounds__(256) void k_sub(const double *__restrict__ a,
+                                             const double *__restrict__ b, double *__restrict__ out,
+                                             int n) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < n) out[k] = a[k] - b[k];
 }
 
 hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *dzf,
                             const double *zal, const double *zga, double *fbar, double *m,
                             hipStream_t st) {
-  const size_t shm = (size_t)3 * nz * sizeof(double);
-  hipLaunchKernelGGL(k_zero_mode, dim3(1), dim3(256), shm, st, sums, dzf, zal, zga, fbar, m, ny, nz,
-                     1.0 / ((double)nx * (double)ny));
+  const double inv = 1.0 / ((double)nx * (double)ny);
+  hipLaunchKernelGGL(k_plane_means, dim3(nz), dim3(256), 0, st, sums, fbar, ny, inv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_solve, dim3(1), dim3(256), (size_t)6 * nz * sizeof(double), st, fbar,
+                     dzf, zal, zga, m, nz);
   return hipGetLastError();
 }
 
+// zm = m - (plane means of the iterate p0), from its float64 line sums;
+// p0mean is scratch of nz doubles.
 hipError_t launch_zero_shift(int nx, int ny, int nz, const double *sums_p0, const double *m,
-                             double *zm, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_shift, dim3(1), dim3(256), 0, st, sums_p0, m, zm, ny, nz,
-                     1.0 / ((double)nx * (double)ny));
+                             double *p0mean, double *zm, hipStream_t st) {
+  const double inv = 1.0 / ((double)nx * (double)ny);
+  hipLaunchKernelGGL(k_plane_means, dim3(nz), dim3(256), 0, st, sums_p0, p0mean, ny, inv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sub, dim3((nz + 255) / 256), dim3(256), 0, st, m, p0mean, zm, nz);
   return hipGetLastError();
 }
 
@@ -311,7 +390,8 @@ struct HelmArgs {
 // double, TC = float with REFINE: a float32 solve, the float64 residual
 // r - (I - s L_z) u in registers, a float32 solve for the correction.
 // CW columns per chunk: 64 (one wave per chunk, wave-uniform coefficient
-// addresses) or 32 (two chunks per wave, for columns of up to 32 chunks).
+// addresses), 32 or 16 (two or four chunks per wave: smaller workgroups, so
+// that several fit on a compute unit).
 template <typename TS, typename TC, int M, int CW, bool REFINE>
 __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   extern __shared__ unsigned char shraw[];
@@ -389,15 +469,17 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   }
 }
 
-hipError_t launch_helm(int precision, int chunk_rows, int count, const HelmJob *jobs,
+int helm_default_cw(int P) { return P <= 16 ? 64 : 32; }
+
+hipError_t launch_helm(int precision, int chunk_rows, int cw, int count, const HelmJob *jobs,
                        hipStream_t st) {
   if (count < 1 || count > kMaxHelmJobs) return hipErrorInvalidValue;
   HelmArgs a;
   a.count = count;
   int maxP = 0;
   for (int t = 0; t < count; ++t) maxP = jobs[t].c.P > maxP ? jobs[t].c.P : maxP;
-  const int CW = maxP <= 16 ? 64 : 32;
-  if (maxP < 1 || maxP * CW > 1024) return hipErrorInvalidValue;
+  const int CW = cw;
+  if (maxP < 1 || maxP * CW > 1024 || (CW != 16 && CW != 32 && CW != 64)) return hipErrorInvalidValue;
   long maxblk = 0;
   for (int t = 0; t < count; ++t) {
     a.job[t] = jobs[t];
@@ -418,8 +500,10 @@ hipError_t launch_helm(int precision, int chunk_rows, int count, const HelmJob *
   case M:                             \
     if (CW == 64) {                   \
       PF_HELM_CW(M, 64)               \
-    } else {                          \
+    } else if (CW == 32) {            \
       PF_HELM_CW(M, 32)               \
+    } else {                          \
+      PF_HELM_CW(M, 16)               \
     }                                 \
     break;
   switch (chunk_rows) {

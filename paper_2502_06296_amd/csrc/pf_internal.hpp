@@ -78,20 +78,27 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double>
                        hipStream_t st);
 
 // Poisson z solve on the doubly packed spectrum (in place), float64
-// elimination in registers; the (0,0) slot column is set to zero.
+// elimination in registers; the (0,0) slot column is set to zero. `variant`
+// indexes a table of launch shapes (rows per thread, columns per workgroup,
+// occupancy bound, reciprocal flavour); the z tables must be padded to a
+// multiple of 16 rows.
 template <typename TS>
 hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
-                         const double *zex, const double *sx, const double *sy, int chunk_rows,
+                         const double *zex, const double *sx, const double *sy, int variant,
                          hipStream_t st);
+int zsolve_variant_count();
+bool zsolve_variant_fits(int variant, int nx, int nz);
+int zsolve_default_variant(int nx, int nz);
 // Singular (0,0) mode: plane means fbar[nz] of the right-hand side from its
 // line sums, projection, pinned Neumann solve for the plane-mean profile
 // m[nz] of p.
 hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *dzf,
                             const double *zal, const double *zga, double *fbar, double *m,
                             hipStream_t st);
-// zm = m - plane means of an iterate (from its float64 line sums).
+// zm = m - plane means of an iterate (from its float64 line sums; p0mean is
+// nz doubles of scratch).
 hipError_t launch_zero_shift(int nx, int ny, int nz, const double *sums_p0, const double *m,
-                             double *zm, hipStream_t st);
+                             double *p0mean, double *zm, hipStream_t st);
 
 // Helmholtz apply (Algorithm 2, Steps 2-4).
 struct HelmCoef {
@@ -110,8 +117,10 @@ struct HelmJob {
 constexpr int kMaxHelmJobs = 4;
 // precision: 0 float64, 1 float32 storage, 2 float64 I/O with a float32
 // solve and one float64-residual correction.
-hipError_t launch_helm(int precision, int chunk_rows, int count, const HelmJob *jobs,
+// cw: columns per chunk, 16, 32 or 64, with P*cw <= 1024.
+hipError_t launch_helm(int precision, int chunk_rows, int cw, int count, const HelmJob *jobs,
                        hipStream_t st);
+int helm_default_cw(int P);
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 

@@ -112,3 +112,12 @@ def test_pcr_prepare_rejects_bad_rows():
     a2, g2, e2 = np.zeros(big), np.zeros(big), np.zeros(big)
     assert L.pcr_prepare(C.byref(h), big, a2.ctypes.data_as(pd), g2.ctypes.data_as(pd),
                          e2.ctypes.data_as(pd), 1e-3, 0, 32, None) == N.PF_ERR_UNSUPPORTED
+
+
+def test_autotune_cache_ignores_corrupt_file(tmp_path):
+    from paper_2502_06296_amd import autotune
+    p = tmp_path / "tune.json"
+    p.write_text("{not json")
+    assert autotune.load_cache(str(p)) == {}
+    autotune.save_cache({"k": {"zsolve_variant": 3}}, str(p))
+    assert autotune.load_cache(str(p)) == {"k": {"zsolve_variant": 3}}
