@@ -186,8 +186,9 @@ pf_status poisson_variant_count(pf_poisson_plan *plan, int32_t stage, int32_t *c
 pf_status poisson_set_variant(pf_poisson_plan *plan, int32_t stage, int32_t variant);
 pf_status poisson_get_variant(pf_poisson_plan *plan, int32_t stage, int32_t *variant);
 /* Re-shape a Helmholtz plan: rows per chunk (8, 16 or 32) and columns per
- * chunk (16, 32 or 64); re-runs Step 1 and re-uploads the tables
- * (synchronises the plan's stream; allocates). */
+ * chunk (16, 32 or 64; negated for persistent workgroups that stage the
+ * Step 1 tables in LDS, at most 512 threads); re-runs Step 1 and re-uploads
+ * the tables (synchronises the plan's stream; allocates). */
 pf_status pcr_set_shape(pf_pcr_plan *plan, int32_t chunk_rows, int32_t columns_per_chunk);
 pf_status pcr_get_shape(pf_pcr_plan *plan, int32_t *chunk_rows, int32_t *columns_per_chunk);
 

@@ -237,6 +237,7 @@ struct pf_poisson_plan {
 
 struct pf_pcr_plan {
   int n, prec, M, P, steps, cw;
+  bool staged;
   double s;
   hipStream_t st;
   std::vector<double> al, ga, ex;
@@ -417,7 +418,7 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
     return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
   if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
-  int zc = pf::zsolve_default_variant(g->nx, g->nz);
+  int zc = pf::zsolve_default_variant(g->nx, g->nz, precision == PF_FP64);
   if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
     const int v = std::atoi(ev);
     if (pf::zsolve_variant_fits(v, g->nx, g->nz)) zc = v;
@@ -651,10 +652,12 @@ pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const d
   pl->steps = 0;
   while ((1 << pl->steps) < 2 * P) ++pl->steps;
   pl->cw = pf::helm_default_cw(P);
+  pl->staged = false;
   if (const char *ev = std::getenv("PF_PCR_CW")) {
     const int c = std::atoi(ev);
     if ((c == 16 || c == 32 || c == 64) && c * P <= 1024) pl->cw = c;
   }
+  if (const char *ev = std::getenv("PF_PCR_STAGED")) pl->staged = std::atoi(ev) != 0 && pl->cw * P <= 512;
   pl->st = (hipStream_t)stream;
   pl->al.assign(alpha, alpha + n);
   pl->ga.assign(gamma, gamma + n);
@@ -677,14 +680,18 @@ pf_status pcr_update_coef(pf_pcr_plan *pl, double s) {
   return pcr_upload(pl, false);
 }
 
-pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw) {
+pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw_in) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  const bool staged = cw_in < 0;
+  const int cw = staged ? -cw_in : cw_in;
   const int M = chunk_rows;
   if (M != 8 && M != 16 && M != 32) return fail(PF_ERR_UNSUPPORTED, "chunk_rows must be 8, 16 or 32");
   if (cw != 16 && cw != 32 && cw != 64) return fail(PF_ERR_UNSUPPORTED, "columns per chunk must be 16, 32 or 64");
   const int P = (pl->n + M - 1) / M;
-  if (P > 32 || P * cw > 1024) return fail(PF_ERR_UNSUPPORTED, "%d chunks of %d columns exceed a workgroup", P, cw);
+  if (P > 32 || P * cw > (staged ? 512 : 1024))
+    return fail(PF_ERR_UNSUPPORTED, "%d chunks of %d columns exceed a workgroup", P, cw);
   PF_HIP(hipStreamSynchronize(pl->st));
+  pl->staged = staged;
   char *old = pl->ar.base;
   pl->M = M;
   pl->P = P;
@@ -700,7 +707,7 @@ pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw) {
 pf_status pcr_get_shape(pf_pcr_plan *pl, int32_t *chunk_rows, int32_t *cw) {
   if (!pl || !chunk_rows || !cw) return fail(PF_ERR_ARG, "NULL argument");
   *chunk_rows = pl->M;
-  *cw = pl->cw;
+  *cw = pl->staged ? -pl->cw : pl->cw;
   return PF_OK;
 }
 
@@ -716,6 +723,7 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
   if (!plans || !fields || !nx || !ny) return fail(PF_ERR_ARG, "NULL argument array");
   pf::HelmJob jobs[pf::kMaxHelmJobs];
   int M = 0, cw = 1 << 30;
+  bool staged = true;
   for (int t = 0; t < count; ++t) {
     const pf_pcr_plan *pl = plans[t];
     if (!pl || !fields[t]) return fail(PF_ERR_ARG, "plan or field %d is NULL", t);
@@ -727,6 +735,7 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
     if ((uintptr_t)fields[t] % esz) return fail(PF_ERR_ARG, "field %d misaligned", t);
     M = M > pl->M ? M : pl->M;
     cw = cw < pl->cw ? cw : pl->cw;
+    staged = staged && pl->staged;
     jobs[t].field = fields[t];
     jobs[t].nx = nx[t];
     jobs[t].ny = ny[t];
@@ -741,7 +750,7 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
   const int prec = plans[0]->prec == PF_FP64 ? 0 : (plans[0]->prec == PF_FP32 ? 1 : 2);
   pf_pcr_plan *p0 = plans[0];
   return run_stage(p0->tm, p0->st, PF_STAGE_PCR_APPLY,
-                   [&]() { return pf::launch_helm(prec, M, cw, count, jobs, p0->st); });
+                   [&]() { return pf::launch_helm(prec, M, cw, staged, count, jobs, p0->st); });
 }
 
 pf_status pcr_apply(pf_pcr_plan *pl, void *field, int32_t nx, int32_t ny) {

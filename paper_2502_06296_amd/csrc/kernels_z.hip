@@ -157,15 +157,186 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, in
     if (r0 + q < nz) cp[(size_t)q * plane] = (TS)(zero_col ? 0.0 : d[q]);
 }
 
+// Paired variant: each thread takes two adjacent slot columns (i, i+1), i
+// even. Slots 2q and 2q+1 carry the real and imaginary parts of the same x
+// mode, so the two columns share the shift lambda and the whole Step 1
+// (pivots, reciprocals, reduced-row coefficients, the cyclic-reduction
+// multipliers): only the right-hand sides are doubled. The one pair whose
+// slots differ in mode (slots 0 and 1: the mean and the Nyquist mode) lives
+// in the workgroups with ib == 0; those run two passes, pass p solving
+// column p of every pair with that column's own shift.
+template <int NR>
+__device__ __forceinline__ double rcpn(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const double e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+  }
+  return r;
+}
+
+// The z tables are deliberately not restrict-qualified: the workgroup
+// barriers then force them to be re-read (from L1) after the reduced solve
+// instead of being held in registers through it.
+template <typename TS, int M, int TP, int NR>
+__global__ __launch_bounds__(512) void k_zsolve2(TS *data, int nx, int ny, int nz, int P,
+                                               const double *zal, const double *zga,
+                                               const double *zex, const double *sx,
+                                               const double *sy) {
+  using V = cplx<TS>;  // the pair (column i, column i+1) of one row
+  extern __shared__ double red[];  // [5][2P][TP]: alpha, gamma, eps, d0, d1 of the reduced rows
+  const int nr = 2 * P;
+  double *RA = red, *RG = red + nr * TP, *RE = red + 2 * nr * TP, *R0 = red + 3 * nr * TP,
+         *R1 = red + 4 * nr * TP;
+  const int nib = nx / (2 * TP);
+  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int ib = blk % nib;
+  const int j = blk / nib;
+  const int pc = threadIdx.x % TP;
+  const int ch = threadIdx.x / TP;
+  const int i = 2 * (ib * TP + pc);
+  const int r0 = ch * M;
+  const size_t plane = (size_t)nx * ny;
+  V *cp = reinterpret_cast<V *>(data + (size_t)j * nx + i + (size_t)r0 * plane);
+  const size_t vplane = plane / 2;
+  const double *al = zal + r0, *ga = zga + r0, *ex = zex + r0;
+  const int npass = ib == 0 ? 2 : 1;  // uniform per workgroup
+  for (int pass = 0; pass < npass; ++pass) {
+    // pass 1 exists only for the pair of slots 0 and 1; other lanes redo
+    // pass 0's work on already solved data and store nothing
+    const int ci = i + pass;
+    const bool zero_col = (ci == 0 && j == 0);
+    const double lam = zero_col ? 1.0 : sx[ci] + sy[j];
+    // pass 0 stores both columns of every pair except column 1 of the pair
+    // (0, 1); pass 1 stores only that column
+    const bool st0 = pass == 0;
+    const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
+
+    double d0[M], d1[M], ib_[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      V v = V{};
+      if (r0 + q < nz) v = cp[(size_t)q * vplane];
+      d0[q] = -(double)v.x;
+      d1[q] = -(double)v.y;
+    }
+    // upward sweep (reduced first row) and downward sweep (pivots, reduced last row)
+    double uc = ga[M - 2];
+    double ue = ex[M - 2] + lam;
+    double ud0 = d0[M - 2], ud1 = d1[M - 2];
+    double ub = al[M - 2] + uc + ue;
+#pragma unroll
+    for (int q = M - 3; q >= 0; --q) {
+      const double tq = ga[q] * rcpn<NR>(ub);
+      uc = tq * uc;
+      ue = (ex[q] + lam) + tq * ue;
+      ud0 = d0[q] + tq * ud0;
+      ud1 = d1[q] + tq * ud1;
+      ub = al[q] + uc + ue;
+    }
+    double fa = al[1];
+    double fe = ex[1] + lam;
+    ib_[1] = rcpn<NR>(ga[1] + fa + fe);
+#pragma unroll
+    for (int q = 2; q < M; ++q) {
+      const double tq = al[q] * ib_[q - 1];
+      fa = tq * fa;
+      fe = (ex[q] + lam) + tq * fe;
+      d0[q] = d0[q] + tq * d0[q - 1];
+      d1[q] = d1[q] + tq * d1[q - 1];
+      ib_[q] = rcpn<NR>(ga[q] + fa + fe);
+    }
+    double ra0 = al[0], rg0 = uc, re0 = ue, ra1 = fa, rg1 = ga[M - 1], re1 = fe;
+    double a00 = ud0, a01 = ud1, a10 = d0[M - 1], a11 = d1[M - 1];  // reduced right-hand sides
+    const int w0 = (2 * ch) * TP + pc, w1 = (2 * ch + 1) * TP + pc;
+    for (int s = 1; s < nr; s *= 2) {
+      RA[w0] = ra0; RG[w0] = rg0; RE[w0] = re0; R0[w0] = a00; R1[w0] = a01;
+      RA[w1] = ra1; RG[w1] = rg1; RE[w1] = re1; R0[w1] = a10; R1[w1] = a11;
+      __syncthreads();
+      double na[2], ng[2], ne[2], n0[2], n1[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = 2 * ch + h;
+        const double a = h ? ra1 : ra0, g = h ? rg1 : rg0, e = h ? re1 : re0;
+        const double x0 = h ? a10 : a00, x1 = h ? a11 : a01;
+        double k1 = 0.0, k2 = 0.0, am = 0.0, em = 0.0, m0 = 0.0, m1 = 0.0;
+        double gp = 0.0, ep = 0.0, p0 = 0.0, p1 = 0.0;
+        if (r - s >= 0) {
+          const int o = (r - s) * TP + pc;
+          am = RA[o]; em = RE[o]; m0 = R0[o]; m1 = R1[o];
+          k1 = a * rcpn<NR>(am + RG[o] + em);
+        }
+        if (r + s < nr) {
+          const int o = (r + s) * TP + pc;
+          gp = RG[o]; ep = RE[o]; p0 = R0[o]; p1 = R1[o];
+          k2 = g * rcpn<NR>(RA[o] + gp + ep);
+        }
+        na[h] = k1 * am;
+        ng[h] = k2 * gp;
+        ne[h] = e + k1 * em + k2 * ep;
+        n0[h] = x0 + k1 * m0 + k2 * p0;
+        n1[h] = x1 + k1 * m1 + k2 * p1;
+      }
+      __syncthreads();
+      ra0 = na[0]; rg0 = ng[0]; re0 = ne[0]; a00 = n0[0]; a01 = n1[0];
+      ra1 = na[1]; rg1 = ng[1]; re1 = ne[1]; a10 = n0[1]; a11 = n1[1];
+    }
+    const double i0 = rcpn<NR>(ra0 + rg0 + re0), i1 = rcpn<NR>(ra1 + rg1 + re1);
+    const double x00 = a00 * i0, x01 = a01 * i0, xl0 = a10 * i1, xl1 = a11 * i1;
+    // interior: forward y_q = (d_q + |a_q| x0) / b_q, backward x_q = y_q + gamma_q x_{q+1} / b_q
+    double a = al[1];
+#pragma unroll
+    for (int q = 1; q < M - 1; ++q) {
+      if (q >= 2) a = al[q] * ib_[q - 1] * a;
+      d0[q] = (d0[q] + a * x00) * ib_[q];
+      d1[q] = (d1[q] + a * x01) * ib_[q];
+    }
+    d0[M - 1] = xl0;
+    d1[M - 1] = xl1;
+#pragma unroll
+    for (int q = M - 2; q >= 1; --q) {
+      const double c = ga[q] * ib_[q];
+      d0[q] = d0[q] + c * d0[q + 1];
+      d1[q] = d1[q] + c * d1[q + 1];
+    }
+    d0[0] = x00;
+    d1[0] = x01;
+    if (st0 || st1) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (r0 + q < nz) {
+          TS *e = reinterpret_cast<TS *>(cp + (size_t)q * vplane);
+          if (st0 && st1) {
+            cp[(size_t)q * vplane] = V{(TS)(zero_col ? 0.0 : d0[q]), (TS)d1[q]};
+          } else if (st0) {
+            e[0] = (TS)(zero_col ? 0.0 : d0[q]);
+          } else {
+            e[1] = (TS)d1[q];
+          }
+        }
+      }
+    }
+  }
+}
+
 // Launch shapes of the z solve: rows per thread M, columns per workgroup
 // TI, minimum waves per SIMD (0: none), fast reciprocals.
+// Paired variants (two columns per thread sharing their shift) take TI
+// columns per workgroup as TI/2 thread pairs; nr is the Newton-step count
+// of their reciprocal.
 struct ZVariant {
   int M, TI, waves;
   bool fast;
+  bool paired;
+  int nr;
 };
 static const ZVariant kZVariants[] = {
-    {16, 16, 0, false}, {16, 16, 4, true}, {16, 16, 0, true}, {8, 8, 0, true},
-    {16, 8, 0, true},   {8, 16, 0, true},  {16, 32, 0, true}, {8, 8, 4, true},
+    {16, 16, 0, false, false, 2}, {16, 16, 4, true, false, 2}, {16, 16, 0, true, false, 2},
+    {8, 8, 0, true, false, 2},    {16, 8, 0, true, false, 2},  {8, 16, 0, true, false, 2},
+    {16, 32, 0, true, false, 2},  {8, 8, 4, true, false, 2},   {16, 16, 0, true, true, 1},
+    {8, 16, 0, true, true, 1},    {16, 32, 0, true, true, 1},  {8, 32, 0, true, true, 1},
+    {16, 16, 0, true, true, 2},   {8, 8, 0, true, true, 1},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
@@ -175,13 +346,17 @@ bool zsolve_variant_fits(int v, int nx, int nz) {
   if (v < 0 || v >= kZVariantCount) return false;
   const ZVariant &z = kZVariants[v];
   const int P = (nz + z.M - 1) / z.M;
-  return P * z.TI <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16;
+  const int threads = z.paired ? P * z.TI / 2 : P * z.TI;
+  return threads <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16;
 }
 
-int zsolve_default_variant(int nx, int nz) {
-  // measured order on MI355X at 1024x512x512: 4 (1.55 ms, float32 storage),
-  // 3, 7 (1.66), 2 (2.03), 0 (2.14), 1 (2.63: spills)
-  for (int v : {4, 3, 2})
+int zsolve_default_variant(int nx, int nz, bool fp64) {
+  // fastest measured on MI355X at 1024x512x512: float64 storage 10 (1.23 ms:
+  // paired, 16 rows, 32 columns), 8 (1.35); float32 storage 13 (1.21 ms:
+  // paired, 8 rows, 8 columns), 8 (1.23); the unpaired 4 (1.55 / 1.98) and 3
+  // as fall-backs
+  static const int f64[] = {10, 8, 12, 4, 3}, f32[] = {13, 8, 10, 4, 3};
+  for (int v : fp64 ? f64 : f32)
     if (zsolve_variant_fits(v, nx, nz)) return v;
   return -1;
 }
@@ -194,8 +369,9 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, co
   if (!zsolve_variant_fits(variant, nx, nz)) return hipErrorInvalidValue;
   const ZVariant &z = kZVariants[variant];
   const int P = (nz + z.M - 1) / z.M;
-  const size_t shm = (size_t)4 * 2 * P * z.TI * sizeof(double);
-  dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(P * z.TI);
+  const size_t shm = z.paired ? (size_t)5 * 2 * P * (z.TI / 2) * sizeof(double)
+                              : (size_t)4 * 2 * P * z.TI * sizeof(double);
+  dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(z.paired ? P * z.TI / 2 : P * z.TI);
 #define PF_ZV(ID, M_, TI_, W_, F_)                                                                \
   case ID:                                                                                        \
     hipLaunchKernelGGL((k_zsolve<TS, M_, TI_, W_, F_>), g, b, shm, st, data, nx, ny, nz, P, zal, \
@@ -210,6 +386,18 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, co
     PF_ZV(5, 8, 16, 0, true)
     PF_ZV(6, 16, 32, 0, true)
     PF_ZV(7, 8, 8, 4, true)
+#define PF_ZP(ID, M_, TI_, NR_)                                                                  \
+  case ID:                                                                                       \
+    hipLaunchKernelGGL((k_zsolve2<TS, M_, TI_ / 2, NR_>), g, b, shm, st, data, nx, ny, nz, P,   \
+                       zal, zga, zex, sx, sy);                                                   \
+    break;
+    PF_ZP(8, 16, 16, 1)
+    PF_ZP(9, 8, 16, 1)
+    PF_ZP(10, 16, 32, 1)
+    PF_ZP(11, 8, 32, 1)
+    PF_ZP(12, 16, 16, 2)
+    PF_ZP(13, 8, 8, 1)
+#undef PF_ZP
     default:
       return hipErrorInvalidValue;
   }
@@ -469,10 +657,163 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   }
 }
 
+// Same algorithm, coefficient tables staged in LDS. A persistent workgroup
+// (CW columns per chunk, any CW) copies its job's Step 1 tables into LDS once
+// and then walks column blocks; chunks that share a wave read their
+// different coefficient rows from LDS instead of global memory, so CW = 32
+// gives 512-thread workgroups that keep more than one resident per compute
+// unit and overlap one block's loads with another's elimination.
+template <typename TC, int M>
+__device__ __forceinline__ void helm_solve_lds(TC (&d)[M], TC &x0, TC &xl, int r0, const TC *fa,
+                                               const TC *bg, const TC *ib, const TC *ra,
+                                               const TC *rc, const TC *k1, const TC *k2,
+                                               const TC *invd, int P, int steps, TC *RD, int w,
+                                               int lane, bool active, int CW) {
+  if (active) {
+#pragma unroll
+    for (int q = 2; q < M; ++q) d[q] = d[q] + fa[r0 + q] * d[q - 1];
+#pragma unroll
+    for (int q = M - 3; q >= 0; --q) d[q] = d[q] + bg[r0 + q] * d[q + 1];
+  }
+  const int nr = 2 * P;
+  x0 = d[0];
+  xl = d[M - 1];
+  for (int st = 0; st < steps; ++st) {
+    const int s = 1 << st;
+    if (active) {
+      RD[(2 * w) * CW + lane] = x0;
+      RD[(2 * w + 1) * CW + lane] = xl;
+    }
+    __syncthreads();
+    if (active) {
+      const int ra0 = 2 * w, ra1 = 2 * w + 1;
+      TC n0 = x0, n1 = xl;
+      if (ra0 - s >= 0) n0 += k1[st * nr + ra0] * RD[(ra0 - s) * CW + lane];
+      if (ra0 + s < nr) n0 += k2[st * nr + ra0] * RD[(ra0 + s) * CW + lane];
+      if (ra1 - s >= 0) n1 += k1[st * nr + ra1] * RD[(ra1 - s) * CW + lane];
+      if (ra1 + s < nr) n1 += k2[st * nr + ra1] * RD[(ra1 + s) * CW + lane];
+      x0 = n0;
+      xl = n1;
+    }
+    __syncthreads();
+  }
+  if (active) {
+    x0 = x0 * invd[2 * w];
+    xl = xl * invd[2 * w + 1];
+#pragma unroll
+    for (int q = 1; q < M - 1; ++q) d[q] = (d[q] + ra[r0 + q] * x0 + rc[r0 + q] * xl) * ib[r0 + q];
+    d[0] = x0;
+    d[M - 1] = xl;
+  }
+}
+
+template <typename TS, typename TC, int M, int CW, bool REFINE>
+__global__ __launch_bounds__(512, 4) void k_helm_lds(HelmArgs args) {
+  extern __shared__ double shd[];
+  const HelmJob &J = args.job[blockIdx.y];
+  const HelmCoef &C = J.c;
+  const int P = C.P, steps = C.steps, nr = 2 * P, npad = P * M;
+  // LDS layout (in TC units unless noted): fa bg ib ra rc [npad each],
+  // k1 k2 [steps*nr], invd [nr], RD [nr*CW]; then float64: al ga ep [npad]
+  // (refinement only), NB [nr*CW]
+  TC *L = reinterpret_cast<TC *>(shd);
+  TC *fa = L, *bg = fa + npad, *ibv = bg + npad, *ra = ibv + npad, *rc = ra + npad;
+  TC *k1 = rc + npad, *k2 = k1 + steps * nr, *invd = k2 + steps * nr, *RD = invd + nr;
+  double *D = reinterpret_cast<double *>(
+      (reinterpret_cast<uintptr_t>(RD + nr * CW) + 7) & ~uintptr_t(7));
+  double *mal = D, *mga = D + npad, *mep = D + 2 * npad, *NB = D + 3 * npad;
+  {
+    const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
+    const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
+    for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+      fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
+      if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mep[r] = C.ep[r]; }
+    }
+    const TC *sk1 = (const TC *)C.k1, *sk2 = (const TC *)C.k2, *sinv = (const TC *)C.invd;
+    for (int r = threadIdx.x; r < steps * nr; r += blockDim.x) { k1[r] = sk1[r]; k2[r] = sk2[r]; }
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) invd[r] = sinv[r];
+  }
+  __syncthreads();
+  const int w = threadIdx.x / CW;
+  const int lane = threadIdx.x % CW;
+  const bool active = w < P;
+  const int n = C.n;
+  const int r0 = active ? w * M : 0;
+  const int nib = J.nx / CW;
+  const long nblk = (long)nib * J.ny;
+  const size_t plane = (size_t)J.nx * J.ny;
+  for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {   // uniform per block
+    const int ibk = (int)(blk % nib);
+    const long j = blk / nib;
+    TS *cp = reinterpret_cast<TS *>(J.field) + (size_t)j * J.nx + (size_t)ibk * CW + lane +
+             (size_t)r0 * plane;
+    TC x0, xl;
+    if constexpr (!REFINE) {
+      TC d[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) d[q] = (active && r0 + q < n) ? (TC)cp[(size_t)q * plane] : TC(0);
+      helm_solve_lds<TC, M>(d, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, P, steps, RD, w,
+                            lane, active, CW);
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+          if (r0 + q < n) cp[(size_t)q * plane] = (TS)d[q];
+      }
+    } else {
+      double r[M];
+      TC u[M], dd[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
+        u[q] = (TC)r[q];
+      }
+      helm_solve_lds<TC, M>(u, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, P, steps, RD, w,
+                            lane, active, CW);
+      if (active) {
+        NB[(2 * w) * CW + lane] = (double)u[0];
+        NB[(2 * w + 1) * CW + lane] = (double)u[M - 1];
+      }
+      __syncthreads();
+      double below = 0.0, above = 0.0;
+      if (active) {
+        if (w > 0) below = NB[(2 * w - 1) * CW + lane];
+        if (w < P - 1) above = NB[(2 * w + 2) * CW + lane];
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          const double al = mal[r0 + q], ga = mga[r0 + q], ep = mep[r0 + q];
+          const double um = q == 0 ? below : (double)u[q == 0 ? 0 : q - 1];
+          const double up = q == M - 1 ? above : (double)u[q == M - 1 ? q : q + 1];
+          const double uc = (double)u[q];
+          dd[q] = (TC)(r[q] - ((al + ga + ep) * uc - al * um - ga * up));
+        }
+      }
+      helm_solve_lds<TC, M>(dd, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, P, steps, RD, w,
+                            lane, active, CW);
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+          if (r0 + q < n) cp[(size_t)q * plane] = (TS)((double)u[q] + (double)dd[q]);
+      }
+    }
+  }
+}
+
+size_t helm_lds_bytes(int precision, int M, int P, int steps, int CW) {
+  const size_t tc = precision == 0 ? 8 : 4;
+  const size_t npad = (size_t)P * M, nr = 2 * (size_t)P;
+  size_t b = tc * (5 * npad + 2 * steps * nr + nr + nr * CW);
+  b = (b + 7) & ~size_t(7);
+  b += 8 * (3 * npad + nr * CW);
+  return b;
+}
+
 int helm_default_cw(int P) { return P <= 16 ? 64 : 32; }
 
-hipError_t launch_helm(int precision, int chunk_rows, int cw, int count, const HelmJob *jobs,
-                       hipStream_t st) {
+hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int count,
+                       const HelmJob *jobs, hipStream_t st) {
   if (count < 1 || count > kMaxHelmJobs) return hipErrorInvalidValue;
   HelmArgs a;
   a.count = count;
@@ -486,6 +827,43 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, int count, const H
     if (jobs[t].nx % CW) return hipErrorInvalidValue;
     const long nb = (long)(jobs[t].nx / CW) * jobs[t].ny;
     if (nb > maxblk) maxblk = nb;
+  }
+  if (staged) {
+    if (maxP * CW > 512) return hipErrorInvalidValue;
+    int maxsteps = 0;
+    for (int t = 0; t < count; ++t) maxsteps = jobs[t].c.steps > maxsteps ? jobs[t].c.steps : maxsteps;
+    const size_t shm = helm_lds_bytes(precision, chunk_rows, maxP, maxsteps, CW);
+    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    // persistent: a few workgroups per compute unit walk the column blocks
+    const long gx = maxblk < 2048 ? maxblk : 2048;
+    dim3 g((unsigned)gx, (unsigned)count), b(CW * maxP);
+#define PF_HELMS_CW(M, CWV)                                                                      \
+  if (precision == 0)                                                                            \
+    hipLaunchKernelGGL((k_helm_lds<double, double, M, CWV, false>), g, b, shm, st, a);           \
+  else if (precision == 1)                                                                       \
+    hipLaunchKernelGGL((k_helm_lds<float, float, M, CWV, false>), g, b, shm, st, a);             \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_helm_lds<double, float, M, CWV, true>), g, b, shm, st, a);
+#define PF_HELMS(M)                   \
+  case M:                             \
+    if (CW == 64) {                   \
+      PF_HELMS_CW(M, 64)              \
+    } else if (CW == 32) {            \
+      PF_HELMS_CW(M, 32)              \
+    } else {                          \
+      PF_HELMS_CW(M, 16)              \
+    }                                 \
+    break;
+    switch (chunk_rows) {
+      PF_HELMS(8)
+      PF_HELMS(16)
+      PF_HELMS(32)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef PF_HELMS
+#undef PF_HELMS_CW
+    return hipGetLastError();
   }
   dim3 g((unsigned)maxblk, (unsigned)count), b(CW * maxP);
   const size_t shm = (size_t)2 * maxP * CW * sizeof(double);

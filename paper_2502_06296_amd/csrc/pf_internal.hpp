@@ -88,7 +88,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, co
                          hipStream_t st);
 int zsolve_variant_count();
 bool zsolve_variant_fits(int variant, int nx, int nz);
-int zsolve_default_variant(int nx, int nz);
+int zsolve_default_variant(int nx, int nz, bool fp64);
 // Singular (0,0) mode: plane means fbar[nz] of the right-hand side from its
 // line sums, projection, pinned Neumann solve for the plane-mean profile
 // m[nz] of p.
@@ -117,9 +117,10 @@ struct HelmJob {
 constexpr int kMaxHelmJobs = 4;
 // precision: 0 float64, 1 float32 storage, 2 float64 I/O with a float32
 // solve and one float64-residual correction.
-// cw: columns per chunk, 16, 32 or 64, with P*cw <= 1024.
-hipError_t launch_helm(int precision, int chunk_rows, int cw, int count, const HelmJob *jobs,
-                       hipStream_t st);
+// cw: columns per chunk, 16, 32 or 64, with P*cw <= 1024 (<= 512 staged).
+// staged: persistent workgroups with the Step 1 tables in LDS.
+hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int count,
+                       const HelmJob *jobs, hipStream_t st);
 int helm_default_cw(int P);
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
