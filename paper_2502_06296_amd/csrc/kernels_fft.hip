@@ -38,33 +38,22 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   using C = cplx<double>;
   __shared__ C lds[LPW * lds_len(N)];
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
-  __shared__ double red[SUMS ? 2 * LPW * TPL : 2];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
-  double sa = 0.0, sb = 0.0;
   if (ok) {
     const double *a = in + (size_t)(2 * c) * N;
     const double *b = a + N;
 #pragma unroll
     for (int s = 0; s < N / TPL; ++s) {
       const int pos = t + s * TPL;
-      const double va = a[pos], vb = b[pos];
-      if (SUMS) { sa += va; sb += vb; }
-      buf[lds_idx(pos)] = mkc<double>(va, vb);
+      buf[lds_idx(pos)] = mkc<double>(a[pos], b[pos]);
     }
   }
-  if (SUMS) { red[2 * tid] = sa; red[2 * tid + 1] = sb; }
   __syncthreads();
   fft_line<double, N, TPL, false>(buf, tw, t);
   if (!ok) return;
-  if (SUMS && t == 0) {
-    double A = 0.0, B = 0.0;
-    for (int u = 0; u < TPL; ++u) { A += red[2 * (l * TPL + u)]; B += red[2 * (l * TPL + u) + 1]; }
-    sums[2 * c] = A;
-    sums[2 * c + 1] = B;
-  }
   T *oa = out + (size_t)(2 * c) * N;
   T *ob = oa + N;
 #pragma unroll
@@ -74,6 +63,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
       const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
       A = mkc<double>(z0.x, zh.x);
       B = mkc<double>(z0.y, zh.y);
+      // the float64 zero mode of each line is its sum (a tree of exact
+      // unit-twiddle butterflies)
+      if (SUMS) {
+        sums[2 * c] = z0.x;
+        sums[2 * c + 1] = z0.y;
+      }
     } else {
       split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
     }
@@ -89,85 +84,134 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 // zeroed), so removing the plane means of f keeps the large constant-per-
 // plane part out of the float32 spectrum, where its rounding would spread
 // into the weakly damped (0,j) and (i,0) modes.
-// One workgroup per line pair (j, j+1) of plane k, TPL threads: every load
-// (f, the pair and its y neighbours j-1, j+2 at plane k, the pair at k-1 and
-// k+1) is issued up front; the plane-k lines go to LDS for the x and y
-// differences. Each XCD walks a contiguous run of planes, so the neighbour
-// lines read by other workgroups are still in its L2.
-template <int N, int TPL>
-__global__ __launch_bounds__(TPL) void k_xfwd_resid(
+//
+// A workgroup takes R = 2*LPW consecutive x lines j0..j0+R-1 of plane k, in
+// the transform shape of k_xfwd (TPL threads per complex line). Every global
+// load is issued up front as G-wide vectors: the p0 tile of rows j0-1..j0+R
+// (periodic in y), and per thread the f values and the p0 values of planes
+// k-1 and k+1 of its groups (two lines x G columns). The tile goes to LDS,
+// aliased onto the transform buffer; the x and y differences read it there,
+// and the residual is held in registers until the tile is dead. Each XCD
+// walks a contiguous run of planes, so the neighbour-plane lines read by
+// other workgroups are still in its L2.
+template <typename T, int G>
+struct alignas(sizeof(T) * G > 16 ? 16 : sizeof(T) * G) vec_t {
+  T v[G];
+};
+
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
-    double idy2, long ncl) {
+    double idy2) {
   using C = cplx<double>;
-  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
-  constexpr int S = N / TPL;
-  __shared__ C buf[lds_len(N)];
-  __shared__ float P[4][N];          // lines j-1, j, j+1, j+2 of plane k
-  __shared__ double red[2 * TPL];
-  const int t = threadIdx.x;
-  const long c = (long)xcd_block(blockIdx.x, gridDim.x);
-  const long line0 = 2 * c;
-  const int k = (int)(line0 / ny);
-  const int j0 = (int)(line0 % ny);
-  const double ak = zal[k], gk = zga[k], dk = ak + gk, fb = fbar[k];
+  constexpr int NT = TPL * LPW;
+  constexpr int R = 2 * LPW;
+  constexpr int G = (N / TPL) % 4 == 0 ? 4 : ((N / TPL) % 2 == 0 ? 2 : 1);
+  constexpr int NG = N / G;            // column groups per line
+  static_assert((LPW * NG) % NT == 0, "whole groups per thread");
+  constexpr int GS = LPW * NG / NT;    // groups (2 lines x G columns) per thread
+  constexpr int TV = (R + 2) * NG;     // vectors in the p0 tile
+  constexpr int TS = (TV + NT - 1) / NT;
+  constexpr int TSUM = NT / R >= 64 ? 64 : (NT / R >= 32 ? 32 : (NT / R >= 16 ? 16 : 8));
+  static_assert(NT / R >= 8 && N % TSUM == 0, "line-sum lanes");
+  using VF = vec_t<float, G>;
+  using VD = vec_t<double, G>;
+  __shared__ C lds[LPW * lds_len(N)];
+  static_assert((R + 2) * N * sizeof(float) <= sizeof(lds), "p0 tile fits the transform buffer");
+  float *P = reinterpret_cast<float *>(lds);  // tile row u = line j0 - 1 + u
+  const int tid = threadIdx.x;
+  const long line0 = (long)xcd_block(blockIdx.x, gridDim.x) * R;
+  const int k = (int)(line0 / ny), j0 = (int)(line0 % ny);
   const size_t plane = (size_t)ny * N;
-  const size_t row0 = ((size_t)k * ny + j0) * N;
-  const size_t rym = ((size_t)k * ny + (j0 == 0 ? ny - 1 : j0 - 1)) * N;
-  const size_t ryp = ((size_t)k * ny + (j0 + 2 == ny ? 0 : j0 + 2)) * N;
-  double acc[2][S];
-  float pc[2][S];
+  const float *pk = p0 + (size_t)k * plane;
+  const double *fk = f + (size_t)k * plane;
+  const bool lo = k > 0, hi = k < nz - 1;
+
+  VF tv[TS];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int i = t + s * TPL;
+  for (int s = 0; s < TS; ++s) {
+    const int e = tid + s * NT;
+    if (TV % NT == 0 || e < TV) {
+      const int u = e / NG, c = e % NG;
+      int j = j0 - 1 + u;
+      j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+      tv[s] = *reinterpret_cast<const VF *>(pk + (size_t)j * N + c * G);
+    }
+  }
+  VD fv[GS][2];
+  VF zm[GS][2], zp[GS][2];
+#pragma unroll
+  for (int s = 0; s < GS; ++s) {
+    const int g = tid + s * NT, m = g / NG, c = g % NG;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const size_t o = row0 + (size_t)h * N + i;
-      pc[h][s] = p0[o];
-      double z = 0.0;
-      if (k > 0) z += ak * (double)p0[o - plane];
-      if (k < nz - 1) z += gk * (double)p0[o + plane];
-      acc[h][s] = (f[o] - fb) - (z - dk * (double)pc[h][s]);
+      const size_t o = (size_t)(j0 + 2 * m + h) * N + c * G;
+      fv[s][h] = *reinterpret_cast<const VD *>(fk + o);
+      if (lo) zm[s][h] = *reinterpret_cast<const VF *>(pk - plane + o);
+      if (hi) zp[s][h] = *reinterpret_cast<const VF *>(pk + plane + o);
     }
-    P[0][i] = p0[rym + i];
-    P[3][i] = p0[ryp + i];
   }
-  double sp0 = 0.0, sp1 = 0.0;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int i = t + s * TPL;
-    P[1][i] = pc[0][s];
-    P[2][i] = pc[1][s];
-    sp0 += (double)pc[0][s];
-    sp1 += (double)pc[1][s];
+  for (int s = 0; s < TS; ++s) {
+    const int e = tid + s * NT;
+    if (TV % NT == 0 || e < TV) *reinterpret_cast<VF *>(P + (e / NG) * N + (e % NG) * G) = tv[s];
   }
-  red[2 * t] = sp0;
-  red[2 * t + 1] = sp1;
   __syncthreads();
+
+  // float64 sums of the R lines of p0 (tile rows 1..R)
+  if (tid < R * TSUM) {
+    const int l = tid / TSUM, u = tid % TSUM;
+    const float *row = P + (l + 1) * N;
+    double sum = 0.0;
+#pragma unroll 8
+    for (int i = u; i < N; i += TSUM) sum += (double)row[i];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int i = t + s * TPL;
-    const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-    double r[2];
+    for (int w = TSUM / 2; w > 0; w /= 2) sum += __shfl_xor(sum, w, TSUM);
+    if (u == 0) sums_p[line0 + l] = sum;
+  }
+
+  const double ak = zal[k], gk = zga[k], dk = ak + gk, fb = fbar[k];
+  double r[GS][2][G];
+#pragma unroll
+  for (int s = 0; s < GS; ++s) {
+    const int g = tid + s * NT, m = g / NG, i0 = (g % NG) * G;
+    const int il = i0 == 0 ? N - 1 : i0 - 1, ir = i0 + G == N ? 0 : i0 + G;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const double c0 = (double)P[h + 1][i];
-      const double lx = ((double)P[h + 1][ip] - 2.0 * c0 + (double)P[h + 1][im]) * idx2;
-      const double ly = ((double)P[h + 2][i] - 2.0 * c0 + (double)P[h][i]) * idy2;
-      r[h] = acc[h][s] - (lx + ly);
+      const float *row = P + (2 * m + h + 1) * N;
+      const VF cv = *reinterpret_cast<const VF *>(row + i0);
+      const VF up = *reinterpret_cast<const VF *>(row + N + i0);
+      const VF dn = *reinterpret_cast<const VF *>(row - N + i0);
+      const double xl = (double)row[il], xr = (double)row[ir];
+#pragma unroll
+      for (int v = 0; v < G; ++v) {
+        const double c0 = (double)cv.v[v];
+        double z = 0.0;
+        if (lo) z += ak * (double)zm[s][h].v[v];
+        if (hi) z += gk * (double)zp[s][h].v[v];
+        const double acc = (fv[s][h].v[v] - fb) - (z - dk * c0);
+        const double xm = v == 0 ? xl : (double)cv.v[v - 1];
+        const double xp = v == G - 1 ? xr : (double)cv.v[v + 1];
+        const double lx = (xp - 2.0 * c0 + xm) * idx2;
+        const double ly = ((double)up.v[v] - 2.0 * c0 + (double)dn.v[v]) * idy2;
+        r[s][h][v] = acc - (lx + ly);
+      }
     }
-    buf[lds_idx(i)] = mkc<double>(r[0], r[1]);
+  }
+  __syncthreads();  // the tile is dead: the transform buffer takes the residual
+#pragma unroll
+  for (int s = 0; s < GS; ++s) {
+    const int g = tid + s * NT, m = g / NG, i0 = (g % NG) * G;
+#pragma unroll
+    for (int v = 0; v < G; ++v) lds[m * lds_len(N) + lds_idx(i0 + v)] = mkc<double>(r[s][0][v], r[s][1][v]);
   }
   __syncthreads();
+  const int l = tid / TPL, t = tid % TPL;
+  C *buf = lds + l * lds_len(N);
   fft_line<double, N, TPL, false>(buf, tw, t);
-  if (t == 0) {
-    double b0 = 0, b1 = 0;
-    for (int u = 0; u < TPL; ++u) { b0 += red[2 * u]; b1 += red[2 * u + 1]; }
-    sums_p[2 * c] = b0;
-    sums_p[2 * c + 1] = b1;
-  }
-  float *oa = out + row0;
+  float *oa = out + (size_t)(line0 + 2 * l) * N;
   float *ob = oa + N;
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
@@ -364,13 +408,14 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const doub
                              const float *p0, float *out, const cplx<double> *tw, double *sums_p0,
                              const double *zal, const double *zga, double idx2, double idy2,
                              hipStream_t st) {
-  const long ncl = (long)ny * nz / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
-    constexpr int TPL = N / 4 > 256 ? 256 : N / 4;                                               \
-    hipLaunchKernelGGL((k_xfwd_resid<N, TPL>), dim3((unsigned)ncl), dim3(TPL), 0, st, f, fbar,   \
-                       p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2, ncl);                 \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                                \
+    if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
+    const long nblk = (long)ny * nz / (2 * LPW);                                                 \
+    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0, st, \
+                       f, fbar, p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2);             \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
