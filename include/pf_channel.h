@@ -105,7 +105,9 @@ pf_status pf_grid_faces(const pf_grid *g, double *zf_out);
  * PF_FP32_REFINE, 0 or 1 (one correction reaches 1e-10 relative at
  * nz <= 1024; 0 is PF_FP32), ignored otherwise. *workspace_bytes (may be NULL) receives the
  * device workspace poisson_solve needs: 0 for PF_FP64 (p doubles as the
- * spectral buffer), 4*N for PF_FP32, 8*N for PF_FP32_REFINE. */
+ * spectral buffer); for PF_FP32 a float32 spectrum whose z planes are
+ * padded by 64 elements, 4*nz*(nx*ny + 64) bytes; for PF_FP32_REFINE that
+ * plus the float32 iterate, 4*N more. */
 pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision,
                        int32_t n_refine, void *stream, size_t *workspace_bytes);
 /* Caller-owned device workspace of at least *workspace_bytes, 256-byte

@@ -233,6 +233,8 @@ struct pf_poisson_plan {
   size_t ws_bytes = 0, ws_need = 0;
   Timing tm;
   size_t npts() const { return (size_t)nx * ny * nz; }
+  // plane stride of the float32 spectrum work array
+  size_t sp32() const { return (size_t)nx * ny + pf::kPlanePad; }
 };
 
 struct pf_pcr_plan {
@@ -466,7 +468,10 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
     return fail(PF_ERR_DEVICE, "plan tables: %s", hipGetErrorString(e));
   }
   const size_t N = pl->npts();
-  pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * N : 8 * N);
+  // float32: the padded spectrum; float32 + refinement: the dense iterate,
+  // then the padded spectrum
+  const size_t S = pl->sp32() * (size_t)pl->nz;
+  pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * S : 4 * (N + S));
   if (workspace_bytes) *workspace_bytes = pl->ws_need;
   *out = pl;
   return PF_OK;
@@ -520,42 +525,45 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
     return s;
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<double>(nx, rhs, p, twx, sums, lines, st));
+    // the spectrum lives in p itself, dense
+    const size_t sd = (size_t)nx * ny;
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
     STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, twy, st));
-    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, twy, st));
-    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, p, twx, mm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, st));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, st));
+    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   float *W0 = (float *)pl->ws;
+  const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W0, twx, sums, lines, st));
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
     STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, twy, st));
-    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, twy, st));
-    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, p, twx, mm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
+    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
   // float32 solve without the zero mode, then one correction for the
   // float64 residual of the plane-mean-free problem; the zero mode is solved
   // once, in float64, from the plane means of f
   float *W1 = W0 + pl->npts();
-  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, rhs, W1, twx, sums, lines, st));
+  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W1, sp, twx, sums, lines, st));
   STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
-  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
-  STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, W0, twx, nullptr, nullptr, scale, lines, st)));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, sp, W0, twx, nullptr, nullptr, scale, lines, st)));
   const double idx2 = (double)nx * nx / (pl->lx * pl->lx), idy2 = (double)ny * ny / (pl->ly * pl->ly);
-  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, fbar, W0, W1, twx, sump, zal, zga, idx2, idy2, st));
+  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, zal, zga, idx2, idy2, st));
   STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, twy, st));
-  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, twy, st));
-  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W1, p, twx, zm, W0, scale, lines, st)));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W1, sp, p, twx, zm, W0, scale, lines, st)));
 #undef STAGE
   return PF_OK;
 }

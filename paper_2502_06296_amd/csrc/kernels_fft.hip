@@ -34,7 +34,8 @@ bool fft_size_supported(int n) {
 template <typename T, int N, int TPL, int LPW, bool SUMS>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
                                                    const cplx<double> *__restrict__ tw,
-                                                   double *__restrict__ sums, long ncl) {
+                                                   double *__restrict__ sums, long ncl, int ny,
+                                                   size_t sp) {
   using C = cplx<double>;
   __shared__ C lds[LPW * lds_len(N)];
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   __syncthreads();
   fft_line<double, N, TPL, false>(buf, tw, t);
   if (!ok) return;
-  T *oa = out + (size_t)(2 * c) * N;
+  T *oa = out + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
   T *ob = oa + N;
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
-    double idy2) {
+    double idy2, size_t sp) {
   using C = cplx<double>;
   constexpr int NT = TPL * LPW;
   constexpr int R = 2 * LPW;
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
   const int l = tid / TPL, t = tid % TPL;
   C *buf = lds + l * lds_len(N);
   fft_line<double, N, TPL, false>(buf, tw, t);
-  float *oa = out + (size_t)(line0 + 2 * l) * N;
+  float *oa = out + (size_t)k * sp + (size_t)(j0 + 2 * l) * N;
   float *ob = oa + N;
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
@@ -242,7 +243,7 @@ __device__ __forceinline__ void st2(T *p, double x, double y) {
 template <typename T, int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw, int nx,
-                                                   int nib) {
+                                                   int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const int ib = blk % nib;
   const long k = blk / nib;
-  T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
+  T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
 template <typename T, int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw, int nx,
-                                                   int nib) {
+                                                   int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const int ib = blk % nib;
   const long k = blk / nib;
-  T *base = data + (size_t)k * N * nx + (size_t)ib * 2 * LPW;
+  T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
 #pragma unroll
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
                                                    const cplx<double> *__restrict__ tw,
                                                    const double *__restrict__ zm,
                                                    const float *__restrict__ p0, double scale,
-                                                   int ny, long ncl) {
+                                                   int ny, long ncl, size_t sp) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
   if (ok) {
-    const TS *a = in + (size_t)(2 * c) * N;
+    const TS *a = in + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
     const TS *b = a + N;
 #pragma unroll
     for (int q = t; q < N / 2; q += TPL) {
@@ -381,8 +382,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
 
 // ------------------------------------------------------------- launchers
 template <typename T>
-hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw, double *sums,
-                       long lines, hipStream_t st) {
+hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
+                       const cplx<double> *tw, double *sums, long lines, hipStream_t st) {
   const long ncl = lines / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                              \
@@ -391,10 +392,10 @@ hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw,
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
     if (sums)                                                                                   \
       hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, in, out, tw, \
-                         sums, ncl);                                                            \
+                         sums, ncl, ny, sp);                                                    \
     else                                                                                        \
       hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, false>), g, dim3(TPL * LPW), 0, st, in, out,    \
-                         tw, sums, ncl);                                                        \
+                         tw, sums, ncl, ny, sp);                                                \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -405,9 +406,9 @@ hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw,
 }
 
 hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, const cplx<double> *tw, double *sums_p0,
-                             const double *zal, const double *zga, double idx2, double idy2,
-                             hipStream_t st) {
+                             const float *p0, float *out, size_t sp, const cplx<double> *tw,
+                             double *sums_p0, const double *zal, const double *zga, double idx2,
+                             double idy2, hipStream_t st) {
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
@@ -415,7 +416,7 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const doub
     if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
     hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0, st, \
-                       f, fbar, p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2);             \
+                       f, fbar, p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2, sp);         \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -426,7 +427,8 @@ hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const doub
 }
 
 template <typename T>
-hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st) {
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
+                       hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -434,7 +436,7 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, 
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
-                       dim3(TPL * LPW), 0, st, data, tw, nx, nib);                            \
+                       dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -445,7 +447,8 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, 
 }
 
 template <typename T>
-hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st) {
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
+                       hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -453,7 +456,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, 
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
-                       dim3(TPL * LPW), 0, st, data, tw, nx, nib);                            \
+                       dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -464,7 +467,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, 
 }
 
 template <typename TS, typename TO>
-hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double> *tw,
+hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const float *p0, double scale, long lines,
                        hipStream_t st) {
   const long ncl = lines / 2;
@@ -475,13 +478,13 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double>
     dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
     if (zm && p0)                                                                               \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
-                         zm, p0, scale, ny, ncl);                                               \
+                         zm, p0, scale, ny, ncl, sp);                                               \
     else if (zm)                                                                                \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, false>), g, b, 0, st, in, out, tw, \
-                         zm, p0, scale, ny, ncl);                                               \
+                         zm, p0, scale, ny, ncl, sp);                                               \
     else                                                                                        \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, false, false>), g, b, 0, st, in, out,    \
-                         tw, zm, p0, scale, ny, ncl);                                           \
+                         tw, zm, p0, scale, ny, ncl, sp);                                           \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -491,21 +494,25 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double>
   }
 }
 
-template hipError_t launch_xfwd<double>(int, const double *, double *, const cplx<double> *,
-                                        double *, long, hipStream_t);
-template hipError_t launch_xfwd<float>(int, const double *, float *, const cplx<double> *,
-                                       double *, long, hipStream_t);
-template hipError_t launch_yfwd<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
-template hipError_t launch_yfwd<float>(int, int, int, float *, const cplx<double> *, hipStream_t);
-template hipError_t launch_yinv<double>(int, int, int, double *, const cplx<double> *, hipStream_t);
-template hipError_t launch_yinv<float>(int, int, int, float *, const cplx<double> *, hipStream_t);
-template hipError_t launch_xinv<double, double>(int, int, const double *, double *,
+template hipError_t launch_xfwd<double>(int, int, const double *, double *, size_t,
+                                        const cplx<double> *, double *, long, hipStream_t);
+template hipError_t launch_xfwd<float>(int, int, const double *, float *, size_t,
+                                       const cplx<double> *, double *, long, hipStream_t);
+template hipError_t launch_yfwd<double>(int, int, int, double *, size_t, const cplx<double> *,
+                                        hipStream_t);
+template hipError_t launch_yfwd<float>(int, int, int, float *, size_t, const cplx<double> *,
+                                       hipStream_t);
+template hipError_t launch_yinv<double>(int, int, int, double *, size_t, const cplx<double> *,
+                                        hipStream_t);
+template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cplx<double> *,
+                                       hipStream_t);
+template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
                                                 const float *, double, long, hipStream_t);
-template hipError_t launch_xinv<float, float>(int, int, const float *, float *,
+template hipError_t launch_xinv<float, float>(int, int, const float *, size_t, float *,
                                               const cplx<double> *, const double *, const float *,
                                               double, long, hipStream_t);
-template hipError_t launch_xinv<float, double>(int, int, const float *, double *,
+template hipError_t launch_xinv<float, double>(int, int, const float *, size_t, double *,
                                                const cplx<double> *, const double *, const float *,
                                                double, long, hipStream_t);
 

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, in
                                                  const double *__restrict__ zga,
                                                  const double *__restrict__ zex,
                                                  const double *__restrict__ sx,
-                                                 const double *__restrict__ sy) {
+                                                 const double *__restrict__ sy, size_t sp) {
   extern __shared__ double red[];  // [4][2P][TI]: alpha, gamma, eps, d of the reduced rows
   const int nr = 2 * P;
   double *RA = red, *RG = red + nr * TI, *RE = red + 2 * nr * TI, *RD = red + 3 * nr * TI;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, in
   const int ch = threadIdx.x / TI;
   const int i = ib * TI + col;
   const int r0 = ch * M;
-  const size_t plane = (size_t)nx * ny;
+  const size_t plane = sp;
   TS *cp = data + (size_t)j * nx + i + (size_t)r0 * plane;
   const bool zero_col = (i == 0 && j == 0);
   const double lam = zero_col ? 1.0 : sx[i] + sy[j];
@@ -179,16 +179,35 @@ __device__ __forceinline__ double rcpn(double b) {
 // The z tables are deliberately not restrict-qualified: the workgroup
 // barriers then force them to be re-read (from L1) after the reduced solve
 // instead of being held in registers through it.
-template <typename TS, int M, int TP, int NR>
-__global__ __launch_bounds__(512) void k_zsolve2(TS *data, int nx, int ny, int nz, int P,
+// LDS slot of reduced row `row` of thread pair pc: consecutive pairs are
+// adjacent, and with fewer than 8 pairs per workgroup every row pair is
+// followed by a gap of TP slots, so the 8 lanes of one 128-bit LDS access
+// (two chunks) fall in different banks.
+__host__ __device__ constexpr int zskew(int tp, bool sk) { return sk && tp < 8 ? tp : 0; }
+template <int TP, bool SK>
+__device__ __forceinline__ int zslot(int row, int pc) {
+  return (row >> 1) * (2 * TP + zskew(TP, SK)) + (row & 1) * TP + pc;
+}
+
+template <typename TS, int M, int TP, int NR, int WAVES, bool SK>
+__global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny, int nz, int P,
                                                const double *zal, const double *zga,
                                                const double *zex, const double *sx,
-                                               const double *sy) {
+                                               const double *sy, size_t sp) {
   using V = cplx<TS>;  // the pair (column i, column i+1) of one row
-  extern __shared__ double red[];  // [5][2P][TP]: alpha, gamma, eps, d0, d1 of the reduced rows
+  // LDS: the z tables of the column, (alpha, gamma) and eps of row
+  // ch*M + q at [q*P + ch] (the chunks of one wave read consecutive
+  // entries), then three double2 arrays of the 2P reduced rows (zslot)
+  extern __shared__ double red[];
+  using D2 = cplx<double>;
   const int nr = 2 * P;
-  double *RA = red, *RG = red + nr * TP, *RE = red + 2 * nr * TP, *R0 = red + 3 * nr * TP,
-         *R1 = red + 4 * nr * TP;
+  D2 *tag = reinterpret_cast<D2 *>(red);
+  double *tex = reinterpret_cast<double *>(tag + P * M);
+  for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
+    const int o = (e % M) * P + e / M;
+    tag[o] = mkc<double>(zal[e], zga[e]);
+    tex[o] = zex[e];
+  }
   const int nib = nx / (2 * TP);
   const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
   const int ib = blk % nib;
@@ -197,10 +216,15 @@ __global__ __launch_bounds__(512) void k_zsolve2(TS *data, int nx, int ny, int n
   const int ch = threadIdx.x / TP;
   const int i = 2 * (ib * TP + pc);
   const int r0 = ch * M;
-  const size_t plane = (size_t)nx * ny;
+  const size_t plane = sp;
   V *cp = reinterpret_cast<V *>(data + (size_t)j * nx + i + (size_t)r0 * plane);
   const size_t vplane = plane / 2;
-  const double *al = zal + r0, *ga = zga + r0, *ex = zex + r0;
+  const D2 *agc = tag + ch;
+  const double *exc = tex + ch;
+  auto al = [&](int q) { return agc[q * P].x; };
+  auto ga = [&](int q) { return agc[q * P].y; };
+  auto ex = [&](int q) { return exc[q * P]; };
+  __syncthreads();
   const int npass = ib == 0 ? 2 : 1;  // uniform per workgroup
   for (int pass = 0; pass < npass; ++pass) {
     // pass 1 exists only for the pair of slots 0 and 1; other lanes redo
@@ -222,73 +246,86 @@ __global__ __launch_bounds__(512) void k_zsolve2(TS *data, int nx, int ny, int n
       d1[q] = -(double)v.y;
     }
     // upward sweep (reduced first row) and downward sweep (pivots, reduced last row)
-    double uc = ga[M - 2];
-    double ue = ex[M - 2] + lam;
+    double uc = ga(M - 2);
+    double ue = ex(M - 2) + lam;
     double ud0 = d0[M - 2], ud1 = d1[M - 2];
-    double ub = al[M - 2] + uc + ue;
+    double ub = al(M - 2) + uc + ue;
 #pragma unroll
     for (int q = M - 3; q >= 0; --q) {
-      const double tq = ga[q] * rcpn<NR>(ub);
+      const double tq = ga(q) * rcpn<NR>(ub);
       uc = tq * uc;
-      ue = (ex[q] + lam) + tq * ue;
+      ue = (ex(q) + lam) + tq * ue;
       ud0 = d0[q] + tq * ud0;
       ud1 = d1[q] + tq * ud1;
-      ub = al[q] + uc + ue;
+      ub = al(q) + uc + ue;
     }
-    double fa = al[1];
-    double fe = ex[1] + lam;
-    ib_[1] = rcpn<NR>(ga[1] + fa + fe);
+    double fa = al(1);
+    double fe = ex(1) + lam;
+    ib_[1] = rcpn<NR>(ga(1) + fa + fe);
 #pragma unroll
     for (int q = 2; q < M; ++q) {
-      const double tq = al[q] * ib_[q - 1];
+      const double tq = al(q) * ib_[q - 1];
       fa = tq * fa;
-      fe = (ex[q] + lam) + tq * fe;
+      fe = (ex(q) + lam) + tq * fe;
       d0[q] = d0[q] + tq * d0[q - 1];
       d1[q] = d1[q] + tq * d1[q - 1];
-      ib_[q] = rcpn<NR>(ga[q] + fa + fe);
+      ib_[q] = rcpn<NR>(ga(q) + fa + fe);
     }
-    double ra0 = al[0], rg0 = uc, re0 = ue, ra1 = fa, rg1 = ga[M - 1], re1 = fe;
-    double a00 = ud0, a01 = ud1, a10 = d0[M - 1], a11 = d1[M - 1];  // reduced right-hand sides
-    const int w0 = (2 * ch) * TP + pc, w1 = (2 * ch + 1) * TP + pc;
+    // The reduced rows 2ch (first row of the chunk) and 2ch+1 (last row),
+    // each kept divided by its own diagonal: coupling below A, above G,
+    // excess E (A + G + E = 1) and the right-hand sides D0, D1. A cyclic-
+    // reduction step on normalised rows needs no division by a neighbour's
+    // pivot: row r takes A' D[r-s] and G' D[r+s] into its parts, sums its
+    // new diagonal from non-negative terms and divides once. A row with no
+    // neighbour at distance s already has A (or G) exactly zero, so the
+    // clamped read contributes nothing.
+    D2 *X1 = reinterpret_cast<D2 *>(tex + P * M);  // (A, E)
+    const int span = (nr / 2) * (2 * TP + zskew(TP, SK));
+    D2 *X2 = X1 + span;                    // (D0, D1)
+    D2 *X3 = X2 + span;                    // (G, E)
+    double A[2], G[2], E[2], D0[2], D1[2];
+    {
+      const double b0 = rcpn<NR>(al(0) + uc + ue), b1 = rcpn<NR>(fa + ga(M - 1) + fe);
+      A[0] = al(0) * b0; G[0] = uc * b0; E[0] = ue * b0; D0[0] = ud0 * b0; D1[0] = ud1 * b0;
+      A[1] = fa * b1; G[1] = ga(M - 1) * b1; E[1] = fe * b1; D0[1] = d0[M - 1] * b1; D1[1] = d1[M - 1] * b1;
+    }
     for (int s = 1; s < nr; s *= 2) {
-      RA[w0] = ra0; RG[w0] = rg0; RE[w0] = re0; R0[w0] = a00; R1[w0] = a01;
-      RA[w1] = ra1; RG[w1] = rg1; RE[w1] = re1; R0[w1] = a10; R1[w1] = a11;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int o = zslot<TP, SK>(2 * ch + h, pc);
+        X1[o] = mkc<double>(A[h], E[h]);
+        X2[o] = mkc<double>(D0[h], D1[h]);
+        X3[o] = mkc<double>(G[h], E[h]);
+      }
       __syncthreads();
       double na[2], ng[2], ne[2], n0[2], n1[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int r = 2 * ch + h;
-        const double a = h ? ra1 : ra0, g = h ? rg1 : rg0, e = h ? re1 : re0;
-        const double x0 = h ? a10 : a00, x1 = h ? a11 : a01;
-        double k1 = 0.0, k2 = 0.0, am = 0.0, em = 0.0, m0 = 0.0, m1 = 0.0;
-        double gp = 0.0, ep = 0.0, p0 = 0.0, p1 = 0.0;
-        if (r - s >= 0) {
-          const int o = (r - s) * TP + pc;
-          am = RA[o]; em = RE[o]; m0 = R0[o]; m1 = R1[o];
-          k1 = a * rcpn<NR>(am + RG[o] + em);
-        }
-        if (r + s < nr) {
-          const int o = (r + s) * TP + pc;
-          gp = RG[o]; ep = RE[o]; p0 = R0[o]; p1 = R1[o];
-          k2 = g * rcpn<NR>(RA[o] + gp + ep);
-        }
-        na[h] = k1 * am;
-        ng[h] = k2 * gp;
-        ne[h] = e + k1 * em + k2 * ep;
-        n0[h] = x0 + k1 * m0 + k2 * p0;
-        n1[h] = x1 + k1 * m1 + k2 * p1;
+        const int lo = zslot<TP, SK>(r - s < 0 ? 0 : r - s, pc);
+        const int hi = zslot<TP, SK>(r + s >= nr ? nr - 1 : r + s, pc);
+        const D2 ae = X1[lo], dl = X2[lo], ge = X3[hi], dh = X2[hi];
+        na[h] = A[h] * ae.x;
+        ng[h] = G[h] * ge.x;
+        ne[h] = E[h] + A[h] * ae.y + G[h] * ge.y;
+        n0[h] = D0[h] + A[h] * dl.x + G[h] * dh.x;
+        n1[h] = D1[h] + A[h] * dl.y + G[h] * dh.y;
       }
       __syncthreads();
-      ra0 = na[0]; rg0 = ng[0]; re0 = ne[0]; a00 = n0[0]; a01 = n1[0];
-      ra1 = na[1]; rg1 = ng[1]; re1 = ne[1]; a10 = n0[1]; a11 = n1[1];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double ib = rcpn<NR>(na[h] + ng[h] + ne[h]);
+        A[h] = na[h] * ib; G[h] = ng[h] * ib; E[h] = ne[h] * ib;
+        D0[h] = n0[h] * ib; D1[h] = n1[h] * ib;
+      }
     }
-    const double i0 = rcpn<NR>(ra0 + rg0 + re0), i1 = rcpn<NR>(ra1 + rg1 + re1);
-    const double x00 = a00 * i0, x01 = a01 * i0, xl0 = a10 * i1, xl1 = a11 * i1;
+    // decoupled: every diagonal is 1
+    const double x00 = D0[0], x01 = D1[0], xl0 = D0[1], xl1 = D1[1];
     // interior: forward y_q = (d_q + |a_q| x0) / b_q, backward x_q = y_q + gamma_q x_{q+1} / b_q
-    double a = al[1];
+    double a = al(1);
 #pragma unroll
     for (int q = 1; q < M - 1; ++q) {
-      if (q >= 2) a = al[q] * ib_[q - 1] * a;
+      if (q >= 2) a = al(q) * ib_[q - 1] * a;
       d0[q] = (d0[q] + a * x00) * ib_[q];
       d1[q] = (d1[q] + a * x01) * ib_[q];
     }
@@ -296,12 +333,177 @@ __global__ __launch_bounds__(512) void k_zsolve2(TS *data, int nx, int ny, int n
     d1[M - 1] = xl1;
 #pragma unroll
     for (int q = M - 2; q >= 1; --q) {
-      const double c = ga[q] * ib_[q];
+      const double c = ga(q) * ib_[q];
       d0[q] = d0[q] + c * d0[q + 1];
       d1[q] = d1[q] + c * d1[q + 1];
     }
     d0[0] = x00;
     d1[0] = x01;
+    if (st0 || st1) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (r0 + q < nz) {
+          TS *e = reinterpret_cast<TS *>(cp + (size_t)q * vplane);
+          if (st0 && st1) {
+            cp[(size_t)q * vplane] = V{(TS)(zero_col ? 0.0 : d0[q]), (TS)d1[q]};
+          } else if (st0) {
+            e[0] = (TS)(zero_col ? 0.0 : d0[q]);
+          } else {
+            e[1] = (TS)d1[q];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Separator form of the paired solve. The last row of every chunk is a
+// separator; the other M-1 rows of the chunk are interior to it. A downward
+// sweep from the chunk's first row (which couples to the previous separator
+// by its alpha) reduces the chunk to its separator row; an upward sweep over
+// the interior rows reduces the chunk's first row to its couplings with the
+// previous and the own separator. The separator row then eliminates the
+// next chunk's first row (read from LDS), which leaves one tridiagonal row
+// per chunk in the separators alone: P rows instead of the 2P of the first-
+// and-last-row reduction, one row per thread, and one cyclic-reduction step
+// fewer. Every pivot is still a sum of non-negative parts:
+//   separator row:  -SA x[s-1] + (SA + SG + SE) x[s] - SG x[s+1] = SD,
+//   SA = fa, SG = t ug', SE = fe + t ue', SD = D + t U', t = gamma / C',
+// with (fa, fe, D) from the downward sweep and (ug', ue', U', C') the next
+// chunk's reduced first row.
+template <typename TS, int M, int TP, int NR, int WAVES>
+__global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
+                                                      const double *zal, const double *zga,
+                                                      const double *zex, const double *sx,
+                                                      const double *sy, size_t sp) {
+  static_assert(M >= 3, "a chunk needs interior rows");
+  using V = cplx<TS>;
+  using D2 = cplx<double>;
+  // LDS: the z tables as in k_zsolve2, then three double2 arrays [P][TP]
+  extern __shared__ double red[];
+  D2 *tag = reinterpret_cast<D2 *>(red);
+  double *tex = reinterpret_cast<double *>(tag + P * M);
+  for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
+    const int o = (e % M) * P + e / M;
+    tag[o] = mkc<double>(zal[e], zga[e]);
+    tex[o] = zex[e];
+  }
+  D2 *X1 = reinterpret_cast<D2 *>(tex + P * M);
+  D2 *X2 = X1 + P * TP;
+  D2 *X3 = X2 + P * TP;
+  const int nib = nx / (2 * TP);
+  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int ib = blk % nib;
+  const int j = blk / nib;
+  const int pc = threadIdx.x % TP;
+  const int ch = threadIdx.x / TP;
+  const int i = 2 * (ib * TP + pc);
+  const int r0 = ch * M;
+  const size_t plane = sp;
+  V *cp = reinterpret_cast<V *>(data + (size_t)j * nx + i + (size_t)r0 * plane);
+  const size_t vplane = plane / 2;
+  const D2 *agc = tag + ch;
+  const double *exc = tex + ch;
+  auto al = [&](int q) { return agc[q * P].x; };
+  auto ga = [&](int q) { return agc[q * P].y; };
+  auto ex = [&](int q) { return exc[q * P]; };
+  const int me = ch * TP + pc;
+  const int nch = ch + 1 < P ? ch + 1 : ch;  // the last chunk's gamma is 0
+  const int nb = nch * TP + pc;
+  __syncthreads();
+  const int npass = ib == 0 ? 2 : 1;  // uniform per workgroup
+  for (int pass = 0; pass < npass; ++pass) {
+    // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1
+    const int ci = i + pass;
+    const bool zero_col = (ci == 0 && j == 0);
+    const double lam = zero_col ? 1.0 : sx[ci] + sy[j];
+    const bool st0 = pass == 0;
+    const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
+
+    double d0[M], d1[M], ib_[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      V v = V{};
+      if (r0 + q < nz) v = cp[(size_t)q * vplane];
+      d0[q] = -(double)v.x;
+      d1[q] = -(double)v.y;
+    }
+    // upward sweep over the interior: the chunk's first row in terms of the
+    // previous separator (alpha_0) and the own separator (ug)
+    {
+      double ug = ga(M - 2), ue = ex(M - 2) + lam, u0 = d0[M - 2], u1 = d1[M - 2];
+      double cb = al(M - 2) + ug + ue;
+#pragma unroll
+      for (int q = M - 3; q >= 0; --q) {
+        const double t = ga(q) * rcpn<NR>(cb);
+        ug = t * ug;
+        ue = (ex(q) + lam) + t * ue;
+        u0 = d0[q] + t * u0;
+        u1 = d1[q] + t * u1;
+        cb = al(q) + ug + ue;
+      }
+      X1[me] = mkc<double>(ug, ue);
+      X2[me] = mkc<double>(u0, u1);
+    }
+    // downward sweep from the first row (coupled to the previous separator)
+    double fa = al(0), fe = ex(0) + lam;
+    ib_[0] = rcpn<NR>(fa + ga(0) + fe);
+#pragma unroll
+    for (int q = 1; q < M; ++q) {
+      const double t = al(q) * ib_[q - 1];
+      fa = t * fa;
+      fe = (ex(q) + lam) + t * fe;
+      d0[q] = d0[q] + t * d0[q - 1];
+      d1[q] = d1[q] + t * d1[q - 1];
+      if (q < M - 1) ib_[q] = rcpn<NR>(fa + ga(q) + fe);
+    }
+    __syncthreads();
+    double A, G, E, S0, S1;
+    {
+      const D2 gu = X1[nb], uu = X2[nb];
+      const double t = ga(M - 1) * rcpn<NR>(tag[nch].x + gu.x + gu.y);
+      const double sa = fa, sg = t * gu.x, se = fe + t * gu.y;
+      const double s0 = d0[M - 1] + t * uu.x, s1 = d1[M - 1] + t * uu.y;
+      const double b = rcpn<NR>(sa + sg + se);
+      A = sa * b; G = sg * b; E = se * b; S0 = s0 * b; S1 = s1 * b;
+    }
+    __syncthreads();
+    // cyclic reduction on the P separator rows (normalised, see k_zsolve2)
+    for (int s = 1; s < P; s *= 2) {
+      X1[me] = mkc<double>(A, E);
+      X2[me] = mkc<double>(S0, S1);
+      X3[me] = mkc<double>(G, E);
+      __syncthreads();
+      const int lo = (ch - s < 0 ? 0 : ch - s) * TP + pc;
+      const int hi = (ch + s >= P ? P - 1 : ch + s) * TP + pc;
+      const D2 ae = X1[lo], dl = X2[lo], ge = X3[hi], dh = X2[hi];
+      const double na = A * ae.x, ng = G * ge.x, ne = E + A * ae.y + G * ge.y;
+      const double n0 = S0 + A * dl.x + G * dh.x, n1 = S1 + A * dl.y + G * dh.y;
+      __syncthreads();
+      const double b = rcpn<NR>(na + ng + ne);
+      A = na * b; G = ng * b; E = ne * b; S0 = n0 * b; S1 = n1 * b;
+    }
+    // separator values: the own one and the previous chunk's
+    X2[me] = mkc<double>(S0, S1);
+    __syncthreads();
+    const D2 xl = ch > 0 ? X2[me - TP] : mkc<double>(0.0, 0.0);
+    __syncthreads();
+    // interior: forward y_q = (D_q + fa_q x_lo) / b_q, backward x_q = y_q + gamma_q x_{q+1} / b_q
+    double a = al(0);
+#pragma unroll
+    for (int q = 0; q < M - 1; ++q) {
+      if (q >= 1) a = al(q) * ib_[q - 1] * a;
+      d0[q] = (d0[q] + a * xl.x) * ib_[q];
+      d1[q] = (d1[q] + a * xl.y) * ib_[q];
+    }
+    d0[M - 1] = S0;
+    d1[M - 1] = S1;
+#pragma unroll
+    for (int q = M - 2; q >= 0; --q) {
+      const double c = ga(q) * ib_[q];
+      d0[q] = d0[q] + c * d0[q + 1];
+      d1[q] = d1[q] + c * d1[q + 1];
+    }
     if (st0 || st1) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
@@ -330,52 +532,72 @@ struct ZVariant {
   bool fast;
   bool paired;
   int nr;
+  bool skew = true;  // paired: gaps between reduced row pairs in LDS
+  bool sep = false;  // paired: separator form, P reduced rows
 };
 static const ZVariant kZVariants[] = {
     {16, 16, 0, false, false, 2}, {16, 16, 4, true, false, 2}, {16, 16, 0, true, false, 2},
     {8, 8, 0, true, false, 2},    {16, 8, 0, true, false, 2},  {8, 16, 0, true, false, 2},
     {16, 32, 0, true, false, 2},  {8, 8, 4, true, false, 2},   {16, 16, 0, true, true, 1},
     {8, 16, 0, true, true, 1},    {16, 32, 0, true, true, 1},  {8, 32, 0, true, true, 1},
-    {16, 16, 0, true, true, 2},   {8, 8, 0, true, true, 1},
+    {16, 16, 0, true, true, 2},   {8, 8, 0, true, true, 1},    {8, 8, 4, true, true, 1},
+    {8, 16, 4, true, true, 1},    {8, 8, 4, true, true, 1, false}, {8, 16, 4, true, true, 1, false},
+    // separator form (k_zsolve3)
+    {8, 8, 4, true, true, 1, false, true},   {8, 16, 4, true, true, 1, false, true},
+    {16, 16, 0, true, true, 1, false, true}, {16, 32, 0, true, true, 1, false, true},
+    {8, 32, 4, true, true, 1, false, true},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
 int zsolve_variant_count() { return kZVariantCount; }
+
+// LDS bytes of a launch: paired variants hold the column's z tables and
+// three double2 arrays of the reduced rows, unpaired ones four double arrays.
+static size_t zsolve_lds(const ZVariant &z, int P) {
+  const int tp = z.TI / 2;
+  const size_t tables = (size_t)3 * P * z.M * sizeof(double);
+  if (z.paired && z.sep) return tables + (size_t)3 * P * tp * 2 * sizeof(double);
+  return z.paired ? (size_t)3 * P * (2 * tp + zskew(tp, z.skew)) * 2 * sizeof(double) + tables
+                  : (size_t)4 * 2 * P * z.TI * sizeof(double);
+}
 
 bool zsolve_variant_fits(int v, int nx, int nz) {
   if (v < 0 || v >= kZVariantCount) return false;
   const ZVariant &z = kZVariants[v];
   const int P = (nz + z.M - 1) / z.M;
   const int threads = z.paired ? P * z.TI / 2 : P * z.TI;
-  return threads <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16;
+  return threads <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16 &&
+         zsolve_lds(z, P) <= 65536;
 }
 
 int zsolve_default_variant(int nx, int nz, bool fp64) {
-  // fastest measured on MI355X at 1024x512x512: float64 storage 10 (1.23 ms:
-  // paired, 16 rows, 32 columns), 8 (1.35); float32 storage 13 (1.21 ms:
-  // paired, 8 rows, 8 columns), 8 (1.23); the unpaired 4 (1.55 / 1.98) and 3
-  // as fall-backs
-  static const int f64[] = {10, 8, 12, 4, 3}, f32[] = {13, 8, 10, 4, 3};
-  for (int v : fp64 ? f64 : f32)
-    if (zsolve_variant_fits(v, nx, nz)) return v;
+  // fastest measured on MI355X at 1024x512x512: float64 storage 21 (1.05 ms:
+  // separator form, 16 rows, 32 columns), 10 (1.12); float32 storage (padded
+  // planes) 18 (0.86 ms: separator form, 8 rows, 8 columns), 19 (0.87), 16
+  // (0.95); the unpaired 4 and 3 as fall-backs where the LDS or thread
+  // budget excludes the paired shapes
+  static const int f64[] = {21, 10, 19, 8, 4, 3}, f32[] = {18, 19, 16, 13, 8, 4, 3};
+  const int *list = fp64 ? f64 : f32;
+  const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
+  for (int k = 0; k < len; ++k)
+    if (zsolve_variant_fits(list[k], nx, nz)) return list[k];
   return -1;
 }
 
 template <typename TS>
-hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
-                         const double *zex, const double *sx, const double *sy, int variant,
-                         hipStream_t st) {
+hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const double *zal,
+                         const double *zga, const double *zex, const double *sx, const double *sy,
+                         int variant, hipStream_t st) {
   // the z tables hold whole 16-row chunks (identity padding past nz)
   if (!zsolve_variant_fits(variant, nx, nz)) return hipErrorInvalidValue;
   const ZVariant &z = kZVariants[variant];
   const int P = (nz + z.M - 1) / z.M;
-  const size_t shm = z.paired ? (size_t)5 * 2 * P * (z.TI / 2) * sizeof(double)
-                              : (size_t)4 * 2 * P * z.TI * sizeof(double);
+  const size_t shm = zsolve_lds(z, P);
   dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(z.paired ? P * z.TI / 2 : P * z.TI);
 #define PF_ZV(ID, M_, TI_, W_, F_)                                                                \
   case ID:                                                                                        \
     hipLaunchKernelGGL((k_zsolve<TS, M_, TI_, W_, F_>), g, b, shm, st, data, nx, ny, nz, P, zal, \
-                       zga, zex, sx, sy);                                                         \
+                       zga, zex, sx, sy, sp);                                                         \
     break;
   switch (variant) {
     PF_ZV(0, 16, 16, 0, false)
@@ -386,17 +608,32 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, co
     PF_ZV(5, 8, 16, 0, true)
     PF_ZV(6, 16, 32, 0, true)
     PF_ZV(7, 8, 8, 4, true)
-#define PF_ZP(ID, M_, TI_, NR_)                                                                  \
+#define PF_ZP(ID, M_, TI_, NR_, W_, SK_)                                                         \
   case ID:                                                                                       \
-    hipLaunchKernelGGL((k_zsolve2<TS, M_, TI_ / 2, NR_>), g, b, shm, st, data, nx, ny, nz, P,   \
-                       zal, zga, zex, sx, sy);                                                   \
+    hipLaunchKernelGGL((k_zsolve2<TS, M_, TI_ / 2, NR_, W_, SK_>), g, b, shm, st, data, nx, ny,  \
+                       nz, P, zal, zga, zex, sx, sy, sp);                                            \
     break;
-    PF_ZP(8, 16, 16, 1)
-    PF_ZP(9, 8, 16, 1)
-    PF_ZP(10, 16, 32, 1)
-    PF_ZP(11, 8, 32, 1)
-    PF_ZP(12, 16, 16, 2)
-    PF_ZP(13, 8, 8, 1)
+    PF_ZP(8, 16, 16, 1, 1, true)
+    PF_ZP(9, 8, 16, 1, 1, true)
+    PF_ZP(10, 16, 32, 1, 1, true)
+    PF_ZP(11, 8, 32, 1, 1, true)
+    PF_ZP(12, 16, 16, 2, 1, true)
+    PF_ZP(13, 8, 8, 1, 1, true)
+    PF_ZP(14, 8, 8, 1, 4, true)
+    PF_ZP(15, 8, 16, 1, 4, true)
+    PF_ZP(16, 8, 8, 1, 4, false)
+    PF_ZP(17, 8, 16, 1, 4, false)
+#define PF_ZS(ID, M_, TI_, W_)                                                                   \
+  case ID:                                                                                       \
+    hipLaunchKernelGGL((k_zsolve3<TS, M_, TI_ / 2, 1, W_>), g, b, shm, st, data, nx, ny, nz, P,  \
+                       zal, zga, zex, sx, sy, sp);                                                   \
+    break;
+    PF_ZS(18, 8, 8, 4)
+    PF_ZS(19, 8, 16, 4)
+    PF_ZS(20, 16, 16, 1)
+    PF_ZS(21, 16, 32, 1)
+    PF_ZS(22, 8, 32, 4)
+#undef PF_ZS
 #undef PF_ZP
     default:
       return hipErrorInvalidValue;
@@ -404,10 +641,10 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, co
 #undef PF_ZV
   return hipGetLastError();
 }
-template hipError_t launch_zsolve<double>(int, int, int, double *, const double *, const double *,
+template hipError_t launch_zsolve<double>(int, int, int, double *, size_t, const double *, const double *,
                                           const double *, const double *, const double *, int,
                                           hipStream_t);
-template hipError_t launch_zsolve<float>(int, int, int, float *, const double *, const double *,
+template hipError_t launch_zsolve<float>(int, int, int, float *, size_t, const double *, const double *,
                                          const double *, const double *, const double *, int,
                                          hipStream_t);
 

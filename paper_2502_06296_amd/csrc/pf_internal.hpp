@@ -24,6 +24,9 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 
 bool fft_size_supported(int n);
 
+// Padding (elements) between the z planes of a float32 spectrum work array.
+constexpr size_t kPlanePad = 64;
+
 // Kernel shapes of the line transforms: TPL threads per complex line, LPW
 // complex lines per workgroup. The LDS holds float64 complex lines whatever
 // the storage type. x lines are contiguous; y lines are columns gathered as
@@ -52,28 +55,33 @@ constexpr int y_lpw(int n) {
 // All return hipSuccess or the launch error. Lengths are runtime checked by
 // the caller against fft_size_supported.
 
-// Every transform runs in float64; T, TS and TO are storage types.
+// Every transform runs in float64; T, TS and TO are storage types. A
+// packed spectrum array holds its z planes sp >= nx*ny elements apart (the
+// float32 work arrays are padded so that the z columns do not all fall on
+// the same memory channels); real-space arrays are dense.
 // x forward: rhs (float64 lines of nx) -> packed spectrum (T). Optional
 // float64 sums of every input line (sums may be null).
 template <typename T>
-hipError_t launch_xfwd(int nx, const double *in, T *out, const cplx<double> *tw, double *sums,
-                       long lines, hipStream_t st);
+hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
+                       const cplx<double> *tw, double *sums, long lines, hipStream_t st);
 // x forward of the float64 7-point residual r = (f - fbar[k]) - L7 p0 (p0
 // float32, fbar the float64 plane means of f), with the float64 sums of p0
 // per line; the spectrum is float32.
 hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, const cplx<double> *tw, double *sums_p0,
-                             const double *zal, const double *zga, double idx2, double idy2,
-                             hipStream_t st);
+                             const float *p0, float *out, size_t sp, const cplx<double> *tw,
+                             double *sums_p0, const double *zal, const double *zga, double idx2,
+                             double idy2, hipStream_t st);
 // y forward / inverse, in place on the packed (T) data.
 template <typename T>
-hipError_t launch_yfwd(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st);
+hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
+                       hipStream_t st);
 template <typename T>
-hipError_t launch_yinv(int nx, int ny, int nz, T *data, const cplx<double> *tw, hipStream_t st);
+hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
+                       hipStream_t st);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k] and float32 base field p0 added.
 template <typename TS, typename TO>
-hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double> *tw,
+hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const float *p0, double scale, long lines,
                        hipStream_t st);
 
@@ -83,9 +91,9 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, TO *out, const cplx<double>
 // occupancy bound, reciprocal flavour); the z tables must be padded to a
 // multiple of 16 rows.
 template <typename TS>
-hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, const double *zal, const double *zga,
-                         const double *zex, const double *sx, const double *sy, int variant,
-                         hipStream_t st);
+hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const double *zal,
+                         const double *zga, const double *zex, const double *sx, const double *sy,
+                         int variant, hipStream_t st);
 int zsolve_variant_count();
 bool zsolve_variant_fits(int variant, int nx, int nz);
 int zsolve_default_variant(int nx, int nz, bool fp64);

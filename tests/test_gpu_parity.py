@@ -49,6 +49,7 @@ POISSON_SHAPES = [
     (384, 768, 20, 1.5, 7),
     (1536, 128, 17, 1.8, 8),
     (128, 1024, 4, 1.5, 9),     # smallest nz
+    (64, 64, 1024, 1.5, 10),    # largest nz: the z solve falls back to a shape that fits the LDS
 ]
 
 
