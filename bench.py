@@ -158,13 +158,14 @@ def roofline(prec, stages, traffic):
 
 def cpu_baseline():
     """The float64 oracle on a bounded sample of the workload: the same z
-    grid (512 rows, stretching 1.5) with a 256 x 128 plane, Poisson plus the
-    three Helmholtz solves, timed on the host."""
+    grid (512 rows, stretching 1.5) on a 512 x 256 plane (a quarter of the
+    workload's points), Poisson plus the three Helmholtz solves, timed on the
+    host (10-20 s on one core)."""
     import numpy as np
     import synth
     from oracle import grid as og
     from oracle import poisson as op
-    nx, ny = 256, 128
+    nx, ny = NX // 2, NY // 2
     f, zf = synth.channel_rhs(0, nx, ny, NZ, beta=BETA)
     r = [synth.normal01(1 + c, (NZ if c < 2 else NZ - 1, ny, nx)) for c in range(3)]
     t0 = time.perf_counter()
