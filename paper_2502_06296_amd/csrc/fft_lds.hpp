@@ -147,6 +147,27 @@ __host__ __device__ constexpr int pick_radix() {
                                       : 0;
 }
 
+// Twiddles w[r] = W^(e r), r = 1..R-1, of one butterfly from at most two
+// table reads: W^e and, for R >= 8, W^(4e); the others are products of
+// these, at most three multiplications deep (a few ulp), instead of R-1
+// table reads per butterfly.
+template <typename T, int R>
+__device__ __forceinline__ void pass_twiddles(cplx<T> (&w)[R], const cplx<T> *__restrict__ tw, int e) {
+  w[1] = tw[e];
+  if constexpr (R >= 3) w[2] = cmul<T>(w[1], w[1]);
+  if constexpr (R >= 4) w[3] = cmul<T>(w[2], w[1]);
+  if constexpr (R >= 8) {
+    w[4] = tw[4 * e];
+#pragma unroll
+    for (int r = 5; r < 8; ++r) w[r] = cmul<T>(w[4], w[r - 4]);
+  }
+  if constexpr (R >= 16) {
+    w[8] = cmul<T>(w[4], w[4]);
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul<T>(w[8], w[r - 8]);
+  }
+}
+
 // One Stockham pass of radix R on a line of N held in LDS (in place: all
 // reads, barrier, all writes, barrier). tw[t] = exp(-2 pi i t / N).
 template <typename T, int N, int R, int NS, int TPL, bool INV>
@@ -161,12 +182,10 @@ __device__ __forceinline__ void stockham_pass(cplx<T> *buf, const cplx<T> *__res
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = buf[lds_idx(j + r * NB)];
       if constexpr (NS > 1) {
-        const int jm = j % NS;
+        cplx<T> w[R];
+        pass_twiddles<T, R>(w, tw, (j % NS) * (N / (NS * R)));
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cplx<T> w = tw[jm * r * (N / (NS * R))];
-          v[it][r] = INV ? cmulc<T>(v[it][r], w) : cmul<T>(v[it][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[it][r] = INV ? cmulc<T>(v[it][r], w[r]) : cmul<T>(v[it][r], w[r]);
       }
       dft_r<T, R, INV>(v[it]);
     }

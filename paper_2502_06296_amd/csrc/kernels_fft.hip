@@ -92,9 +92,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 // (periodic in y), and per thread the f values and the p0 values of planes
 // k-1 and k+1 of its groups (two lines x G columns). The tile goes to LDS,
 // aliased onto the transform buffer; the x and y differences read it there,
-// and the residual is held in registers until the tile is dead. Each XCD
-// walks a contiguous run of planes, so the neighbour-plane lines read by
-// other workgroups are still in its L2.
+// and the residual is held in registers until the tile is dead.
 template <typename T, int G>
 struct alignas(sizeof(T) * G > 16 ? 16 : sizeof(T) * G) vec_t {
   T v[G];
@@ -123,8 +121,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
   static_assert((R + 2) * N * sizeof(float) <= sizeof(lds), "p0 tile fits the transform buffer");
   float *P = reinterpret_cast<float *>(lds);  // tile row u = line j0 - 1 + u
   const int tid = threadIdx.x;
-  const long line0 = (long)xcd_block(blockIdx.x, gridDim.x) * R;
-  const int k = (int)(line0 / ny), j0 = (int)(line0 % ny);
+  // planes fastest: the workgroups of planes k-1, k, k+1 of one y block run
+  // next to each other on one XCD, so the plane-(k+-1) lines that this one
+  // reads are the other two's own lines, still in L2
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int k = (int)(b % nz), j0 = (int)(b / nz) * R;
+  const long line0 = (long)k * ny + j0;
   const size_t plane = (size_t)ny * N;
   const float *pk = p0 + (size_t)k * plane;
   const double *fk = f + (size_t)k * plane;
