@@ -149,7 +149,7 @@ __host__ __device__ constexpr int pick_radix() {
 
 // Twiddles w[r] = W^(e r), r = 1..R-1, of one butterfly from at most two
 // table reads: W^e and, for R >= 8, W^(4e); the others are products of
-// these, at most three multiplications deep (a few ulp), instead of R-1
+// these, at most four multiplications deep (a few ulp), instead of R-1
 // table reads per butterfly.
 template <typename T, int R>
 __device__ __forceinline__ void pass_twiddles(cplx<T> (&w)[R], const cplx<T> *__restrict__ tw, int e) {

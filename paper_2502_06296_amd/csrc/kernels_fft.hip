@@ -248,7 +248,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
                                                    int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
-  __shared__ C lds[LPW * lds_len(N)];
+  __shared__ C lds[LPW * y_stride(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
@@ -259,16 +259,16 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
     const int l = e % LPW, y = e / LPW;
-    lds[l * lds_len(N) + lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l);
+    lds[l * y_stride(N) + lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l);
   }
   __syncthreads();
   const int l = tid / TPL, t = tid % TPL;
-  fft_line<double, N, TPL, false>(lds + l * lds_len(N), tw, t);
+  fft_line<double, N, TPL, false>(lds + l * y_stride(N), tw, t);
 #pragma unroll
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, q = e / LPW;
-    const C *buf = lds + l2 * lds_len(N);
+    const C *buf = lds + l2 * y_stride(N);
     C r0, r1;
     if (q == 0) {
       r0 = buf[lds_idx(0)];
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
-  __shared__ C lds[LPW * lds_len(N)];
+  __shared__ C lds[LPW * y_stride(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, q = e / LPW;
-    C *buf = lds + l2 * lds_len(N);
+    C *buf = lds + l2 * y_stride(N);
     const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
     const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
     if (q == 0) {
@@ -317,12 +317,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   }
   __syncthreads();
   const int l = tid / TPL, t = tid % TPL;
-  fft_line<double, N, TPL, true>(lds + l * lds_len(N), tw, t);
+  fft_line<double, N, TPL, true>(lds + l * y_stride(N), tw, t);
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
     const int l2 = e % LPW, y = e / LPW;
-    const C v = lds[l2 * lds_len(N) + lds_idx(y)];
+    const C v = lds[l2 * y_stride(N) + lds_idx(y)];
     st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
   }
 }

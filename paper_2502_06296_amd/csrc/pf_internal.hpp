@@ -42,6 +42,14 @@ constexpr int x_lpw(int n) {
   return v;
 }
 constexpr int y_tpl(int n) { return n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16); }
+// LDS stride (complex elements) between the lines of a y workgroup: 2 mod 16,
+// so that the load and store phases, whose lanes run over the lines first,
+// put the 16 lanes of one 128-bit LDS access in different banks.
+constexpr int y_stride(int n) {
+  int s = lds_len(n);
+  while (s % 16 != 2) ++s;
+  return s;
+}
 template <typename T>
 constexpr int y_lpw(int n) {
   const int want = sizeof(T) == 8 ? 8 : 16;
