@@ -38,7 +38,7 @@ KERNEL_SOURCES = ["paper_2502_06296_amd/csrc/kernels_fft.hip", "paper_2502_06296
 # algorithmic HBM bytes per grid point of one launch of each stage (one read
 # and one write of what the stage must touch; stencil neighbours not counted)
 BYTES_PER_POINT = {
-    "fp32_refine": {"xfwd": 8 + 4, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8,
+    "fp32_refine": {"xfwd": 8 + 4, "yfwd": 8, "zsolve": 8, "yinv": 8,
                     "xfwd_resid": 8 + 4 + 4, "xinv_final": 4 + 4 + 8, "zero_mode": 0,
                     "pcr_apply": 16},
     "fp64": {"xfwd": 16, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "zero_mode": 0,

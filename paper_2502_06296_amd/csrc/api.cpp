@@ -468,10 +468,10 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
     return fail(PF_ERR_DEVICE, "plan tables: %s", hipGetErrorString(e));
   }
   const size_t N = pl->npts();
-  // float32: the padded spectrum; float32 + refinement: the dense iterate,
-  // then the padded spectrum
+  // float32: the padded spectrum; float32 + refinement: the iterate's and
+  // the correction's padded spectra
   const size_t S = pl->sp32() * (size_t)pl->nz;
-  pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * S : 4 * (N + S));
+  pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * S : 8 * S);
   if (workspace_bytes) *workspace_bytes = pl->ws_need;
   *out = pl;
   return PF_OK;
@@ -547,23 +547,24 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
     STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, mm, nullptr, scale, lines, st)));
     return PF_OK;
   }
-  // float32 solve without the zero mode, then one correction for the
-  // float64 residual of the plane-mean-free problem; the zero mode is solved
-  // once, in float64, from the plane means of f
-  float *W1 = W0 + pl->npts();
-  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W1, sp, twx, sums, lines, st));
+  // float32 solve without the zero mode, kept as its x spectrum W0 after the
+  // y inverse; the float64 residual of the plane-mean-free problem formed in
+  // x-spectral space into W1; the correction; one x inverse of W0 + W1 with
+  // the zero mode, which is solved once, in float64, from the plane means of
+  // f and shifted by the iterate's plane means
+  float *W1 = W0 + sp * (size_t)nz;
+  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
   STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
-  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
-  STAGE(PF_STAGE_XINV, (pf::launch_xinv<float, float>(nx, ny, W1, sp, W0, twx, nullptr, nullptr, scale, lines, st)));
-  const double idx2 = (double)nx * nx / (pl->lx * pl->lx), idy2 = (double)ny * ny / (pl->ly * pl->ly);
-  STAGE(PF_STAGE_XFWD_RESID, pf::launch_xfwd_resid(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, zal, zga, idx2, idy2, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
+  const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
+  STAGE(PF_STAGE_XFWD_RESID, pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, idy2, st));
   STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
-  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W1, sp, p, twx, zm, W0, scale, lines, st)));
+  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, scale, lines, st)));
 #undef STAGE
   return PF_OK;
 }

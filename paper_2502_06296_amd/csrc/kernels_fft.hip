@@ -30,6 +30,17 @@ bool fft_size_supported(int n) {
   }
 }
 
+// pairs of storage values (two adjacent slots) as float64
+template <typename T>
+__device__ __forceinline__ cplx<double> ld2(const T *p) {
+  const cplx<T> v = *reinterpret_cast<const cplx<T> *>(p);
+  return mkc<double>((double)v.x, (double)v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *p, double x, double y) {
+  *reinterpret_cast<cplx<T> *>(p) = mkc<T>((T)x, (T)y);
+}
+
 // ----------------------------------------------------------- x forward
 template <typename T, int N, int TPL, int LPW, bool SUMS>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
@@ -78,169 +89,96 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   }
 }
 
-// -------------------------------------- x forward of the 7-point residual
-// r = (f - fbar[k]) - L7 p0 in float64 from the float32 iterate p0 (Neumann
-// z rows: alpha_0 = 0, gamma_{nz-1} = 0, no excess), then the float32
-// transform of r. The iterate carries no plane means (its (0,0) slot was
-// zeroed), so removing the plane means of f keeps the large constant-per-
-// plane part out of the float32 spectrum, where its rounding would spread
-// into the weakly damped (0,j) and (i,0) modes.
-//
-// A workgroup takes R = 2*LPW consecutive x lines j0..j0+R-1 of plane k, in
-// the transform shape of k_xfwd (TPL threads per complex line). Every global
-// load is issued up front as G-wide vectors: the p0 tile of rows j0-1..j0+R
-// (periodic in y), and per thread the f values and the p0 values of planes
-// k-1 and k+1 of its groups (two lines x G columns). The tile goes to LDS,
-// aliased onto the transform buffer; the x and y differences read it there,
-// and the residual is held in registers until the tile is dead.
-template <typename T, int G>
-struct alignas(sizeof(T) * G > 16 ? 16 : sizeof(T) * G) vec_t {
-  T v[G];
-};
-
+// ------------------------------ residual of the correction in x-spectral space
+// The first float32 solution is kept as its x spectrum W (after the y
+// inverse; W = ny X(p0), X the unnormalised x transform), so the correction's
+// right-hand side is formed without going back to real space:
+//   R = X(f) - nx fbar[k] e_0 - (1/ny) L7^ W,
+//   L7^ W = -sx[s] W + (W[j-1] - 2 W + W[j+1]) / dy^2
+//           + alpha_k W[k-1] + gamma_k W[k+1] - (alpha_k + gamma_k) W,
+// slot by slot of the packed layout: the periodic x second difference is
+// -sx[s] (its eigenvalue, the modified wavenumber of the slot) on each
+// packed slot, and the y and z parts act on every slot alike. X(f) is the
+// float64 transform of the float64 right-hand side; the iterate is exactly
+// the stored float32 W, so R is the residual of that iterate (Neumann z rows:
+// alpha_0 = 0, gamma_{nz-1} = 0, no excess). The float64 line sums of the
+// iterate, W[slot 0] / ny, feed its plane means. The x inverse of the
+// iterate disappears: the final pass transforms W + (correction) at once.
+// Shape of k_xfwd; a workgroup takes LPW line pairs of one plane (2*LPW
+// divides ny), planes fastest so that the neighbour planes' W is in L2.
 template <int N, int TPL, int LPW>
-__global__ __launch_bounds__(TPL *LPW) void k_xfwd_resid(
-    const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ p0,
+__global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
+    const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
-    const double *__restrict__ zal, const double *__restrict__ zga, int ny, int nz, double idx2,
-    double idy2, size_t sp) {
+    const double *__restrict__ sx, const double *__restrict__ zal, const double *__restrict__ zga,
+    int ny, int nz, double idy2, double inv_ny, size_t sp) {
   using C = cplx<double>;
-  constexpr int NT = TPL * LPW;
-  constexpr int R = 2 * LPW;
-  constexpr int G = (N / TPL) % 4 == 0 ? 4 : ((N / TPL) % 2 == 0 ? 2 : 1);
-  constexpr int NG = N / G;            // column groups per line
-  static_assert((LPW * NG) % NT == 0, "whole groups per thread");
-  constexpr int GS = LPW * NG / NT;    // groups (2 lines x G columns) per thread
-  constexpr int TV = (R + 2) * NG;     // vectors in the p0 tile
-  constexpr int TS = (TV + NT - 1) / NT;
-  constexpr int TSUM = NT / R >= 64 ? 64 : (NT / R >= 32 ? 32 : (NT / R >= 16 ? 16 : 8));
-  static_assert(NT / R >= 8 && N % TSUM == 0, "line-sum lanes");
-  using VF = vec_t<float, G>;
-  using VD = vec_t<double, G>;
+  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
-  static_assert((R + 2) * N * sizeof(float) <= sizeof(lds), "p0 tile fits the transform buffer");
-  float *P = reinterpret_cast<float *>(lds);  // tile row u = line j0 - 1 + u
-  const int tid = threadIdx.x;
-  // planes fastest: the workgroups of planes k-1, k, k+1 of one y block run
-  // next to each other on one XCD, so the plane-(k+-1) lines that this one
-  // reads are the other two's own lines, still in L2
+  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const int k = (int)(b % nz), j0 = (int)(b / nz) * R;
-  const long line0 = (long)k * ny + j0;
-  const size_t plane = (size_t)ny * N;
-  const float *pk = p0 + (size_t)k * plane;
-  const double *fk = f + (size_t)k * plane;
-  const bool lo = k > 0, hi = k < nz - 1;
-
-  VF tv[TS];
-#pragma unroll
-  for (int s = 0; s < TS; ++s) {
-    const int e = tid + s * NT;
-    if (TV % NT == 0 || e < TV) {
-      const int u = e / NG, c = e % NG;
-      int j = j0 - 1 + u;
-      j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
-      tv[s] = *reinterpret_cast<const VF *>(pk + (size_t)j * N + c * G);
-    }
-  }
-  VD fv[GS][2];
-  VF zm[GS][2], zp[GS][2];
-#pragma unroll
-  for (int s = 0; s < GS; ++s) {
-    const int g = tid + s * NT, m = g / NG, c = g % NG;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const size_t o = (size_t)(j0 + 2 * m + h) * N + c * G;
-      fv[s][h] = *reinterpret_cast<const VD *>(fk + o);
-      if (lo) zm[s][h] = *reinterpret_cast<const VF *>(pk - plane + o);
-      if (hi) zp[s][h] = *reinterpret_cast<const VF *>(pk + plane + o);
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < TS; ++s) {
-    const int e = tid + s * NT;
-    if (TV % NT == 0 || e < TV) *reinterpret_cast<VF *>(P + (e / NG) * N + (e % NG) * G) = tv[s];
-  }
-  __syncthreads();
-
-  // float64 sums of the R lines of p0 (tile rows 1..R)
-  if (tid < R * TSUM) {
-    const int l = tid / TSUM, u = tid % TSUM;
-    const float *row = P + (l + 1) * N;
-    double sum = 0.0;
-#pragma unroll 8
-    for (int i = u; i < N; i += TSUM) sum += (double)row[i];
-#pragma unroll
-    for (int w = TSUM / 2; w > 0; w /= 2) sum += __shfl_xor(sum, w, TSUM);
-    if (u == 0) sums_p[line0 + l] = sum;
-  }
-
-  const double ak = zal[k], gk = zga[k], dk = ak + gk, fb = fbar[k];
-  double r[GS][2][G];
-#pragma unroll
-  for (int s = 0; s < GS; ++s) {
-    const int g = tid + s * NT, m = g / NG, i0 = (g % NG) * G;
-    const int il = i0 == 0 ? N - 1 : i0 - 1, ir = i0 + G == N ? 0 : i0 + G;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float *row = P + (2 * m + h + 1) * N;
-      const VF cv = *reinterpret_cast<const VF *>(row + i0);
-      const VF up = *reinterpret_cast<const VF *>(row + N + i0);
-      const VF dn = *reinterpret_cast<const VF *>(row - N + i0);
-      const double xl = (double)row[il], xr = (double)row[ir];
-#pragma unroll
-      for (int v = 0; v < G; ++v) {
-        const double c0 = (double)cv.v[v];
-        double z = 0.0;
-        if (lo) z += ak * (double)zm[s][h].v[v];
-        if (hi) z += gk * (double)zp[s][h].v[v];
-        const double acc = (fv[s][h].v[v] - fb) - (z - dk * c0);
-        const double xm = v == 0 ? xl : (double)cv.v[v - 1];
-        const double xp = v == G - 1 ? xr : (double)cv.v[v + 1];
-        const double lx = (xp - 2.0 * c0 + xm) * idx2;
-        const double ly = ((double)up.v[v] - 2.0 * c0 + (double)dn.v[v]) * idy2;
-        r[s][h][v] = acc - (lx + ly);
-      }
-    }
-  }
-  __syncthreads();  // the tile is dead: the transform buffer takes the residual
-#pragma unroll
-  for (int s = 0; s < GS; ++s) {
-    const int g = tid + s * NT, m = g / NG, i0 = (g % NG) * G;
-#pragma unroll
-    for (int v = 0; v < G; ++v) lds[m * lds_len(N) + lds_idx(i0 + v)] = mkc<double>(r[s][0][v], r[s][1][v]);
-  }
-  __syncthreads();
-  const int l = tid / TPL, t = tid % TPL;
+  const int k = (int)(b % nz), j = (int)(b / nz) * 2 * LPW + 2 * l;  // lines j, j+1
   C *buf = lds + l * lds_len(N);
+  {
+    const double *fa = f + ((size_t)k * ny + j) * N;
+    const double *fb = fa + N;
+#pragma unroll
+    for (int s = 0; s < N / TPL; ++s) {
+      const int pos = t + s * TPL;
+      buf[lds_idx(pos)] = mkc<double>(fa[pos], fb[pos]);
+    }
+  }
+  __syncthreads();
   fft_line<double, N, TPL, false>(buf, tw, t);
-  float *oa = out + (size_t)k * sp + (size_t)(j0 + 2 * l) * N;
+  const double ak = zal[k], gk = zga[k], dk = ak + gk, fk = (double)N * fbar[k];
+  const bool lo = k > 0, hi = k < nz - 1;
+  const int jm = j == 0 ? ny - 1 : j - 1, jp2 = j + 2 == ny ? 0 : j + 2;
+  const float *Wk = W + (size_t)k * sp;
+  const float *w0 = Wk + (size_t)j * N, *w1 = w0 + N;          // lines j, j+1
+  const float *wm = Wk + (size_t)jm * N, *wp = Wk + (size_t)jp2 * N;
+  float *oa = out + (size_t)k * sp + (size_t)j * N;
   float *ob = oa + N;
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
     if (q == 0) {
       const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
-      A = mkc<double>(z0.x, zh.x);
-      B = mkc<double>(z0.y, zh.y);
+      A = mkc<double>(z0.x - fk, zh.x);
+      B = mkc<double>(z0.y - fk, zh.y);
     } else {
       split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
     }
-    *reinterpret_cast<cplx<float> *>(oa + 2 * q) = mkc<float>((float)A.x, (float)A.y);
-    *reinterpret_cast<cplx<float> *>(ob + 2 * q) = mkc<float>((float)B.x, (float)B.y);
+    const C c0 = ld2<float>(w0 + 2 * q), c1 = ld2<float>(w1 + 2 * q);
+    const C cm = ld2<float>(wm + 2 * q), cp = ld2<float>(wp + 2 * q);
+    C za = mkc<double>(0.0, 0.0), zb = za;
+    if (lo) {
+      const C a0 = ld2<float>(w0 - sp + 2 * q), a1 = ld2<float>(w1 - sp + 2 * q);
+      za = mkc<double>(ak * a0.x, ak * a0.y);
+      zb = mkc<double>(ak * a1.x, ak * a1.y);
+    }
+    if (hi) {
+      const C g0 = ld2<float>(w0 + sp + 2 * q), g1 = ld2<float>(w1 + sp + 2 * q);
+      za = mkc<double>(za.x + gk * g0.x, za.y + gk * g0.y);
+      zb = mkc<double>(zb.x + gk * g1.x, zb.y + gk * g1.y);
+    }
+    // slots 2q, 2q+1 (for q = 0: slot 0 the mean, slot 1 the Nyquist mode)
+    const double s0 = sx[2 * q], s1 = sx[2 * q + 1];
+    const double la0 = (cm.x - 2.0 * c0.x + c1.x) * idy2 + za.x - (dk + s0) * c0.x;
+    const double la1 = (cm.y - 2.0 * c0.y + c1.y) * idy2 + za.y - (dk + s1) * c0.y;
+    const double lb0 = (c0.x - 2.0 * c1.x + cp.x) * idy2 + zb.x - (dk + s0) * c1.x;
+    const double lb1 = (c0.y - 2.0 * c1.y + cp.y) * idy2 + zb.y - (dk + s1) * c1.y;
+    *reinterpret_cast<cplx<float> *>(oa + 2 * q) =
+        mkc<float>((float)(A.x - inv_ny * la0), (float)(A.y - inv_ny * la1));
+    *reinterpret_cast<cplx<float> *>(ob + 2 * q) =
+        mkc<float>((float)(B.x - inv_ny * lb0), (float)(B.y - inv_ny * lb1));
+    if (q == 0) {
+      sums_p[(size_t)k * ny + j] = c0.x * inv_ny;
+      sums_p[(size_t)k * ny + j + 1] = c1.x * inv_ny;
+    }
   }
 }
 
 // ------------------------------------------------------------- y forward
-template <typename T>
-__device__ __forceinline__ cplx<double> ld2(const T *p) {
-  const cplx<T> v = *reinterpret_cast<const cplx<T> *>(p);
-  return mkc<double>((double)v.x, (double)v.y);
-}
-template <typename T>
-__device__ __forceinline__ void st2(T *p, double x, double y) {
-  *reinterpret_cast<cplx<T> *>(p) = mkc<T>((T)x, (T)y);
-}
 
 template <typename T, int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
@@ -330,11 +268,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
 // ------------------------------------------------------------- x inverse
 // in and out may be the same array (each workgroup reads its line pair into
 // LDS before writing it), so they are not marked restrict.
-template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool ADDP0>
+// SUM2: the transform of in + in2 (two spectra of the same layout, summed
+// in float64 before the inverse).
+template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool SUM2>
 __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
                                                    const cplx<double> *__restrict__ tw,
                                                    const double *__restrict__ zm,
-                                                   const float *__restrict__ p0, double scale,
+                                                   const TS *__restrict__ in2, double scale,
                                                    int ny, long ncl, size_t sp) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
@@ -344,12 +284,20 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
   if (ok) {
-    const TS *a = in + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
+    const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
+    const TS *a = in + o;
     const TS *b = a + N;
+    const TS *a2 = SUM2 ? in2 + o : nullptr;
+    const TS *b2 = SUM2 ? a2 + N : nullptr;
 #pragma unroll
     for (int q = t; q < N / 2; q += TPL) {
-      const C A = ld2<TS>(a + 2 * q);
-      const C B = ld2<TS>(b + 2 * q);
+      C A = ld2<TS>(a + 2 * q);
+      C B = ld2<TS>(b + 2 * q);
+      if (SUM2) {
+        const C A2 = ld2<TS>(a2 + 2 * q), B2 = ld2<TS>(b2 + 2 * q);
+        A = mkc<double>(A.x + A2.x, A.y + A2.y);
+        B = mkc<double>(B.x + B2.x, B.y + B2.y);
+      }
       if (q == 0) {
         buf[lds_idx(0)] = mkc<double>(A.x, B.x);
         buf[lds_idx(N / 2)] = mkc<double>(A.y, B.y);
@@ -368,17 +316,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   if (ADDZ) add = zm[(2 * c) / ny];
   TO *oa = out + (size_t)(2 * c) * N;
   TO *ob = oa + N;
-  const float *pa = ADDP0 ? p0 + (size_t)(2 * c) * N : nullptr;
-  const float *pb = ADDP0 ? pa + N : nullptr;
 #pragma unroll
   for (int s = 0; s < N / TPL; ++s) {
     const int pos = t + s * TPL;
     const C z = buf[lds_idx(pos)];
-    double va = z.x * scale + add;
-    double vb = z.y * scale + add;
-    if (ADDP0) { va += (double)pa[pos]; vb += (double)pb[pos]; }
-    oa[pos] = (TO)va;
-    ob[pos] = (TO)vb;
+    oa[pos] = (TO)(z.x * scale + add);
+    ob[pos] = (TO)(z.y * scale + add);
   }
 }
 
@@ -407,18 +350,18 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
   }
 }
 
-hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, size_t sp, const cplx<double> *tw,
-                             double *sums_p0, const double *zal, const double *zga, double idx2,
-                             double idy2, hipStream_t st) {
+hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
+                             const float *W, float *out, size_t sp, const cplx<double> *tw,
+                             double *sums_p, const double *sx, const double *zal,
+                             const double *zga, double idy2, hipStream_t st) {
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
     constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                                \
     if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
-    hipLaunchKernelGGL((k_xfwd_resid<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0, st, \
-                       f, fbar, p0, out, tw, sums_p0, zal, zga, ny, nz, idx2, idy2, sp);         \
+    hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \
+                       st, f, fbar, W, out, tw, sums_p, sx, zal, zga, ny, nz, idy2, 1.0 / ny, sp); \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -470,7 +413,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
-                       const double *zm, const float *p0, double scale, long lines,
+                       const double *zm, const TS *in2, double scale, long lines,
                        hipStream_t st) {
   const long ncl = lines / 2;
   switch (nx) {
@@ -478,15 +421,15 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const c
   case N: {                                                                                     \
     constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
-    if (zm && p0)                                                                               \
+    if (zm && in2)                                                                              \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
-                         zm, p0, scale, ny, ncl, sp);                                               \
+                         zm, in2, scale, ny, ncl, sp);                                               \
     else if (zm)                                                                                \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, false>), g, b, 0, st, in, out, tw, \
-                         zm, p0, scale, ny, ncl, sp);                                               \
+                         zm, in2, scale, ny, ncl, sp);                                               \
     else                                                                                        \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, false, false>), g, b, 0, st, in, out,    \
-                         tw, zm, p0, scale, ny, ncl, sp);                                           \
+                         tw, zm, in2, scale, ny, ncl, sp);                                           \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -510,7 +453,7 @@ template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cpl
                                        hipStream_t);
 template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
-                                                const float *, double, long, hipStream_t);
+                                                const double *, double, long, hipStream_t);
 template hipError_t launch_xinv<float, float>(int, int, const float *, size_t, float *,
                                               const cplx<double> *, const double *, const float *,
                                               double, long, hipStream_t);

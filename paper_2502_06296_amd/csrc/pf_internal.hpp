@@ -72,13 +72,14 @@ constexpr int y_lpw(int n) {
 template <typename T>
 hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
                        const cplx<double> *tw, double *sums, long lines, hipStream_t st);
-// x forward of the float64 7-point residual r = (f - fbar[k]) - L7 p0 (p0
-// float32, fbar the float64 plane means of f), with the float64 sums of p0
-// per line; the spectrum is float32.
-hipError_t launch_xfwd_resid(int nx, int ny, int nz, const double *f, const double *fbar,
-                             const float *p0, float *out, size_t sp, const cplx<double> *tw,
-                             double *sums_p0, const double *zal, const double *zga, double idx2,
-                             double idy2, hipStream_t st);
+// x spectrum of the float64 7-point residual of the plane-mean-free
+// problem, R = X(f - fbar[k]) - L7 of the iterate whose x spectrum (times ny)
+// is W (float32, after the y inverse); the x operator is -sx per packed
+// slot. Also the float64 line sums of the iterate. R is float32.
+hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
+                             const float *W, float *out, size_t sp, const cplx<double> *tw,
+                             double *sums_p, const double *sx, const double *zal,
+                             const double *zga, double idy2, hipStream_t st);
 // y forward / inverse, in place on the packed (T) data.
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
@@ -87,10 +88,11 @@ template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
                        hipStream_t st);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
-// per-plane float64 profile zm[k] and float32 base field p0 added.
+// per-plane float64 profile zm[k]; with in2 (requires zm) the inverse of
+// in + in2, summed in float64.
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
-                       const double *zm, const float *p0, double scale, long lines,
+                       const double *zm, const TS *in2, double scale, long lines,
                        hipStream_t st);
 
 // Poisson z solve on the doubly packed spectrum (in place), float64
