@@ -166,9 +166,10 @@ pf_status pf_graph_destroy(pf_graph *graph);
  * plan's stream. pf_*_timing_read synchronises the stream and returns, per
  * stage, the summed milliseconds and the launch count since the last read
  * (arrays of PF_STAGE_COUNT). PF_STAGE_XINV is the x inverse of the FP64
- * and FP32 solves; PF_STAGE_XFWD_RESID is the correction's right-hand side
- * of PF_FP32_REFINE (the float64 residual formed in x-spectral space) and
- * PF_STAGE_XINV_FINAL its x inverse of iterate plus correction. */
+ * solve, PF_STAGE_XINV_FINAL the last x inverse of the float32 solves (for
+ * PF_FP32_REFINE: of iterate plus correction); PF_STAGE_XFWD_RESID is the
+ * correction's right-hand side of PF_FP32_REFINE (the float64 residual
+ * formed in x-spectral space). */
 enum {
   PF_STAGE_XFWD = 0, PF_STAGE_YFWD = 1, PF_STAGE_ZSOLVE = 2, PF_STAGE_YINV = 3,
   PF_STAGE_XINV = 4, PF_STAGE_ZERO_MODE = 5, PF_STAGE_XFWD_RESID = 6, PF_STAGE_XINV_FINAL = 7,

@@ -168,10 +168,19 @@ __device__ __forceinline__ void pass_twiddles(cplx<T> (&w)[R], const cplx<T> *__
   }
 }
 
-// One Stockham pass of radix R on a line of N held in LDS (in place: all
-// reads, barrier, all writes, barrier). tw[t] = exp(-2 pi i t / N).
-template <typename T, int N, int R, int NS, int TPL, bool INV>
-__device__ __forceinline__ void stockham_pass(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t) {
+// One Stockham pass of radix R on a line of N: every thread reads the R
+// inputs j + r N/R of its butterflies through src, applies the twiddles and
+// the R-point DFT in registers, and writes the outputs through dst (Stockham
+// autosort order). LDS_IN / LDS_OUT tell whether src / dst are the LDS line:
+// a pass that reads and writes it in place separates its reads from its
+// writes by a barrier, and every pass that writes it ends with one. A first
+// pass may read straight from global memory and a last pass may write
+// straight to it, which saves a sweep over the LDS line and two barriers.
+// tw[t] = exp(-2 pi i t / N).
+template <typename T, int N, int R, int NS, int TPL, bool INV, bool LDS_IN, bool LDS_OUT, class Src,
+          class Dst>
+__device__ __forceinline__ void stockham_pass_io(const cplx<T> *__restrict__ tw, int t, Src src,
+                                                 Dst dst) {
   constexpr int NB = N / R;
   constexpr int IT = (NB + TPL - 1) / TPL;
   cplx<T> v[IT][R];
@@ -180,7 +189,7 @@ __device__ __forceinline__ void stockham_pass(cplx<T> *buf, const cplx<T> *__res
     const int j = t + it * TPL;
     if (NB % TPL == 0 || j < NB) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[lds_idx(j + r * NB)];
+      for (int r = 0; r < R; ++r) v[it][r] = src(j + r * NB);
       if constexpr (NS > 1) {
         cplx<T> w[R];
         pass_twiddles<T, R>(w, tw, (j % NS) * (N / (NS * R)));
@@ -190,34 +199,54 @@ __device__ __forceinline__ void stockham_pass(cplx<T> *buf, const cplx<T> *__res
       dft_r<T, R, INV>(v[it]);
     }
   }
-  __syncthreads();
+  if constexpr (LDS_IN && LDS_OUT) __syncthreads();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int j = t + it * TPL;
     if (NB % TPL == 0 || j < NB) {
       const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_idx(base + r * NS)] = v[it][r];
+      for (int r = 0; r < R; ++r) dst(base + r * NS, v[it][r]);
     }
   }
-  __syncthreads();
+  if constexpr (LDS_OUT) __syncthreads();
 }
 
-template <typename T, int N, int NS, int TPL, bool INV>
-__device__ __forceinline__ void fft_passes(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t) {
+// GIN: the first pass reads the line through src instead of LDS (nothing
+// may be reading the LDS line when the transform starts); GOUT: the last
+// pass writes the result through dst instead of LDS (the LDS line is left
+// partly stale). Otherwise the line must be in LDS, published by a barrier,
+// and the result is left there, published by a barrier.
+template <typename T, int N, int NS, int TPL, bool INV, bool GIN, bool GOUT, class Src, class Dst>
+__device__ __forceinline__ void fft_passes_io(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t,
+                                              Src src, Dst dst) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix<N / NS>();
     static_assert(R != 0, "transform length must be 2^a 3^b");
-    stockham_pass<T, N, R, NS, TPL, INV>(buf, tw, t);
-    fft_passes<T, N, NS * R, TPL, INV>(buf, tw, t);
+    constexpr bool gin = GIN && NS == 1, gout = GOUT && NS * R == N;
+    auto lrd = [buf](int i) { return buf[lds_idx(i)]; };
+    auto lwr = [buf](int i, const cplx<T> &x) { buf[lds_idx(i)] = x; };
+    if constexpr (gin && gout) stockham_pass_io<T, N, R, NS, TPL, INV, false, false>(tw, t, src, dst);
+    else if constexpr (gin) stockham_pass_io<T, N, R, NS, TPL, INV, false, true>(tw, t, src, lwr);
+    else if constexpr (gout) stockham_pass_io<T, N, R, NS, TPL, INV, true, false>(tw, t, lrd, dst);
+    else stockham_pass_io<T, N, R, NS, TPL, INV, true, true>(tw, t, lrd, lwr);
+    fft_passes_io<T, N, NS * R, TPL, INV, GIN, GOUT>(buf, tw, t, src, dst);
   }
 }
 
-// Full complex transform of one LDS line (unnormalised). Every thread of
-// the workgroup must call it (it contains barriers).
+template <typename T, int N, int TPL, bool INV, bool GIN, bool GOUT, class Src, class Dst>
+__device__ __forceinline__ void fft_line_io(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t,
+                                            Src src, Dst dst) {
+  fft_passes_io<T, N, 1, TPL, INV, GIN, GOUT>(buf, tw, t, src, dst);
+}
+
+// Full complex transform of one LDS line, in place (unnormalised). Every
+// thread of the workgroup must call it (it contains barriers).
 template <typename T, int N, int TPL, bool INV>
 __device__ __forceinline__ void fft_line(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t) {
-  fft_passes<T, N, 1, TPL, INV>(buf, tw, t);
+  auto none_rd = [](int) { return cplx<T>{}; };
+  auto none_wr = [](int, const cplx<T> &) {};
+  fft_line_io<T, N, TPL, INV, false, false>(buf, tw, t, none_rd, none_wr);
 }
 
 // Split the transform Z of z = a + i b (a, b real) into the spectra of a and

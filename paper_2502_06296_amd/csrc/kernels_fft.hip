@@ -54,17 +54,11 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
-  if (ok) {
-    const double *a = in + (size_t)(2 * c) * N;
-    const double *b = a + N;
-#pragma unroll
-    for (int s = 0; s < N / TPL; ++s) {
-      const int pos = t + s * TPL;
-      buf[lds_idx(pos)] = mkc<double>(a[pos], b[pos]);
-    }
-  }
-  __syncthreads();
-  fft_line<double, N, TPL, false>(buf, tw, t);
+  // the first pass reads the line pair straight from global memory
+  const double *a = in + (ok ? (size_t)(2 * c) * N : 0);
+  const double *b = a + N;
+  auto src = [&](int i) { return ok ? mkc<double>(a[i], b[i]) : mkc<double>(0.0, 0.0); };
+  fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
   if (!ok) return;
   T *oa = out + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
   T *ob = oa + N;
@@ -120,16 +114,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
   const int k = (int)(b % nz), j = (int)(b / nz) * 2 * LPW + 2 * l;  // lines j, j+1
   C *buf = lds + l * lds_len(N);
   {
+    // the first pass reads the line pair of f straight from global memory
     const double *fa = f + ((size_t)k * ny + j) * N;
     const double *fb = fa + N;
-#pragma unroll
-    for (int s = 0; s < N / TPL; ++s) {
-      const int pos = t + s * TPL;
-      buf[lds_idx(pos)] = mkc<double>(fa[pos], fb[pos]);
-    }
+    auto src = [&](int i) { return mkc<double>(fa[i], fb[i]); };
+    fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
   }
-  __syncthreads();
-  fft_line<double, N, TPL, false>(buf, tw, t);
   const double ak = zal[k], gk = zga[k], dk = ak + gk, fk = (double)N * fbar[k];
   const bool lo = k > 0, hi = k < nz - 1;
   const int jm = j == 0 ? ny - 1 : j - 1, jp2 = j + 2 == ny ? 0 : j + 2;
@@ -193,15 +183,14 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   const int ib = blk % nib;
   const long k = blk / nib;
   T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
-#pragma unroll
-  for (int s = 0; s < N / TPL; ++s) {
-    const int e = tid + s * NT;
-    const int l = e % LPW, y = e / LPW;
-    lds[l * y_stride(N) + lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l);
+  {
+    // lines run fastest across the lanes, so the first pass's reads of row
+    // y cover the 2*LPW contiguous slots of the workgroup
+    const int l = tid % LPW, t = tid / LPW;
+    auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
+    fft_line_io<double, N, TPL, false, true, false>(lds + l * y_stride(N), tw, t, src,
+                                                    [](int, const C &) {});
   }
-  __syncthreads();
-  const int l = tid / TPL, t = tid % TPL;
-  fft_line<double, N, TPL, false>(lds + l * y_stride(N), tw, t);
 #pragma unroll
   for (int s = 0; s < N / (2 * TPL); ++s) {
     const int e = tid + s * NT;
@@ -254,15 +243,11 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
     }
   }
   __syncthreads();
-  const int l = tid / TPL, t = tid % TPL;
-  fft_line<double, N, TPL, true>(lds + l * y_stride(N), tw, t);
-#pragma unroll
-  for (int s = 0; s < N / TPL; ++s) {
-    const int e = tid + s * NT;
-    const int l2 = e % LPW, y = e / LPW;
-    const C v = lds[l2 * y_stride(N) + lds_idx(y)];
-    st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
-  }
+  // the last pass writes row y of all lines straight to global memory
+  const int l = tid % LPW, t = tid / LPW;
+  auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
+  fft_line_io<double, N, TPL, true, false, true>(lds + l * y_stride(N), tw, t,
+                                                 [](int) { return C{}; }, dst);
 }
 
 // ------------------------------------------------------------- x inverse
@@ -310,19 +295,17 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
     }
   }
   __syncthreads();
-  fft_line<double, N, TPL, true>(buf, tw, t);
-  if (!ok) return;
-  double add = 0.0;
-  if (ADDZ) add = zm[(2 * c) / ny];
-  TO *oa = out + (size_t)(2 * c) * N;
+  // the last pass writes both real lines straight to global memory
+  const double add = ADDZ && ok ? zm[(2 * c) / ny] : 0.0;
+  TO *oa = out + (ok ? (size_t)(2 * c) * N : 0);
   TO *ob = oa + N;
-#pragma unroll
-  for (int s = 0; s < N / TPL; ++s) {
-    const int pos = t + s * TPL;
-    const C z = buf[lds_idx(pos)];
-    oa[pos] = (TO)(z.x * scale + add);
-    ob[pos] = (TO)(z.y * scale + add);
-  }
+  auto dst = [&](int pos, const C &z) {
+    if (ok) {
+      oa[pos] = (TO)(z.x * scale + add);
+      ob[pos] = (TO)(z.y * scale + add);
+    }
+  };
+  fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dst);
 }
 
 // ------------------------------------------------------------- launchers
