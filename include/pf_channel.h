@@ -160,6 +160,37 @@ pf_status pf_graph_end(void *stream, pf_graph **out);
 pf_status pf_graph_launch(pf_graph *graph, void *stream);
 pf_status pf_graph_destroy(pf_graph *graph);
 
+/* ------------------------------------------------------------- task batch
+ * Independent work of several problems (the batch of uneven channel grids
+ * of the paper's use: a pressure solve and the velocity components of each
+ * problem), spread over `lanes` (1..8) internal streams forked from `stream`
+ * and joined back into it, so that small problems run side by side instead
+ * of leaving the GPU underfilled one after another.
+ *
+ * A task is an optional Poisson solve (poisson, rhs, p as for poisson_solve)
+ * and an optional group of ncomp (0..4) Helmholtz fields applied in one
+ * launch (pcr[], field[], nx[], ny[] as for pcr_apply_batched: the plans of
+ * a group share chunk rows and precision). Tasks are assigned largest first
+ * to the least-loaded lane. Every task is ordered after the work already on
+ * `stream`, and work enqueued on `stream` afterwards after every task; tasks
+ * must not share plans or buffers. Inside pf_graph_begin/pf_graph_end on
+ * `stream` the fork and join become graph edges. The lanes (default-priority
+ * streams) and their events are created once per device by the first call,
+ * which must not be inside a capture, and are kept until the process ends.
+ * Every task is validated before anything is enqueued. Calls from several
+ * host threads are serialised. Plans keep their own streams for their other
+ * calls. */
+typedef struct {
+  pf_poisson_plan *poisson; /* NULL: no Poisson solve */
+  const double *rhs;
+  double *p;
+  int32_t ncomp;            /* Helmholtz fields, 0..4 */
+  pf_pcr_plan *pcr[4];
+  void *field[4];
+  int32_t nx[4], ny[4];
+} pf_task;
+pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, void *stream);
+
 /* --------------------------------------------------------- measurement
  * Stage timing in the style of the paper's per-operation GPU timers: when
  * enabled, each kernel a plan launches is bracketed by HIP events on the

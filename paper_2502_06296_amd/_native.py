@@ -31,6 +31,7 @@ EXPORTS = [
     "pf_copy_kernel",
     "poisson_variant_count", "poisson_set_variant", "poisson_get_variant",
     "pcr_set_shape", "pcr_get_shape",
+    "pf_run_batched",
 ]
 
 
@@ -38,6 +39,12 @@ class PfGrid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("beta", C.c_double), ("zf", C.POINTER(C.c_double))]
+
+
+class PfTask(C.Structure):
+    _fields_ = [("poisson", C.c_void_p), ("rhs", C.c_void_p), ("p", C.c_void_p),
+                ("ncomp", C.c_int32), ("pcr", C.c_void_p * 4), ("field", C.c_void_p * 4),
+                ("nx", C.c_int32 * 4), ("ny", C.c_int32 * 4)]
 
 
 class PfError(RuntimeError):
@@ -92,6 +99,7 @@ def lib():
             "poisson_get_variant": (i32, [vp, i32, C.POINTER(i32)]),
             "pcr_set_shape": (i32, [vp, i32, i32]),
             "pcr_get_shape": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+            "pf_run_batched": (i32, [i32, C.POINTER(PfTask), i32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -508,11 +509,10 @@ static pf_status poisson_check_solve(pf_poisson_plan *pl, const double *rhs, dou
   return PF_OK;
 }
 
-static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p) {
+static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st) {
   const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
   const long lines = (long)ny * nz;
   const double scale = 1.0 / ((double)nx * ny);
-  hipStream_t st = pl->st;
   const DevArena &A = pl->ar;
   const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
   const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
@@ -572,7 +572,7 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
 pf_status poisson_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
   pf_status s = poisson_check_solve(pl, rhs, p);
   if (s) return s;
-  return poisson_enqueue(pl, rhs, p);
+  return poisson_enqueue(pl, rhs, p, pl->st);
 }
 
 pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans, const double *const *rhs,
@@ -583,10 +583,7 @@ pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans, co
     if (s) return s;
   }
   for (int t = 0; t < count; ++t) {
-    hipStream_t keep = plans[t]->st;
-    plans[t]->st = plans[0]->st;
-    pf_status s = poisson_enqueue(plans[t], rhs[t], p[t]);
-    plans[t]->st = keep;
+    pf_status s = poisson_enqueue(plans[t], rhs[t], p[t], plans[0]->st);
     if (s) return s;
   }
   return PF_OK;
@@ -726,11 +723,19 @@ pf_status pcr_set_stream(pf_pcr_plan *pl, void *stream) {
   return PF_OK;
 }
 
-pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *const *fields, const int32_t *nx,
-                            const int32_t *ny) {
+// Validates a group of Helmholtz fields for one fused launch and fills its
+// job table and launch shape.
+struct HelmGroup {
+  pf::HelmJob jobs[pf::kMaxHelmJobs];
+  int count = 0, M = 0, cw = 1 << 30, prec = 0;
+  bool staged = true;
+};
+
+static pf_status pcr_group(int32_t count, pf_pcr_plan *const *plans, void *const *fields, const int32_t *nx,
+                           const int32_t *ny, HelmGroup &G) {
   if (count < 1 || count > pf::kMaxHelmJobs) return fail(PF_ERR_ARG, "count must be 1..%d", pf::kMaxHelmJobs);
   if (!plans || !fields || !nx || !ny) return fail(PF_ERR_ARG, "NULL argument array");
-  pf::HelmJob jobs[pf::kMaxHelmJobs];
+  pf::HelmJob *jobs = G.jobs;
   int M = 0, cw = 1 << 30;
   bool staged = true;
   for (int t = 0; t < count; ++t) {
@@ -756,10 +761,25 @@ pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *cons
       const size_t b = (size_t)plans[u]->n * nx[u] * ny[u] * (plans[u]->prec == PF_FP32 ? 4 : 8);
       if (overlaps(fields[t], a, fields[u], b)) return fail(PF_ERR_ARG, "fields %d and %d overlap", t, u);
     }
-  const int prec = plans[0]->prec == PF_FP64 ? 0 : (plans[0]->prec == PF_FP32 ? 1 : 2);
-  pf_pcr_plan *p0 = plans[0];
-  return run_stage(p0->tm, p0->st, PF_STAGE_PCR_APPLY,
-                   [&]() { return pf::launch_helm(prec, M, cw, staged, count, jobs, p0->st); });
+  G.count = count;
+  G.M = M;
+  G.cw = cw;
+  G.staged = staged;
+  G.prec = plans[0]->prec == PF_FP64 ? 0 : (plans[0]->prec == PF_FP32 ? 1 : 2);
+  return PF_OK;
+}
+
+static pf_status pcr_enqueue(pf_pcr_plan *p0, const HelmGroup &G, hipStream_t st) {
+  return run_stage(p0->tm, st, PF_STAGE_PCR_APPLY,
+                   [&]() { return pf::launch_helm(G.prec, G.M, G.cw, G.staged, G.count, G.jobs, st); });
+}
+
+pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *const *fields, const int32_t *nx,
+                            const int32_t *ny) {
+  HelmGroup G;
+  pf_status s = pcr_group(count, plans, fields, nx, ny, G);
+  if (s) return s;
+  return pcr_enqueue(plans[0], G, plans[0]->st);
 }
 
 pf_status pcr_apply(pf_pcr_plan *pl, void *field, int32_t nx, int32_t ny) {
@@ -789,6 +809,90 @@ pf_status pcr_timing_read(pf_pcr_plan *pl, double *ms, int32_t *count) {
 }
 
 // ---------------------------------------------------------------- graphs
+// ------------------------------------------------------------- task batch
+// A pool of internal streams (default priority) and fork/join events per
+// device, created on first use and kept until the process ends.
+namespace {
+constexpr int kMaxLanes = 8;
+struct Lanes {
+  bool ready = false;
+  hipStream_t s[kMaxLanes] = {};
+  hipEvent_t fork = nullptr, join[kMaxLanes] = {};
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_lanes_mu;
+Lanes g_lanes[kMaxDevices];
+}  // namespace
+
+static pf_status lanes_ready(int dev, Lanes *&L) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(PF_ERR_UNSUPPORTED, "device %d beyond the lane pool", dev);
+  L = &g_lanes[dev];
+  if (L->ready) return PF_OK;
+  for (int l = 0; l < kMaxLanes; ++l) {
+    PF_HIP(hipStreamCreateWithFlags(&L->s[l], hipStreamNonBlocking));
+    PF_HIP(hipEventCreateWithFlags(&L->join[l], hipEventDisableTiming));
+  }
+  PF_HIP(hipEventCreateWithFlags(&L->fork, hipEventDisableTiming));
+  L->ready = true;
+  return PF_OK;
+}
+
+pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, void *stream) {
+  if (count < 0 || (count > 0 && !tasks)) return fail(PF_ERR_ARG, "bad batch arguments");
+  if (lanes < 1 || lanes > kMaxLanes) return fail(PF_ERR_ARG, "lanes must be 1..%d", kMaxLanes);
+  std::vector<HelmGroup> groups((size_t)count);
+  std::vector<double> cost((size_t)count, 0.0);
+  for (int t = 0; t < count; ++t) {
+    const pf_task &T = tasks[t];
+    if (T.poisson) {
+      pf_status s = poisson_check_solve(T.poisson, T.rhs, T.p);
+      if (s) return s;
+      cost[t] += (double)T.poisson->npts();
+    }
+    if (T.ncomp < 0 || T.ncomp > pf::kMaxHelmJobs) return fail(PF_ERR_ARG, "task %d: ncomp must be 0..%d", t, pf::kMaxHelmJobs);
+    if (!T.poisson && T.ncomp == 0) return fail(PF_ERR_ARG, "task %d is empty", t);
+    if (T.ncomp) {
+      pf_status s = pcr_group(T.ncomp, T.pcr, T.field, T.nx, T.ny, groups[t]);
+      if (s) return s;
+      for (int c = 0; c < T.ncomp; ++c) cost[t] += (double)T.pcr[c]->n * T.nx[c] * T.ny[c] / 3.0;
+    }
+  }
+  if (count == 0) return PF_OK;
+  int dev = 0;
+  PF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_lanes_mu);
+  Lanes *L = nullptr;
+  pf_status s = lanes_ready(dev, L);
+  if (s) return s;
+  hipStream_t origin = (hipStream_t)stream;
+  const int nl = lanes < count ? lanes : count;
+  PF_HIP(hipEventRecord(L->fork, origin));
+  for (int l = 0; l < nl; ++l) PF_HIP(hipStreamWaitEvent(L->s[l], L->fork, 0));
+  // largest tasks first, each to the least-loaded lane
+  std::vector<int> order((size_t)count);
+  for (int t = 0; t < count; ++t) order[t] = t;
+  for (int a = 1; a < count; ++a)
+    for (int b = a; b > 0 && cost[order[b]] > cost[order[b - 1]]; --b) std::swap(order[b], order[b - 1]);
+  double load[kMaxLanes] = {};
+  pf_status err = PF_OK;
+  for (int t : order) {
+    int l = 0;
+    for (int u = 1; u < nl; ++u)
+      if (load[u] < load[l]) l = u;
+    load[l] += cost[t];
+    const pf_task &T = tasks[t];
+    if (!err && T.ncomp) err = pcr_enqueue(T.pcr[0], groups[t], L->s[l]);
+    if (!err && T.poisson) err = poisson_enqueue(T.poisson, T.rhs, T.p, L->s[l]);
+  }
+  // join every lane back, also after a failed launch, so that a capture
+  // on the origin stream stays well formed
+  for (int l = 0; l < nl; ++l) {
+    PF_HIP(hipEventRecord(L->join[l], L->s[l]));
+    PF_HIP(hipStreamWaitEvent(origin, L->join[l], 0));
+  }
+  return err;
+}
+
 pf_status pf_graph_begin(void *stream) {
   if (!stream) return fail(PF_ERR_ARG, "capture needs a non-default stream");
   PF_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));

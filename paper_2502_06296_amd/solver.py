@@ -178,6 +178,34 @@ def pcr_set_stream(plan, stream):
     plan.stream = stream
 
 
+# -------------------------------------------------------------- task batch
+def run_batched(tasks, lanes=4, stream=None):
+    """Independent tasks spread over `lanes` internal streams forked from and
+    joined back into `stream` (pf_run_batched). Each task is a dict with an
+    optional Poisson solve (``poisson``, ``rhs``, ``p``) and an optional group
+    of up to 4 Helmholtz fields (``pcr``: plans, ``fields``: tensors)."""
+    import torch
+    arr = (N.PfTask * max(1, len(tasks)))()
+    for t, task in enumerate(tasks):
+        T = arr[t]
+        pl = task.get("poisson")
+        if pl is not None:
+            _check_field(task["rhs"], pl.shape, torch.float64)
+            _check_field(task["p"], pl.shape, torch.float64)
+            T.poisson, T.rhs, T.p = pl.handle, task["rhs"].data_ptr(), task["p"].data_ptr()
+        plans, fields = task.get("pcr", []), task.get("fields", [])
+        if len(plans) != len(fields) or len(plans) > 4:
+            raise ValueError("a task takes up to 4 Helmholtz plans with one field each")
+        T.ncomp = len(plans)
+        for c, (hp, f) in enumerate(zip(plans, fields)):
+            if f.shape[0] != hp.n:
+                raise ValueError("field rows do not match plan")
+            _check_field(f, f.shape, _pcr_dtype(hp))
+            T.pcr[c], T.field[c] = hp.handle, f.data_ptr()
+            T.nx[c], T.ny[c] = f.shape[2], f.shape[1]
+    N.check(N.lib().pf_run_batched(len(tasks), arr, int(lanes), N.stream_handle(stream)))
+
+
 # ------------------------------------------------------------------ graphs
 class Graph:
     def __init__(self, handle):

@@ -91,6 +91,22 @@ def test_null_arguments():
     assert L.poisson_destroy(None) == N.PF_OK
 
 
+def test_task_batch_validates_before_any_device_call():
+    L = N.lib()
+    tasks = (N.PfTask * 2)()
+    assert L.pf_run_batched(0, tasks, 4, None) == N.PF_OK          # nothing to do
+    assert L.pf_run_batched(-1, tasks, 4, None) == N.PF_ERR_ARG
+    assert L.pf_run_batched(1, None, 4, None) == N.PF_ERR_ARG
+    assert L.pf_run_batched(1, tasks, 0, None) == N.PF_ERR_ARG     # lanes 1..8
+    assert L.pf_run_batched(1, tasks, 9, None) == N.PF_ERR_ARG
+    assert L.pf_run_batched(1, tasks, 4, None) == N.PF_ERR_ARG     # empty task
+    tasks[0].ncomp = 5
+    assert L.pf_run_batched(1, tasks, 4, None) == N.PF_ERR_ARG
+    tasks[0].ncomp = 1                                              # NULL plan
+    assert L.pf_run_batched(1, tasks, 4, None) == N.PF_ERR_ARG
+    assert L.pf_last_error()
+
+
 def test_pcr_prepare_rejects_bad_rows():
     L = N.lib()
     pd = C.POINTER(C.c_double)

@@ -87,3 +87,81 @@ def test_graph_replay_equals_eager(prec):
         assert torch.equal(p, pe), rep
         for a, b in zip(u, ue):
             assert torch.equal(a, b), rep
+
+
+def _uneven_tasks(prec="fp32_refine", count=16, stream=None):
+    shapes = synth.draw_uneven_batch(3, count)
+    items = []
+    for t, sh in enumerate(shapes):
+        nx, ny, nz, beta = sh["nx"], sh["ny"], sh["nz"], sh["beta"]
+        f, zf = synth.channel_rhs(300 + t, nx, ny, nz, beta=beta)
+        pp = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, stream=stream)
+        pcr, r3 = [], []
+        for c, bc in enumerate((ogrid.DIRICHLET_CENTRE, ogrid.DIRICHLET_CENTRE, ogrid.DIRICHLET_FACE)):
+            al, ga, ex = ogrid.zop(zf, bc)
+            pcr.append(pf.pcr_prepare(al, ga, ex, S, precision=prec, stream=stream))
+            r3.append(torch.from_numpy(synth.normal01(400 + 3 * t + c, (nz if c < 2 else nz - 1, ny, nx))).to(_dev()))
+        items.append(dict(poisson=pp, rhs=torch.from_numpy(f).to(_dev()), pcr=pcr, r3=r3, shape=(nx, ny, nz)))
+    return items
+
+
+def _fresh(items):
+    for it in items:
+        it["p"] = torch.full_like(it["rhs"], -1.0)
+        it["fields"] = [r.clone() for r in it["r3"]]
+    return [dict(poisson=it["poisson"], rhs=it["rhs"], p=it["p"], pcr=it["pcr"], fields=it["fields"])
+            for it in items]
+
+
+def test_task_batch_on_lanes_equals_one_by_one():
+    """The uneven batch spread over 4 lanes gives, bitwise, what each
+    problem gives alone (every kernel is deterministic and the lanes only
+    change where the work runs)."""
+    stream = torch.cuda.Stream(device=_dev())
+    items = _uneven_tasks(stream=stream)
+    # one by one on the plans' own stream
+    ref_p, ref_u = [], []
+    for t, it in enumerate(items):
+        print(f"task {t}: {it['shape']}", flush=True)
+        p = torch.empty_like(it["rhs"])
+        u = [r.clone() for r in it["r3"]]
+        with torch.cuda.stream(stream):
+            pf.pcr_apply_batched(it["pcr"], u)
+            pf.poisson_solve(it["poisson"], it["rhs"], p)
+        ref_p.append(p)
+        ref_u.append(u)
+    stream.synchronize()
+    tasks = _fresh(items)
+    pf.run_batched(tasks, lanes=4, stream=stream)
+    stream.synchronize()
+    for t, it in enumerate(items):
+        assert torch.equal(it["p"], ref_p[t]), t
+        for a, b in zip(it["fields"], ref_u[t]):
+            assert torch.equal(a, b), t
+
+
+def test_task_batch_graph_replays_equal_eager():
+    stream = torch.cuda.Stream(device=_dev())
+    items = _uneven_tasks(count=8, stream=stream)
+    tasks = _fresh(items)
+    pf.run_batched(tasks, lanes=4, stream=stream)       # eager; also creates the lanes
+    stream.synchronize()
+    eager_p = [it["p"].clone() for it in items]
+    eager_u = [[f.clone() for f in it["fields"]] for it in items]
+    tasks = _fresh(items)
+    pf.pf_graph_begin(stream)
+    pf.run_batched(tasks, lanes=4, stream=stream)
+    g = pf.pf_graph_end(stream)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            for it in items:
+                it["p"].fill_(-1.0)
+                for a, b in zip(it["fields"], it["r3"]):
+                    a.copy_(b)            # eager work between the replays
+        g.launch(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for t, it in enumerate(items):
+            assert torch.equal(it["p"], eager_p[t]), (rep, t)
+            for a, b in zip(it["fields"], eager_u[t]):
+                assert torch.equal(a, b), (rep, t)
