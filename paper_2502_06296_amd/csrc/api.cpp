@@ -443,7 +443,16 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   ex.resize(zpad(g->nz), 1.0);
   std::vector<double> dzf(g->nz);
   for (int k = 0; k < g->nz; ++k) dzf[k] = zf[k + 1] - zf[k];
+  // y: the packed slots of x slots 0 and 1, then the complex modes 0..ny-1
+  // of every other slot pair
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
+  {
+    const double dy = g->ly / g->ny;
+    for (int m = 0; m < g->ny; ++m) {
+      const long double v = std::sin((long double)M_PI * m / g->ny);
+      sy.push_back((double)(4.0L * v * v / ((long double)dy * dy)));
+    }
+  }
   auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
   DevArena &A = pl->ar;
   pl->o_zal = A.add(al.data(), al.size());

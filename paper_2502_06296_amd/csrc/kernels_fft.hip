@@ -183,35 +183,53 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   const int ib = blk % nib;
   const long k = blk / nib;
   T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
-  {
-    // lines run fastest across the lanes, so the first pass's reads of row
-    // y cover the 2*LPW contiguous slots of the workgroup
-    const int l = tid % LPW, t = tid / LPW;
-    auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
-    fft_line_io<double, N, TPL, false, true, false>(lds + l * y_stride(N), tw, t, src,
-                                                    [](int, const C &) {});
+  // lines run fastest across the lanes, so the first pass's reads (and the
+  // last pass's writes) of row y cover the 2*LPW contiguous slots
+  const int l = tid % LPW, t = tid / LPW;
+  C *buf = lds + l * y_stride(N);
+  auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
+  if (ib != 0) {
+    // slot pairs (2m, 2m+1), m >= 1, are the real and imaginary parts of x
+    // mode m: their y transform is the complex spectrum itself, written in
+    // natural order (row ky) by the last pass
+    auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
+    fft_line_io<double, N, TPL, false, true, true>(buf, tw, t, src, dst);
+    return;
   }
+  // the workgroup of slots 0..2*LPW-1: slots 0 and 1 are two real columns
+  // (x modes 0 and nx/2), split into two packed real y spectra (rows 2q,
+  // 2q+1 hold the real and imaginary parts of mode q; rows 0 and 1 the
+  // modes 0 and ny/2) in float64 before rounding to the storage type
+  fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
 #pragma unroll
-  for (int s = 0; s < N / (2 * TPL); ++s) {
+  for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
-    const int l2 = e % LPW, q = e / LPW;
-    const C *buf = lds + l2 * y_stride(N);
-    C r0, r1;
-    if (q == 0) {
-      r0 = buf[lds_idx(0)];
-      r1 = buf[lds_idx(N / 2)];
-    } else {
-      C A, B;
-      split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
-      r0 = mkc<double>(A.x, B.x);
-      r1 = mkc<double>(A.y, B.y);
+    const int l2 = e % LPW, y = e / LPW;
+    const C *b2 = lds + l2 * y_stride(N);
+    if (l2 != 0) {
+      const C v = b2[lds_idx(y)];
+      st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
+    } else if (y < N / 2) {
+      const int q = y;
+      C r0, r1;
+      if (q == 0) {
+        r0 = b2[lds_idx(0)];
+        r1 = b2[lds_idx(N / 2)];
+      } else {
+        C A, B;
+        split_pair<double>(b2[lds_idx(q)], b2[lds_idx(N - q)], A, B);
+        r0 = mkc<double>(A.x, B.x);
+        r1 = mkc<double>(A.y, B.y);
+      }
+      st2<T>(base + (size_t)(2 * q) * nx, r0.x, r0.y);
+      st2<T>(base + (size_t)(2 * q + 1) * nx, r1.x, r1.y);
     }
-    st2<T>(base + (size_t)(2 * q) * nx + 2 * l2, r0.x, r0.y);
-    st2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2, r1.x, r1.y);
   }
 }
 
 // ------------------------------------------------------------- y inverse
+// Inverse of k_yfwd's layout: complex spectra in natural order for slot
+// pairs m >= 1, two packed real spectra for slots 0 and 1.
 template <typename T, int N, int TPL, int LPW>
 __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw, int nx,
@@ -225,29 +243,39 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   const int ib = blk % nib;
   const long k = blk / nib;
   T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
+  const int l = tid % LPW, t = tid / LPW;
+  C *buf = lds + l * y_stride(N);
+  auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
+  if (ib != 0) {
+    // the first pass reads the complex spectrum straight from row ky
+    auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
+    fft_line_io<double, N, TPL, true, true, true>(buf, tw, t, src, dst);
+    return;
+  }
 #pragma unroll
-  for (int s = 0; s < N / (2 * TPL); ++s) {
+  for (int s = 0; s < N / TPL; ++s) {
     const int e = tid + s * NT;
-    const int l2 = e % LPW, q = e / LPW;
-    C *buf = lds + l2 * y_stride(N);
-    const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
-    const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
-    if (q == 0) {
-      buf[lds_idx(0)] = r0;
-      buf[lds_idx(N / 2)] = r1;
-    } else {
-      C zq, zn;
-      join_pair<double>(mkc<double>(r0.x, r1.x), mkc<double>(r0.y, r1.y), zq, zn);
-      buf[lds_idx(q)] = zq;
-      buf[lds_idx(N - q)] = zn;
+    const int l2 = e % LPW, y = e / LPW;
+    C *b2 = lds + l2 * y_stride(N);
+    if (l2 != 0) {
+      b2[lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l2);
+    } else if (y < N / 2) {
+      const int q = y;
+      const C r0 = ld2<T>(base + (size_t)(2 * q) * nx);
+      const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx);
+      if (q == 0) {
+        b2[lds_idx(0)] = r0;
+        b2[lds_idx(N / 2)] = r1;
+      } else {
+        C zq, zn;
+        join_pair<double>(mkc<double>(r0.x, r1.x), mkc<double>(r0.y, r1.y), zq, zn);
+        b2[lds_idx(q)] = zq;
+        b2[lds_idx(N - q)] = zn;
+      }
     }
   }
   __syncthreads();
-  // the last pass writes row y of all lines straight to global memory
-  const int l = tid % LPW, t = tid / LPW;
-  auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
-  fft_line_io<double, N, TPL, true, false, true>(lds + l * y_stride(N), tw, t,
-                                                 [](int) { return C{}; }, dst);
+  fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dst);
 }
 
 // ------------------------------------------------------------- x inverse

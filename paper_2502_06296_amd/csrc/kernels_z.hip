@@ -24,7 +24,10 @@ namespace pf {
 // gamma = 0, excess = 1), which decouple exactly because the last real row
 // has gamma = 0; the padding keeps every loop and register index a compile-
 // time constant. The chunk's Step 1 coefficients depend on the column's
-// shift lambda = sx[i] + sy[j] (the modified wavenumbers), so they are
+// shift lambda = sx[i] + sy[j] (the modified wavenumbers; sy holds the
+// packed-slot values for the x slots 0 and 1 and, from index ny on, the
+// values of the natural-order complex y modes of the other slot pairs), so
+// they are
 // rebuilt in registers: an upward sweep gives the reduced first row, a
 // downward sweep (Algorithm 2, Step 1 and the forward half of Step 2, fused)
 // gives the reduced last row and leaves the forward-reduced d and the pivots
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, in
   const size_t plane = sp;
   TS *cp = data + (size_t)j * nx + i + (size_t)r0 * plane;
   const bool zero_col = (i == 0 && j == 0);
-  const double lam = zero_col ? 1.0 : sx[i] + sy[j];
+  const double lam = zero_col ? 1.0 : sx[i] + sy[(i >= 2 ? ny : 0) + j];
   const double *al = zal + r0, *ga = zga + r0, *ex = zex + r0;
 
   double d[M], ib_[M];
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
     // pass 0's work on already solved data and store nothing
     const int ci = i + pass;
     const bool zero_col = (ci == 0 && j == 0);
-    const double lam = zero_col ? 1.0 : sx[ci] + sy[j];
+    const double lam = zero_col ? 1.0 : sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
     // pass 0 stores both columns of every pair except column 1 of the pair
     // (0, 1); pass 1 stores only that column
     const bool st0 = pass == 0;
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
     // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1
     const int ci = i + pass;
     const bool zero_col = (ci == 0 && j == 0);
-    const double lam = zero_col ? 1.0 : sx[ci] + sy[j];
+    const double lam = zero_col ? 1.0 : sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
     const bool st0 = pass == 0;
     const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
 
