@@ -245,7 +245,7 @@ struct pf_pcr_plan {
   hipStream_t st;
   std::vector<double> al, ga, ex;
   DevArena ar;
-  size_t o_d[8], o_f[8], o_m[3];  // double tables, float tables, M-matrix rows
+  size_t o_d[11], o_f[11], o_m[4];  // double tables, float tables, M-matrix rows
   Timing tm;
 };
 
@@ -256,9 +256,13 @@ struct pf_graph {
 
 namespace {
 
-// Algorithm 2, Step 1 (subtraction-free) for every chunk, then the
-// cyclic-reduction multipliers of the reduced system. Fills 8 tables:
-// fa, bg, ib, ra, rc (n each), k1, k2 (steps*2P), invd (2P).
+constexpr int kPcrTables = 11;
+
+// Algorithm 2, Step 1 (subtraction-free) for every chunk, then two solvers
+// of the reduced system. Fills 11 tables: fa, bg, ib, ra, rc (n each); the
+// cyclic-reduction multipliers k1, k2 (steps*2P) and invd (2P); the twisted
+// elimination's forward and backward multipliers tf, tb and reciprocal
+// twisted pivots ti (2P each).
 void pcr_tables(const pf_pcr_plan &pl, std::vector<std::vector<double>> &T) {
   const int n = pl.n, P = pl.P, M = pl.M, np = P * M;
   // rows past n are identity rows: they decouple because gamma[n-1] = 0
@@ -268,7 +272,7 @@ void pcr_tables(const pf_pcr_plan &pl, std::vector<std::vector<double>> &T) {
     G[r] = pl.s * pl.ga[r];
     E[r] = 1.0 + pl.s * pl.ex[r];
   }
-  T.assign(8, {});
+  T.assign(kPcrTables, {});
   for (int t = 0; t < 5; ++t) T[t].assign(np, 0.0);
   std::vector<double> RA(2 * P), RG(2 * P), RE(2 * P);
   for (int p = 0; p < P; ++p) {
@@ -302,6 +306,30 @@ void pcr_tables(const pf_pcr_plan &pl, std::vector<std::vector<double>> &T) {
     }
   }
   const int nr = 2 * P;
+  // Twisted elimination of the reduced rows -RA x[r-1] + (RA+RG+RE) x[r] -
+  // RG x[r+1] = D[r]: a forward sweep y[r] = D[r] + tf[r] y[r-1] and a
+  // backward sweep z[r] = D[r] + tb[r] z[r+1] meet at any row r, where
+  // x[r] = (y[r] + tb[r] z[r+1]) ti[r]. Pivots are kept as off-diagonal plus
+  // excess (forward: RG + fe, backward: RA + be), and the twisted pivot is a
+  // sum of the excess and the two eliminated couplings' remainders, so no
+  // pivot is formed by subtraction.
+  {
+    std::vector<double> fe(nr), be(nr);
+    fe[0] = RA[0] + RE[0];
+    for (int r = 1; r < nr; ++r) fe[r] = RE[r] + RA[r] * fe[r - 1] / (RG[r - 1] + fe[r - 1]);
+    be[nr - 1] = RG[nr - 1] + RE[nr - 1];
+    for (int r = nr - 2; r >= 0; --r) be[r] = RE[r] + RG[r] * be[r + 1] / (RA[r + 1] + be[r + 1]);
+    for (int t = 8; t < 11; ++t) T[t].assign(nr, 0.0);
+    for (int r = 0; r < nr; ++r) {
+      const double fp = r > 0 ? RG[r - 1] + fe[r - 1] : 1.0;
+      const double bp = r < nr - 1 ? RA[r + 1] + be[r + 1] : 1.0;
+      const double lo = r > 0 ? RA[r] * fe[r - 1] / fp : RA[r];
+      const double hi = r < nr - 1 ? RG[r] * be[r + 1] / bp : RG[r];
+      T[8][r] = r > 0 ? RA[r] / fp : 0.0;
+      T[9][r] = r < nr - 1 ? RG[r] / bp : 0.0;
+      T[10][r] = 1.0 / (RE[r] + lo + hi);
+    }
+  }
   T[5].assign((size_t)pl.steps * nr, 0.0);
   T[6].assign((size_t)pl.steps * nr, 0.0);
   for (int st = 0; st < pl.steps; ++st) {
@@ -327,24 +355,27 @@ pf_status pcr_upload(pf_pcr_plan *pl, bool first) {
   std::vector<std::vector<double>> T;
   pcr_tables(*pl, T);
   if (first) {
-    for (int t = 0; t < 8; ++t) pl->o_d[t] = pl->ar.add(T[t].data(), T[t].size());
-    for (int t = 0; t < 8; ++t) pl->o_f[t] = pl->ar.add<float>(nullptr, T[t].size());
-    for (int t = 0; t < 3; ++t) pl->o_m[t] = pl->ar.add<double>(nullptr, (size_t)pl->P * pl->M);
+    for (int t = 0; t < kPcrTables; ++t) pl->o_d[t] = pl->ar.add(T[t].data(), T[t].size());
+    for (int t = 0; t < kPcrTables; ++t) pl->o_f[t] = pl->ar.add<float>(nullptr, T[t].size());
+    for (int t = 0; t < 4; ++t) pl->o_m[t] = pl->ar.add<double>(nullptr, (size_t)pl->P * pl->M);
   } else {
-    for (int t = 0; t < 8; ++t) std::memcpy(pl->ar.host.data() + pl->o_d[t], T[t].data(), T[t].size() * 8);
+    for (int t = 0; t < kPcrTables; ++t)
+      std::memcpy(pl->ar.host.data() + pl->o_d[t], T[t].data(), T[t].size() * 8);
   }
-  for (int t = 0; t < 8; ++t) {
+  for (int t = 0; t < kPcrTables; ++t) {
     float *f = reinterpret_cast<float *>(pl->ar.host.data() + pl->o_f[t]);
     for (size_t i = 0; i < T[t].size(); ++i) f[i] = (float)T[t][i];
   }
   double *mA = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[0]);
   double *mG = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[1]);
   double *mE = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[2]);
+  double *mD = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[3]);
   for (int r = 0; r < pl->P * pl->M; ++r) {
     const bool real = r < pl->n;
     mA[r] = real ? pl->s * pl->al[r] : 0.0;
     mG[r] = real ? pl->s * pl->ga[r] : 0.0;
     mE[r] = real ? 1.0 + pl->s * pl->ex[r] : 1.0;
+    mD[r] = mA[r] + mG[r] + mE[r];
   }
   if (first) {
     pl->ar.cap = pl->ar.used;
@@ -367,9 +398,12 @@ pf::HelmCoef helm_coef(const pf_pcr_plan *pl) {
   c.k1 = pl->ar.base + o[5];
   c.k2 = pl->ar.base + o[6];
   c.invd = pl->ar.base + o[7];
+  c.tf = pl->ar.base + o[8];
+  c.tb = pl->ar.base + o[9];
+  c.ti = pl->ar.base + o[10];
   c.al = pl->ar.at<double>(pl->o_m[0]);
   c.ga = pl->ar.at<double>(pl->o_m[1]);
-  c.ep = pl->ar.at<double>(pl->o_m[2]);
+  c.dg = pl->ar.at<double>(pl->o_m[3]);
   c.n = pl->n;
   c.P = pl->P;
   c.steps = pl->steps;

@@ -758,55 +758,89 @@ hipError_t launch_zero_shift(int nx, int ny, int nz, const double *sums_p0, cons
 // wave (64 consecutive columns) per chunk of M rows, so every coefficient
 // address is uniform across the wave. Columns are padded to P*M rows with
 // identity rows (see the Poisson z solve). The reduced 2P-row system is the
-// same for all columns; its cyclic-reduction multipliers are precomputed,
-// and only the right-hand sides cross LDS.
-template <typename TC, int M>
-__device__ __forceinline__ void helm_solve_regs(TC (&d)[M], TC &x0, TC &xl, int r0,
-                                                const TC *__restrict__ fa, const TC *__restrict__ bg,
-                                                const TC *__restrict__ ib, const TC *__restrict__ ra,
-                                                const TC *__restrict__ rc, const TC *__restrict__ k1,
-                                                const TC *__restrict__ k2, const TC *__restrict__ invd,
-                                                int P, int steps, TC *RD, int w, int lane, bool active,
-                                                int CW) {
-  // Step 2: forward and backward reduction of d
+// same for all columns, so its eliminations are precomputed and only the
+// right-hand sides cross LDS.
+// Read-only tables through the constant address space: wave-uniform reads of
+// them stay scalar loads even after the kernel has stored to LDS.
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const void *p) {
+  return (cptr<T>)p;
+}
+
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Steps 2-4 on the M rows d of one chunk. Step 3 is a twisted elimination:
+// after one barrier every wave reads the 2P reduced right-hand sides of its
+// columns and sweeps from the top down to its first reduced row and from the
+// bottom up to its last, with the plan's multipliers; the two sweeps meet at
+// the chunk's rows. With NBR it also returns the end values of the
+// neighbouring chunks, x[2w-1] and x[2w+2] (0 past the walls), by extending
+// its sweeps two rows. Those must equal bitwise what the neighbouring waves
+// compute for their own rows (the residual has to see the values that are
+// stored), so every sweep step is an explicit fused multiply-add: each
+// y[r] and z[r] is then the same chain of roundings in every wave. RD holds
+// 2P rows of CW values and is written once per call.
+template <typename TC, int M, bool NBR, typename CP>
+__device__ __forceinline__ void helm_solve_regs(TC (&d)[M], int r0, CP fa, CP bg, CP ib, CP ra,
+                                                CP rc, CP tf, CP tb, CP ti, int P, TC *RD, int w,
+                                                int lane, bool active, int CW, TC &below,
+                                                TC &above) {
   if (active) {
+    // Step 2: forward and backward reduction of d
 #pragma unroll
     for (int q = 2; q < M; ++q) d[q] = d[q] + fa[r0 + q] * d[q - 1];
 #pragma unroll
     for (int q = M - 3; q >= 0; --q) d[q] = d[q] + bg[r0 + q] * d[q + 1];
+    RD[(2 * w) * CW + lane] = d[0];
+    RD[(2 * w + 1) * CW + lane] = d[M - 1];
   }
-  // Step 3: the reduced system; rows 2w and 2w+1 belong to this wave
-  const int nr = 2 * P;
-  x0 = d[0];
-  xl = d[M - 1];
-  for (int st = 0; st < steps; ++st) {
-    const int s = 1 << st;
-    if (active) {
-      RD[(2 * w) * CW + lane] = x0;
-      RD[(2 * w + 1) * CW + lane] = xl;
-    }
-    __syncthreads();
-    if (active) {
-      const int ra0 = 2 * w, ra1 = 2 * w + 1;
-      TC n0 = x0, n1 = xl;
-      if (ra0 - s >= 0) n0 += k1[st * nr + ra0] * RD[(ra0 - s) * CW + lane];
-      if (ra0 + s < nr) n0 += k2[st * nr + ra0] * RD[(ra0 + s) * CW + lane];
-      if (ra1 - s >= 0) n1 += k1[st * nr + ra1] * RD[(ra1 - s) * CW + lane];
-      if (ra1 + s < nr) n1 += k2[st * nr + ra1] * RD[(ra1 + s) * CW + lane];
-      x0 = n0;
-      xl = n1;
-    }
-    __syncthreads();
+  __syncthreads();
+  if (!active) return;
+  // Step 3: forward sweep y[r] = D[r] + tf[r] y[r-1] down to row lo, backward
+  // sweep z[r] = D[r] + tb[r] z[r+1] up to row hi = lo + 1
+  const int nr = 2 * P, lo = 2 * w, hi = lo + 1;
+  const TC *col = RD + lane;
+  TC y = col[0], y1 = TC(0), y2 = TC(0);
+#pragma unroll 8
+  for (int r = 1; r <= lo; ++r) {
+    y2 = y1;
+    y1 = y;
+    y = fmad(tf[r], y, col[r * CW]);
   }
-  if (active) {
-    x0 = x0 * invd[2 * w];
-    xl = xl * invd[2 * w + 1];
-    // Step 4: rebuild the interior in place
+  TC z = col[(nr - 1) * CW], z1 = TC(0), z2 = TC(0);
+  const int nb = nr - 1 - hi;  // rows nr-2 down to hi
+#pragma unroll 8
+  for (int k = 0; k < nb; ++k) {
+    const int r = nr - 2 - k;
+    z2 = z1;
+    z1 = z;
+    z = fmad(tb[r], z, col[r * CW]);
+  }
+  // x[lo] = (y[lo] + tb z[hi]) ti[lo], x[hi] = (z[hi] + tf y[lo]) ti[hi]
+  const TC x0 = fmad(tb[lo], z, y) * ti[lo];
+  const TC xl = fmad(tf[hi], y, z) * ti[hi];
+  if constexpr (NBR) {
+    below = TC(0);
+    above = TC(0);
+    if (lo > 0) {  // extend the backward sweep by rows lo and lo-1
+      const TC zl = fmad(tb[lo], z, col[lo * CW]);
+      const TC zm = fmad(tb[lo - 1], zl, col[(lo - 1) * CW]);
+      below = fmad(tf[lo - 1], y2, zm) * ti[lo - 1];
+    }
+    if (hi < nr - 1) {  // extend the forward sweep by rows hi and hi+1
+      const TC yh = fmad(tf[hi], y, col[hi * CW]);
+      const TC yp = fmad(tf[hi + 1], yh, col[(hi + 1) * CW]);
+      above = fmad(tb[hi + 1], z2, yp) * ti[hi + 1];
+    }
+  }
+  // Step 4: rebuild the interior in place
 #pragma unroll
-    for (int q = 1; q < M - 1; ++q) d[q] = (d[q] + ra[r0 + q] * x0 + rc[r0 + q] * xl) * ib[r0 + q];
-    d[0] = x0;
-    d[M - 1] = xl;
-  }
+  for (int q = 1; q < M - 1; ++q) d[q] = (d[q] + ra[r0 + q] * x0 + rc[r0 + q] * xl) * ib[r0 + q];
+  d[0] = x0;
+  d[M - 1] = xl;
 }
 
 struct HelmArgs {
@@ -828,6 +862,7 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   const int nib = J.nx / CW;
   const long nblk = (long)nib * J.ny;
   if ((long)blockIdx.x >= nblk) return;  // uniform per block
+  // one array of 2P reduced rows per solve
   TC *RD = reinterpret_cast<TC *>(shraw);
   const int w = CW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / CW;
   const int lane = threadIdx.x % CW;
@@ -838,23 +873,25 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   const int r0 = active ? w * M : 0;
   const size_t plane = (size_t)J.nx * J.ny;
   TS *cp = reinterpret_cast<TS *>(J.field) + (size_t)j * J.nx + ib * CW + lane + (size_t)r0 * plane;
-  const TC *fa = (const TC *)C.fa, *bg = (const TC *)C.bg, *ibv = (const TC *)C.ib;
-  const TC *ra = (const TC *)C.ra, *rc = (const TC *)C.rc;
-  const TC *k1 = (const TC *)C.k1, *k2 = (const TC *)C.k2, *invd = (const TC *)C.invd;
-  TC x0, xl;
+  const cptr<TC> fa = as_const<TC>(C.fa), bg = as_const<TC>(C.bg), ibv = as_const<TC>(C.ib);
+  const cptr<TC> ra = as_const<TC>(C.ra), rc = as_const<TC>(C.rc);
+  const cptr<TC> tf = as_const<TC>(C.tf), tb = as_const<TC>(C.tb), ti = as_const<TC>(C.ti);
+  TC below, above;
 
   if constexpr (!REFINE) {
     TC d[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) d[q] = (active && r0 + q < n) ? (TC)cp[(size_t)q * plane] : TC(0);
-    helm_solve_regs<TC, M>(d, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
-                           lane, active, CW);
+    helm_solve_regs<TC, M, false>(d, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD, w, lane, active,
+                                  CW, below, above);
     if (active) {
 #pragma unroll
       for (int q = 0; q < M; ++q)
         if (r0 + q < n) cp[(size_t)q * plane] = (TS)d[q];
     }
   } else {
+    const cptr<double> mal = as_const<double>(C.al), mga = as_const<double>(C.ga);
+    const cptr<double> mdg = as_const<double>(C.dg);
     double r[M];
     TC u[M], dd[M];
 #pragma unroll
@@ -862,33 +899,20 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
       r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
       u[q] = (TC)r[q];
     }
-    helm_solve_regs<TC, M>(u, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
-                           lane, active, CW);
-    // the neighbours across chunk ends, for the residual
-    double *NB = reinterpret_cast<double *>(shraw);
-    if (active) {
-      NB[(2 * w) * CW + lane] = (double)u[0];
-      NB[(2 * w + 1) * CW + lane] = (double)u[M - 1];
-    }
-    __syncthreads();
-    double below = 0.0, above = 0.0;
-    if (active) {
-      if (w > 0) below = NB[(2 * w - 1) * CW + lane];
-      if (w < C.P - 1) above = NB[(2 * w + 2) * CW + lane];
-    }
-    __syncthreads();
+    // the first solve also gives the neighbours across the chunk ends
+    helm_solve_regs<TC, M, true>(u, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD, w, lane, active,
+                                 CW, below, above);
     if (active) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
-        const double al = C.al[r0 + q], ga = C.ga[r0 + q], ep = C.ep[r0 + q];
-        const double um = q == 0 ? below : (double)u[q == 0 ? 0 : q - 1];
-        const double up = q == M - 1 ? above : (double)u[q == M - 1 ? q : q + 1];
-        const double uc = (double)u[q];
-        dd[q] = (TC)(r[q] - ((al + ga + ep) * uc - al * um - ga * up));
+        const double al = mal[r0 + q], ga = mga[r0 + q], dg = mdg[r0 + q];
+        const double um = q == 0 ? (double)below : (double)u[q == 0 ? 0 : q - 1];
+        const double up = q == M - 1 ? (double)above : (double)u[q == M - 1 ? q : q + 1];
+        dd[q] = (TC)(r[q] - (dg * (double)u[q] - al * um - ga * up));
       }
     }
-    helm_solve_regs<TC, M>(dd, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, C.P, C.steps, RD, w,
-                           lane, active, CW);
+    helm_solve_regs<TC, M, false>(dd, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD + 2 * C.P * CW,
+                                  w, lane, active, CW, below, above);
     if (active) {
 #pragma unroll
       for (int q = 0; q < M; ++q)
@@ -961,13 +985,13 @@ __global__ __launch_bounds__(512, 4) void k_helm_lds(HelmArgs args) {
   TC *k1 = rc + npad, *k2 = k1 + steps * nr, *invd = k2 + steps * nr, *RD = invd + nr;
   double *D = reinterpret_cast<double *>(
       (reinterpret_cast<uintptr_t>(RD + nr * CW) + 7) & ~uintptr_t(7));
-  double *mal = D, *mga = D + npad, *mep = D + 2 * npad, *NB = D + 3 * npad;
+  double *mal = D, *mga = D + npad, *mdg = D + 2 * npad, *NB = D + 3 * npad;
   {
     const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
     const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
     for (int r = threadIdx.x; r < npad; r += blockDim.x) {
       fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
-      if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mep[r] = C.ep[r]; }
+      if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mdg[r] = C.dg[r]; }
     }
     const TC *sk1 = (const TC *)C.k1, *sk2 = (const TC *)C.k2, *sinv = (const TC *)C.invd;
     for (int r = threadIdx.x; r < steps * nr; r += blockDim.x) { k1[r] = sk1[r]; k2[r] = sk2[r]; }
@@ -1023,11 +1047,10 @@ __global__ __launch_bounds__(512, 4) void k_helm_lds(HelmArgs args) {
       if (active) {
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-          const double al = mal[r0 + q], ga = mga[r0 + q], ep = mep[r0 + q];
+          const double al = mal[r0 + q], ga = mga[r0 + q], dg = mdg[r0 + q];
           const double um = q == 0 ? below : (double)u[q == 0 ? 0 : q - 1];
           const double up = q == M - 1 ? above : (double)u[q == M - 1 ? q : q + 1];
-          const double uc = (double)u[q];
-          dd[q] = (TC)(r[q] - ((al + ga + ep) * uc - al * um - ga * up));
+          dd[q] = (TC)(r[q] - (dg * (double)u[q] - al * um - ga * up));
         }
       }
       helm_solve_lds<TC, M>(dd, x0, xl, r0, fa, bg, ibv, ra, rc, k1, k2, invd, P, steps, RD, w,
@@ -1106,6 +1129,7 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
     return hipGetLastError();
   }
   dim3 g((unsigned)maxblk, (unsigned)count), b(CW * maxP);
+  // the reduced rows: one float64 array, or two float32 arrays (refinement)
   const size_t shm = (size_t)2 * maxP * CW * sizeof(double);
 #define PF_HELM_CW(M, CWV)                                                                      \
   if (precision == 0)                                                                           \

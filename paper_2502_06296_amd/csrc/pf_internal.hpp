@@ -123,8 +123,9 @@ struct HelmCoef {
   // per row r (n): forward multiplier alpha_r/b_{r-1}, backward multiplier
   // gamma_r/b_{r+1}, 1/b_r, |a_r|, |c_r|; M-matrix rows for the residual
   const void *fa, *bg, *ib, *ra, *rc;  // float or double per plan precision
-  const double *al, *ga, *ep;          // float64 rows (s alpha, s gamma, 1 + s excess)
+  const double *al, *ga, *dg;          // float64 rows: s alpha, s gamma, diagonal
   const void *k1, *k2, *invd;          // reduced-system PCR multipliers [steps][2P], [2P]
+  const void *tf, *tb, *ti;            // reduced-system twisted elimination [2P] each
   int n, P, steps;
 };
 struct HelmJob {

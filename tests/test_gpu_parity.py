@@ -150,14 +150,17 @@ def test_helmholtz_matches_oracle(nx, ny, nz, bc, prec, s):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("chunk_rows", [8, 16, 32])
-def test_helmholtz_chunkings_agree(chunk_rows):
-    nz = 200
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("nz,chunk_rows", [(200, 8), (200, 16), (200, 32), (64, 8), (128, 8), (512, 32)])
+def test_helmholtz_chunkings_agree(nz, chunk_rows, prec):
+    # s = 1e-2 couples the chunks strongly: the refinement's residual must see
+    # exactly the chunk-end values that the neighbouring chunks store
+    print(f"helmholtz {prec} nz={nz} chunk_rows={chunk_rows}", flush=True)
     zf = synth.tanh_faces(nz, 2.0, 1.5)
     r = synth.normal01(4, (nz, 4, 64))
     ref = op.solve_helmholtz(r, zf, 1e-2, ogrid.DIRICHLET_CENTRE)
-    got = _helm(r, zf, 1e-2, ogrid.DIRICHLET_CENTRE, "fp64", chunk_rows)
-    assert op.rel_l2(got, ref) < 1e-12
+    got = _helm(r, zf, 1e-2, ogrid.DIRICHLET_CENTRE, prec, chunk_rows)
+    assert op.rel_l2(got, ref) < TOL[prec]
 
 
 def test_helmholtz_s_zero_is_identity():
