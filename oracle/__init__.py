@@ -20,10 +20,13 @@ floor), slow and direct:
                     eq. (proj3_impl1d).
 * ``dense``      -- brute-force assembled operators for tiny grids, built
                     from face fluxes rather than from ``grid``.
+* ``projection`` -- the pressure projection of a Runge-Kutta substep on the
+                    staggered grid: divergence right-hand side, face
+                    gradient correction, pressure update.
 
 Every function is pinned by tests under ``tests/`` (dense brute force,
 closed-form discrete eigenfunctions, direct DFT, long-double floor,
 algorithm equalities); none is marked "parity unpinned" except the tanh
 stretching convention, which the paper does not define.
 """
-from . import grid, transforms, tridiag, poisson, dense  # noqa: F401
+from . import grid, transforms, tridiag, poisson, dense, projection  # noqa: F401

@@ -87,3 +87,72 @@ def _dropped_forward_term(orig):
 def test_planted_mistake_is_caught(monkeypatch, target, attr, mut):
     monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
     assert _pin_errors() > 1e-6
+
+
+# ------------------------------------------------------------ projection
+from oracle import projection  # noqa: E402
+
+
+def _projection_pin_errors():
+    """Largest error of the projection pins: D G = L7, a divergence-free
+    result, and the removal of a pure gradient field."""
+    nx, ny, nz = 8, 6, 7
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    phi = synth.uniform_pm1(31, (nz, ny, nx))
+    gx, gy, gz = projection.gradient(phi, zf, LX, LY)
+    ref = poisson.apply_L7(phi, zf, LX, LY)
+    errs = [np.max(np.abs(projection.divergence(gx, gy, gz, zf, LX, LY) - ref)) / np.max(np.abs(ref))]
+    u = synth.uniform_pm1(32, (nz, ny, nx))
+    v = synth.uniform_pm1(33, (nz, ny, nx))
+    w = synth.uniform_pm1(34, (nz - 1, ny, nx))
+    d0 = np.abs(projection.divergence(u, v, w, zf, LX, LY)).max()
+    u1, v1, w1, _, _ = projection.project(u, v, w, np.zeros_like(u), zf, LX, LY, gdt=0.3)
+    errs.append(np.abs(projection.divergence(u1, v1, w1, zf, LX, LY)).max() / d0)
+    u1, v1, w1, _, _ = projection.project(gx, gy, gz, np.zeros_like(u), zf, LX, LY, gdt=0.3)
+    errs.append(max(np.abs(x).max() for x in (u1, v1, w1)) / np.abs(gx).max())
+    return max(errs)
+
+
+def test_unmutated_projection_passes():
+    assert _projection_pin_errors() < 1e-10
+
+
+def _div_with_centre_distances(orig):
+    def f(u, v, w, zf, lx, ly):
+        zf = np.asarray(zf)
+        zc = (zf[1:] + zf[:-1]) / 2
+        fake = np.concatenate([[zf[0]], zc[:-1] + np.diff(zc) / 2, [zf[-1]]])
+        fake[1:-1] = zf[1:-1] + 0.25 * (np.diff(zc))    # cell widths no longer dzf
+        return orig(u, v, w, fake, lx, ly)
+    return f
+
+
+def _backward_x_gradient(orig):
+    def f(phi, zf, lx, ly):
+        gx, gy, gz = orig(phi, zf, lx, ly)
+        return np.roll(gx, 1, axis=2), gy, gz
+    return f
+
+
+def _swapped_w_faces(orig):
+    def f(u, v, w, zf, lx, ly):
+        return orig(u, v, -w, zf, lx, ly)
+    return f
+
+
+def _correction_without_gdt(orig):
+    def f(u, v, w, p, zf, lx, ly, gdt, c=0.0):
+        u1, v1, w1, p1, phi = orig(u, v, w, p, zf, lx, ly, gdt, c)
+        return u + (u1 - u) / gdt, v + (v1 - v) / gdt, w + (w1 - w) / gdt, p1, phi
+    return f
+
+
+@pytest.mark.parametrize("attr,mut", [
+    ("divergence", _div_with_centre_distances),
+    ("gradient", _backward_x_gradient),
+    ("divergence", _swapped_w_faces),
+    ("project", _correction_without_gdt),
+])
+def test_planted_projection_mistake_is_caught(monkeypatch, attr, mut):
+    monkeypatch.setattr(projection, attr, mut(getattr(projection, attr)))
+    assert _projection_pin_errors() > 1e-6
