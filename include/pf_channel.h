@@ -116,6 +116,24 @@ pf_status poisson_set_workspace(pf_poisson_plan *plan, void *workspace, size_t b
 /* p <- L7^{-1} f. rhs: device (nz,ny,nx) float64, read only. p: device
  * (nz,ny,nx) float64, must not overlap rhs or the workspace. */
 pf_status poisson_solve(pf_poisson_plan *plan, const double *rhs, double *p);
+/* Pressure projection of a Runge-Kutta substep on the staggered grid
+ * (paper Sec. 2.1, eqs. proj1_Lphi, proj1_ukp1, proj1_Pkp1; with implicit
+ * wall-normal diffusion the z part of eq. proj2_Pkp1):
+ *   L7 phi = D u* / gdt,   u <- u* - gdt G phi,   p <- p + phi - c L_z phi.
+ * u: x-face velocity, u[k][j][i] on face i+1/2 of cell (i,j,k); v: y-face
+ * velocity, v[k][j][i] on face j+1/2; both (nz,ny,nx). w: (nz-1,ny,nx), the
+ * interior z faces 1..nz-1 (w[m] between cells m and m+1; w = 0 on the
+ * walls, not stored). D is the cell divergence (face fluxes over dx, dy,
+ * dzf), G the face gradient (over dx, dy and the centre distances), L_z the
+ * zero-gradient z operator; D G = L7. gdt = gamma_k * dt > 0; c >= 0 (0 for
+ * explicit diffusion, gamma_k * nu * dt / 2 with the z-implicit Helmholtz).
+ * phi: device (nz,ny,nx) float64, receives the correction pressure (zero
+ * dzf-weighted mean) and serves the solve as its spectral buffer (PF_FP64)
+ * or as the stash of f (PF_FP32_REFINE). u, v, w, p are updated in place.
+ * All device float64, 16-byte aligned, pairwise disjoint and disjoint from
+ * the workspace; the workspace rules of poisson_solve apply. */
+pf_status poisson_project(pf_poisson_plan *plan, double *u, double *v, double *w, double *p,
+                          double *phi, double gdt, double c);
 /* The same solve for several plans, launched back to back on the first
  * plan's stream. */
 pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans,
@@ -200,11 +218,13 @@ pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, voi
  * solve, PF_STAGE_XINV_FINAL the last x inverse of the float32 solves (for
  * PF_FP32_REFINE: of iterate plus correction); PF_STAGE_XFWD_RESID is the
  * correction's right-hand side of PF_FP32_REFINE (the float64 residual
- * formed in x-spectral space). */
+ * formed in x-spectral space); PF_STAGE_PROJECT is the velocity and pressure
+ * update of poisson_project (whose first x pass, which forms the divergence,
+ * counts as PF_STAGE_XFWD). */
 enum {
   PF_STAGE_XFWD = 0, PF_STAGE_YFWD = 1, PF_STAGE_ZSOLVE = 2, PF_STAGE_YINV = 3,
   PF_STAGE_XINV = 4, PF_STAGE_ZERO_MODE = 5, PF_STAGE_XFWD_RESID = 6, PF_STAGE_XINV_FINAL = 7,
-  PF_STAGE_PCR_APPLY = 8, PF_STAGE_COUNT = 9
+  PF_STAGE_PCR_APPLY = 8, PF_STAGE_PROJECT = 9, PF_STAGE_COUNT = 10
 };
 pf_status poisson_timing(pf_poisson_plan *plan, int32_t enable);
 pf_status poisson_timing_read(pf_poisson_plan *plan, double *ms, int32_t *count);

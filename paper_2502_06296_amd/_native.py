@@ -16,13 +16,13 @@ PF_OK, PF_ERR_ARG, PF_ERR_UNSUPPORTED, PF_ERR_DEVICE, PF_ERR_WORKSPACE = 0, -1, 
 PF_FP64, PF_FP32, PF_FP32_REFINE = 0, 1, 2
 PF_BC_NEUMANN, PF_BC_DIRICHLET_CENTRE, PF_BC_DIRICHLET_FACE = 0, 1, 2
 STAGES = ["xfwd", "yfwd", "zsolve", "yinv", "xinv", "zero_mode", "xfwd_resid", "xinv_final",
-          "pcr_apply"]
+          "pcr_apply", "project"]
 PF_STAGE_COUNT = len(STAGES)
 
 # every symbol include/pf_channel.h declares
 EXPORTS = [
     "pf_last_error", "pf_abi_version", "pf_zop_rows", "pf_grid_faces",
-    "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_solve_batched",
+    "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_project", "poisson_solve_batched",
     "poisson_set_stream", "poisson_destroy",
     "pcr_prepare", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
     "pcr_destroy",
@@ -75,6 +75,7 @@ def lib():
             "poisson_plan": (i32, [C.POINTER(vp), C.POINTER(PfGrid), i32, i32, vp, C.POINTER(sz)]),
             "poisson_set_workspace": (i32, [vp, vp, sz]),
             "poisson_solve": (i32, [vp, vp, vp]),
+            "poisson_project": (i32, [vp, vp, vp, vp, vp, vp, C.c_double, C.c_double]),
             "poisson_solve_batched": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
             "poisson_set_stream": (i32, [vp, vp]),
             "poisson_destroy": (i32, [vp]),

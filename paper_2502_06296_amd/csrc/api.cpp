@@ -229,7 +229,7 @@ struct pf_poisson_plan {
   int zchunk;
   DevArena ar;
   size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
-      o_fbar, o_m, o_zm, o_p0m;
+      o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   Timing tm;
@@ -475,8 +475,11 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   al.resize(zpad(g->nz), 0.0);
   ga.resize(zpad(g->nz), 0.0);
   ex.resize(zpad(g->nz), 1.0);
-  std::vector<double> dzf(g->nz);
+  std::vector<double> dzf(g->nz), rdzf(g->nz), rdzc(g->nz - 1);
   for (int k = 0; k < g->nz; ++k) dzf[k] = zf[k + 1] - zf[k];
+  // the projection's metrics: 1/dzf per cell, 1/dzc per interior face
+  for (int k = 0; k < g->nz; ++k) rdzf[k] = 1.0 / dzf[k];
+  for (int k = 0; k + 1 < g->nz; ++k) rdzc[k] = 2.0 / (zf[k + 2] - zf[k]);
   // y: the packed slots of x slots 0 and 1, then the complex modes 0..ny-1
   // of every other slot pair
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
@@ -503,6 +506,8 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->o_m = A.add<double>(nullptr, (size_t)g->nz);
   pl->o_zm = A.add<double>(nullptr, (size_t)g->nz);
   pl->o_p0m = A.add<double>(nullptr, (size_t)g->nz);
+  pl->o_rdzf = A.add(rdzf.data(), rdzf.size());
+  pl->o_rdzc = A.add(rdzc.data(), rdzc.size());
   A.cap = A.used;
   hipError_t e = hipMalloc((void **)&A.base, A.cap);
   if (e == hipSuccess) e = hipMemcpy(A.base, A.host.data(), A.used, hipMemcpyHostToDevice);
@@ -552,7 +557,11 @@ static pf_status poisson_check_solve(pf_poisson_plan *pl, const double *rhs, dou
   return PF_OK;
 }
 
-static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st) {
+// With div, the right-hand side is D u* / gdt formed in the first x pass
+// (rhs unused); for the float32 refinement f is stashed in p, which the
+// residual reads before the last pass overwrites it.
+static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                 const pf::DivArgs *div = nullptr) {
   const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
   const long lines = (long)ny * nz;
   const double scale = 1.0 / ((double)nx * ny);
@@ -570,7 +579,8 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
     // the spectrum lives in p itself, dense
     const size_t sd = (size_t)nx * ny;
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
+    STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
+                             : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
     STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
@@ -582,7 +592,8 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   float *W0 = (float *)pl->ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
+    STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
+                             : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
     STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
@@ -596,7 +607,14 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   // the zero mode, which is solved once, in float64, from the plane means of
   // f and shifted by the iterate's plane means
   float *W1 = W0 + sp * (size_t)nz;
-  STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
+  if (div) {
+    pf::DivArgs d = *div;
+    d.stash = p;
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd_div<float>(nx, ny, nz, d, W0, sp, twx, sums, st));
+    rhs = p;
+  } else {
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
+  }
   STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
@@ -616,6 +634,44 @@ pf_status poisson_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
   pf_status s = poisson_check_solve(pl, rhs, p);
   if (s) return s;
   return poisson_enqueue(pl, rhs, p, pl->st);
+}
+
+pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, double *p, double *phi,
+                          double gdt, double c) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
+  if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
+  if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");
+  const size_t nb = pl->npts() * sizeof(double);
+  const size_t nbw = (size_t)pl->nx * pl->ny * (pl->nz - 1) * sizeof(double);
+  const void *ptr[5] = {u, v, w, p, phi};
+  const size_t len[5] = {nb, nb, nbw, nb, nb};
+  for (int a = 0; a < 5; ++a) {
+    if ((uintptr_t)ptr[a] & 15) return fail(PF_ERR_ARG, "fields must be 16-byte aligned");
+    for (int b = a + 1; b < 5; ++b)
+      if (overlaps(ptr[a], len[a], ptr[b], len[b])) return fail(PF_ERR_ARG, "u, v, w, p, phi must not overlap");
+    if (pl->ws_need && overlaps(pl->ws, pl->ws_need, ptr[a], len[a]))
+      return fail(PF_ERR_ARG, "workspace overlaps a field");
+  }
+  if (pl->ws_need && (!pl->ws || pl->ws_bytes < pl->ws_need))
+    return fail(PF_ERR_WORKSPACE, "workspace of %zu bytes required (poisson_set_workspace)", pl->ws_need);
+  const DevArena &A = pl->ar;
+  pf::DivArgs d;
+  d.u = u;
+  d.v = v;
+  d.w = w;
+  d.rdzf = A.at<double>(pl->o_rdzf);
+  d.idx = pl->nx / pl->lx;
+  d.idy = pl->ny / pl->ly;
+  d.igdt = 1.0 / gdt;
+  d.stash = nullptr;
+  pf_status s = poisson_enqueue(pl, nullptr, phi, pl->st, &d);
+  if (s) return s;
+  return run_stage(pl->tm, pl->st, PF_STAGE_PROJECT, [&]() {
+    return pf::launch_project(pl->nx, pl->ny, pl->nz, phi, u, v, w, p, A.at<double>(pl->o_zal),
+                              A.at<double>(pl->o_zga), A.at<double>(pl->o_rdzc), gdt * d.idx,
+                              gdt * d.idy, gdt, c, pl->st);
+  });
 }
 
 pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans, const double *const *rhs,

@@ -83,6 +83,166 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   }
 }
 
+// ------------------------------------------- x forward of the divergence
+// Right-hand side of a projection (eq. proj1_Lphi), f = D u* / gdt, formed
+// while the first pass reads its positions: u on the x faces i+1/2 (the west
+// face of cell i is the east face of cell i-1, periodic), v on the y faces
+// j+1/2, w on the interior z faces (w[k] is the top face of cell k, 0 on
+// both walls). The two lines of a pair are rows j, j+1 of one plane (ny is
+// even), so they share the v row j. With STASH, f itself is also written
+// (float64, real space) for the residual of a refinement; the first pass
+// reads every position exactly once. Otherwise as k_xfwd with line sums.
+template <typename T, int N, int TPL, int LPW, bool STASH>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd_div(DivArgs d, T *__restrict__ out,
+                                                       const cplx<double> *__restrict__ tw,
+                                                       double *__restrict__ sums, long ncl, int ny,
+                                                       int nz, size_t sp) {
+  using C = cplx<double>;
+  __shared__ C lds[LPW * lds_len(N)];
+  static_assert(N % TPL == 0, "every thread takes N / TPL positions");
+  const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
+  const long c = (long)blockIdx.x * LPW + l;
+  const bool ok = c < ncl;
+  C *buf = lds + l * lds_len(N);
+  const long L = ok ? 2 * c : 0;  // line of row j; L + 1 is row j + 1
+  const int k = (int)(L / ny), j = (int)(L % ny);
+  const size_t o = (size_t)L * N;
+  const double *ua = d.u + o, *ub = ua + N;
+  const double *va = d.v + o, *vb = va + N;
+  const double *vm = d.v + ((size_t)k * ny + (j == 0 ? ny - 1 : j - 1)) * N;
+  const bool top = k < nz - 1, bot = k > 0;
+  const double *wta = top ? d.w + o : d.w;                   // top faces of rows j, j+1
+  const double *wba = bot ? d.w + (o - (size_t)ny * N) : d.w;  // bottom faces
+  const double rz = d.rdzf[k];
+  auto src = [&](int i) {
+    if (!ok) return mkc<double>(0.0, 0.0);
+    const int im = i == 0 ? N - 1 : i - 1;
+    const double v0 = va[i];
+    double fa = (ua[i] - ua[im]) * d.idx + (v0 - vm[i]) * d.idy;
+    double fb = (ub[i] - ub[im]) * d.idx + (vb[i] - v0) * d.idy;
+    if (top) {
+      fa += wta[i] * rz;
+      fb += wta[N + i] * rz;
+    }
+    if (bot) {
+      fa -= wba[i] * rz;
+      fb -= wba[N + i] * rz;
+    }
+    fa *= d.igdt;
+    fb *= d.igdt;
+    if (STASH) {
+      d.stash[o + i] = fa;
+      d.stash[o + N + i] = fb;
+    }
+    return mkc<double>(fa, fb);
+  };
+  fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
+  if (!ok) return;
+  T *oa = out + (size_t)k * sp + (size_t)j * N;
+  T *ob = oa + N;
+#pragma unroll
+  for (int q = t; q < N / 2; q += TPL) {
+    C A, B;
+    if (q == 0) {
+      const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
+      A = mkc<double>(z0.x, zh.x);
+      B = mkc<double>(z0.y, zh.y);
+      sums[2 * c] = z0.x;
+      sums[2 * c + 1] = z0.y;
+    } else {
+      split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
+    }
+    *reinterpret_cast<cplx<T> *>(oa + 2 * q) = mkc<T>((T)A.x, (T)A.y);
+    *reinterpret_cast<cplx<T> *>(ob + 2 * q) = mkc<T>((T)B.x, (T)B.y);
+  }
+}
+
+// ------------------------------------------------ projection correction
+// u -= gdt G phi on the faces and p += phi - c L_z phi (eqs. proj1_ukp1,
+// proj1_Pkp1; proj2_Pkp1 with L_z for implicit wall-normal diffusion). A
+// thread owns one (i, j) column and marches up the planes with phi[k-1],
+// phi[k], phi[k+1] in registers; a wave covers 64 consecutive i, so every
+// access is a 512-byte row segment and the x and y neighbours of phi come
+// from lines the neighbouring lanes and rows read. The Neumann rows have
+// alpha_0 = 0 and gamma_{nz-1} = 0, so the zeros past the walls drop out.
+template <bool LZ>
+__global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
+                                                 double *__restrict__ u, double *__restrict__ v,
+                                                 double *__restrict__ w, double *__restrict__ p,
+                                                 const double *__restrict__ zal,
+                                                 const double *__restrict__ zga,
+                                                 const double *__restrict__ rdzc, int nx, int ny,
+                                                 int nz, double gx, double gy, double gdt, double c) {
+  const int i = blockIdx.x * 64 + (int)(threadIdx.x % 64);
+  const int j = blockIdx.y * 4 + (int)(threadIdx.x / 64);
+  if (i >= nx || j >= ny) return;  // no barrier follows
+  const size_t plane = (size_t)nx * ny;
+  const size_t o = (size_t)j * nx + i;
+  const size_t ox = (size_t)j * nx + (i + 1 == nx ? 0 : i + 1);
+  const size_t oy = (size_t)(j + 1 == ny ? 0 : j + 1) * nx + i;
+  double fm = 0.0, f0 = phi[o];
+#pragma unroll 2
+  for (int k = 0; k < nz; ++k) {
+    const size_t b = (size_t)k * plane;
+    const bool up = k + 1 < nz;
+    const double fp = up ? phi[b + plane + o] : 0.0;
+    const double fx = phi[b + ox], fy = phi[b + oy];
+    u[b + o] -= gx * (fx - f0);
+    v[b + o] -= gy * (fy - f0);
+    if (up) w[b + o] -= gdt * rdzc[k] * (fp - f0);  // w is (nz-1, ny, nx)
+    double dp = f0;
+    if (LZ) {
+      const double a = zal[k], g = zga[k];
+      dp -= c * (a * fm + g * fp - (a + g) * f0);
+    }
+    p[b + o] += dp;
+    fm = f0;
+    f0 = fp;
+  }
+}
+
+template <typename T>
+hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
+                           const cplx<double> *tw, double *sums, hipStream_t st) {
+  const long ncl = (long)ny * nz / 2;
+  switch (nx) {
+#define PF_CASE(N)                                                                               \
+  case N: {                                                                                      \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                                \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
+    if (d.stash)                                                                                 \
+      hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, d, out,  \
+                         tw, sums, ncl, ny, nz, sp);                                             \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, false>), g, dim3(TPL * LPW), 0, st, d, out, \
+                         tw, sums, ncl, ny, nz, sp);                                             \
+    return hipGetLastError();                                                                    \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_xfwd_div<double>(int, int, int, const DivArgs &, double *, size_t,
+                                            const cplx<double> *, double *, hipStream_t);
+template hipError_t launch_xfwd_div<float>(int, int, int, const DivArgs &, float *, size_t,
+                                           const cplx<double> *, double *, hipStream_t);
+
+hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
+                          double *w, double *p, const double *zal, const double *zga,
+                          const double *rdzc, double gx, double gy, double gdt, double c,
+                          hipStream_t st) {
+  dim3 g((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4));
+  if (c != 0.0)
+    hipLaunchKernelGGL((k_project<true>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc, nx,
+                       ny, nz, gx, gy, gdt, c);
+  else
+    hipLaunchKernelGGL((k_project<false>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc,
+                       nx, ny, nz, gx, gy, gdt, c);
+  return hipGetLastError();
+}
+
 // ------------------------------ residual of the correction in x-spectral space
 // The first float32 solution is kept as its x spectrum W (after the y
 // inverse; W = ny X(p0), X the unnormalised x transform), so the correction's

@@ -95,6 +95,27 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const c
                        const double *zm, const TS *in2, double scale, long lines,
                        hipStream_t st);
 
+// Pressure projection (eqs. proj1_Lphi, proj1_ukp1, proj1_Pkp1, proj2_Pkp1).
+// x forward of f = D u* / gdt built from the face velocities u, v (nz, ny,
+// nx) and w (nz-1, ny, nx); rdzf[k] = 1/dzf[k], idx = nx/lx, idy = ny/ly,
+// igdt = 1/gdt. A non-null stash receives f (real space, float64). Line sums
+// always (sums must not be null).
+struct DivArgs {
+  const double *u, *v, *w, *rdzf;
+  double idx, idy, igdt;
+  double *stash;
+};
+template <typename T>
+hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
+                           const cplx<double> *tw, double *sums, hipStream_t st);
+// u -= gx (phi[i+1] - phi[i]), v -= gy (phi[j+1] - phi[j]), w -= gdt rdzc[k]
+// (phi[k+1] - phi[k]) (gx = gdt/dx, gy = gdt/dy), p += phi - c L_z phi with
+// the Neumann rows zal, zga.
+hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
+                          double *w, double *p, const double *zal, const double *zga,
+                          const double *rdzc, double gx, double gy, double gdt, double c,
+                          hipStream_t st);
+
 // Poisson z solve on the doubly packed spectrum (in place), float64
 // elimination in registers; the (0,0) slot column is set to zero. `variant`
 // indexes a table of launch shapes (rows per thread, columns per workgroup,

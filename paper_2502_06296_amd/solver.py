@@ -96,6 +96,21 @@ def poisson_solve(plan, rhs, p):
     return p
 
 
+def poisson_project(plan, u, v, w, p, phi, gdt, c=0.0):
+    """Pressure projection: L7 phi = D u* / gdt, u <- u* - gdt G phi, p <- p +
+    phi - c L_z phi. u, v, p, phi: float64 (nz, ny, nx); w: float64 (nz-1,
+    ny, nx) on the interior z faces. u, v, w, p are updated in place; phi
+    receives the correction pressure."""
+    import torch
+    nz, ny, nx = plan.shape
+    for t in (u, v, p, phi):
+        _check_field(t, plan.shape, torch.float64)
+    _check_field(w, (nz - 1, ny, nx), torch.float64)
+    N.check(N.lib().poisson_project(plan.handle, _ptr(u), _ptr(v), _ptr(w), _ptr(p), _ptr(phi),
+                                    float(gdt), float(c)))
+    return phi
+
+
 def poisson_solve_batched(plans, rhs, p):
     import torch
     n = len(plans)

@@ -84,6 +84,7 @@ def test_plan_rejects_non_monotone_faces():
 def test_null_arguments():
     L = N.lib()
     assert L.poisson_solve(None, None, None) == N.PF_ERR_ARG
+    assert L.poisson_project(None, None, None, None, None, None, 1.0, 0.0) == N.PF_ERR_ARG
     assert L.pcr_apply(None, None, 64, 64) == N.PF_ERR_ARG
     assert L.poisson_set_workspace(None, None, 0) == N.PF_ERR_ARG
     assert L.pf_graph_begin(None) == N.PF_ERR_ARG
