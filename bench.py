@@ -46,6 +46,17 @@ BYTES_PER_POINT = {
 }
 
 
+# the coupled step (divergence right-hand side, projection correction): the
+# first x pass reads u, v, w instead of f (and, refined, stashes f for the
+# residual); the correction reads phi, u, v, w, p and writes u, v, w, p
+COUPLED_BYTES = {
+    "fp32_refine": {"xfwd": 24 + 4 + 8, "project": 8 + 32 + 32},
+    "fp64": {"xfwd": 24 + 8, "project": 8 + 32 + 32},
+}
+GDT = 1e-4                      # gamma_k * dt of the projection
+C_IMPL = S_HELM                 # gamma_k * nu * dt / 2: implicit z diffusion
+
+
 def sources_hash():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -87,6 +98,36 @@ class Step:
         t = self.pf.poisson_timing_read(self.poisson)
         t.update(self.pf.pcr_timing_read(self.pcr[0]))
         return t
+
+
+class CoupledStep:
+    """One Runge-Kutta substep's implicit part on real fields: the three
+    z-implicit Helmholtz solves of (u, v, w) (u, v on the x and y faces at
+    cell-centre heights, w on the interior z faces), then the pressure
+    projection of the result (divergence right-hand side, Poisson solve,
+    face-gradient correction, pressure update with the implicit-diffusion
+    term)."""
+
+    def __init__(self, pf, torch, dev, prec, r3):
+        self.pf, self.torch, self.prec = pf, torch, prec
+        self.stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(self.stream):
+            self.poisson = pf.poisson_plan(NX, NY, NZ, LX, LY, LZ, BETA, precision=prec, n_refine=1,
+                                           stream=self.stream, device=dev)
+            self.pcr = []
+            for bc in ("dirichlet_centre", "dirichlet_centre", "dirichlet_face"):
+                al, ga, ex = pf.zop_rows(NZ, bc, LZ, BETA)
+                self.pcr.append(pf.pcr_prepare(al, ga, ex, S_HELM, precision=prec, stream=self.stream))
+            self.vel = [r.clone() for r in r3]
+            self.p = torch.zeros_like(r3[0])
+            self.phi = torch.empty_like(r3[0])
+
+    def run(self):
+        self.pf.pcr_apply_batched(self.pcr, self.vel)
+        self.pf.poisson_project(self.poisson, *self.vel, self.p, self.phi, GDT, C_IMPL)
+
+    timing = Step.timing
+    read_timing = Step.read_timing
 
 
 def time_steps(step, steps, warmup):
@@ -212,6 +253,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -294,6 +336,31 @@ def main():
                         "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in r64["stages"].items()},
                         "roofline": roofline("fp64", r64["stages"], traffic)}
         line["speedup_fp32_refine_vs_fp64"] = round(r64["ms"] / main["ms"], 4)
+    if not args.no_coupled:
+        # free the headline steps' buffers first
+        for r in results.values():
+            r.pop("step", None)
+        outs.clear()
+        torch.cuda.empty_cache()
+        coupled = {}
+        for prec in (["fp32_refine"] if args.no_fp64 else ["fp32_refine", "fp64"]):
+            log(f"bench: coupled step {prec}")
+            cs = CoupledStep(pf, torch, dev, prec, r3)
+            ms, _, stages = time_steps(cs, args.steps, args.warmup)
+            per = {k: round(v[0] / v[1], 4) for k, v in stages.items()}
+            pj = per.get("project")
+            coupled[prec] = {"ms_per_step": round(ms, 4),
+                             "gpoints_per_s": round(npts / (ms * 1e-3) / 1e9, 3),
+                             "stages_ms_per_launch": per,
+                             "project_gbs": round(COUPLED_BYTES[prec]["project"] * npts / (pj * 1e-3) / 1e9, 1)
+                             if pj else None,
+                             "xfwd_div_gbs": round(COUPLED_BYTES[prec]["xfwd"] * npts / (per["xfwd"] * 1e-3) / 1e9, 1)}
+            del cs
+            torch.cuda.empty_cache()
+        line["coupled_step"] = {"workload": "3 z-Helmholtz of (u, v, w) then poisson_project: divergence "
+                                            "right-hand side, Poisson, face-gradient correction, pressure "
+                                            f"update (gamma dt = {GDT}, c = {C_IMPL:.4g}), same grid",
+                                **coupled}
     if not args.no_cpu_baseline:
         log("bench: oracle cpu baseline")
         line["cpu_baseline"] = cpu_baseline()
