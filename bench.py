@@ -246,6 +246,45 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}))
 
 
+def weak_share(args):
+    """The paper's per-GPU share of its weak-scaling runs (Sec. 3.1),
+    3456 x 3072 x 30: the headline step (3 Helmholtz + Poisson) in both
+    precisions, and the Helmholtz apply with 1, 2 and 4 chunks per column
+    (one chunk is a plain elimination; more chunks add the reduced system)."""
+    global NX, NY, NZ
+    NX, NY, NZ = 3456, 3072, 30
+    import torch
+    import paper_2502_06296_amd as pf
+    from paper_2502_06296_amd import autotune
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g = torch.Generator(device=dev).manual_seed(3)
+    f = torch.rand((NZ, NY, NX), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+    f -= f.mean()
+    r3 = [torch.randn((NZ if c < 2 else NZ - 1, NY, NX), dtype=torch.float64, device=dev, generator=g)
+          for c in range(3)]
+    npts = NX * NY * NZ
+    out = {"workload": f"weak-scaling share {NX}x{NY}x{NZ}, tanh 1.5: 3 z-Helmholtz + pressure Poisson",
+           "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
+    for prec in ("fp32_refine", "fp64"):
+        log(f"weak share: {prec}")
+        st = Step(pf, torch, dev, prec, f, r3)
+        ms, _, stages = time_steps(st, args.steps, args.warmup)
+        entry = {"value": round(npts / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
+                 "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in stages.items()}}
+        chunking = {}
+        for rows in (32, 16, 8):
+            if not autotune.set_pcr_shape(st.pcr, rows, 64):
+                continue
+            ms_c, _, stg = time_steps(st, args.steps, 1)
+            chunking[f"chunk_rows_{rows}_P{(NZ + rows - 1) // rows}"] = round(stg["pcr_apply"][0] / stg["pcr_apply"][1], 4)
+        entry["pcr_apply_ms_by_chunking"] = chunking
+        out[prec] = entry
+        del st
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +294,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0)
+    ap.add_argument("--workload", choices=["channel", "weak_share"], default="channel",
+                    help="channel: 1024x512x512 (the headline); weak_share: the paper's per-GPU "
+                         "weak-scaling share 3456x3072x30")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
@@ -262,6 +304,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "weak_share":
+        weak_share(args)
         return
 
     import numpy as np

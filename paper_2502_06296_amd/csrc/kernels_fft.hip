@@ -30,6 +30,17 @@ bool fft_size_supported(int n) {
   }
 }
 
+bool fft_size_supported_y(int n) {
+  switch (n) {
+#define PF_CASE(N) case N:
+    PF_FOR_FFT_SIZES_Y(PF_CASE)
+#undef PF_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
 // pairs of storage values (two adjacent slots) as float64
 template <typename T>
 __device__ __forceinline__ cplx<double> ld2(const T *p) {
@@ -555,7 +566,7 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
                        dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
     return hipGetLastError();                                                                 \
   }
-    PF_FOR_FFT_SIZES(PF_CASE)
+    PF_FOR_FFT_SIZES_Y(PF_CASE)
 #undef PF_CASE
     default:
       return hipErrorInvalidValue;
@@ -575,7 +586,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
                        dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
     return hipGetLastError();                                                                 \
   }
-    PF_FOR_FFT_SIZES(PF_CASE)
+    PF_FOR_FFT_SIZES_Y(PF_CASE)
 #undef PF_CASE
     default:
       return hipErrorInvalidValue;

@@ -549,6 +549,9 @@ static const ZVariant kZVariants[] = {
     {8, 8, 4, true, true, 1, false, true},   {8, 16, 4, true, true, 1, false, true},
     {16, 16, 0, true, true, 1, false, true}, {16, 32, 0, true, true, 1, false, true},
     {8, 32, 4, true, true, 1, false, true},
+    // wide separator shapes for short columns (few chunks per column)
+    {8, 64, 4, true, true, 1, false, true},  {8, 128, 4, true, true, 1, false, true},
+    {16, 64, 1, true, true, 1, false, true}, {16, 128, 1, true, true, 1, false, true},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
@@ -579,9 +582,20 @@ int zsolve_default_variant(int nx, int nz, bool fp64) {
   // planes) 18 (0.86 ms: separator form, 8 rows, 8 columns), 19 (0.87), 16
   // (0.95); the unpaired 4 and 3 as fall-backs where the LDS or thread
   // budget excludes the paired shapes
-  static const int f64[] = {21, 10, 19, 8, 4, 3}, f32[] = {18, 19, 16, 13, 8, 4, 3};
+  // fall-backs. Short columns (few chunks) would leave those shapes with
+  // tiny workgroups, so the first fitting shape with at least 128 threads
+  // wins, widened by the 64- and 128-column shapes.
+  static const int f64[] = {21, 10, 19, 26, 25, 24, 23, 8, 4, 3},
+                   f32[] = {18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
   const int *list = fp64 ? f64 : f32;
   const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
+  auto threads = [&](int v) {
+    const ZVariant &z = kZVariants[v];
+    const int P = (nz + z.M - 1) / z.M;
+    return z.paired ? P * z.TI / 2 : P * z.TI;
+  };
+  for (int k = 0; k < len; ++k)
+    if (zsolve_variant_fits(list[k], nx, nz) && threads(list[k]) >= 128) return list[k];
   for (int k = 0; k < len; ++k)
     if (zsolve_variant_fits(list[k], nx, nz)) return list[k];
   return -1;
@@ -636,6 +650,10 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
     PF_ZS(20, 16, 16, 1)
     PF_ZS(21, 16, 32, 1)
     PF_ZS(22, 8, 32, 4)
+    PF_ZS(23, 8, 64, 4)
+    PF_ZS(24, 8, 128, 4)
+    PF_ZS(25, 16, 64, 1)
+    PF_ZS(26, 16, 128, 1)
 #undef PF_ZS
 #undef PF_ZP
     default:

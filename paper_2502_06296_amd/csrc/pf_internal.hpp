@@ -19,10 +19,16 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return (b % kXcd) * (nb / kXcd) + b / kXcd;
 }
 
-// Transform lengths instantiated for the x and y directions.
-#define PF_FOR_FFT_SIZES(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+// Transform lengths instantiated for the x and y directions: even 2^a 3^b
+// up to 2048, and the lengths of the paper's per-GPU weak-scaling share,
+// 3456 x 3072 (x: 3072 and 3456; y: 3072).
+#define PF_FOR_FFT_SIZES_COMMON(X) \
+  X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072)
+#define PF_FOR_FFT_SIZES(X) PF_FOR_FFT_SIZES_COMMON(X) X(3456)
+#define PF_FOR_FFT_SIZES_Y(X) PF_FOR_FFT_SIZES_COMMON(X)
 
-bool fft_size_supported(int n);
+bool fft_size_supported(int n);    // x direction
+bool fft_size_supported_y(int n);  // y direction
 
 // Padding (elements) between the z planes of a float32 spectrum work array.
 constexpr size_t kPlanePad = 64;
@@ -41,7 +47,11 @@ constexpr int x_lpw(int n) {
   while (v * 2 <= by_threads && v * 2 <= by_lds) v *= 2;
   return v;
 }
-constexpr int y_tpl(int n) { return n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16); }
+constexpr int y_tpl(int n) {
+  int t = n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16);
+  while (t > 8 && n % (2 * t)) t /= 2;  // every thread takes pairs of positions
+  return t;
+}
 // LDS stride (complex elements) between the lines of a y workgroup: 2 mod 16,
 // so that the load and store phases, whose lanes run over the lines first,
 // put the 16 lanes of one 128-bit LDS access in different banks.

@@ -150,6 +150,52 @@ def test_poisson_1024x512x512_fp64_residual_and_fp32_refine():
 
 
 @pytest.mark.gpu
+def test_weak_scaling_share_3456x3072x30():
+    """The paper's per-GPU share of its weak-scaling runs (Sec. 3.1):
+    Poisson in both precisions and the three Helmholtz components with one
+    chunk (plain Thomas-like elimination) and with four chunks."""
+    dev = torch.device("cuda", 0)
+    nx, ny, nz = 3456, 3072, 30
+    print(f"poisson {nx}x{ny}x{nz}", flush=True)
+    zf = synth.tanh_faces(nz, LZ, BETA)
+    f = _project(_uniform((nz, ny, nx), 111, dev), zf)
+    p64 = torch.empty_like(f)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, BETA, precision="fp64")
+    pf.poisson_solve(plan, f, p64)
+    torch.cuda.synchronize()
+    res = _poisson_residual(p64, f, zf)
+    print(f"fp64 residual {res:.2e}", flush=True)
+    assert res < 1e-12
+    del plan
+    p32 = torch.empty_like(f)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, BETA, precision="fp32_refine")
+    pf.poisson_solve(plan, f, p32)
+    torch.cuda.synchronize()
+    err = _rel(p32, p64)
+    print(f"fp32_refine vs fp64 {err:.2e}", flush=True)
+    assert err < 1e-10
+    del plan, p32, p64, f
+    torch.cuda.empty_cache()
+    bcs = ("dirichlet_centre", "dirichlet_centre", "dirichlet_face")
+    obc = (ogrid.DIRICHLET_CENTRE, ogrid.DIRICHLET_CENTRE, ogrid.DIRICHLET_FACE)
+    r3 = [_normal((nz if c < 2 else nz - 1, ny, nx), 210 + c, dev) for c in range(3)]
+    for prec, bar in (("fp64", 1e-13), ("fp32_refine", 2e-10)):
+        for rows in (32, 8):
+            plans = []
+            for bc in bcs:
+                al, ga, ex = pf.zop_rows(nz, bc, LZ, BETA)
+                plans.append(pf.pcr_prepare(al, ga, ex, S_C3, precision=prec, chunk_rows=rows))
+            u = [r.clone() for r in r3]
+            pf.pcr_apply_batched(plans, u)
+            torch.cuda.synchronize()
+            for c in range(3):
+                res = _helmholtz_residual(u[c], r3[c], zf, S_C3, obc[c])
+                print(f"helmholtz {prec} chunk_rows {rows} component {c}: residual {res:.2e}", flush=True)
+                assert res < bar
+            del u, plans
+
+
+@pytest.mark.gpu
 def test_helmholtz_1024x1024x512_three_components():
     dev = torch.device("cuda", 0)
     nx, ny, nz = 1024, 1024, 512

@@ -50,6 +50,9 @@ POISSON_SHAPES = [
     (1536, 128, 17, 1.8, 8),
     (128, 1024, 4, 1.5, 9),     # smallest nz
     (64, 64, 1024, 1.5, 10),    # largest nz: the z solve falls back to a shape that fits the LDS
+    (3456, 64, 30, 1.5, 11),    # the weak-scaling share's lengths: x = 3456 (2^7 3^3)
+    (3072, 64, 30, 1.5, 12),    # x = 3072
+    (64, 3072, 30, 1.5, 13),    # y = 3072
 ]
 
 
@@ -122,6 +125,7 @@ HELM_CASES = [
     (64, 16, 512, ogrid.DIRICHLET_FACE),       # 511 unknowns
     (128, 4, 1000, ogrid.DIRICHLET_CENTRE),    # more than 16 chunks: 32-column layout
     (64, 2, 5, ogrid.DIRICHLET_CENTRE),        # 5 unknowns, one chunk
+    (3456, 2, 30, ogrid.DIRICHLET_FACE),       # the weak-scaling share's x length and nz
 ]
 
 
