@@ -21,6 +21,10 @@ def _pin_errors():
         r = synth.normal01(2, (n, 3))
         errs.append(poisson.rel_l2(poisson.solve_helmholtz(r, zf, 1e-2, bc),
                                    dense.helmholtz_dense(r, zf, 1e-2, bc)))
+    zf5 = synth.tanh_faces(5, 2.0, 1.5)
+    r = synth.normal01(5, (4, 4, 6))                   # w faces: 4 unknowns per column
+    errs.append(poisson.rel_l2(poisson.solve_helmholtz3d(r, zf5, 0.2, grid.DIRICHLET_FACE, LX, LY),
+                               dense.helmholtz3d_dense(r, zf5, 0.2, grid.DIRICHLET_FACE, LX, LY)))
     for n in (6, 7):
         x = synth.uniform_pm1(n, (n,))
         X = transforms.dft_direct(x)
