@@ -143,6 +143,29 @@ pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans,
 pf_status poisson_set_stream(pf_poisson_plan *plan, void *stream);
 pf_status poisson_destroy(pf_poisson_plan *plan);
 
+/* ------------------------------------------------- 3-D Helmholtz
+ * The fully implicit diffusion of a Runge-Kutta substep (paper Sec. 2.1,
+ * eq. proj2_ustar): u with (I - s L) u = r, L the 3-D second-order operator
+ * of the staggered grid, periodic in x and y, with the Dirichlet z rows of
+ * family bc (PF_BC_DIRICHLET_CENTRE: nz unknowns per column, u and v;
+ * PF_BC_DIRICHLET_FACE: nz-1, w), s = gamma_k nu dt / 2 > 0. The solver is
+ * the Poisson machinery (packed transforms in x and y, one z system per
+ * slot pair) with the diagonal of every mode shifted by 1/s; no mode is
+ * singular. helmholtz3d_plan takes the grid, precision, n_refine, stream
+ * and workspace rules of poisson_plan (the workspace is sized by the n =
+ * nz or nz-1 planes of the field); the plan is destroyed with
+ * poisson_destroy and takes poisson_set_workspace, poisson_set_stream and
+ * the stage timers. helmholtz3d_solve: r and u device (n, ny, nx) float64,
+ * u must not overlap r or the workspace. helmholtz3d_update changes s for
+ * the next substep (host recompute, upload enqueued on the plan's stream).
+ * Errors as poisson_solve; a Helmholtz plan is refused by poisson_solve and
+ * poisson_project, and a Poisson plan by helmholtz3d_solve. */
+pf_status helmholtz3d_plan(pf_poisson_plan **out, const pf_grid *g, int32_t bc, double s,
+                           int32_t precision, int32_t n_refine, void *stream,
+                           size_t *workspace_bytes);
+pf_status helmholtz3d_solve(pf_poisson_plan *plan, const double *r, double *u);
+pf_status helmholtz3d_update(pf_poisson_plan *plan, double s);
+
 /* ---------------------------------------------------------- Helmholtz
  * pcr_prepare (Algorithm 2, Step 1): host arrays alpha, gamma, excess of
  * length n in the form of pf_zop_rows describe -L_z; the plan solves

@@ -8,7 +8,8 @@ importing this package does not load it, the first call does (and fails
 loudly if it is missing).
 """
 from .solver import (  # noqa: F401
-    BCS, PRECISIONS, Graph, PcrPlan, PoissonPlan, grid_faces, pcr_apply, pcr_apply_batched,
+    BCS, PRECISIONS, Graph, PcrPlan, PoissonPlan, grid_faces, helmholtz3d_plan, helmholtz3d_solve,
+    helmholtz3d_update, pcr_apply, pcr_apply_batched,
     pcr_prepare, pcr_set_stream, pcr_timing, pcr_timing_read, pcr_update_coef, pf_copy_kernel,
     pf_graph_begin, pf_graph_end, poisson_plan, poisson_project, poisson_set_stream,
     poisson_solve, poisson_solve_batched, poisson_timing, poisson_timing_read, run_batched, zop_rows)

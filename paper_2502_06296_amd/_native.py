@@ -23,6 +23,7 @@ PF_STAGE_COUNT = len(STAGES)
 EXPORTS = [
     "pf_last_error", "pf_abi_version", "pf_zop_rows", "pf_grid_faces",
     "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_project", "poisson_solve_batched",
+    "helmholtz3d_plan", "helmholtz3d_solve", "helmholtz3d_update",
     "poisson_set_stream", "poisson_destroy",
     "pcr_prepare", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
     "pcr_destroy",
@@ -76,6 +77,10 @@ def lib():
             "poisson_set_workspace": (i32, [vp, vp, sz]),
             "poisson_solve": (i32, [vp, vp, vp]),
             "poisson_project": (i32, [vp, vp, vp, vp, vp, vp, C.c_double, C.c_double]),
+            "helmholtz3d_plan": (i32, [C.POINTER(vp), C.POINTER(PfGrid), i32, C.c_double, i32, i32, vp,
+                                       C.POINTER(sz)]),
+            "helmholtz3d_solve": (i32, [vp, vp, vp]),
+            "helmholtz3d_update": (i32, [vp, C.c_double]),
             "poisson_solve_batched": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
             "poisson_set_stream": (i32, [vp, vp]),
             "poisson_destroy": (i32, [vp]),

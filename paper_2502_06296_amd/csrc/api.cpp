@@ -222,8 +222,11 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 // ====================================================================== plans
 struct pf_poisson_plan {
-  int nx, ny, nz;
+  int nx, ny, nz;  // nz: planes of the field (nz - 1 for a face-centred Helmholtz)
   double lx, ly;
+  int bc = PF_BC_NEUMANN;  // NEUMANN: pressure Poisson; DIRICHLET_*: 3-D Helmholtz
+  double kappa = 0.0;      // 1/s of the 3-D Helmholtz, folded into the sx table
+  std::vector<double> sx_host;  // modified wavenumbers of the x slots without kappa
   int prec, nref;
   hipStream_t st;
   int zchunk;
@@ -445,8 +448,13 @@ pf_status pf_zop_rows(const pf_grid *g, int32_t bc, double *alpha, double *gamma
   return PF_OK;
 }
 
-pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision, int32_t n_refine,
-                       void *stream, size_t *workspace_bytes) {
+// The pressure Poisson plan (bc NEUMANN, s = 0) and the 3-D Helmholtz plan
+// (bc DIRICHLET_CENTRE or _FACE, s > 0) share the machinery: the Helmholtz
+// per mode is the same z system with its Dirichlet rows and 1/s added to
+// the shift, and has no singular column.
+static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision,
+                              int32_t n_refine, void *stream, size_t *workspace_bytes, int bc,
+                              double hs) {
   if (!out) return fail(PF_ERR_ARG, "out is NULL");
   *out = nullptr;
   pf_status s = check_grid(g, true);
@@ -455,26 +463,29 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
     return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
   if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
-  int zc = pf::zsolve_default_variant(g->nx, g->nz, precision == PF_FP64);
+  const int nzu = bc == PF_BC_DIRICHLET_FACE ? g->nz - 1 : g->nz;  // planes of the field
+  int zc = pf::zsolve_default_variant(g->nx, nzu, precision == PF_FP64);
   if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
     const int v = std::atoi(ev);
-    if (pf::zsolve_variant_fits(v, g->nx, g->nz)) zc = v;
+    if (pf::zsolve_variant_fits(v, g->nx, nzu)) zc = v;
   }
-  if (zc < 0) return fail(PF_ERR_UNSUPPORTED, "no z-solve shape fits nx=%d nz=%d", g->nx, g->nz);
+  if (zc < 0) return fail(PF_ERR_UNSUPPORTED, "no z-solve shape fits nx=%d nz=%d", g->nx, nzu);
   auto *pl = new pf_poisson_plan();
-  pl->nx = g->nx; pl->ny = g->ny; pl->nz = g->nz;
+  pl->nx = g->nx; pl->ny = g->ny; pl->nz = nzu;
   pl->lx = g->lx; pl->ly = g->ly;
+  pl->bc = bc;
+  pl->kappa = bc == PF_BC_NEUMANN ? 0.0 : 1.0 / hs;
   pl->prec = precision;
   pl->nref = precision == PF_FP32_REFINE ? n_refine : 0;
   if (precision == PF_FP32_REFINE && n_refine == 0) pl->prec = PF_FP32;
   pl->st = (hipStream_t)stream;
   pl->zchunk = zc;
   std::vector<double> zf = faces_of(g), al, ga, ex;
-  zrows(zf, PF_BC_NEUMANN, al, ga, ex);
+  zrows(zf, bc, al, ga, ex);
   // identity rows pad the z tables to whole chunks
-  al.resize(zpad(g->nz), 0.0);
-  ga.resize(zpad(g->nz), 0.0);
-  ex.resize(zpad(g->nz), 1.0);
+  al.resize(zpad(nzu), 0.0);
+  ga.resize(zpad(nzu), 0.0);
+  ex.resize(zpad(nzu), 1.0);
   std::vector<double> dzf(g->nz), rdzf(g->nz), rdzc(g->nz - 1);
   for (int k = 0; k < g->nz; ++k) dzf[k] = zf[k + 1] - zf[k];
   // the projection's metrics: 1/dzf per cell, 1/dzc per interior face
@@ -483,6 +494,8 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   // y: the packed slots of x slots 0 and 1, then the complex modes 0..ny-1
   // of every other slot pair
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
+  pl->sx_host = sx;
+  for (double &v : sx) v += pl->kappa;
   {
     const double dy = g->ly / g->ny;
     for (int m = 0; m < g->ny; ++m) {
@@ -500,12 +513,13 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->o_sy = A.add(sy.data(), sy.size());
   pl->o_twx_d = A.add(twxd.data(), twxd.size());
   pl->o_twy_d = A.add(twyd.data(), twyd.size());
-  pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * g->nz);
-  pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * g->nz);
-  pl->o_fbar = A.add<double>(nullptr, (size_t)g->nz);
-  pl->o_m = A.add<double>(nullptr, (size_t)g->nz);
-  pl->o_zm = A.add<double>(nullptr, (size_t)g->nz);
-  pl->o_p0m = A.add<double>(nullptr, (size_t)g->nz);
+  // per-plane buffers; fbar and zm stay zero for the Helmholtz (no zero mode)
+  pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * nzu);
+  pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * nzu);
+  pl->o_fbar = A.add<double>(nullptr, (size_t)nzu);
+  pl->o_m = A.add<double>(nullptr, (size_t)nzu);
+  pl->o_zm = A.add<double>(nullptr, (size_t)nzu);
+  pl->o_p0m = A.add<double>(nullptr, (size_t)nzu);
   pl->o_rdzf = A.add(rdzf.data(), rdzf.size());
   pl->o_rdzc = A.add(rdzc.data(), rdzc.size());
   A.cap = A.used;
@@ -523,6 +537,32 @@ pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precisio
   pl->ws_need = pl->prec == PF_FP64 ? 0 : (pl->prec == PF_FP32 ? 4 * S : 8 * S);
   if (workspace_bytes) *workspace_bytes = pl->ws_need;
   *out = pl;
+  return PF_OK;
+}
+
+pf_status poisson_plan(pf_poisson_plan **out, const pf_grid *g, int32_t precision, int32_t n_refine,
+                       void *stream, size_t *workspace_bytes) {
+  return channel_plan(out, g, precision, n_refine, stream, workspace_bytes, PF_BC_NEUMANN, 0.0);
+}
+
+pf_status helmholtz3d_plan(pf_poisson_plan **out, const pf_grid *g, int32_t bc, double s, int32_t precision,
+                           int32_t n_refine, void *stream, size_t *workspace_bytes) {
+  if (out) *out = nullptr;
+  if (bc != PF_BC_DIRICHLET_CENTRE && bc != PF_BC_DIRICHLET_FACE)
+    return fail(PF_ERR_ARG, "bc must be PF_BC_DIRICHLET_CENTRE or PF_BC_DIRICHLET_FACE (got %d)", bc);
+  if (!(s > 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and > 0");
+  return channel_plan(out, g, precision, n_refine, stream, workspace_bytes, bc, s);
+}
+
+pf_status helmholtz3d_update(pf_poisson_plan *pl, double s) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (pl->bc == PF_BC_NEUMANN) return fail(PF_ERR_ARG, "not a Helmholtz plan");
+  if (!(s > 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and > 0");
+  pl->kappa = 1.0 / s;
+  double *h = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_sx);
+  for (size_t i = 0; i < pl->sx_host.size(); ++i) h[i] = pl->sx_host[i] + pl->kappa;
+  PF_HIP(hipMemcpyAsync(pl->ar.base + pl->o_sx, h, pl->sx_host.size() * sizeof(double),
+                        hipMemcpyHostToDevice, pl->st));
   return PF_OK;
 }
 
@@ -572,6 +612,10 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   double *fbar = A.at<double>(pl->o_fbar), *mm = A.at<double>(pl->o_m), *zm = A.at<double>(pl->o_zm);
   Timing &tm = pl->tm;
   pf_status s;
+  // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
+  // and the chain solves (L - kappa) u' = r, so u = -kappa u'
+  const bool helm = pl->bc != PF_BC_NEUMANN;
+  const double oscale = helm ? -pl->kappa * scale : scale;
 #define STAGE(id, expr)                                      \
   if ((s = run_stage(tm, st, id, [&]() { return (expr); }))) \
     return s;
@@ -581,11 +625,12 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
     const size_t sd = (size_t)nx * ny;
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
                              : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
-    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
+    if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
     STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, st));
-    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, mm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, helm ? zm : mm, nullptr, oscale,
+                                                          lines, st)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
@@ -594,11 +639,12 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
                              : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
-    STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
+    if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
     STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
     STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
-    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, mm, nullptr, scale, lines, st)));
+    STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, helm ? zm : mm, nullptr,
+                                                               oscale, lines, st)));
     return PF_OK;
   }
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
@@ -615,17 +661,18 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   } else {
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
   }
-  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
+  if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
   const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
-  STAGE(PF_STAGE_XFWD_RESID, pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, idy2, st));
-  STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
+  STAGE(PF_STAGE_XFWD_RESID,
+        pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2, st));
+  if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
-  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, scale, lines, st)));
+  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st)));
 #undef STAGE
   return PF_OK;
 }
@@ -633,12 +680,21 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
 pf_status poisson_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
   pf_status s = poisson_check_solve(pl, rhs, p);
   if (s) return s;
+  if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "a 3-D Helmholtz plan: use helmholtz3d_solve");
   return poisson_enqueue(pl, rhs, p, pl->st);
+}
+
+pf_status helmholtz3d_solve(pf_poisson_plan *pl, const double *r, double *u) {
+  pf_status s = poisson_check_solve(pl, r, u);
+  if (s) return s;
+  if (pl->bc == PF_BC_NEUMANN) return fail(PF_ERR_ARG, "a Poisson plan: use poisson_solve");
+  return poisson_enqueue(pl, r, u, pl->st);
 }
 
 pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, double *p, double *phi,
                           double gdt, double c) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "poisson_project needs a Poisson plan");
   if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
   if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");

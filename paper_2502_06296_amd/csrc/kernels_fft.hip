@@ -260,7 +260,9 @@ hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, 
 // right-hand side is formed without going back to real space:
 //   R = X(f) - nx fbar[k] e_0 - (1/ny) L7^ W,
 //   L7^ W = -sx[s] W + (W[j-1] - 2 W + W[j+1]) / dy^2
-//           + alpha_k W[k-1] + gamma_k W[k+1] - (alpha_k + gamma_k) W,
+//           + alpha_k W[k-1] + gamma_k W[k+1] - (alpha_k + gamma_k + eps_k) W,
+// (eps_k = 0 for the pressure rows; the 3-D Helmholtz passes its wall excess,
+// 1/s folded into sx, and fbar = 0),
 // slot by slot of the packed layout: the periodic x second difference is
 // -sx[s] (its eigenvalue, the modified wavenumber of the slot) on each
 // packed slot, and the y and z parts act on every slot alike. X(f) is the
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ sx, const double *__restrict__ zal, const double *__restrict__ zga,
-    int ny, int nz, double idy2, double inv_ny, size_t sp) {
+    const double *__restrict__ zex, int ny, int nz, double idy2, double inv_ny, size_t sp) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     auto src = [&](int i) { return mkc<double>(fa[i], fb[i]); };
     fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
   }
-  const double ak = zal[k], gk = zga[k], dk = ak + gk, fk = (double)N * fbar[k];
+  const double ak = zal[k], gk = zga[k], dk = ak + gk + zex[k], fk = (double)N * fbar[k];
   const bool lo = k > 0, hi = k < nz - 1;
   const int jm = j == 0 ? ny - 1 : j - 1, jp2 = j + 2 == ny ? 0 : j + 2;
   const float *Wk = W + (size_t)k * sp;
@@ -535,7 +537,7 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
-                             const double *zga, double idy2, hipStream_t st) {
+                             const double *zga, const double *zex, double idy2, hipStream_t st) {
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
@@ -543,7 +545,8 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
     if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
     hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \
-                       st, f, fbar, W, out, tw, sums_p, sx, zal, zga, ny, nz, idy2, 1.0 / ny, sp); \
+                       st, f, fbar, W, out, tw, sums_p, sx, zal, zga, zex, ny, nz, idy2, 1.0 / ny,  \
+                       sp);                                                                      \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)

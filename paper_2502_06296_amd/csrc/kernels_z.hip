@@ -69,8 +69,11 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve(TS *__restrict__ data, in
   const int r0 = ch * M;
   const size_t plane = sp;
   TS *cp = data + (size_t)j * nx + i + (size_t)r0 * plane;
-  const bool zero_col = (i == 0 && j == 0);
-  const double lam = zero_col ? 1.0 : sx[i] + sy[(i >= 2 ? ny : 0) + j];
+  // the singular column is the one with no shift at all (Poisson's (0,0);
+  // the 3-D Helmholtz has 1/s in every entry of sx)
+  const double lam0 = sx[i] + sy[(i >= 2 ? ny : 0) + j];
+  const bool zero_col = lam0 == 0.0;
+  const double lam = zero_col ? 1.0 : lam0;
   const double *al = zal + r0, *ga = zga + r0, *ex = zex + r0;
 
   double d[M], ib_[M];
@@ -233,8 +236,9 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
     // pass 1 exists only for the pair of slots 0 and 1; other lanes redo
     // pass 0's work on already solved data and store nothing
     const int ci = i + pass;
-    const bool zero_col = (ci == 0 && j == 0);
-    const double lam = zero_col ? 1.0 : sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
+    const double lam0 = sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
+    const bool zero_col = lam0 == 0.0;  // Poisson's (0,0) only
+    const double lam = zero_col ? 1.0 : lam0;
     // pass 0 stores both columns of every pair except column 1 of the pair
     // (0, 1); pass 1 stores only that column
     const bool st0 = pass == 0;
@@ -418,8 +422,9 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
   for (int pass = 0; pass < npass; ++pass) {
     // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1
     const int ci = i + pass;
-    const bool zero_col = (ci == 0 && j == 0);
-    const double lam = zero_col ? 1.0 : sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
+    const double lam0 = sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
+    const bool zero_col = lam0 == 0.0;  // Poisson's (0,0) only
+    const double lam = zero_col ? 1.0 : lam0;
     const bool st0 = pass == 0;
     const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
 

@@ -85,11 +85,12 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 // x spectrum of the float64 7-point residual of the plane-mean-free
 // problem, R = X(f - fbar[k]) - L7 of the iterate whose x spectrum (times ny)
 // is W (float32, after the y inverse); the x operator is -sx per packed
-// slot. Also the float64 line sums of the iterate. R is float32.
+// slot, the z rows (zal, zga, zex). Also the float64 line sums of the
+// iterate. R is float32.
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
-                             const double *zga, double idy2, hipStream_t st);
+                             const double *zga, const double *zex, double idy2, hipStream_t st);
 // y forward / inverse, in place on the packed (T) data.
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,

@@ -79,6 +79,40 @@ def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0,
     return plan
 
 
+def helmholtz3d_plan(nx, ny, nz, bc, s, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
+                     zf=None, precision="fp64", n_refine=1, stream=None, device=None):
+    """Plan the 3-D implicit Helmholtz (I - s L) u = r (bc "dirichlet_centre":
+    fields of nz planes; "dirichlet_face": nz - 1); allocates the workspace."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    b = BCS[bc] if isinstance(bc, str) else int(bc)
+    with torch.cuda.device(dev):
+        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf)
+        h = C.c_void_p()
+        ws = C.c_size_t(0)
+        N.check(N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), b, float(s), _prec(precision),
+                                         int(n_refine), N.stream_handle(stream), C.byref(ws)))
+        n = nz - 1 if b == N.PF_BC_DIRICHLET_FACE else nz
+        plan = PoissonPlan(h, (n, ny, nx), _prec(precision), stream, None)
+        if ws.value:
+            plan.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
+            N.check(N.lib().poisson_set_workspace(h, _ptr(plan.workspace), ws.value))
+    return plan
+
+
+def helmholtz3d_solve(plan, r, u):
+    """u <- (I - s L)^{-1} r (float64 device tensors of the plan's shape)."""
+    import torch
+    _check_field(r, plan.shape, torch.float64)
+    _check_field(u, plan.shape, torch.float64)
+    N.check(N.lib().helmholtz3d_solve(plan.handle, _ptr(r), _ptr(u)))
+    return u
+
+
+def helmholtz3d_update(plan, s):
+    N.check(N.lib().helmholtz3d_update(plan.handle, float(s)))
+
+
 def _check_field(t, shape, dtype):
     import torch
     if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():

@@ -93,6 +93,19 @@ def test_null_arguments():
     assert L.poisson_destroy(None) == N.PF_OK
 
 
+def test_helmholtz3d_plan_validates_before_any_device_call():
+    L = N.lib()
+    g, keep = N.make_grid(64, 64, 16, 2 * np.pi, np.pi, 2.0, 1.5, None)
+    h = C.c_void_p()
+    ws = C.c_size_t(0)
+    for bc, s in ((N.PF_BC_NEUMANN, 0.1), (7, 0.1), (N.PF_BC_DIRICHLET_CENTRE, 0.0),
+                  (N.PF_BC_DIRICHLET_FACE, -1.0), (N.PF_BC_DIRICHLET_FACE, float("inf"))):
+        assert L.helmholtz3d_plan(C.byref(h), C.byref(g), bc, s, 0, 1, None, C.byref(ws)) == N.PF_ERR_ARG
+        assert L.pf_last_error()
+    assert L.helmholtz3d_solve(None, None, None) == N.PF_ERR_ARG
+    assert L.helmholtz3d_update(None, 1.0) == N.PF_ERR_ARG
+
+
 def test_task_batch_validates_before_any_device_call():
     L = N.lib()
     tasks = (N.PfTask * 2)()
