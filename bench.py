@@ -402,6 +402,34 @@ def main():
                              "xfwd_div_gbs": round(COUPLED_BYTES[prec]["xfwd"] * npts / (per["xfwd"] * 1e-3) / 1e9, 1)}
             del cs
             torch.cuda.empty_cache()
+        # the fully implicit variant's Helmholtz (eq. proj2_ustar) of the
+        # three components, one 3-D solve each
+        h3 = {}
+        for prec in (["fp32_refine"] if args.no_fp64 else ["fp32_refine", "fp64"]):
+            log(f"bench: 3-D Helmholtz {prec}")
+            plans = [pf.helmholtz3d_plan(NX, NY, NZ, bc, S_HELM, LX, LY, LZ, BETA, precision=prec)
+                     for bc in ("dirichlet_centre", "dirichlet_centre", "dirichlet_face")]
+            outs3 = [torch.empty_like(r) for r in r3]
+
+            def run3():
+                for pl, r, o in zip(plans, r3, outs3):
+                    pf.helmholtz3d_solve(pl, r, o)
+            for _ in range(args.warmup):
+                run3()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.steps):
+                run3()
+            b.record()
+            torch.cuda.synchronize()
+            ms3 = a.elapsed_time(b) / args.steps
+            h3[prec] = {"ms_three_components": round(ms3, 4),
+                        "gpoints_per_s": round(stage_points("pcr_apply") / (ms3 * 1e-3) / 1e9, 3)}
+            del plans, outs3
+            torch.cuda.empty_cache()
+        line["helmholtz3d"] = {"workload": "(I - s L) u = r for u, v (centres) and w (faces), 3-D, "
+                                           "1024x512x512, s = 9.615e-9", **h3}
         line["coupled_step"] = {"workload": "3 z-Helmholtz of (u, v, w) then poisson_project: divergence "
                                             "right-hand side, Poisson, face-gradient correction, pressure "
                                             f"update (gamma dt = {GDT}, c = {C_IMPL:.4g}), same grid",

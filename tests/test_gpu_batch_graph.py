@@ -56,6 +56,7 @@ def _projection_setup(prec, nx=128, ny=64, nz=96, beta=1.5):
         rhs = torch.from_numpy(f).to(_dev())
         r3 = [torch.from_numpy(synth.normal01(20 + c, (nz if c < 2 else nz - 1, ny, nx))).to(_dev())
               for c in range(3)]
+    stream.synchronize()     # callers clone these on torch's current stream
     return pp, pcr, rhs, r3, stream
 
 
@@ -67,6 +68,7 @@ def test_graph_replay_equals_eager(prec):
     # eager reference
     ue = [r.clone() for r in r3]
     pe = torch.empty_like(rhs)
+    torch.cuda.synchronize()  # the clones ran on torch's current stream, not on `stream`
     with torch.cuda.stream(stream):
         pf.pcr_apply_batched(pcr, ue)
         pf.poisson_solve(pp, rhs, pe)
@@ -97,12 +99,14 @@ def test_coupled_step_graph_replays_equal_eager(prec):
     p0 = torch.from_numpy(synth.uniform_pm1(30, tuple(r3[0].shape))).to(_dev())
     ue = [r.clone() for r in r3]
     pe, phie = p0.clone(), torch.empty_like(p0)
+    torch.cuda.synchronize()  # the clones ran on torch's current stream, not on `stream`
     with torch.cuda.stream(stream):
         pf.pcr_apply_batched(pcr, ue)
         pf.poisson_project(pp, *ue, pe, phie, 0.3, 1e-3)
     stream.synchronize()
     u = [r.clone() for r in r3]
     p, phi = p0.clone(), torch.empty_like(p0)
+    torch.cuda.synchronize()
     pf.pf_graph_begin(stream)
     pf.pcr_apply_batched(pcr, u)
     pf.poisson_project(pp, *u, p, phi, 0.3, 1e-3)
@@ -142,6 +146,9 @@ def _fresh(items):
     for it in items:
         it["p"] = torch.full_like(it["rhs"], -1.0)
         it["fields"] = [r.clone() for r in it["r3"]]
+    # the copies ran on torch's current stream; the batch forks from another
+    # (non-blocking) stream, which does not wait for them by itself
+    torch.cuda.synchronize()
     return [dict(poisson=it["poisson"], rhs=it["rhs"], p=it["p"], pcr=it["pcr"], fields=it["fields"])
             for it in items]
 
@@ -158,6 +165,7 @@ def test_task_batch_on_lanes_equals_one_by_one():
         print(f"task {t}: {it['shape']}", flush=True)
         p = torch.empty_like(it["rhs"])
         u = [r.clone() for r in it["r3"]]
+        torch.cuda.synchronize()  # the clones ran on torch's current stream, not on `stream`
         with torch.cuda.stream(stream):
             pf.pcr_apply_batched(it["pcr"], u)
             pf.poisson_solve(it["poisson"], it["rhs"], p)
