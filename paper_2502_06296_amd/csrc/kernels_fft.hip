@@ -541,7 +541,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
-    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                                \
+    constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                        \
     if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
     hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \

@@ -47,6 +47,16 @@ constexpr int x_lpw(int n) {
   while (v * 2 <= by_threads && v * 2 <= by_lds) v *= 2;
   return v;
 }
+// the residual: twice the threads per line of the x transforms (its stencil
+// loads after the transform need the extra waves to hide their latency)
+constexpr int resid_tpl(int n) { return 2 * x_tpl(n) <= 256 && n % (2 * x_tpl(n)) == 0 ? 2 * x_tpl(n) : x_tpl(n); }
+constexpr int resid_lpw(int n) {
+  const int by_threads = 256 / resid_tpl(n) < 1 ? 1 : 256 / resid_tpl(n);
+  const int by_lds = 32768 / (n * 16);
+  int v = 1;
+  while (v * 2 <= by_threads && v * 2 <= by_lds) v *= 2;
+  return v;
+}
 constexpr int y_tpl(int n) {
   int t = n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16);
   while (t > 8 && n % (2 * t)) t /= 2;  // every thread takes pairs of positions
