@@ -58,7 +58,7 @@ constexpr int resid_lpw(int n) {
   return v;
 }
 constexpr int y_tpl(int n) {
-  int t = n / 16 < 8 ? 8 : (n / 16 > 128 ? 128 : n / 16);
+  int t = n / 8 < 8 ? 8 : (n / 8 > 256 ? 256 : n / 8);
   while (t > 8 && n % (2 * t)) t /= 2;  // every thread takes pairs of positions
   return t;
 }
