@@ -246,6 +246,65 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}))
 
 
+def uneven_batch(args):
+    """16 independent problems of uneven sizes (64-256 x 64-256 x 96-384, tanh
+    stretching drawn per problem), each a pressure Poisson solve and the
+    three Helmholtz fields, FP32+refine, run as one task batch on 1, 2, 4
+    and 8 internal streams, eager and replayed from one captured graph."""
+    import torch
+    import paper_2502_06296_amd as pf
+    import synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    shapes = synth.draw_uneven_batch(0, 16)
+    stream = torch.cuda.Stream(device=dev)
+    tasks, pts = [], 0
+    with torch.cuda.stream(stream):
+        for t, sh in enumerate(shapes):
+            nx, ny, nz, beta = sh["nx"], sh["ny"], sh["nz"], sh["beta"]
+            pts += nx * ny * nz
+            pp = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, beta, precision="fp32_refine", stream=stream,
+                                 device=dev)
+            g = torch.Generator(device=dev).manual_seed(t)
+            f = torch.rand((nz, ny, nx), generator=g, dtype=torch.float64, device=dev)
+            pcr, fl = [], []
+            for c, bc in enumerate(("dirichlet_centre", "dirichlet_centre", "dirichlet_face")):
+                al, ga, ex = pf.zop_rows(nz, bc, LZ, beta)
+                pcr.append(pf.pcr_prepare(al, ga, ex, S_HELM, precision="fp32_refine", stream=stream))
+                fl.append(torch.randn((nz if c < 2 else nz - 1, ny, nx), generator=g, dtype=torch.float64,
+                                      device=dev))
+            tasks.append(dict(poisson=pp, rhs=f, p=torch.empty_like(f), pcr=pcr, fields=fl))
+    stream.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for lanes in (1, 2, 4, 8):
+        for _ in range(args.warmup):
+            pf.run_batched(tasks, lanes=lanes, stream=stream)
+        stream.synchronize()
+        a.record(stream)
+        for _ in range(args.steps):
+            pf.run_batched(tasks, lanes=lanes, stream=stream)
+        b.record(stream)
+        stream.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        pf.pf_graph_begin(stream)
+        pf.run_batched(tasks, lanes=lanes, stream=stream)
+        gr = pf.pf_graph_end(stream)
+        gr.launch(stream)
+        stream.synchronize()
+        a.record(stream)
+        for _ in range(args.steps):
+            gr.launch(stream)
+        b.record(stream)
+        stream.synchronize()
+        gms = a.elapsed_time(b) / args.steps
+        rows.append({"lanes": lanes, "ms": round(ms, 3), "graph_ms": round(gms, 3),
+                     "gpoints_per_s": round(pts / ms / 1e6, 2), "graph_gpoints_per_s": round(pts / gms / 1e6, 2)})
+    print(json.dumps({"workload": f"16 uneven problems ({pts} points): Poisson + 3 Helmholtz each, FP32+refine",
+                      "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "by_lanes": rows}), flush=True)
+
+
 def weak_share(args):
     """The paper's per-GPU share of its weak-scaling runs (Sec. 3.1),
     3456 x 3072 x 30: the headline step (3 Helmholtz + Poisson) in both
@@ -294,9 +353,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0)
-    ap.add_argument("--workload", choices=["channel", "weak_share"], default="channel",
+    ap.add_argument("--workload", choices=["channel", "weak_share", "uneven_batch"], default="channel",
                     help="channel: 1024x512x512 (the headline); weak_share: the paper's per-GPU "
-                         "weak-scaling share 3456x3072x30")
+                         "weak-scaling share 3456x3072x30; uneven_batch: 16 problems of uneven "
+                         "sizes on 1-8 internal streams, eager and from one graph")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
@@ -307,6 +367,9 @@ def main():
         return
     if args.workload == "weak_share":
         weak_share(args)
+        return
+    if args.workload == "uneven_batch":
+        uneven_batch(args)
         return
 
     import numpy as np
