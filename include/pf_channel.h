@@ -118,6 +118,26 @@ pf_status poisson_set_workspace(pf_poisson_plan *plan, void *workspace, size_t b
 /* p <- L7^{-1} f. rhs: device (nz,ny,nx) float64, read only. p: device
  * (nz,ny,nx) float64, must not overlap rhs or the workspace. */
 pf_status poisson_solve(pf_poisson_plan *plan, const double *rhs, double *p);
+/* A-posteriori status of the solves of a plan (device memory, written by
+ * every later poisson_solve, poisson_project and helmholtz3d_solve on the
+ * plan's stream; no host readback, so it is graph-capturable). For
+ * PF_FP32_REFINE, est_rel_err = (max|correction| / max|iterate|)^2 over the
+ * x spectra the last pass sums: the first iterate's relative error is about
+ * max|correction| / max|iterate|, and one correction squares it. flags has
+ * PF_STATUS_NOT_CONVERGED when est_rel_err > tol. Solves without a
+ * correction record est_rel_err = -1 and no flag. The two max words are
+ * working storage (bit patterns of non-negative doubles). */
+typedef struct pf_solve_status {
+  uint64_t max_iterate, max_correction;
+  double est_rel_err;
+  uint64_t flags;
+} pf_solve_status;
+enum { PF_STATUS_NOT_CONVERGED = 1 };
+/* dev_status: device pointer to a pf_solve_status, 8-byte aligned, or NULL
+ * to stop recording; tol >= 0. Calls that share a status word must be
+ * ordered (same stream). */
+pf_status poisson_set_status(pf_poisson_plan *plan, void *dev_status, double tol);
+
 /* Pressure projection of a Runge-Kutta substep on the staggered grid
  * (paper Sec. 2.1, eqs. proj1_Lphi, proj1_ukp1, proj1_Pkp1; with implicit
  * wall-normal diffusion the z part of eq. proj2_Pkp1):

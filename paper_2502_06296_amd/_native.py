@@ -23,7 +23,7 @@ PF_STAGE_COUNT = len(STAGES)
 EXPORTS = [
     "pf_last_error", "pf_abi_version", "pf_zop_rows", "pf_grid_faces",
     "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_project", "poisson_solve_batched",
-    "helmholtz3d_plan", "helmholtz3d_solve", "helmholtz3d_update",
+    "helmholtz3d_plan", "helmholtz3d_solve", "helmholtz3d_update", "poisson_set_status",
     "poisson_set_stream", "poisson_destroy",
     "pcr_prepare", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
     "pcr_destroy",
@@ -80,6 +80,7 @@ def lib():
             "helmholtz3d_plan": (i32, [C.POINTER(vp), C.POINTER(PfGrid), i32, C.c_double, i32, i32, vp,
                                        C.POINTER(sz)]),
             "helmholtz3d_solve": (i32, [vp, vp, vp]),
+            "poisson_set_status": (i32, [vp, vp, C.c_double]),
             "helmholtz3d_update": (i32, [vp, C.c_double]),
             "poisson_solve_batched": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
             "poisson_set_stream": (i32, [vp, vp]),

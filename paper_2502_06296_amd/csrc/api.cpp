@@ -235,6 +235,8 @@ struct pf_poisson_plan {
       o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
+  unsigned long long *stat = nullptr;  // caller's pf_solve_status (device) or null
+  double stat_tol = 1e-10;
   Timing tm;
   size_t npts() const { return (size_t)nx * ny * nz; }
   // plane stride of the float32 spectrum work array
@@ -600,25 +602,43 @@ static pf_status poisson_check_solve(pf_poisson_plan *pl, const double *rhs, dou
 // With div, the right-hand side is D u* / gdt formed in the first x pass
 // (rhs unused); for the float32 refinement f is stashed in p, which the
 // residual reads before the last pass overwrites it.
-static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                 const pf::DivArgs *div = nullptr) {
-  const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
-  const long lines = (long)ny * nz;
-  const double scale = 1.0 / ((double)nx * ny);
-  const DevArena &A = pl->ar;
-  const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
-  const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
-  double *sums = A.at<double>(pl->o_sums), *sump = A.at<double>(pl->o_sump);
-  double *fbar = A.at<double>(pl->o_fbar), *mm = A.at<double>(pl->o_m), *zm = A.at<double>(pl->o_zm);
-  Timing &tm = pl->tm;
-  pf_status s;
-  // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
-  // and the chain solves (L - kappa) u' = r, so u = -kappa u'
-  const bool helm = pl->bc != PF_BC_NEUMANN;
-  const double oscale = helm ? -pl->kappa * scale : scale;
+static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                       const pf::DivArgs *div, bool helm, double oscale);
+static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                         const pf::DivArgs *div, bool helm, double oscale);
+
 #define STAGE(id, expr)                                      \
   if ((s = run_stage(tm, st, id, [&]() { return (expr); }))) \
     return s;
+
+static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                 const pf::DivArgs *div = nullptr) {
+  // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
+  // and the chain solves (L - kappa) u' = r, so u = -kappa u'
+  const double scale = 1.0 / ((double)pl->nx * pl->ny);
+  const bool helm = pl->bc != PF_BC_NEUMANN;
+  const double oscale = helm ? -pl->kappa * scale : scale;
+  if (pl->stat) PF_HIP(pf::launch_status_reset(pl->stat, st));
+  if (pl->prec != PF_FP32_REFINE) {
+    pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, helm, oscale);
+    if (!s && pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, false, st));
+    return s;
+  }
+  return poisson_enqueue_refined(pl, rhs, p, st, div, helm, oscale);
+}
+
+// float64, or float32 without a correction
+static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                       const pf::DivArgs *div, bool helm, double oscale) {
+  const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
+  const long lines = (long)ny * nz;
+  const DevArena &A = pl->ar;
+  const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
+  const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
+  double *sums = A.at<double>(pl->o_sums);
+  double *fbar = A.at<double>(pl->o_fbar), *mm = A.at<double>(pl->o_m), *zm = A.at<double>(pl->o_zm);
+  Timing &tm = pl->tm;
+  pf_status s;
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
     // the spectrum lives in p itself, dense
@@ -647,6 +667,24 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
                                                                oscale, lines, st)));
     return PF_OK;
   }
+  return fail(PF_ERR_ARG, "unexpected precision");
+}
+
+// float32 with one float64-residual correction
+static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
+                                         const pf::DivArgs *div, bool helm, double oscale) {
+  const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
+  const long lines = (long)ny * nz;
+  const DevArena &A = pl->ar;
+  const double *zal = A.at<double>(pl->o_zal), *zga = A.at<double>(pl->o_zga), *zex = A.at<double>(pl->o_zex);
+  const double *dzf = A.at<double>(pl->o_dzf), *sx = A.at<double>(pl->o_sx), *sy = A.at<double>(pl->o_sy);
+  double *sums = A.at<double>(pl->o_sums), *sump = A.at<double>(pl->o_sump);
+  double *fbar = A.at<double>(pl->o_fbar), *mm = A.at<double>(pl->o_m), *zm = A.at<double>(pl->o_zm);
+  Timing &tm = pl->tm;
+  pf_status s;
+  const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
+  float *W0 = (float *)pl->ws;
+  const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
   // y inverse; the float64 residual of the plane-mean-free problem formed in
   // x-spectral space into W1; the correction; one x inverse of W0 + W1 with
@@ -672,8 +710,19 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
   STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
-  STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st)));
+  STAGE(PF_STAGE_XINV_FINAL,
+        (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat)));
+  if (pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, true, st));
 #undef STAGE
+  return PF_OK;
+}
+
+pf_status poisson_set_status(pf_poisson_plan *pl, void *dev_status, double tol) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (!(tol >= 0.0) || std::isnan(tol)) return fail(PF_ERR_ARG, "tol must be >= 0");
+  if ((uintptr_t)dev_status & 7) return fail(PF_ERR_ARG, "dev_status must be 8-byte aligned");
+  pl->stat = reinterpret_cast<unsigned long long *>(dev_status);
+  pl->stat_tol = tol;
   return PF_OK;
 }
 

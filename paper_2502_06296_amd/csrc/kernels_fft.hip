@@ -212,6 +212,34 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
   }
 }
 
+// ------------------------------------------------ a-posteriori status
+// stat[0], stat[1]: largest |iterate| and |correction| spectra (bit
+// patterns, atomic max); stat[2]: the estimate (max|corr| / max|iter|)^2 of
+// the relative error one correction leaves, -1 without a correction;
+// stat[3]: flags (1: the estimate exceeds tol).
+__global__ void k_status_reset(unsigned long long *stat) {
+  if (threadIdx.x < 4) stat[threadIdx.x] = 0ull;
+}
+__global__ void k_status_final(unsigned long long *stat, double tol, int refined) {
+  if (threadIdx.x != 0) return;
+  double est = -1.0;
+  if (refined) {
+    const double m0 = __longlong_as_double((long long)stat[0]);
+    const double m1 = __longlong_as_double((long long)stat[1]);
+    est = m0 > 0.0 ? (m1 / m0) * (m1 / m0) : (m1 > 0.0 ? 1.0 : 0.0);
+  }
+  stat[2] = (unsigned long long)__double_as_longlong(est);
+  stat[3] = refined && !(est <= tol) ? 1ull : 0ull;
+}
+hipError_t launch_status_reset(unsigned long long *stat, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, st, stat);
+  return hipGetLastError();
+}
+hipError_t launch_status_final(unsigned long long *stat, double tol, bool refined, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_final, dim3(1), dim3(64), 0, st, stat, tol, refined ? 1 : 0);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
                            const cplx<double> *tw, double *sums, hipStream_t st) {
@@ -461,7 +489,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
                                                    const cplx<double> *__restrict__ tw,
                                                    const double *__restrict__ zm,
                                                    const TS *__restrict__ in2, double scale,
-                                                   int ny, long ncl, size_t sp) {
+                                                   int ny, long ncl, size_t sp,
+                                                   unsigned long long *__restrict__ stat) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -469,6 +498,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   const long c = (long)blockIdx.x * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
+  double m0 = 0.0, m1 = 0.0;  // largest |iterate| and |correction| seen (SUM2)
   if (ok) {
     const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
     const TS *a = in + o;
@@ -481,6 +511,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
       C B = ld2<TS>(b + 2 * q);
       if (SUM2) {
         const C A2 = ld2<TS>(a2 + 2 * q), B2 = ld2<TS>(b2 + 2 * q);
+        m0 = fmax(m0, fmax(fmax(fabs(A.x), fabs(A.y)), fmax(fabs(B.x), fabs(B.y))));
+        m1 = fmax(m1, fmax(fmax(fabs(A2.x), fabs(A2.y)), fmax(fabs(B2.x), fabs(B2.y))));
         A = mkc<double>(A.x + A2.x, A.y + A2.y);
         B = mkc<double>(B.x + B2.x, B.y + B2.y);
       }
@@ -493,6 +525,17 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
         buf[lds_idx(q)] = zq;
         buf[lds_idx(N - q)] = zn;
       }
+    }
+  }
+  if (SUM2 && stat) {  // uniform: the a-posteriori estimate of the refinement
+    for (int o = 32; o > 0; o >>= 1) {
+      m0 = fmax(m0, __shfl_xor(m0, o));
+      m1 = fmax(m1, __shfl_xor(m1, o));
+    }
+    // non-negative doubles order like their bit patterns
+    if ((threadIdx.x & 63) == 0) {
+      atomicMax(stat, (unsigned long long)__double_as_longlong(m0));
+      atomicMax(stat + 1, (unsigned long long)__double_as_longlong(m1));
     }
   }
   __syncthreads();
@@ -599,7 +642,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const TS *in2, double scale, long lines,
-                       hipStream_t st) {
+                       hipStream_t st, unsigned long long *stat) {
   const long ncl = lines / 2;
   switch (nx) {
 #define PF_CASE(N)                                                                              \
@@ -608,13 +651,13 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const c
     dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
     if (zm && in2)                                                                              \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
-                         zm, in2, scale, ny, ncl, sp);                                               \
+                         zm, in2, scale, ny, ncl, sp, stat);                                         \
     else if (zm)                                                                                \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, false>), g, b, 0, st, in, out, tw, \
-                         zm, in2, scale, ny, ncl, sp);                                               \
+                         zm, in2, scale, ny, ncl, sp, nullptr);                                      \
     else                                                                                        \
       hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, false, false>), g, b, 0, st, in, out,    \
-                         tw, zm, in2, scale, ny, ncl, sp);                                           \
+                         tw, zm, in2, scale, ny, ncl, sp, nullptr);                                  \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -638,12 +681,15 @@ template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cpl
                                        hipStream_t);
 template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
-                                                const double *, double, long, hipStream_t);
+                                                const double *, double, long, hipStream_t,
+                                                unsigned long long *);
 template hipError_t launch_xinv<float, float>(int, int, const float *, size_t, float *,
                                               const cplx<double> *, const double *, const float *,
-                                              double, long, hipStream_t);
+                                              double, long, hipStream_t,
+                                                unsigned long long *);
 template hipError_t launch_xinv<float, double>(int, int, const float *, size_t, double *,
                                                const cplx<double> *, const double *, const float *,
-                                               double, long, hipStream_t);
+                                               double, long, hipStream_t,
+                                                unsigned long long *);
 
 }  // namespace pf

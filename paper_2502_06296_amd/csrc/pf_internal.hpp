@@ -111,10 +111,17 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k]; with in2 (requires zm) the inverse of
 // in + in2, summed in float64.
+// With in2, a non-null stat (4 unsigned 64-bit words) receives the largest
+// |in| and |in2| values by atomic max (see launch_status_final).
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const TS *in2, double scale, long lines,
-                       hipStream_t st);
+                       hipStream_t st, unsigned long long *stat = nullptr);
+// a-posteriori status of a solve: zero the 4 words; then the estimate
+// (max|in2| / max|in|)^2 into word 2 (-1 unless refined) and flag word 3
+// when it exceeds tol
+hipError_t launch_status_reset(unsigned long long *stat, hipStream_t st);
+hipError_t launch_status_final(unsigned long long *stat, double tol, bool refined, hipStream_t st);
 
 // Pressure projection (eqs. proj1_Lphi, proj1_ukp1, proj1_Pkp1, proj2_Pkp1).
 // x forward of f = D u* / gdt built from the face velocities u, v (nz, ny,

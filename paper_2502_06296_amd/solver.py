@@ -130,6 +130,23 @@ def poisson_solve(plan, rhs, p):
     return p
 
 
+def poisson_set_status(plan, status, tol=1e-10):
+    """Record the a-posteriori status of the plan's solves into `status`, a
+    device int64 tensor of 4 elements (None stops recording)."""
+    import torch
+    if status is not None:
+        if not status.is_cuda or status.dtype != torch.int64 or status.numel() != 4 or not status.is_contiguous():
+            raise ValueError("status must be a contiguous cuda int64 tensor of 4 elements")
+    N.check(N.lib().poisson_set_status(plan.handle, _ptr(status) if status is not None else None, float(tol)))
+    plan.status = status
+
+
+def read_status(status):
+    """(est_rel_err, flags) of a status tensor (synchronises with its stream)."""
+    v = status.cpu()
+    return float(v[2:3].view(__import__("torch").float64)[0]), int(v[3])
+
+
 def poisson_project(plan, u, v, w, p, phi, gdt, c=0.0):
     """Pressure projection: L7 phi = D u* / gdt, u <- u* - gdt G phi, p <- p +
     phi - c L_z phi. u, v, p, phi: float64 (nz, ny, nx); w: float64 (nz-1,

@@ -86,6 +86,7 @@ def test_null_arguments():
     L = N.lib()
     assert L.poisson_solve(None, None, None) == N.PF_ERR_ARG
     assert L.poisson_project(None, None, None, None, None, None, 1.0, 0.0) == N.PF_ERR_ARG
+    assert L.poisson_set_status(None, None, 1e-10) == N.PF_ERR_ARG
     assert L.pcr_apply(None, None, 64, 64) == N.PF_ERR_ARG
     assert L.poisson_set_workspace(None, None, 0) == N.PF_ERR_ARG
     assert L.pf_graph_begin(None) == N.PF_ERR_ARG
