@@ -1,6 +1,6 @@
 """Builds the HIP library libpf_channel.so for gfx950, in-tree.
 
-    python -m paper_2502_06296_amd.build      (or __graft_entry__.build())
+    python -m paper_2502_06296_amd.build
 
 hipcc compiles each translation unit to an object in parallel, then links
 the shared library next to this file (lib/libpf_channel.so).
