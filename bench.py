@@ -305,13 +305,22 @@ def uneven_batch(args):
                       "by_lanes": rows}), flush=True)
 
 
-def weak_share(args):
-    """The paper's per-GPU share of its weak-scaling runs (Sec. 3.1),
-    3456 x 3072 x 30: the headline step (3 Helmholtz + Poisson) in both
-    precisions, and the Helmholtz apply with 1, 2 and 4 chunks per column
-    (one chunk is a plain elimination; more chunks add the reduced system)."""
+SHARES = {
+    # the paper's per-GPU share of its weak-scaling runs (Sec. 3.1)
+    "weak_share": ((3456, 3072, 30), "weak-scaling share"),
+    # one z slab of its strong-scaling grid 3200 x 3456 x 900 over 32 GPUs
+    # (Sec. 3.1, 1-D slabs): 28 planes (four of the 32 slabs hold 29)
+    "strong_slab": ((3200, 3456, 28), "strong-scaling slab of 3200x3456x900 over 32 GPUs,"),
+}
+
+
+def per_gpu_share(args):
+    """One GPU's share of the paper's scaling runs (Sec. 3.1): the headline
+    step (3 Helmholtz + Poisson) in both precisions, and the Helmholtz apply
+    with 1, 2 and 4 chunks per column (one chunk is a plain elimination;
+    more chunks add the reduced system)."""
     global NX, NY, NZ
-    NX, NY, NZ = 3456, 3072, 30
+    (NX, NY, NZ), label = SHARES[args.workload]
     import torch
     import paper_2502_06296_amd as pf
     from paper_2502_06296_amd import autotune
@@ -323,10 +332,10 @@ def weak_share(args):
     r3 = [torch.randn((NZ if c < 2 else NZ - 1, NY, NX), dtype=torch.float64, device=dev, generator=g)
           for c in range(3)]
     npts = NX * NY * NZ
-    out = {"workload": f"weak-scaling share {NX}x{NY}x{NZ}, tanh 1.5: 3 z-Helmholtz + pressure Poisson",
+    out = {"workload": f"{label} {NX}x{NY}x{NZ}, tanh 1.5: 3 z-Helmholtz + pressure Poisson",
            "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
     for prec in ("fp32_refine", "fp64"):
-        log(f"weak share: {prec}")
+        log(f"{args.workload}: {prec}")
         st = Step(pf, torch, dev, prec, f, r3)
         ms, _, stages = time_steps(st, args.steps, args.warmup)
         entry = {"value": round(npts / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
@@ -353,9 +362,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0)
-    ap.add_argument("--workload", choices=["channel", "weak_share", "uneven_batch"], default="channel",
+    ap.add_argument("--workload", choices=["channel", "weak_share", "strong_slab", "uneven_batch"],
+                    default="channel",
                     help="channel: 1024x512x512 (the headline); weak_share: the paper's per-GPU "
-                         "weak-scaling share 3456x3072x30; uneven_batch: 16 problems of uneven "
+                         "weak-scaling share 3456x3072x30; strong_slab: a 3200x3456x28 z slab of "
+                         "its strong-scaling grid; uneven_batch: 16 problems of uneven "
                          "sizes on 1-8 internal streams, eager and from one graph")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -365,8 +376,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload == "weak_share":
-        weak_share(args)
+    if args.workload in SHARES:
+        per_gpu_share(args)
         return
     if args.workload == "uneven_batch":
         uneven_batch(args)

@@ -47,12 +47,14 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
   if (need_fft) {
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
+#define PF_LEN_STR(N) " " #N
     if (!pf::fft_size_supported(g->nx))
-      return fail(PF_ERR_UNSUPPORTED,
-                  "x length %d not built (64 96 128 192 256 384 512 768 1024 1536 2048 3072 3456)", g->nx);
+      return fail(PF_ERR_UNSUPPORTED, "x length %d not built (built:" PF_FOR_FFT_SIZES(PF_LEN_STR) ")",
+                  g->nx);
     if (!pf::fft_size_supported_y(g->ny))
-      return fail(PF_ERR_UNSUPPORTED,
-                  "y length %d not built (64 96 128 192 256 384 512 768 1024 1536 2048 3072)", g->ny);
+      return fail(PF_ERR_UNSUPPORTED, "y length %d not built (built:" PF_FOR_FFT_SIZES_Y(PF_LEN_STR) ")",
+                  g->ny);
+#undef PF_LEN_STR
   }
   if (g->zf) {
     for (int k = 0; k < g->nz; ++k)

@@ -4,7 +4,7 @@
 // real lines are carried as the real and imaginary parts of one complex
 // line, so every real transform of the solver runs as a complex transform
 // followed by the split into two packed real spectra (paper App. A layout).
-// The transform is a Stockham autosort over radix-16/8/4/2/3 passes: each
+// The transform is a Stockham autosort over radix-16/8/4/2/3/5 passes: each
 // pass reads R elements spaced N/R apart, applies the twiddles and an
 // R-point DFT in registers, and writes them back R-interleaved; every pass is
 // separated from the next by a workgroup barrier, and TPL threads share a
@@ -76,6 +76,29 @@ __device__ __forceinline__ void dft3(cplx<T> &v0, cplx<T> &v1, cplx<T> &v2) {
   v2 = csub<T>(m, u);
 }
 
+// 5-point DFT from the sums and differences of the mirrored inputs:
+// X_k = x0 + cos(2 pi k/5)-weighted sums -+ i sin(2 pi k/5)-weighted
+// differences, with X_{5-k} the same terms with the other sign of i.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cplx<T> &v0, cplx<T> &v1, cplx<T> &v2, cplx<T> &v3, cplx<T> &v4) {
+  const T c1 = T(0.30901699437494742410229341718282);   // cos(2 pi / 5)
+  const T c2 = T(-0.80901699437494742410229341718282);  // cos(4 pi / 5)
+  const T s1 = T(0.95105651629515357211643933337938);   // sin(2 pi / 5)
+  const T s2 = T(0.58778525229247312916870595463907);   // sin(4 pi / 5)
+  const cplx<T> t1 = cadd<T>(v1, v4), t2 = cadd<T>(v2, v3);
+  const cplx<T> t3 = csub<T>(v1, v4), t4 = csub<T>(v2, v3);
+  const cplx<T> a1 = mkc<T>(v0.x + c1 * t1.x + c2 * t2.x, v0.y + c1 * t1.y + c2 * t2.y);
+  const cplx<T> a2 = mkc<T>(v0.x + c2 * t1.x + c1 * t2.x, v0.y + c2 * t1.y + c1 * t2.y);
+  // -i b (forward) or +i b (inverse) of the sine-weighted differences
+  const cplx<T> b1 = rot90<T, INV>(mkc<T>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+  const cplx<T> b2 = rot90<T, INV>(mkc<T>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+  v0 = cadd<T>(v0, cadd<T>(t1, t2));
+  v1 = cadd<T>(a1, b1);
+  v4 = csub<T>(a1, b1);
+  v2 = cadd<T>(a2, b2);
+  v3 = csub<T>(a2, b2);
+}
+
 // 8-point DFT in natural order, as two 4-point DFTs of the even and odd
 // samples joined by the eighth roots of unity.
 template <typename T, bool INV>
@@ -132,6 +155,7 @@ __device__ __forceinline__ void dft_r(cplx<T> *v) {
   if constexpr (R == 2) dft2<T, INV>(v[0], v[1]);
   else if constexpr (R == 3) dft3<T, INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 5) dft5<T, INV>(v[0], v[1], v[2], v[3], v[4]);
   else if constexpr (R == 8) dft8<T, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);
 }
@@ -144,6 +168,7 @@ __host__ __device__ constexpr int pick_radix() {
          : (REM % 4 == 0)             ? 4
          : (REM % 2 == 0)             ? 2
          : (REM % 3 == 0)             ? 3
+         : (REM % 5 == 0)             ? 5
                                       : 0;
 }
 
@@ -156,6 +181,7 @@ __device__ __forceinline__ void pass_twiddles(cplx<T> (&w)[R], const cplx<T> *__
   w[1] = tw[e];
   if constexpr (R >= 3) w[2] = cmul<T>(w[1], w[1]);
   if constexpr (R >= 4) w[3] = cmul<T>(w[2], w[1]);
+  if constexpr (R == 5) w[4] = cmul<T>(w[2], w[2]);
   if constexpr (R >= 8) {
     w[4] = tw[4 * e];
 #pragma unroll
@@ -222,7 +248,7 @@ __device__ __forceinline__ void fft_passes_io(cplx<T> *buf, const cplx<T> *__res
                                               Src src, Dst dst) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix<N / NS>();
-    static_assert(R != 0, "transform length must be 2^a 3^b");
+    static_assert(R != 0, "transform length must be 2^a 3^b 5^c");
     constexpr bool gin = GIN && NS == 1, gout = GOUT && NS * R == N;
     auto lrd = [buf](int i) { return buf[lds_idx(i)]; };
     auto lwr = [buf](int i, const cplx<T> &x) { buf[lds_idx(i)] = x; };

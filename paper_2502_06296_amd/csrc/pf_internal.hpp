@@ -20,11 +20,12 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 }
 
 // Transform lengths instantiated for the x and y directions: even 2^a 3^b
-// up to 2048, and the lengths of the paper's per-GPU weak-scaling share,
-// 3456 x 3072 (x: 3072 and 3456; y: 3072).
-#define PF_FOR_FFT_SIZES_COMMON(X) \
-  X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072)
-#define PF_FOR_FFT_SIZES(X) PF_FOR_FFT_SIZES_COMMON(X) X(3456)
+// up to 2048, the lengths of the paper's per-GPU weak-scaling share,
+// 3456 x 3072, and of its strong-scaling grid, 3200 x 3456 (3200 = 2^7 5^2).
+#define PF_FOR_FFT_SIZES_COMMON(X)                                                              \
+  X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(3200) \
+  X(3456)
+#define PF_FOR_FFT_SIZES(X) PF_FOR_FFT_SIZES_COMMON(X)
 #define PF_FOR_FFT_SIZES_Y(X) PF_FOR_FFT_SIZES_COMMON(X)
 
 bool fft_size_supported(int n);    // x direction
@@ -59,7 +60,12 @@ constexpr int resid_lpw(int n) {
 }
 constexpr int y_tpl(int n) {
   int t = n / 8 < 8 ? 8 : (n / 8 > 256 ? 256 : n / 8);
-  while (t > 8 && n % (2 * t)) t /= 2;  // every thread takes pairs of positions
+  // every thread takes pairs of positions (2 t divides n); among such t the
+  // largest multiple of 32 keeps the workgroups of the long lines, whose LDS
+  // allows one per CU, at several whole waves (3456: 192, 3200: 160)
+  for (int c = t - t % 32; c >= 64; c -= 32)
+    if (n % (2 * c) == 0) return c;
+  while (t > 8 && n % (2 * t)) t /= 2;
   return t;
 }
 // LDS stride (complex elements) between the lines of a y workgroup: 2 mod 16,

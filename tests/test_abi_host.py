@@ -64,7 +64,7 @@ def _plan_status(nx, ny, nz, prec=0, nref=1, zf=None, beta=1.5):
     ((64, 64, 3), N.PF_ERR_ARG),              # nz too small
     ((64, 64, 2048), N.PF_ERR_UNSUPPORTED),   # nz too large
     ((4096, 64, 64), N.PF_ERR_UNSUPPORTED),
-    ((64, 3456, 64), N.PF_ERR_UNSUPPORTED),  # 3456 is built along x only
+    ((64, 3000, 64), N.PF_ERR_UNSUPPORTED),  # 2^3 3 5^3: a length not in the built list
 ])
 def test_plan_rejects_bad_grids_before_any_device_call(args, code):
     assert _plan_status(*args) == code

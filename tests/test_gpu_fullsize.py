@@ -196,6 +196,33 @@ def test_weak_scaling_share_3456x3072x30():
 
 
 @pytest.mark.gpu
+def test_strong_scaling_slab_3200x3456x28():
+    """One z slab of the paper's strong-scaling grid 3200 x 3456 x 900 over
+    32 GPUs (Sec. 3.1): 3200 = 2^7 5^2 along x, 3456 along y."""
+    dev = torch.device("cuda", 0)
+    nx, ny, nz = 3200, 3456, 28
+    print(f"poisson {nx}x{ny}x{nz}", flush=True)
+    zf = synth.tanh_faces(nz, LZ, BETA)
+    f = _project(_uniform((nz, ny, nx), 131, dev), zf)
+    p64 = torch.empty_like(f)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, BETA, precision="fp64")
+    pf.poisson_solve(plan, f, p64)
+    torch.cuda.synchronize()
+    res = _poisson_residual(p64, f, zf)
+    print(f"fp64 residual {res:.2e}", flush=True)
+    assert res < 1e-12
+    assert _weighted_mean_ratio(p64, zf) < 1e-12
+    del plan
+    p32 = torch.empty_like(f)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, BETA, precision="fp32_refine")
+    pf.poisson_solve(plan, f, p32)
+    torch.cuda.synchronize()
+    err = _rel(p32, p64)
+    print(f"fp32_refine vs fp64 {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
+@pytest.mark.gpu
 def test_helmholtz_1024x1024x512_three_components():
     dev = torch.device("cuda", 0)
     nx, ny, nz = 1024, 1024, 512

@@ -42,6 +42,7 @@ CASES = [
     (192, 64, 33, 0.0, ogrid.DIRICHLET_FACE, 0.05, 3),      # uniform z, ragged chunks
     (96, 128, 9, 1.2, ogrid.DIRICHLET_CENTRE, 9.615e-9, 4),  # nearly the identity
     (3456, 64, 30, 1.5, ogrid.DIRICHLET_FACE, 1e-3, 5),     # the weak-scaling share's x length
+    (3200, 64, 28, 1.5, ogrid.DIRICHLET_CENTRE, 1e-3, 6),   # radix-5 x
 ]
 
 

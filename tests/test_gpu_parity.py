@@ -53,6 +53,9 @@ POISSON_SHAPES = [
     (3456, 64, 30, 1.5, 11),    # the weak-scaling share's lengths: x = 3456 (2^7 3^3)
     (3072, 64, 30, 1.5, 12),    # x = 3072
     (64, 3072, 30, 1.5, 13),    # y = 3072
+    (3200, 64, 28, 1.5, 14),    # the strong-scaling grid's x length 3200 = 2^7 5^2: radix-5 passes
+    (64, 3456, 28, 1.5, 15),    # its y length 3456, six-wave y workgroups
+    (128, 3200, 9, 1.5, 16),    # radix 5 along y, five-wave y workgroups
 ]
 
 
