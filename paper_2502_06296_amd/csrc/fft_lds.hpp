@@ -4,7 +4,7 @@
 // real lines are carried as the real and imaginary parts of one complex
 // line, so every real transform of the solver runs as a complex transform
 // followed by the split into two packed real spectra (paper App. A layout).
-// The transform is a Stockham autosort over radix-16/8/4/2/3/5 passes: each
+// The transform is a Stockham autosort over radix-16/9/8/5/4/3/2 passes: each
 // pass reads R elements spaced N/R apart, applies the twiddles and an
 // R-point DFT in registers, and writes them back R-interleaved; every pass is
 // separated from the next by a workgroup barrier, and TPL threads share a
@@ -150,6 +150,33 @@ __device__ __forceinline__ void dft16(cplx<T> *v) {
   for (int i = 0; i < 16; ++i) v[i] = o[i];
 }
 
+// 9-point DFT as 3 x 3: DFTs over n1 for each n2, twiddle by w9^(n2 k1),
+// DFTs over n2 for each k1; output index k1 + 3 k2.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft9(cplx<T> *v) {
+  const T c1 = T(0.76604444311897803520239265055542);   // cos(2 pi / 9)
+  const T s1 = T(0.64278760968653932632264340990726);   // sin(2 pi / 9)
+  const T c2 = T(0.17364817766693034885171662676931);   // cos(4 pi / 9)
+  const T s2 = T(0.98480775301220805936674302458952);   // sin(4 pi / 9)
+  const T c4 = T(-0.93969262078590838405410927732473);  // cos(8 pi / 9)
+  const T s4 = T(0.34202014332566873304409961468226);   // sin(8 pi / 9)
+  for (int n2 = 0; n2 < 3; ++n2) dft3<T, INV>(v[n2], v[n2 + 3], v[n2 + 6]);
+  // after this v[n2 + 3*k1] holds Y_{n2}[k1]; twiddle exponents n2*k1 = 1, 2, 2, 4
+  const T sg = INV ? T(1) : T(-1);
+  auto tw = [&](cplx<T> a, T c, T s) { return mkc<T>(a.x * c - a.y * (sg * s), a.x * (sg * s) + a.y * c); };
+  v[1 + 3] = tw(v[1 + 3], c1, s1);
+  v[1 + 6] = tw(v[1 + 6], c2, s2);
+  v[2 + 3] = tw(v[2 + 3], c2, s2);
+  v[2 + 6] = tw(v[2 + 6], c4, s4);
+  cplx<T> o[9];
+  for (int k1 = 0; k1 < 3; ++k1) {
+    cplx<T> a = v[3 * k1 + 0], b = v[3 * k1 + 1], c = v[3 * k1 + 2];
+    dft3<T, INV>(a, b, c);
+    o[k1] = a; o[k1 + 3] = b; o[k1 + 6] = c;
+  }
+  for (int i = 0; i < 9; ++i) v[i] = o[i];
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_r(cplx<T> *v) {
   if constexpr (R == 2) dft2<T, INV>(v[0], v[1]);
@@ -157,6 +184,7 @@ __device__ __forceinline__ void dft_r(cplx<T> *v) {
   else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
   else if constexpr (R == 5) dft5<T, INV>(v[0], v[1], v[2], v[3], v[4]);
   else if constexpr (R == 8) dft8<T, INV>(v);
+  else if constexpr (R == 9) dft9<T, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);
 }
 
@@ -167,6 +195,7 @@ __host__ __device__ constexpr int pick_radix() {
          : (REM % 8 == 0)             ? 8
          : (REM % 4 == 0)             ? 4
          : (REM % 2 == 0)             ? 2
+         : (REM % 9 == 0)             ? 9
          : (REM % 3 == 0)             ? 3
          : (REM % 5 == 0)             ? 5
                                       : 0;
@@ -187,6 +216,7 @@ __device__ __forceinline__ void pass_twiddles(cplx<T> (&w)[R], const cplx<T> *__
 #pragma unroll
     for (int r = 5; r < 8; ++r) w[r] = cmul<T>(w[4], w[r - 4]);
   }
+  if constexpr (R == 9) w[8] = cmul<T>(w[4], w[4]);
   if constexpr (R >= 16) {
     w[8] = cmul<T>(w[4], w[4]);
 #pragma unroll

@@ -247,7 +247,7 @@ hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, siz
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
-    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                                \
+    constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                             \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
     if (d.stash)                                                                                 \
       hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, d, out,  \
@@ -560,7 +560,7 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
   switch (nx) {
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
-    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
+    constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                            \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
     if (sums)                                                                                   \
       hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, in, out, tw, \

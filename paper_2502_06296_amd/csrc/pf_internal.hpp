@@ -40,7 +40,20 @@ constexpr size_t kPlanePad = 64;
 // LPW pairs of adjacent x slots, 2*LPW contiguous values per row (128 bytes
 // when the LDS budget allows). LPW is a power of two, so 2*LPW (at most 32)
 // divides every supported nx.
-constexpr int x_tpl(int n) { return n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16); }
+// The lines longer than 2048 points keep 52-118 KB of LDS per workgroup, one
+// to three workgroups per CU: the y transforms, the x inverse and the
+// residual take more threads per line, the largest multiple of 32 up to 384
+// that divides n / div (div = 2 where every thread takes pairs of
+// positions), so that a CU still holds several waves per SIMD. The x
+// forward transforms keep 128 threads (more made them slower: 1.23 -> 1.38
+// ms at 3456 points).
+constexpr int long_tpl(int n, int div) {
+  for (int c = 384; c >= 64; c -= 32)
+    if (n % (div * c) == 0) return c;
+  return 0;
+}
+constexpr int xfwd_tpl(int n) { return n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16); }
+constexpr int x_tpl(int n) { return n > 2048 && long_tpl(n, 1) ? long_tpl(n, 1) : xfwd_tpl(n); }
 constexpr int x_lpw(int n) {
   const int by_threads = 256 / x_tpl(n);
   const int by_lds = 32768 / (n * 16);
@@ -59,13 +72,9 @@ constexpr int resid_lpw(int n) {
   return v;
 }
 constexpr int y_tpl(int n) {
+  if (n > 2048 && long_tpl(n, 2)) return long_tpl(n, 2);
   int t = n / 8 < 8 ? 8 : (n / 8 > 256 ? 256 : n / 8);
-  // every thread takes pairs of positions (2 t divides n); among such t the
-  // largest multiple of 32 keeps the workgroups of the long lines, whose LDS
-  // allows one per CU, at several whole waves (3456: 192, 3200: 160)
-  for (int c = t - t % 32; c >= 64; c -= 32)
-    if (n % (2 * c) == 0) return c;
-  while (t > 8 && n % (2 * t)) t /= 2;
+  while (t > 8 && n % (2 * t)) t /= 2;  // every thread takes pairs of positions
   return t;
 }
 // LDS stride (complex elements) between the lines of a y workgroup: 2 mod 16,
