@@ -69,10 +69,11 @@ typedef enum { PF_FP64 = 0, PF_FP32 = 1, PF_FP32_REFINE = 2 } pf_precision;
  *                   nz-1 unknowns per column. */
 typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FACE = 2 } pf_zbc;
 
-/* Channel grid. nx, ny even, of the form 2^a 3^b: 64 <= n <= 2048 in both
- * directions, plus nx in {3072, 3456} and ny = 3072 (the lengths of the
- * paper's per-GPU weak-scaling share; the transform lengths this build
- * instantiates); 4 <= nz <= 1024. zf: host array of
+/* Channel grid. nx and ny each one of the transform lengths this library
+ * instantiates: the even 2^a 3^b from 64 to 2048, and 3072, 3200 (2^7 5^2)
+ * and 3456 (2^7 3^3), the lengths of the paper's per-GPU weak-scaling share
+ * and of its strong-scaling grid; any other length is PF_ERR_UNSUPPORTED.
+ * 4 <= nz <= 1024. zf: host array of
  * nz+1 strictly increasing face coordinates, copied at plan time; if NULL
  * the faces are zf[k] = lz/2 (1 + tanh(beta (2k/nz - 1)) / tanh(beta))
  * (uniform when beta == 0). */

@@ -49,6 +49,8 @@ PROJ_CASES = [
     (128, 96, 40, 2.0, 0.0, 2),    # radix-3 y, ragged z chunks
     (192, 64, 33, 0.0, 5e-4, 3),   # radix-3 x, uniform z
     (96, 128, 9, 1.2, 0.0, 4),     # few planes; nx not a multiple of the update's 64-column tile
+    (3456, 64, 12, 1.5, 1e-3, 5),  # the long x lines: radix-9 divergence pass
+    (3200, 96, 9, 1.5, 0.0, 6),    # radix-5 x
 ]
 
 
