@@ -10,13 +10,15 @@ floor), slow and direct:
 * ``grid``       -- z metrics, the second-order z operator for each boundary
                     family, modified wavenumbers in the packed slot order.
 * ``transforms`` -- packed real Fourier transform of the paper's App. A
-                    layout, on top of numpy's FFT (a library primitive).
+                    layout, on top of numpy's FFT (a library primitive); the
+                    cosine transform for walls in y, from its definition.
 * ``tridiag``    -- subtraction-free Thomas elimination, the paper's
                     Algorithm 1 and Algorithm 2 (plain and subtraction-free),
                     the reduced boundary system of the partition method.
 * ``poisson``    -- the Fourier-x, Fourier-y, tridiagonal-z Poisson solve of
                     eq. (fijk_eq) with the pinned singular zero mode, the
-                    7-point residual, and the z-implicit Helmholtz solve of
+                    7-point residual (y periodic, or zero-gradient y walls
+                    with the cosine transform), and the z-implicit Helmholtz solve of
                     eq. (proj3_impl1d).
 * ``dense``      -- brute-force assembled operators for tiny grids, built
                     from face fluxes rather than from ``grid``.

@@ -60,22 +60,38 @@ def periodic_d2(n, h):
     return M / (h * h)
 
 
-def l7_dense(nx, ny, zf, lx, ly):
-    """Dense 7-point operator for C-order (nz, ny, nx) flattening."""
+def wall_d2(n, h):
+    """Dense second difference on n cell centres of spacing h between two
+    zero-gradient walls: the flux through each wall face is zero, so the end
+    rows keep one neighbour."""
+    M = np.zeros((n, n))
+    for i in range(n):
+        if i > 0:
+            M[i, i - 1] += 1
+            M[i, i] -= 1
+        if i < n - 1:
+            M[i, i + 1] += 1
+            M[i, i] -= 1
+    return M / (h * h)
+
+
+def l7_dense(nx, ny, zf, lx, ly, ybc=0):
+    """Dense 7-point operator for C-order (nz, ny, nx) flattening (ybc = 1:
+    zero-gradient walls at both y ends)."""
     nz = len(zf) - 1
     Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
     Dx = periodic_d2(nx, lx / nx)
-    Dy = periodic_d2(ny, ly / ny)
+    Dy = wall_d2(ny, ly / ny) if ybc == 1 else periodic_d2(ny, ly / ny)
     Dz = lz_dense(zf, NEUMANN)
     return (np.kron(Iz, np.kron(Iy, Dx)) + np.kron(Iz, np.kron(Dy, Ix))
             + np.kron(Dz, np.kron(Iy, Ix)))
 
 
-def poisson_dense(f, zf, lx, ly):
+def poisson_dense(f, zf, lx, ly, ybc=0):
     """Least-squares solution of L7 p = f with the row sum_ijk dzf[k] p = 0
     appended (the solution of the projected problem when f is compatible)."""
     nz, ny, nx = f.shape
-    L = l7_dense(nx, ny, zf, lx, ly)
+    L = l7_dense(nx, ny, zf, lx, ly, ybc)
     w = np.repeat(np.diff(np.asarray(zf, float)), nx * ny)
     # project f onto the range of L (orthogonal to the weights' null vector)
     fv = f.reshape(-1)

@@ -21,6 +21,9 @@ NEUMANN = 0            # pressure, cell centres, zero normal gradient at walls
 DIRICHLET_CENTRE = 1   # u, v at cell centres, value 0 at the walls
 DIRICHLET_FACE = 2     # w at interior faces, w = 0 on the wall faces
 
+Y_PERIODIC = 0         # y periodic (the channel)
+Y_WALLS = 1            # zero-gradient (Neumann) walls at both y ends, cell centres
+
 
 def z_metrics(zf, dtype=np.float64):
     """Centres zc, cell widths dzf (nz), centre distances dzc (nz-1)."""
@@ -84,4 +87,13 @@ def modified_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
     dx = dtype(length) / dtype(n)
     pi = np.pi if dtype is np.float64 else dtype("3.14159265358979323846264338327950288")
     s = np.sin(pi * q / dtype(n))
+    return 4 * s * s / (dx * dx)
+
+
+def wall_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
+    """sigma per cosine mode q = 0..n-1 (natural order) of the cell-centred
+    second difference with zero-gradient walls: 4 sin^2(pi q / (2n)) / dx^2."""
+    q = np.arange(n, dtype=dtype)
+    dx = dtype(length) / dtype(n)
+    s = np.sin(np.pi * q / (2 * dtype(n)))
     return 4 * s * s / (dx * dx)

@@ -50,15 +50,23 @@ def zero_mode_solve(fhat00, zf):
     return m - np.dot(dzf, m) / dzf.sum()
 
 
-def solve_poisson(f, zf, lx, ly):
+def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC):
     """p with L7 p = f (projected), zero dzf-weighted mean. f is (nz, ny, nx),
-    float64 or longdouble; the result has f's dtype."""
+    float64 or longdouble; the result has f's dtype. ybc = grid.Y_WALLS puts
+    zero-gradient walls at both y ends (cell-centred unknowns): the y
+    transform is then the cosine transform and its wavenumbers those of the
+    mirrored second difference (Sec. 2.2.1)."""
     dt = f.dtype.type
     nz, ny, nx = f.shape
     f = project_rhs(f, zf)
-    F = transforms.rfft_packed(transforms.rfft_packed(f, axis=2), axis=1)
+    Fx = transforms.rfft_packed(f, axis=2)
+    if ybc == grid.Y_WALLS:
+        F = transforms.dct2(Fx, axis=1)
+        sy = grid.wall_wavenumbers(ny, ly, dt)
+    else:
+        F = transforms.rfft_packed(Fx, axis=1)
+        sy = grid.modified_wavenumbers(ny, ly, dt)
     sx = grid.modified_wavenumbers(nx, lx, dt)
-    sy = grid.modified_wavenumbers(ny, ly, dt)
     alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
     shift = sy[:, None] + sx[None, :]                  # (ny, nx) >= 0
     shift[0, 0] = 1                                    # placeholder, redone below
@@ -66,16 +74,24 @@ def solve_poisson(f, zf, lx, ly):
     # -(L_z - shift) phi = -fhat in sign-normalised rows
     P = tridiag.thomas_gth(alpha[:, None, None], gamma[:, None, None], eps3, -F)
     P[:, 0, 0] = zero_mode_solve(F[:, 0, 0].copy(), zf)
-    return transforms.irfft_packed(transforms.irfft_packed(P, axis=1), axis=2)
+    Py = transforms.idct2(P, axis=1) if ybc == grid.Y_WALLS else transforms.irfft_packed(P, axis=1)
+    return transforms.irfft_packed(Py, axis=2)
 
 
-def apply_L7(p, zf, lx, ly):
-    """L7 p in the arithmetic of p's dtype (periodic x, y; Neumann z)."""
+def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC):
+    """L7 p in the arithmetic of p's dtype (periodic x; periodic y or, with
+    ybc = grid.Y_WALLS, zero-gradient y walls, whose ghost values mirror the
+    end rows; Neumann z)."""
     dt = p.dtype.type
     nz, ny, nx = p.shape
     dx, dy = dt(lx) / nx, dt(ly) / ny
     out = (np.roll(p, -1, 2) - 2 * p + np.roll(p, 1, 2)) / (dx * dx)
-    out += (np.roll(p, -1, 1) - 2 * p + np.roll(p, 1, 1)) / (dy * dy)
+    if ybc == grid.Y_WALLS:
+        pm = np.concatenate([p[:, :1], p[:, :-1]], axis=1)     # p[j-1], ghost p[-1] = p[0]
+        pp = np.concatenate([p[:, 1:], p[:, -1:]], axis=1)     # p[j+1], ghost p[ny] = p[ny-1]
+        out += (pp - 2 * p + pm) / (dy * dy)
+    else:
+        out += (np.roll(p, -1, 1) - 2 * p + np.roll(p, 1, 1)) / (dy * dy)
     alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
     lz = -(alpha + gamma + eps)[:, None, None] * p
     lz[1:] += alpha[1:, None, None] * p[:-1]
@@ -83,9 +99,9 @@ def apply_L7(p, zf, lx, ly):
     return out + lz
 
 
-def residual7(p, f, zf, lx, ly):
+def residual7(p, f, zf, lx, ly, ybc=grid.Y_PERIODIC):
     """f - L7 p (f projected first)."""
-    return project_rhs(f, zf) - apply_L7(p, zf, lx, ly)
+    return project_rhs(f, zf) - apply_L7(p, zf, lx, ly, ybc)
 
 
 def solve_helmholtz(r, zf, s, bc):

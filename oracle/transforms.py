@@ -69,3 +69,27 @@ def dft_direct(x: np.ndarray) -> np.ndarray:
     for q in range(n):
         X[q] = np.sum(x * np.exp(-2j * np.pi * ((q * t) % n) / n))
     return X
+
+
+def dct2(x: np.ndarray, axis: int) -> np.ndarray:
+    """Cosine transform of ``x`` along ``axis`` for walls at both ends (paper
+    Sec. 2.2.1: the cosine member of the Fourier-based transforms), written
+    out from its definition: X_q = 2 sum_t x_t cos(pi q (2t + 1) / (2n)),
+    q, t = 0..n-1 (the eigenvectors of the second difference with mirrored
+    end values). A dense matrix product; ``x`` may be complex."""
+    x = np.moveaxis(np.asarray(x), axis, -1)
+    n = x.shape[-1]
+    t = np.arange(n)
+    M = 2.0 * np.cos(np.pi * np.outer(t, 2 * t + 1) / (2 * n))
+    return np.moveaxis(x @ M.T, -1, axis)
+
+
+def idct2(X: np.ndarray, axis: int) -> np.ndarray:
+    """Inverse of ``dct2``: x_t = (X_0 / 2 + sum_{q>=1} X_q cos(pi q (2t + 1)
+    / (2n))) / n."""
+    X = np.moveaxis(np.asarray(X), axis, -1)
+    n = X.shape[-1]
+    t = np.arange(n)
+    M = np.cos(np.pi * np.outer(2 * t + 1, t) / (2 * n))
+    M[:, 0] = 0.5
+    return np.moveaxis((X @ M.T) / n, -1, axis)

@@ -1,0 +1,73 @@
+"""Pins of the oracle's wall-bounded y direction (paper Sec. 2.2.1: the
+cosine member of the Fourier-based transforms, for zero-gradient walls at
+both y ends), against facts that do not restate its formulas:
+
+* the cosine transform equals the even-extension DFT of length 2n (direct
+  summation), and its inverse undoes it;
+* the cosine vectors are eigenvectors of the dense wall second difference
+  (assembled from face fluxes) with the stated wavenumbers;
+* the Poisson solve equals the dense least-squares brute force on tiny grids;
+* its 7-point residual vanishes at round-off; it is linear, and mirror
+  symmetric in y.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, grid, poisson, transforms
+
+LX, LY = 2 * np.pi, np.pi
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 12])
+def test_cosine_transform_is_the_even_extension_dft(n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    e = np.concatenate([x, x[::-1]])                       # x_0..x_{n-1}, x_{n-1}..x_0
+    E = transforms.dft_direct(e)
+    q = np.arange(n)
+    # the even extension's DFT is 2 exp(i pi q / 2n) X_q
+    ref = E[:n] * np.exp(-1j * np.pi * q / (2 * n))
+    X = transforms.dct2(x, axis=0)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(transforms.idct2(X, axis=0) - x)) <= 1e-13 * n
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 13])
+def test_cosine_vectors_diagonalise_the_wall_second_difference(n):
+    h = 0.37
+    D = dense.wall_d2(n, h)
+    sig = grid.wall_wavenumbers(n, n * h)
+    t = np.arange(n)
+    for q in range(n):
+        e = np.cos(np.pi * q * (2 * t + 1) / (2 * n))
+        assert np.max(np.abs(D @ e + sig[q] * e)) <= 1e-10 * max(1.0, sig[q])
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,seed", [
+    (4, 3, 5, 1.5, 0), (2, 4, 6, 0.0, 1), (6, 5, 4, 2.0, 2), (4, 1, 5, 1.0, 3), (1, 6, 7, 1.2, 4),
+])
+def test_solve_matches_dense_brute_force(nx, ny, nz, beta, seed):
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    f = synth.uniform_pm1(seed, (nz, ny, nx))
+    got = poisson.solve_poisson(f, zf, LX, LY, ybc=grid.Y_WALLS)
+    ref = dense.poisson_dense(f, zf, LX, LY, ybc=1)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_residual_linearity_and_mirror_symmetry():
+    nx, ny, nz = 16, 12, 20
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    f = synth.uniform_pm1(7, (nz, ny, nx))
+    g = synth.uniform_pm1(8, (nz, ny, nx))
+    p = poisson.solve_poisson(f, zf, LX, LY, ybc=grid.Y_WALLS)
+    r = poisson.residual7(p, f, zf, LX, LY, ybc=grid.Y_WALLS)
+    assert np.max(np.abs(r)) <= 1e-11 * np.max(np.abs(f))
+    # the periodic operator would see a different residual: the walls matter
+    rp = poisson.residual7(p, f, zf, LX, LY)
+    assert np.max(np.abs(rp)) > 1e-3 * np.max(np.abs(f))
+    q = poisson.solve_poisson(g, zf, LX, LY, ybc=grid.Y_WALLS)
+    pq = poisson.solve_poisson(2 * f - 3 * g, zf, LX, LY, ybc=grid.Y_WALLS)
+    assert np.max(np.abs(pq - (2 * p - 3 * q))) <= 1e-11 * np.max(np.abs(pq))
+    pm = poisson.solve_poisson(f[:, ::-1].copy(), zf, LX, LY, ybc=grid.Y_WALLS)
+    assert np.max(np.abs(pm - p[:, ::-1])) <= 1e-11 * np.max(np.abs(p))
