@@ -76,12 +76,19 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * 4 <= nz <= 1024. zf: host array of
  * nz+1 strictly increasing face coordinates, copied at plan time; if NULL
  * the faces are zf[k] = lz/2 (1 + tanh(beta (2k/nz - 1)) / tanh(beta))
- * (uniform when beta == 0). */
+ * (uniform when beta == 0).
+ * ybc: PF_Y_PERIODIC (the channel), or PF_Y_WALLS, zero-gradient walls at
+ * both y ends with ny cell-centred unknowns between them: the y transform
+ * is then the cosine transform (the cosine member of the Fourier-based
+ * transforms of Sec. 2.2.1) with the wavenumbers 4 sin^2(pi q / 2 ny) / dy^2.
+ * PF_Y_WALLS is implemented for poisson_plan / poisson_solve only. */
+enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;
   double lx, ly, lz;
   double beta;
   const double *zf;
+  int32_t ybc;
 } pf_grid;
 
 typedef struct pf_poisson_plan pf_poisson_plan;
@@ -89,7 +96,7 @@ typedef struct pf_pcr_plan pf_pcr_plan;
 typedef struct pf_graph pf_graph;
 
 const char *pf_last_error(void);
-int32_t pf_abi_version(void);
+int32_t pf_abi_version(void); /* 2: pf_grid carries ybc */
 
 /* Host helper: the sign-normalised rows of -L_z for boundary family bc,
  * row k = -alpha[k] x[k-1] + (alpha[k]+gamma[k]+excess[k]) x[k]

@@ -45,6 +45,8 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (g->nz < 4) return fail(PF_ERR_ARG, "nz must be >= 4 (got %d)", g->nz);
   if (!(g->lz > 0.0) && !g->zf) return fail(PF_ERR_ARG, "lz must be > 0");
   if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
+  if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS)
+    return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC or PF_Y_WALLS (got %d)", g->ybc);
   if (need_fft) {
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
 #define PF_LEN_STR(N) " " #N
@@ -234,7 +236,8 @@ struct pf_poisson_plan {
   int zchunk;
   DevArena ar;
   size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
-      o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc;
+      o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc, o_ctw;
+  int ybc = PF_Y_PERIODIC;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   unsigned long long *stat = nullptr;  // caller's pf_solve_status (device) or null
@@ -428,7 +431,7 @@ int zpad(int nz) { return (nz + kZChunk - 1) / kZChunk * kZChunk; }
 extern "C" {
 
 const char *pf_last_error(void) { return g_err.c_str(); }
-int32_t pf_abi_version(void) { return 1; }
+int32_t pf_abi_version(void) { return 2; }
 
 pf_status pf_grid_faces(const pf_grid *g, double *zf_out) {
   pf_status s = check_grid(g, false);
@@ -478,6 +481,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   pl->nx = g->nx; pl->ny = g->ny; pl->nz = nzu;
   pl->lx = g->lx; pl->ly = g->ly;
   pl->bc = bc;
+  pl->ybc = g->ybc;
   pl->kappa = bc == PF_BC_NEUMANN ? 0.0 : 1.0 / hs;
   pl->prec = precision;
   pl->nref = precision == PF_FP32_REFINE ? n_refine : 0;
@@ -496,16 +500,27 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   for (int k = 0; k < g->nz; ++k) rdzf[k] = 1.0 / dzf[k];
   for (int k = 0; k + 1 < g->nz; ++k) rdzc[k] = 2.0 / (zf[k + 2] - zf[k]);
   // y: the packed slots of x slots 0 and 1, then the complex modes 0..ny-1
-  // of every other slot pair
+  // of every other slot pair. With y walls every slot pair holds the cosine
+  // modes q = 0..ny-1 in natural order, wavenumber 4 sin^2(pi q / 2 ny) / dy^2,
+  // and ctw[q] = exp(-i pi q / 2 ny) serves the cosine transform.
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
   pl->sx_host = sx;
   for (double &v : sx) v += pl->kappa;
+  std::vector<double2> ctw;
   {
     const double dy = g->ly / g->ny;
-    for (int m = 0; m < g->ny; ++m) {
-      const long double v = std::sin((long double)M_PI * m / g->ny);
-      sy.push_back((double)(4.0L * v * v / ((long double)dy * dy)));
-    }
+    const bool walls = g->ybc == PF_Y_WALLS;
+    if (walls) sy.clear();
+    for (int h = 0; h < (walls ? 2 : 1); ++h)
+      for (int m = 0; m < g->ny; ++m) {
+        const long double v = std::sin((long double)M_PI * m / ((walls ? 2 : 1) * g->ny));
+        sy.push_back((double)(4.0L * v * v / ((long double)dy * dy)));
+      }
+    if (walls)
+      for (int q = 0; q < g->ny; ++q) {
+        const long double a = (long double)M_PI * q / (2.0L * g->ny);
+        ctw.push_back(double2{(double)std::cos(a), (double)(-std::sin(a))});
+      }
   }
   auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
   DevArena &A = pl->ar;
@@ -517,6 +532,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   pl->o_sy = A.add(sy.data(), sy.size());
   pl->o_twx_d = A.add(twxd.data(), twxd.size());
   pl->o_twy_d = A.add(twyd.data(), twyd.size());
+  pl->o_ctw = ctw.empty() ? 0 : A.add(ctw.data(), ctw.size());
   // per-plane buffers; fbar and zm stay zero for the Helmholtz (no zero mode)
   pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * nzu);
   pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * nzu);
@@ -555,6 +571,7 @@ pf_status helmholtz3d_plan(pf_poisson_plan **out, const pf_grid *g, int32_t bc, 
   if (bc != PF_BC_DIRICHLET_CENTRE && bc != PF_BC_DIRICHLET_FACE)
     return fail(PF_ERR_ARG, "bc must be PF_BC_DIRICHLET_CENTRE or PF_BC_DIRICHLET_FACE (got %d)", bc);
   if (!(s > 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and > 0");
+  if (g && g->ybc != PF_Y_PERIODIC) return fail(PF_ERR_UNSUPPORTED, "helmholtz3d_plan: y walls are not built");
   return channel_plan(out, g, precision, n_refine, stream, workspace_bytes, bc, s);
 }
 
@@ -643,28 +660,30 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
   pf_status s;
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
+  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
     // the spectrum lives in p itself, dense
     const size_t sd = (size_t)nx * ny;
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
                              : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, st));
     STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, helm ? zm : mm, nullptr, oscale,
                                                           lines, st)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
+  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
   float *W0 = (float *)pl->ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
                              : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, st));
     STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, helm ? zm : mm, nullptr,
                                                                oscale, lines, st)));
     return PF_OK;
@@ -685,6 +704,7 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
   Timing &tm = pl->tm;
   pf_status s;
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
+  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
   float *W0 = (float *)pl->ws;
   const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
@@ -702,16 +722,17 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
   }
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, st));
   const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
   STAGE(PF_STAGE_XFWD_RESID,
-        pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2, st));
+        pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2,
+                             pl->ybc == PF_Y_WALLS, st));
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, st));
   STAGE(PF_STAGE_XINV_FINAL,
         (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat)));
   if (pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, true, st));
@@ -746,6 +767,7 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
                           double gdt, double c) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "poisson_project needs a Poisson plan");
+  if (pl->ybc != PF_Y_PERIODIC) return fail(PF_ERR_UNSUPPORTED, "poisson_project: y walls are not built");
   if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
   if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");

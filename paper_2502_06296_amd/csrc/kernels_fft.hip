@@ -306,7 +306,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
     const double *__restrict__ sx, const double *__restrict__ zal, const double *__restrict__ zga,
-    const double *__restrict__ zex, int ny, int nz, double idy2, double inv_ny, size_t sp) {
+    const double *__restrict__ zex, int ny, int nz, double idy2, double inv_ny, int ywalls,
+    size_t sp) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -323,7 +324,10 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
   }
   const double ak = zal[k], gk = zga[k], dk = ak + gk + zex[k], fk = (double)N * fbar[k];
   const bool lo = k > 0, hi = k < nz - 1;
-  const int jm = j == 0 ? ny - 1 : j - 1, jp2 = j + 2 == ny ? 0 : j + 2;
+  // y neighbours of the line pair: periodic wrap, or the mirrored end row
+  // (the ghost value of a zero-gradient wall)
+  const int jm = j == 0 ? (ywalls ? 0 : ny - 1) : j - 1;
+  const int jp2 = j + 2 == ny ? (ywalls ? ny - 1 : 0) : j + 2;
   const float *Wk = W + (size_t)k * sp;
   const float *w0 = Wk + (size_t)j * N, *w1 = w0 + N;          // lines j, j+1
   const float *wm = Wk + (size_t)jm * N, *wp = Wk + (size_t)jp2 * N;
@@ -371,9 +375,18 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 
 // ------------------------------------------------------------- y forward
 
-template <typename T, int N, int TPL, int LPW>
+// WALLS: zero-gradient walls at both y ends instead of periodicity. Every
+// slot pair is then one complex line whose cosine transform
+// X_q = 2 sum_y x_y cos(pi q (2y + 1) / 2N) is written in natural order (row
+// q), for slots 0 and 1 as well: the transform has real coefficients, so it
+// maps the real and imaginary parts separately. It is computed with one
+// complex FFT of length N (Makhoul's reordering): v_n = x_{2n} and
+// v_{N-1-n} = x_{2n+1}, V = FFT(v), X_q = c_q V_q + conj(c_q) V_{N-q} with
+// c_q = exp(-i pi q / 2N) (ctw) and V_N = V_0.
+template <typename T, int N, int TPL, int LPW, bool WALLS>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
-                                                   const cplx<double> *__restrict__ tw, int nx,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw, int nx,
                                                    int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
@@ -389,6 +402,20 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
+  if constexpr (WALLS) {
+    auto srcw = [&](int n) { return src(n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n); };
+    fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, srcw, [](int, const C &) {});
+#pragma unroll
+    for (int s = 0; s < N / TPL; ++s) {
+      const int e = tid + s * NT;
+      const int l2 = e % LPW, q = e / LPW;
+      const C *b2 = lds + l2 * y_stride(N);
+      const C v1 = b2[lds_idx(q)], v2 = b2[lds_idx(q == 0 ? 0 : N - q)], c = ctw[q];
+      st2<T>(base + (size_t)q * nx + 2 * l2, c.x * v1.x - c.y * v1.y + c.x * v2.x + c.y * v2.y,
+             c.x * v1.y + c.y * v1.x + c.x * v2.y - c.y * v2.x);
+    }
+    return;
+  }
   if (ib != 0) {
     // slot pairs (2m, 2m+1), m >= 1, are the real and imaginary parts of x
     // mode m: their y transform is the complex spectrum itself, written in
@@ -431,9 +458,14 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
 // ------------------------------------------------------------- y inverse
 // Inverse of k_yfwd's layout: complex spectra in natural order for slot
 // pairs m >= 1, two packed real spectra for slots 0 and 1.
-template <typename T, int N, int TPL, int LPW>
+// WALLS: inverse of k_yfwd's cosine transform: V_q = conj(c_q) (X_q - i X_{N-q}) / 2
+// (X_N = 0), the inverse FFT of V, and the rows 2n and 2n+1 from v_n and
+// v_{N-1-n}; the 1/N is left to the x inverse's scale, as for the periodic
+// transform.
+template <typename T, int N, int TPL, int LPW, bool WALLS>
 __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
-                                                   const cplx<double> *__restrict__ tw, int nx,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw, int nx,
                                                    int nib, size_t sp) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
@@ -447,6 +479,36 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
+  if constexpr (WALLS) {
+#pragma unroll
+    for (int s = 0; s < N / TPL; ++s) {
+      const int e = tid + s * NT;
+      const int l2 = e % LPW, q = e / LPW;
+      lds[l2 * y_stride(N) + lds_idx(q)] = ld2<T>(base + (size_t)q * nx + 2 * l2);
+    }
+    __syncthreads();
+    // one thread per mode pair (q, N - q), q = 0..N/2: it reads both
+    // coefficients before it overwrites them
+    for (int e = tid; e < LPW * (N / 2 + 1); e += NT) {
+      const int l2 = e % LPW, q = e / LPW;
+      C *b2 = lds + l2 * y_stride(N);
+      const C xq = b2[lds_idx(q)];
+      const C xn = q == 0 ? mkc<double>(0.0, 0.0) : b2[lds_idx(N - q)];
+      const C cq = ctw[q];
+      // conj(c) (a - i b) / 2
+      const double ur = 0.5 * (xq.x + xn.y), ui = 0.5 * (xq.y - xn.x);
+      b2[lds_idx(q)] = mkc<double>(cq.x * ur + cq.y * ui, cq.x * ui - cq.y * ur);
+      if (q != 0 && 2 * q != N) {
+        const C cn = ctw[N - q];
+        const double wr = 0.5 * (xn.x + xq.y), wi = 0.5 * (xn.y - xq.x);
+        b2[lds_idx(N - q)] = mkc<double>(cn.x * wr + cn.y * wi, cn.x * wi - cn.y * wr);
+      }
+    }
+    __syncthreads();
+    auto dstw = [&](int n, const C &v) { dst(n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n, v); };
+    fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dstw);
+    return;
+  }
   if (ib != 0) {
     // the first pass reads the complex spectrum straight from row ky
     auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
@@ -580,7 +642,8 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
-                             const double *zga, const double *zex, double idy2, hipStream_t st) {
+                             const double *zga, const double *zex, double idy2, bool ywalls,
+                             hipStream_t st) {
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
@@ -589,7 +652,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
     hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \
                        st, f, fbar, W, out, tw, sums_p, sx, zal, zga, zex, ny, nz, idy2, 1.0 / ny,  \
-                       sp);                                                                      \
+                       ywalls ? 1 : 0, sp);                                                      \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -601,15 +664,20 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       hipStream_t st) {
+                       const cplx<double> *ctw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
     constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
-    hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
-                       dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
+    const dim3 g((unsigned)((long)nib * nz)), b(TPL * LPW);                                   \
+    if (ctw)                                                                                  \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, true>), g, b, 0, st, data, tw, ctw, nx, nib, \
+                         sp);                                                                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, false>), g, b, 0, st, data, tw, ctw, nx,     \
+                         nib, sp);                                                            \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES_Y(PF_CASE)
@@ -621,15 +689,20 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       hipStream_t st) {
+                       const cplx<double> *ctw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
     constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
-    hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW>), dim3((unsigned)((long)nib * nz)),            \
-                       dim3(TPL * LPW), 0, st, data, tw, nx, nib, sp);                        \
+    const dim3 g((unsigned)((long)nib * nz)), b(TPL * LPW);                                   \
+    if (ctw)                                                                                  \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, true>), g, b, 0, st, data, tw, ctw, nx, nib, \
+                         sp);                                                                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, false>), g, b, 0, st, data, tw, ctw, nx,     \
+                         nib, sp);                                                            \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES_Y(PF_CASE)
@@ -672,13 +745,13 @@ template hipError_t launch_xfwd<double>(int, int, const double *, double *, size
 template hipError_t launch_xfwd<float>(int, int, const double *, float *, size_t,
                                        const cplx<double> *, double *, long, hipStream_t);
 template hipError_t launch_yfwd<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        hipStream_t);
+                                        const cplx<double> *, hipStream_t);
 template hipError_t launch_yfwd<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       hipStream_t);
+                                       const cplx<double> *, hipStream_t);
 template hipError_t launch_yinv<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        hipStream_t);
+                                        const cplx<double> *, hipStream_t);
 template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       hipStream_t);
+                                       const cplx<double> *, hipStream_t);
 template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
                                                 const double *, double, long, hipStream_t,

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     L = N.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.pf_abi_version() == 1
+    assert L.pf_abi_version() == 2
 
 
 @pytest.mark.parametrize("bc", [0, 1, 2])
@@ -69,6 +69,19 @@ def _plan_status(nx, ny, nz, prec=0, nref=1, zf=None, beta=1.5):
 def test_plan_rejects_bad_grids_before_any_device_call(args, code):
     assert _plan_status(*args) == code
     assert N.lib().pf_last_error()
+
+
+def test_plan_validates_the_y_boundary_before_any_device_call():
+    for ybc, code in ((2, N.PF_ERR_ARG), (-1, N.PF_ERR_ARG)):
+        g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, ybc)
+        h, ws = C.c_void_p(), C.c_size_t(0)
+        assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == code
+        assert b"ybc" in N.lib().pf_last_error()
+    # the 3-D Helmholtz has no y-wall variant
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 1)
+    h, ws = C.c_void_p(), C.c_size_t(0)
+    assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
+        N.PF_ERR_UNSUPPORTED
 
 
 def test_plan_rejects_bad_precision_and_refinement():
