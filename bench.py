@@ -246,6 +246,40 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}))
 
 
+def ywalls(args):
+    """Poisson alone on the 1024x512x512 grid, periodic in y and with
+    zero-gradient y walls (cosine transform along y), FP64 and FP32+refine."""
+    import torch
+    import paper_2502_06296_amd as pf
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g = torch.Generator(device=dev).manual_seed(4)
+    f = torch.rand((NZ, NY, NX), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+    f -= f.mean()
+    p = torch.empty_like(f)
+    npts = NX * NY * NZ
+    out = {"workload": f"pressure Poisson alone, {NX}x{NY}x{NZ}, tanh {BETA}: y periodic vs y walls",
+           "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
+    st = torch.cuda.Stream(device=dev)
+    for ybc in ("periodic", "walls"):
+        for prec in ("fp32_refine", "fp64"):
+            log(f"ywalls: {ybc} {prec}")
+            plan = pf.poisson_plan(NX, NY, NZ, beta=BETA, precision=prec, stream=st, ybc=ybc)
+            with torch.cuda.stream(st):
+                for _ in range(args.warmup):
+                    pf.poisson_solve(plan, f, p)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(st)
+                for _ in range(args.steps):
+                    pf.poisson_solve(plan, f, p)
+                b.record(st)
+            b.synchronize()
+            ms = a.elapsed_time(b) / args.steps
+            out[f"{ybc}_{prec}"] = {"ms_per_solve": round(ms, 4), "gpoints_per_s": round(npts / ms / 1e6, 3)}
+            del plan
+    print(json.dumps(out), flush=True)
+
+
 def uneven_batch(args):
     """16 independent problems of uneven sizes (64-256 x 64-256 x 96-384, tanh
     stretching drawn per problem), each a pressure Poisson solve and the
@@ -362,12 +396,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0)
-    ap.add_argument("--workload", choices=["channel", "weak_share", "strong_slab", "uneven_batch"],
+    ap.add_argument("--workload", choices=["channel", "weak_share", "strong_slab", "uneven_batch", "ywalls"],
                     default="channel",
                     help="channel: 1024x512x512 (the headline); weak_share: the paper's per-GPU "
                          "weak-scaling share 3456x3072x30; strong_slab: a 3200x3456x28 z slab of "
                          "its strong-scaling grid; uneven_batch: 16 problems of uneven "
-                         "sizes on 1-8 internal streams, eager and from one graph")
+                         "sizes on 1-8 internal streams, eager and from one graph; ywalls: the "
+                         "Poisson solve with periodic y and with zero-gradient y walls")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X; runs on more than one GPU are not "
@@ -381,6 +416,9 @@ def main():
         return
     if args.workload == "uneven_batch":
         uneven_batch(args)
+        return
+    if args.workload == "ywalls":
+        ywalls(args)
         return
 
     import numpy as np
