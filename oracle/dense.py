@@ -60,18 +60,23 @@ def periodic_d2(n, h):
     return M / (h * h)
 
 
-def wall_d2(n, h):
+def wall_d2(n, h, value_zero=False):
     """Dense second difference on n cell centres of spacing h between two
-    zero-gradient walls: the flux through each wall face is zero, so the end
-    rows keep one neighbour."""
+    walls. Zero-gradient walls: no flux through a wall face, so the end rows
+    keep one neighbour. value_zero: the value vanishes on the wall face, half
+    a cell from the end centre, so the wall flux is (0 - x_end) / (h / 2)."""
     M = np.zeros((n, n))
     for i in range(n):
         if i > 0:
             M[i, i - 1] += 1
             M[i, i] -= 1
+        elif value_zero:
+            M[i, i] -= 2
         if i < n - 1:
             M[i, i + 1] += 1
             M[i, i] -= 1
+        elif value_zero:
+            M[i, i] -= 2
     return M / (h * h)
 
 
@@ -81,7 +86,7 @@ def l7_dense(nx, ny, zf, lx, ly, ybc=0):
     nz = len(zf) - 1
     Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
     Dx = periodic_d2(nx, lx / nx)
-    Dy = wall_d2(ny, ly / ny) if ybc == 1 else periodic_d2(ny, ly / ny)
+    Dy = wall_d2(ny, ly / ny, ybc == 2) if ybc in (1, 2) else periodic_d2(ny, ly / ny)
     Dz = lz_dense(zf, NEUMANN)
     return (np.kron(Iz, np.kron(Iy, Dx)) + np.kron(Iz, np.kron(Dy, Ix))
             + np.kron(Dz, np.kron(Iy, Ix)))
@@ -92,6 +97,8 @@ def poisson_dense(f, zf, lx, ly, ybc=0):
     appended (the solution of the projected problem when f is compatible)."""
     nz, ny, nx = f.shape
     L = l7_dense(nx, ny, zf, lx, ly, ybc)
+    if ybc == 2:                     # value-zero y walls: nonsingular
+        return np.linalg.solve(L, f.reshape(-1)).reshape(f.shape)
     w = np.repeat(np.diff(np.asarray(zf, float)), nx * ny)
     # project f onto the range of L (orthogonal to the weights' null vector)
     fv = f.reshape(-1)

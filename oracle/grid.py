@@ -23,6 +23,7 @@ DIRICHLET_FACE = 2     # w at interior faces, w = 0 on the wall faces
 
 Y_PERIODIC = 0         # y periodic (the channel)
 Y_WALLS = 1            # zero-gradient (Neumann) walls at both y ends, cell centres
+Y_DIRICHLET = 2        # value-zero (Dirichlet) walls at both y ends, cell centres
 
 
 def z_metrics(zf, dtype=np.float64):
@@ -94,6 +95,16 @@ def wall_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
     """sigma per cosine mode q = 0..n-1 (natural order) of the cell-centred
     second difference with zero-gradient walls: 4 sin^2(pi q / (2n)) / dx^2."""
     q = np.arange(n, dtype=dtype)
+    dx = dtype(length) / dtype(n)
+    s = np.sin(np.pi * q / (2 * dtype(n)))
+    return 4 * s * s / (dx * dx)
+
+
+def dirichlet_wall_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
+    """sigma per sine mode q = 0..n-1 (natural order) of the cell-centred
+    second difference whose ghost values negate the end values (value zero on
+    the walls): 4 sin^2(pi (q + 1) / (2n)) / dx^2."""
+    q = np.arange(n, dtype=dtype) + 1
     dx = dtype(length) / dtype(n)
     s = np.sin(np.pi * q / (2 * dtype(n)))
     return 4 * s * s / (dx * dx)

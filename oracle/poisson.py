@@ -55,9 +55,20 @@ def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC):
     float64 or longdouble; the result has f's dtype. ybc = grid.Y_WALLS puts
     zero-gradient walls at both y ends (cell-centred unknowns): the y
     transform is then the cosine transform and its wavenumbers those of the
-    mirrored second difference (Sec. 2.2.1)."""
+    mirrored second difference (Sec. 2.2.1). ybc = grid.Y_DIRICHLET puts walls
+    where the value vanishes: the sine transform; L7 is then nonsingular, so f
+    is not projected and p carries no pin."""
     dt = f.dtype.type
     nz, ny, nx = f.shape
+    if ybc == grid.Y_DIRICHLET:
+        Fx = transforms.rfft_packed(f, axis=2)
+        F = transforms.dst2(Fx, axis=1)
+        sy = grid.dirichlet_wall_wavenumbers(ny, ly, dt)
+        sx = grid.modified_wavenumbers(nx, lx, dt)
+        alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
+        eps3 = eps[:, None, None] + (sy[:, None] + sx[None, :])[None, :, :]
+        P = tridiag.thomas_gth(alpha[:, None, None], gamma[:, None, None], eps3, -F)
+        return transforms.irfft_packed(transforms.idst2(P, axis=1), axis=2)
     f = project_rhs(f, zf)
     Fx = transforms.rfft_packed(f, axis=2)
     if ybc == grid.Y_WALLS:
@@ -86,9 +97,12 @@ def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC):
     nz, ny, nx = p.shape
     dx, dy = dt(lx) / nx, dt(ly) / ny
     out = (np.roll(p, -1, 2) - 2 * p + np.roll(p, 1, 2)) / (dx * dx)
-    if ybc == grid.Y_WALLS:
-        pm = np.concatenate([p[:, :1], p[:, :-1]], axis=1)     # p[j-1], ghost p[-1] = p[0]
-        pp = np.concatenate([p[:, 1:], p[:, -1:]], axis=1)     # p[j+1], ghost p[ny] = p[ny-1]
+    if ybc in (grid.Y_WALLS, grid.Y_DIRICHLET):
+        # ghost rows beyond the walls: the end rows mirrored (zero gradient)
+        # or negated (value zero on the wall)
+        sg = -1 if ybc == grid.Y_DIRICHLET else 1
+        pm = np.concatenate([sg * p[:, :1], p[:, :-1]], axis=1)     # p[j-1]
+        pp = np.concatenate([p[:, 1:], sg * p[:, -1:]], axis=1)     # p[j+1]
         out += (pp - 2 * p + pm) / (dy * dy)
     else:
         out += (np.roll(p, -1, 1) - 2 * p + np.roll(p, 1, 1)) / (dy * dy)
@@ -100,8 +114,9 @@ def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC):
 
 
 def residual7(p, f, zf, lx, ly, ybc=grid.Y_PERIODIC):
-    """f - L7 p (f projected first)."""
-    return project_rhs(f, zf) - apply_L7(p, zf, lx, ly, ybc)
+    """f - L7 p (f projected first where L7 is singular)."""
+    fp = f if ybc == grid.Y_DIRICHLET else project_rhs(f, zf)
+    return fp - apply_L7(p, zf, lx, ly, ybc)
 
 
 def solve_helmholtz(r, zf, s, bc):

@@ -93,3 +93,27 @@ def idct2(X: np.ndarray, axis: int) -> np.ndarray:
     M = np.cos(np.pi * np.outer(2 * t + 1, t) / (2 * n))
     M[:, 0] = 0.5
     return np.moveaxis((X @ M.T) / n, -1, axis)
+
+
+def dst2(x: np.ndarray, axis: int) -> np.ndarray:
+    """Sine transform of ``x`` along ``axis`` for walls at both ends where the
+    value vanishes (the sine member of Sec. 2.2.1's transforms), from its
+    definition: Y_q = 2 sum_t x_t sin(pi (q + 1) (2t + 1) / (2n)), q, t =
+    0..n-1 (the eigenvectors of the second difference whose ghost values are
+    the negated end values)."""
+    x = np.moveaxis(np.asarray(x), axis, -1)
+    n = x.shape[-1]
+    t = np.arange(n)
+    M = 2.0 * np.sin(np.pi * np.outer(t + 1, 2 * t + 1) / (2 * n))
+    return np.moveaxis(x @ M.T, -1, axis)
+
+
+def idst2(Y: np.ndarray, axis: int) -> np.ndarray:
+    """Inverse of ``dst2``: x_t = (sum_{q<n-1} Y_q sin(pi (q + 1) (2t + 1) /
+    (2n)) + Y_{n-1} (-1)^t / 2) / n."""
+    Y = np.moveaxis(np.asarray(Y), axis, -1)
+    n = Y.shape[-1]
+    t = np.arange(n)
+    M = np.sin(np.pi * np.outer(2 * t + 1, t + 1) / (2 * n))
+    M[:, n - 1] *= 0.5
+    return np.moveaxis((Y @ M.T) / n, -1, axis)

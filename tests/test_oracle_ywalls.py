@@ -1,11 +1,12 @@
 """Pins of the oracle's wall-bounded y direction (paper Sec. 2.2.1: the
-cosine member of the Fourier-based transforms, for zero-gradient walls at
-both y ends), against facts that do not restate its formulas:
+cosine and sine members of the Fourier-based transforms, for zero-gradient
+and value-zero walls at both y ends), against facts that do not restate its
+formulas:
 
-* the cosine transform equals the even-extension DFT of length 2n (direct
-  summation), and its inverse undoes it;
-* the cosine vectors are eigenvectors of the dense wall second difference
-  (assembled from face fluxes) with the stated wavenumbers;
+* the cosine (sine) transform equals the even- (odd-) extension DFT of
+  length 2n by direct summation, and its inverse undoes it;
+* the cosine (sine) vectors are eigenvectors of the dense wall second
+  difference (assembled from face fluxes) with the stated wavenumbers;
 * the Poisson solve equals the dense least-squares brute force on tiny grids;
 * its 7-point residual vanishes at round-off; it is linear, and mirror
   symmetric in y.
@@ -70,4 +71,53 @@ def test_residual_linearity_and_mirror_symmetry():
     pq = poisson.solve_poisson(2 * f - 3 * g, zf, LX, LY, ybc=grid.Y_WALLS)
     assert np.max(np.abs(pq - (2 * p - 3 * q))) <= 1e-11 * np.max(np.abs(pq))
     pm = poisson.solve_poisson(f[:, ::-1].copy(), zf, LX, LY, ybc=grid.Y_WALLS)
+    assert np.max(np.abs(pm - p[:, ::-1])) <= 1e-11 * np.max(np.abs(p))
+
+
+# value-zero (Dirichlet) y walls: the sine transform
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 12])
+def test_sine_transform_is_the_odd_extension_dft(n):
+    rng = np.random.default_rng(40 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    e = np.concatenate([x, -x[::-1]])
+    E = transforms.dft_direct(e)
+    q = np.arange(1, n + 1)
+    # the odd extension's DFT at mode q is -i exp(i pi q / 2n) Y_{q-1}
+    ref = 1j * np.exp(-1j * np.pi * q / (2 * n)) * E[1:n + 1]
+    Y = transforms.dst2(x, axis=0)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(transforms.idst2(Y, axis=0) - x)) <= 1e-13 * n
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 13])
+def test_sine_vectors_diagonalise_the_value_zero_second_difference(n):
+    h = 0.29
+    D = dense.wall_d2(n, h, value_zero=True)
+    sig = grid.dirichlet_wall_wavenumbers(n, n * h)
+    t = np.arange(n)
+    for q in range(n):
+        e = np.sin(np.pi * (q + 1) * (2 * t + 1) / (2 * n))
+        assert np.max(np.abs(D @ e + sig[q] * e)) <= 1e-10 * max(1.0, sig[q])
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,seed", [
+    (4, 3, 5, 1.5, 10), (2, 4, 6, 0.0, 11), (6, 5, 4, 2.0, 12), (4, 1, 5, 1.0, 13),
+])
+def test_dirichlet_solve_matches_dense_brute_force(nx, ny, nz, beta, seed):
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    f = synth.uniform_pm1(seed, (nz, ny, nx))
+    got = poisson.solve_poisson(f, zf, LX, LY, ybc=grid.Y_DIRICHLET)
+    ref = dense.poisson_dense(f, zf, LX, LY, ybc=2)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_dirichlet_residual_and_no_mean_projection():
+    nx, ny, nz = 16, 12, 20
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    f = synth.uniform_pm1(17, (nz, ny, nx)) + 0.5     # a non-zero mean stays in the problem
+    p = poisson.solve_poisson(f, zf, LX, LY, ybc=grid.Y_DIRICHLET)
+    lp = poisson.apply_L7(p, zf, LX, LY, ybc=grid.Y_DIRICHLET)
+    assert np.max(np.abs(lp - f)) <= 1e-11 * np.max(np.abs(f))
+    pm = poisson.solve_poisson(f[:, ::-1].copy(), zf, LX, LY, ybc=grid.Y_DIRICHLET)
     assert np.max(np.abs(pm - p[:, ::-1])) <= 1e-11 * np.max(np.abs(p))
