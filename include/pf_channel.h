@@ -77,12 +77,15 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * nz+1 strictly increasing face coordinates, copied at plan time; if NULL
  * the faces are zf[k] = lz/2 (1 + tanh(beta (2k/nz - 1)) / tanh(beta))
  * (uniform when beta == 0).
- * ybc: PF_Y_PERIODIC (the channel), or PF_Y_WALLS, zero-gradient walls at
+ * ybc: PF_Y_PERIODIC (the channel); PF_Y_WALLS, zero-gradient walls at
  * both y ends with ny cell-centred unknowns between them: the y transform
  * is then the cosine transform (the cosine member of the Fourier-based
- * transforms of Sec. 2.2.1) with the wavenumbers 4 sin^2(pi q / 2 ny) / dy^2.
- * PF_Y_WALLS is implemented for poisson_plan / poisson_solve only. */
-enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1 };
+ * transforms of Sec. 2.2.1) with the wavenumbers 4 sin^2(pi q / 2 ny) / dy^2;
+ * PF_Y_DIRICHLET, walls where the solution vanishes: the sine transform,
+ * wavenumbers 4 sin^2(pi (q + 1) / 2 ny) / dy^2, a nonsingular operator (f is
+ * not projected and p is not pinned). Walls are implemented for
+ * poisson_plan / poisson_solve only. */
+enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;
   double lx, ly, lz;

@@ -45,8 +45,8 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (g->nz < 4) return fail(PF_ERR_ARG, "nz must be >= 4 (got %d)", g->nz);
   if (!(g->lz > 0.0) && !g->zf) return fail(PF_ERR_ARG, "lz must be > 0");
   if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
-  if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS)
-    return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC or PF_Y_WALLS (got %d)", g->ybc);
+  if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS && g->ybc != PF_Y_DIRICHLET)
+    return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC, PF_Y_WALLS or PF_Y_DIRICHLET (got %d)", g->ybc);
   if (need_fft) {
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
 #define PF_LEN_STR(N) " " #N
@@ -501,19 +501,21 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   for (int k = 0; k + 1 < g->nz; ++k) rdzc[k] = 2.0 / (zf[k + 2] - zf[k]);
   // y: the packed slots of x slots 0 and 1, then the complex modes 0..ny-1
   // of every other slot pair. With y walls every slot pair holds the cosine
-  // modes q = 0..ny-1 in natural order, wavenumber 4 sin^2(pi q / 2 ny) / dy^2,
-  // and ctw[q] = exp(-i pi q / 2 ny) serves the cosine transform.
+  // modes q = 0..ny-1 in natural order, wavenumber 4 sin^2(pi q / 2 ny) / dy^2
+  // (zero-gradient walls), or the sine modes, 4 sin^2(pi (q + 1) / 2 ny) / dy^2
+  // (value-zero walls); ctw[q] = exp(-i pi q / 2 ny) serves both transforms.
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
   pl->sx_host = sx;
   for (double &v : sx) v += pl->kappa;
   std::vector<double2> ctw;
   {
     const double dy = g->ly / g->ny;
-    const bool walls = g->ybc == PF_Y_WALLS;
+    const bool walls = g->ybc != PF_Y_PERIODIC;
+    const int q0 = g->ybc == PF_Y_DIRICHLET ? 1 : 0;
     if (walls) sy.clear();
     for (int h = 0; h < (walls ? 2 : 1); ++h)
       for (int m = 0; m < g->ny; ++m) {
-        const long double v = std::sin((long double)M_PI * m / ((walls ? 2 : 1) * g->ny));
+        const long double v = std::sin((long double)M_PI * (m + q0) / ((walls ? 2 : 1) * g->ny));
         sy.push_back((double)(4.0L * v * v / ((long double)dy * dy)));
       }
     if (walls)
@@ -633,17 +635,19 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
 static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
                                  const pf::DivArgs *div = nullptr) {
   // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
-  // and the chain solves (L - kappa) u' = r, so u = -kappa u'
+  // and the chain solves (L - kappa) u' = r, so u = -kappa u'. Value-zero y
+  // walls: no singular mode either (nothing projected, no pin)
   const double scale = 1.0 / ((double)pl->nx * pl->ny);
   const bool helm = pl->bc != PF_BC_NEUMANN;
   const double oscale = helm ? -pl->kappa * scale : scale;
+  const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET;
   if (pl->stat) PF_HIP(pf::launch_status_reset(pl->stat, st));
   if (pl->prec != PF_FP32_REFINE) {
-    pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, helm, oscale);
+    pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, nozero, oscale);
     if (!s && pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, false, st));
     return s;
   }
-  return poisson_enqueue_refined(pl, rhs, p, st, div, helm, oscale);
+  return poisson_enqueue_refined(pl, rhs, p, st, div, nozero, oscale);
 }
 
 // float64, or float32 without a correction
@@ -660,30 +664,32 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
   pf_status s;
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
-  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
+  const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
+  const int yw = pl->ybc;
     // the spectrum lives in p itself, dense
     const size_t sd = (size_t)nx * ny;
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
                              : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, yw, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, yw, st));
     STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, helm ? zm : mm, nullptr, oscale,
                                                           lines, st)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
-  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
+  const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
+  const int yw = pl->ybc;
   float *W0 = (float *)pl->ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
                              : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, st));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
     STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, helm ? zm : mm, nullptr,
                                                                oscale, lines, st)));
     return PF_OK;
@@ -704,7 +710,8 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
   Timing &tm = pl->tm;
   pf_status s;
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
-  const double2 *ctw = pl->ybc == PF_Y_WALLS ? A.at<double2>(pl->o_ctw) : nullptr;
+  const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
+  const int yw = pl->ybc;
   float *W0 = (float *)pl->ws;
   const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
@@ -722,17 +729,17 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
   }
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
   const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
   STAGE(PF_STAGE_XFWD_RESID,
         pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2,
-                             pl->ybc == PF_Y_WALLS, st));
+                             pl->ybc, st));
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, st));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st));
   STAGE(PF_STAGE_XINV_FINAL,
         (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat)));
   if (pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, true, st));

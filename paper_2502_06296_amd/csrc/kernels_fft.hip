@@ -324,10 +324,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
   }
   const double ak = zal[k], gk = zga[k], dk = ak + gk + zex[k], fk = (double)N * fbar[k];
   const bool lo = k > 0, hi = k < nz - 1;
-  // y neighbours of the line pair: periodic wrap, or the mirrored end row
-  // (the ghost value of a zero-gradient wall)
+  // y neighbours of the line pair: periodic wrap, or the end row itself as
+  // the ghost value beyond a wall, mirrored (ywalls 1, zero gradient) or
+  // negated (ywalls 2, value zero on the wall)
   const int jm = j == 0 ? (ywalls ? 0 : ny - 1) : j - 1;
   const int jp2 = j + 2 == ny ? (ywalls ? ny - 1 : 0) : j + 2;
+  const double gm = (ywalls == 2 && j == 0) ? -1.0 : 1.0;
+  const double gp = (ywalls == 2 && j + 2 == ny) ? -1.0 : 1.0;
   const float *Wk = W + (size_t)k * sp;
   const float *w0 = Wk + (size_t)j * N, *w1 = w0 + N;          // lines j, j+1
   const float *wm = Wk + (size_t)jm * N, *wp = Wk + (size_t)jp2 * N;
@@ -344,7 +347,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
       split_pair<double>(buf[lds_idx(q)], buf[lds_idx(N - q)], A, B);
     }
     const C c0 = ld2<float>(w0 + 2 * q), c1 = ld2<float>(w1 + 2 * q);
-    const C cm = ld2<float>(wm + 2 * q), cp = ld2<float>(wp + 2 * q);
+    const C cm0 = ld2<float>(wm + 2 * q), cp0 = ld2<float>(wp + 2 * q);
+    const C cm = mkc<double>(gm * cm0.x, gm * cm0.y), cp = mkc<double>(gp * cp0.x, gp * cp0.y);
     C za = mkc<double>(0.0, 0.0), zb = za;
     if (lo) {
       const C a0 = ld2<float>(w0 - sp + 2 * q), a1 = ld2<float>(w1 - sp + 2 * q);
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 
 // ------------------------------------------------------------- y forward
 
-// WALLS: zero-gradient walls at both y ends instead of periodicity. Every
+// YW = 1: zero-gradient walls at both y ends instead of periodicity. Every
 // slot pair is then one complex line whose cosine transform
 // X_q = 2 sum_y x_y cos(pi q (2y + 1) / 2N) is written in natural order (row
 // q), for slots 0 and 1 as well: the transform has real coefficients, so it
@@ -383,7 +387,11 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 // complex FFT of length N (Makhoul's reordering): v_n = x_{2n} and
 // v_{N-1-n} = x_{2n+1}, V = FFT(v), X_q = c_q V_q + conj(c_q) V_{N-q} with
 // c_q = exp(-i pi q / 2N) (ctw) and V_N = V_0.
-template <typename T, int N, int TPL, int LPW, bool WALLS>
+// YW = 2: value-zero walls, the sine transform
+// Y_q = 2 sum_y x_y sin(pi (q + 1) (2y + 1) / 2N), which is the cosine
+// transform of (-1)^y x_y read backwards (Y_q = X'_{N-1-q}): the odd rows are
+// negated as they are read and mode q is written to row N-1-q.
+template <typename T, int N, int TPL, int LPW, int YW>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
@@ -402,8 +410,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
-  if constexpr (WALLS) {
-    auto srcw = [&](int n) { return src(n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n); };
+  if constexpr (YW != 0) {
+    auto srcw = [&](int n) {
+      const int y = n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n;
+      const C v = src(y);
+      return (YW == 2 && (y & 1)) ? mkc<double>(-v.x, -v.y) : v;
+    };
     fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, srcw, [](int, const C &) {});
 #pragma unroll
     for (int s = 0; s < N / TPL; ++s) {
@@ -411,7 +423,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
       const int l2 = e % LPW, q = e / LPW;
       const C *b2 = lds + l2 * y_stride(N);
       const C v1 = b2[lds_idx(q)], v2 = b2[lds_idx(q == 0 ? 0 : N - q)], c = ctw[q];
-      st2<T>(base + (size_t)q * nx + 2 * l2, c.x * v1.x - c.y * v1.y + c.x * v2.x + c.y * v2.y,
+      const int row = YW == 2 ? N - 1 - q : q;
+      st2<T>(base + (size_t)row * nx + 2 * l2, c.x * v1.x - c.y * v1.y + c.x * v2.x + c.y * v2.y,
              c.x * v1.y + c.y * v1.x + c.x * v2.y - c.y * v2.x);
     }
     return;
@@ -458,11 +471,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
 // ------------------------------------------------------------- y inverse
 // Inverse of k_yfwd's layout: complex spectra in natural order for slot
 // pairs m >= 1, two packed real spectra for slots 0 and 1.
-// WALLS: inverse of k_yfwd's cosine transform: V_q = conj(c_q) (X_q - i X_{N-q}) / 2
-// (X_N = 0), the inverse FFT of V, and the rows 2n and 2n+1 from v_n and
-// v_{N-1-n}; the 1/N is left to the x inverse's scale, as for the periodic
-// transform.
-template <typename T, int N, int TPL, int LPW, bool WALLS>
+// YW != 0: inverse of k_yfwd's cosine (sine) transform: V_q = conj(c_q)
+// (X_q - i X_{N-q}) / 2 (X_N = 0), the inverse FFT of V, and the rows 2n and
+// 2n+1 from v_n and v_{N-1-n} (sine: X_q is read from row N-1-q and the odd
+// rows negated); the 1/N is left to the x inverse's scale, as for the
+// periodic transform.
+template <typename T, int N, int TPL, int LPW, int YW>
 __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
@@ -479,12 +493,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
-  if constexpr (WALLS) {
+  if constexpr (YW != 0) {
 #pragma unroll
     for (int s = 0; s < N / TPL; ++s) {
       const int e = tid + s * NT;
       const int l2 = e % LPW, q = e / LPW;
-      lds[l2 * y_stride(N) + lds_idx(q)] = ld2<T>(base + (size_t)q * nx + 2 * l2);
+      const int row = YW == 2 ? N - 1 - q : q;
+      lds[l2 * y_stride(N) + lds_idx(q)] = ld2<T>(base + (size_t)row * nx + 2 * l2);
     }
     __syncthreads();
     // one thread per mode pair (q, N - q), q = 0..N/2: it reads both
@@ -505,7 +520,10 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
       }
     }
     __syncthreads();
-    auto dstw = [&](int n, const C &v) { dst(n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n, v); };
+    auto dstw = [&](int n, const C &v) {
+      const int y = n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n;
+      dst(y, (YW == 2 && (y & 1)) ? mkc<double>(-v.x, -v.y) : v);
+    };
     fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dstw);
     return;
   }
@@ -642,7 +660,7 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
-                             const double *zga, const double *zex, double idy2, bool ywalls,
+                             const double *zga, const double *zex, double idy2, int ywalls,
                              hipStream_t st) {
   switch (nx) {
 #define PF_CASE(N)                                                                               \
@@ -652,7 +670,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
     hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \
                        st, f, fbar, W, out, tw, sums_p, sx, zal, zga, zex, ny, nz, idy2, 1.0 / ny,  \
-                       ywalls ? 1 : 0, sp);                                                      \
+                       ywalls, sp);                                                              \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -664,7 +682,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, hipStream_t st) {
+                       const cplx<double> *ctw, int yw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -672,12 +690,16 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     const dim3 g((unsigned)((long)nib * nz)), b(TPL * LPW);                                   \
-    if (ctw)                                                                                  \
-      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, true>), g, b, 0, st, data, tw, ctw, nx, nib, \
+    if (yw != 0 && !ctw) return hipErrorInvalidValue;                                         \
+    if (yw == 1)                                                                              \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 1>), g, b, 0, st, data, tw, ctw, nx, nib,    \
+                         sp);                                                                 \
+    else if (yw == 2)                                                                         \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 2>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
     else                                                                                      \
-      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, false>), g, b, 0, st, data, tw, ctw, nx,     \
-                         nib, sp);                                                            \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 0>), g, b, 0, st, data, tw, ctw, nx, nib,    \
+                         sp);                                                                 \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES_Y(PF_CASE)
@@ -689,7 +711,7 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, hipStream_t st) {
+                       const cplx<double> *ctw, int yw, hipStream_t st) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -697,12 +719,16 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
     if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
     const int nib = nx / (2 * LPW);                                                           \
     const dim3 g((unsigned)((long)nib * nz)), b(TPL * LPW);                                   \
-    if (ctw)                                                                                  \
-      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, true>), g, b, 0, st, data, tw, ctw, nx, nib, \
+    if (yw != 0 && !ctw) return hipErrorInvalidValue;                                         \
+    if (yw == 1)                                                                              \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 1>), g, b, 0, st, data, tw, ctw, nx, nib,    \
+                         sp);                                                                 \
+    else if (yw == 2)                                                                         \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 2>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
     else                                                                                      \
-      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, false>), g, b, 0, st, data, tw, ctw, nx,     \
-                         nib, sp);                                                            \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 0>), g, b, 0, st, data, tw, ctw, nx, nib,    \
+                         sp);                                                                 \
     return hipGetLastError();                                                                 \
   }
     PF_FOR_FFT_SIZES_Y(PF_CASE)
@@ -745,13 +771,13 @@ template hipError_t launch_xfwd<double>(int, int, const double *, double *, size
 template hipError_t launch_xfwd<float>(int, int, const double *, float *, size_t,
                                        const cplx<double> *, double *, long, hipStream_t);
 template hipError_t launch_yfwd<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        const cplx<double> *, hipStream_t);
+                                        const cplx<double> *, int, hipStream_t);
 template hipError_t launch_yfwd<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       const cplx<double> *, hipStream_t);
+                                       const cplx<double> *, int, hipStream_t);
 template hipError_t launch_yinv<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        const cplx<double> *, hipStream_t);
+                                        const cplx<double> *, int, hipStream_t);
 template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       const cplx<double> *, hipStream_t);
+                                       const cplx<double> *, int, hipStream_t);
 template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
                                                 const double *, double, long, hipStream_t,

@@ -111,22 +111,24 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 // problem, R = X(f - fbar[k]) - L7 of the iterate whose x spectrum (times ny)
 // is W (float32, after the y inverse); the x operator is -sx per packed
 // slot, the z rows (zal, zga, zex). Also the float64 line sums of the
-// iterate. R is float32. ywalls: the y second difference mirrors the end
-// rows (zero-gradient walls) instead of wrapping.
+// iterate. R is float32. ywalls: the y second difference wraps (0), or takes
+// the end rows mirrored (1, zero-gradient walls) or negated (2, value-zero
+// walls) as the ghost values beyond the walls.
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
-                             const double *zga, const double *zex, double idy2, bool ywalls,
+                             const double *zga, const double *zex, double idy2, int ywalls,
                              hipStream_t st);
-// y forward / inverse, in place on the packed (T) data. A non-null ctw
-// (exp(-i pi q / 2 ny), q = 0..ny-1) selects the cosine transform of
-// zero-gradient y walls, in natural order for every slot pair.
+// y forward / inverse, in place on the packed (T) data. yw = 1 (2) selects
+// the cosine (sine) transform of zero-gradient (value-zero) y walls, in
+// natural order for every slot pair; it needs ctw = exp(-i pi q / 2 ny),
+// q = 0..ny-1.
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, hipStream_t st);
+                       const cplx<double> *ctw, int yw, hipStream_t st);
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, hipStream_t st);
+                       const cplx<double> *ctw, int yw, hipStream_t st);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k]; with in2 (requires zm) the inverse of
 // in + in2, summed in float64.

@@ -60,13 +60,14 @@ class PoissonPlan:
             self.handle = None
 
 
-YBCS = {"periodic": 0, "walls": 1}
+YBCS = {"periodic": 0, "walls": 1, "dirichlet": 2}
 
 
 def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
                  zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic"):
     """Plan the channel Poisson solve; allocates the workspace as a torch tensor.
-    ybc "walls": zero-gradient walls at both y ends (cosine transform in y)."""
+    ybc "walls": zero-gradient walls at both y ends (cosine transform in y);
+    "dirichlet": value-zero walls at both y ends (sine transform in y)."""
     import torch
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     yb = YBCS[ybc] if isinstance(ybc, str) else int(ybc)

@@ -72,7 +72,7 @@ def test_plan_rejects_bad_grids_before_any_device_call(args, code):
 
 
 def test_plan_validates_the_y_boundary_before_any_device_call():
-    for ybc, code in ((2, N.PF_ERR_ARG), (-1, N.PF_ERR_ARG)):
+    for ybc, code in ((3, N.PF_ERR_ARG), (-1, N.PF_ERR_ARG)):
         g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, ybc)
         h, ws = C.c_void_p(), C.c_size_t(0)
         assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == code

@@ -1,7 +1,7 @@
-"""Poisson solve with zero-gradient walls at both y ends (the cosine
-transform of Sec. 2.2.1 along y) through the C ABI against the CPU oracle,
-element by element, in the three precisions; and the entry points that do
-not take y walls.
+"""Poisson solve with walls at both y ends -- zero-gradient (the cosine
+transform of Sec. 2.2.1 along y) and value-zero (the sine transform) --
+through the C ABI against the CPU oracle, element by element, in the three
+precisions; and the entry points that do not take y walls.
 
 Bars (relative L2): float64 <= 1e-12, float32 with one float64-residual
 correction <= 1e-10, plain float32 <= 1e-5.
@@ -27,9 +27,12 @@ def _dev():
     return torch.device("cuda", 0)
 
 
-def _solve_gpu(f, zf, beta, prec):
+YBC = {"walls": ogrid.Y_WALLS, "dirichlet": ogrid.Y_DIRICHLET}
+
+
+def _solve_gpu(f, zf, beta, prec, ybc="walls"):
     nz, ny, nx = f.shape
-    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, ybc="walls")
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, ybc=ybc)
     rhs = torch.from_numpy(f).to(_dev())
     p = torch.empty_like(rhs)
     pf.poisson_solve(plan, rhs, p)
@@ -49,27 +52,29 @@ CASES = [
 
 @pytest.mark.parametrize("nx,ny,nz,beta,seed", CASES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
-def test_ywalls_poisson_matches_oracle(nx, ny, nz, beta, seed, prec):
-    print(f"y walls {prec} {nx}x{ny}x{nz} beta={beta} seed={seed}", flush=True)
+@pytest.mark.parametrize("ybc", ["walls", "dirichlet"])
+def test_ywalls_poisson_matches_oracle(nx, ny, nz, beta, seed, prec, ybc):
+    print(f"y {ybc} {prec} {nx}x{ny}x{nz} beta={beta} seed={seed}", flush=True)
     zf = synth.tanh_faces(nz, 2.0, beta)
     f = synth.uniform_pm1(300 + seed, (nz, ny, nx))
-    ref = op.solve_poisson(f, zf, LX, LY, ybc=ogrid.Y_WALLS)
-    got = _solve_gpu(f, zf, beta, prec)
+    ref = op.solve_poisson(f, zf, LX, LY, ybc=YBC[ybc])
+    got = _solve_gpu(f, zf, beta, prec, ybc)
     err = op.rel_l2(got, ref)
     print(f"  rel L2 {err:.3e}", flush=True)
     assert err < TOL[prec]
 
 
-def test_ywalls_residual_at_512x256x64():
+@pytest.mark.parametrize("ybc", ["walls", "dirichlet"])
+def test_ywalls_residual_at_512x256x64(ybc):
     nx, ny, nz, beta = 512, 256, 64, 1.5
     zf = synth.tanh_faces(nz, 2.0, beta)
     f = synth.uniform_pm1(310, (nz, ny, nx))
-    p64 = _solve_gpu(f, zf, beta, "fp64")
-    r = op.residual7(p64, f, zf, LX, LY, ybc=ogrid.Y_WALLS)
+    p64 = _solve_gpu(f, zf, beta, "fp64", ybc)
+    r = op.residual7(p64, f, zf, LX, LY, ybc=YBC[ybc])
     res = np.max(np.abs(r)) / np.max(np.abs(f))
     print(f"fp64 7-point residual {res:.2e}", flush=True)
     assert res < 1e-12
-    p32 = _solve_gpu(f, zf, beta, "fp32_refine")
+    p32 = _solve_gpu(f, zf, beta, "fp32_refine", ybc)
     err = op.rel_l2(p32, p64)
     print(f"fp32_refine vs fp64 {err:.2e}", flush=True)
     assert err < 1e-10
