@@ -247,8 +247,9 @@ def copy_calibration(nbytes):
 
 
 def ywalls(args):
-    """Poisson alone on the 1024x512x512 grid, periodic in y and with
-    zero-gradient y walls (cosine transform along y), FP64 and FP32+refine."""
+    """Poisson alone on the 1024x512x512 grid, periodic in y, with
+    zero-gradient y walls (cosine transform along y) and with value-zero y
+    walls (sine transform), FP64 and FP32+refine."""
     import torch
     import paper_2502_06296_amd as pf
     dev = torch.device("cuda", 0)
@@ -258,10 +259,11 @@ def ywalls(args):
     f -= f.mean()
     p = torch.empty_like(f)
     npts = NX * NY * NZ
-    out = {"workload": f"pressure Poisson alone, {NX}x{NY}x{NZ}, tanh {BETA}: y periodic vs y walls",
+    out = {"workload": f"pressure Poisson alone, {NX}x{NY}x{NZ}, tanh {BETA}: y periodic, zero-gradient "
+                       "y walls, value-zero y walls",
            "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
     st = torch.cuda.Stream(device=dev)
-    for ybc in ("periodic", "walls"):
+    for ybc in ("periodic", "walls", "dirichlet"):
         for prec in ("fp32_refine", "fp64"):
             log(f"ywalls: {ybc} {prec}")
             plan = pf.poisson_plan(NX, NY, NZ, beta=BETA, precision=prec, stream=st, ybc=ybc)
