@@ -116,15 +116,17 @@ def helmholtz_dense(r, zf, s, bc):
     return np.linalg.solve(M, r.reshape(shp[0], -1)).reshape(shp)
 
 
-def helmholtz3d_dense(r, zf, s, bc, lx, ly):
+def helmholtz3d_dense(r, zf, s, bc, lx, ly, ybc=0):
     """Dense solve of (I - s L) u = r, L the 3-D operator of the staggered
-    grid: periodic second differences in x and y plus L_z of family bc
-    (C-order (n, ny, nx) flattening, n = nz or nz - 1)."""
+    grid: periodic second differences in x, in y periodic (ybc 0) or between
+    zero-gradient (1) or value-zero (2) walls, plus L_z of family bc (C-order
+    (n, ny, nx) flattening, n = nz or nz - 1)."""
     n, ny, nx = r.shape
     Ix, Iy = np.eye(nx), np.eye(ny)
     Dz = lz_dense(zf, bc)
     Iz = np.eye(Dz.shape[0])
-    L = (np.kron(Iz, np.kron(Iy, periodic_d2(nx, lx / nx))) + np.kron(Iz, np.kron(periodic_d2(ny, ly / ny), Ix))
+    Dy = wall_d2(ny, ly / ny, ybc == 2) if ybc in (1, 2) else periodic_d2(ny, ly / ny)
+    L = (np.kron(Iz, np.kron(Iy, periodic_d2(nx, lx / nx))) + np.kron(Iz, np.kron(Dy, Ix))
          + np.kron(Dz, np.kron(Iy, Ix)))
     M = np.eye(L.shape[0]) - s * L
     return np.linalg.solve(M, r.reshape(-1)).reshape(r.shape)

@@ -129,24 +129,35 @@ def solve_helmholtz(r, zf, s, bc):
     return tridiag.thomas_gth((s * alpha)[shp], (s * gamma)[shp], (1 + s * eps)[shp], r)
 
 
-def solve_helmholtz3d(r, zf, s, bc, lx, ly):
-    """u with (I - s L) u = r, L the 3-D second-order operator: periodic in x
-    and y, L_z of family bc in z (eq. proj2_ustar, the fully implicit
-    diffusion of a Runge-Kutta substep with s = gamma_k nu dt / 2). Same route
-    as the Poisson solve: packed transforms in x and y, then per slot pair
-    the z rows (s alpha, s gamma, 1 + s excess + s (sigma_x + sigma_y)), all
-    non-negative, so there is no singular column."""
+def _y_transform(ybc):
+    """(forward, inverse, wavenumbers) of the y direction for ybc."""
+    if ybc == grid.Y_WALLS:
+        return transforms.dct2, transforms.idct2, grid.wall_wavenumbers
+    if ybc == grid.Y_DIRICHLET:
+        return transforms.dst2, transforms.idst2, grid.dirichlet_wall_wavenumbers
+    return transforms.rfft_packed, transforms.irfft_packed, grid.modified_wavenumbers
+
+
+def solve_helmholtz3d(r, zf, s, bc, lx, ly, ybc=grid.Y_PERIODIC):
+    """u with (I - s L) u = r, L the 3-D second-order operator: periodic in x,
+    periodic in y or with y walls (ybc, as for the Poisson solve: a field
+    at cell-centre y positions), L_z of family bc in z (eq. proj2_ustar, the
+    fully implicit diffusion of a Runge-Kutta substep with s = gamma_k nu dt /
+    2). Same route as the Poisson solve: transforms in x and y, then per slot
+    pair the z rows (s alpha, s gamma, 1 + s excess + s (sigma_x + sigma_y)),
+    all non-negative, so there is no singular column."""
     dt = r.dtype.type
     n, ny, nx = r.shape
     s = dt(s)
-    R = transforms.rfft_packed(transforms.rfft_packed(r, axis=2), axis=1)
+    fwd, inv, wavenumbers = _y_transform(ybc)
+    R = fwd(transforms.rfft_packed(r, axis=2), axis=1)
     sx = grid.modified_wavenumbers(nx, lx, dt)
-    sy = grid.modified_wavenumbers(ny, ly, dt)
+    sy = wavenumbers(ny, ly, dt)
     alpha, gamma, eps = grid.zop(zf, bc, dt)
     shift = sy[:, None] + sx[None, :]
     diag = (1 + s * eps)[:, None, None] + s * shift[None, :, :]
     U = tridiag.thomas_gth((s * alpha)[:, None, None], (s * gamma)[:, None, None], diag, R)
-    return transforms.irfft_packed(transforms.irfft_packed(U, axis=1), axis=2)
+    return transforms.irfft_packed(inv(U, axis=1), axis=2)
 
 
 def rel_l2(x, ref):

@@ -121,3 +121,15 @@ def test_dirichlet_residual_and_no_mean_projection():
     assert np.max(np.abs(lp - f)) <= 1e-11 * np.max(np.abs(f))
     pm = poisson.solve_poisson(f[:, ::-1].copy(), zf, LX, LY, ybc=grid.Y_DIRICHLET)
     assert np.max(np.abs(pm - p[:, ::-1])) <= 1e-11 * np.max(np.abs(p))
+
+
+@pytest.mark.parametrize("ybc,dense_ybc", [(grid.Y_WALLS, 1), (grid.Y_DIRICHLET, 2)])
+@pytest.mark.parametrize("bc", [grid.DIRICHLET_CENTRE, grid.DIRICHLET_FACE])
+def test_helmholtz3d_with_y_walls_matches_dense(ybc, dense_ybc, bc):
+    nx, ny, nz, s = 4, 5, 6, 0.07
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    n = nz if bc == grid.DIRICHLET_CENTRE else nz - 1
+    r = synth.uniform_pm1(50 + ybc + 3 * bc, (n, ny, nx))
+    got = poisson.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=ybc)
+    ref = dense.helmholtz3d_dense(r, zf, s, bc, LX, LY, ybc=dense_ybc)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
