@@ -84,7 +84,9 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * PF_Y_DIRICHLET, walls where the solution vanishes: the sine transform,
  * wavenumbers 4 sin^2(pi (q + 1) / 2 ny) / dy^2, a nonsingular operator (f is
  * not projected and p is not pinned). Walls are implemented for
- * poisson_plan / poisson_solve only. */
+ * poisson_plan / poisson_solve and for helmholtz3d_plan / helmholtz3d_solve
+ * (a field at cell-centre y positions); poisson_project returns
+ * PF_ERR_UNSUPPORTED for a plan with y walls. */
 enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;

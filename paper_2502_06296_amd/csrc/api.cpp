@@ -573,7 +573,6 @@ pf_status helmholtz3d_plan(pf_poisson_plan **out, const pf_grid *g, int32_t bc, 
   if (bc != PF_BC_DIRICHLET_CENTRE && bc != PF_BC_DIRICHLET_FACE)
     return fail(PF_ERR_ARG, "bc must be PF_BC_DIRICHLET_CENTRE or PF_BC_DIRICHLET_FACE (got %d)", bc);
   if (!(s > 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and > 0");
-  if (g && g->ybc != PF_Y_PERIODIC) return fail(PF_ERR_UNSUPPORTED, "helmholtz3d_plan: y walls are not built");
   return channel_plan(out, g, precision, n_refine, stream, workspace_bytes, bc, s);
 }
 

@@ -77,11 +77,10 @@ def test_plan_validates_the_y_boundary_before_any_device_call():
         h, ws = C.c_void_p(), C.c_size_t(0)
         assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == code
         assert b"ybc" in N.lib().pf_last_error()
-    # the 3-D Helmholtz has no y-wall variant
-    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 1)
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 3)
     h, ws = C.c_void_p(), C.c_size_t(0)
     assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
-        N.PF_ERR_UNSUPPORTED
+        N.PF_ERR_ARG
 
 
 def test_plan_rejects_bad_precision_and_refinement():

@@ -1,7 +1,8 @@
 """Poisson solve with walls at both y ends -- zero-gradient (the cosine
 transform of Sec. 2.2.1 along y) and value-zero (the sine transform) --
 through the C ABI against the CPU oracle, element by element, in the three
-precisions; and the entry points that do not take y walls.
+precisions, for the Poisson solve and the 3-D Helmholtz; and the projection,
+which does not take y walls.
 
 Bars (relative L2): float64 <= 1e-12, float32 with one float64-residual
 correction <= 1e-10, plain float32 <= 1e-5.
@@ -88,3 +89,31 @@ def test_projection_rejects_a_y_wall_plan():
     with pytest.raises(N.PfError) as e:
         pf.poisson_project(plan, t[0], t[1], t[2], t[3], t[4], 0.1, 0.0)
     assert e.value.code == N.PF_ERR_UNSUPPORTED
+
+
+H3D_CASES = [
+    (64, 64, 32, 1.5, ogrid.DIRICHLET_CENTRE, 1e-3, 0),
+    (128, 96, 40, 2.0, ogrid.DIRICHLET_FACE, 0.05, 1),     # radix-3 y, ragged chunks
+    (96, 3200, 6, 1.2, ogrid.DIRICHLET_CENTRE, 1e-2, 2),   # radix-5 y lines
+]
+H3D_BC = {ogrid.DIRICHLET_CENTRE: "dirichlet_centre", ogrid.DIRICHLET_FACE: "dirichlet_face"}
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,bc,s,seed", H3D_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+@pytest.mark.parametrize("ybc", ["walls", "dirichlet"])
+def test_ywalls_helmholtz3d_matches_oracle(nx, ny, nz, beta, bc, s, seed, prec, ybc):
+    print(f"helmholtz3d y {ybc} {prec} {nx}x{ny}x{nz} bc={bc} s={s}", flush=True)
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    n = nz if bc == ogrid.DIRICHLET_CENTRE else nz - 1
+    r = synth.normal01(320 + seed, (n, ny, nx))
+    ref = op.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=YBC[ybc])
+    plan = pf.helmholtz3d_plan(nx, ny, nz, H3D_BC[bc], s, LX, LY, 2.0, beta, zf=zf, precision=prec,
+                               ybc=ybc)
+    rt = torch.from_numpy(r).to(_dev())
+    u = torch.empty_like(rt)
+    pf.helmholtz3d_solve(plan, rt, u)
+    torch.cuda.synchronize()
+    err = op.rel_l2(u.cpu().numpy(), ref)
+    print(f"  rel L2 {err:.3e}", flush=True)
+    assert err < TOL[prec]
