@@ -12,7 +12,10 @@
  *              z whose diagonal is shifted by the modified wavenumbers
  *              (eq. fijk_eq). L7 is singular: f is first projected by
  *              removing its dzf-weighted mean, and p is returned with zero
- *              dzf-weighted mean.
+ *              dzf-weighted mean. A grid may instead put walls at both y
+ *              ends (pf_grid.ybc): the y transform is then the cosine
+ *              (zero-gradient walls) or sine (value-zero walls, a
+ *              nonsingular L7: no projection, no pin) transform.
  *   Helmholtz  (I - s L_z) u = r in every (x,y) column (eq. proj3_impl1d,
  *              with s = alpha * nu * dt; the paper writes gamma_k nu dt / 2),
  *              solved with the reworked cyclic reduction of Algorithm 2:
