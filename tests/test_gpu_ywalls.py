@@ -117,3 +117,32 @@ def test_ywalls_helmholtz3d_matches_oracle(nx, ny, nz, beta, bc, s, seed, prec, 
     err = op.rel_l2(u.cpu().numpy(), ref)
     print(f"  rel L2 {err:.3e}", flush=True)
     assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("ybc", ["walls", "dirichlet"])
+def test_ywalls_graph_replays_equal_eager(ybc):
+    """The wall transforms keep the solve capturable: three replays of one
+    captured FP32+refine solve, with eager work between them, equal the eager
+    solve bitwise."""
+    nx, ny, nz = 128, 96, 40
+    stream = torch.cuda.Stream(device=_dev())
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine",
+                           stream=stream, ybc=ybc)
+    rhs = torch.from_numpy(synth.uniform_pm1(330, (nz, ny, nx))).to(_dev())
+    pe = torch.empty_like(rhs)
+    p = torch.empty_like(rhs)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        pf.poisson_solve(plan, rhs, pe)
+    stream.synchronize()
+    pf.pf_graph_begin(stream)
+    pf.poisson_solve(plan, rhs, p)
+    g = pf.pf_graph_end(stream)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            p.fill_(-1.0)
+        g.launch(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        assert torch.equal(p, pe), rep
