@@ -16,6 +16,12 @@ the face gradient (centre differences over dx, dy and the centre distances
 dzc[m]). With these definitions D G is exactly the 7-point operator L7 with
 zero-gradient walls.
 
+With ybc = grid.Y_WALLS the y ends are walls too: v[:, ny-1, :] is then the
+top wall face, where the flux is zero, so the divergence takes it (and the
+bottom wall face below row 0) as zero, the gradient across it is zero and
+the projection leaves it unchanged; D G is then L7 with zero-gradient y
+walls.
+
 Plain numpy in the dtype of the inputs; test infrastructure only.
 """
 from __future__ import annotations
@@ -25,7 +31,7 @@ import numpy as np
 from . import grid, poisson
 
 
-def divergence(u, v, w, zf, lx, ly):
+def divergence(u, v, w, zf, lx, ly, ybc=grid.Y_PERIODIC):
     """D (u, v, w) at cell centres, shape (nz, ny, nx)."""
     dt = u.dtype.type
     nz, ny, nx = u.shape
@@ -33,7 +39,14 @@ def divergence(u, v, w, zf, lx, ly):
     _, dzf, _ = grid.z_metrics(zf, dt)
     # west face of cell i is the east face of cell i-1 (periodic)
     out = (u - np.roll(u, 1, axis=2)) / dx
-    out = out + (v - np.roll(v, 1, axis=1)) / dy
+    if ybc == grid.Y_WALLS:
+        vn = v.copy()
+        vn[:, ny - 1] = 0                 # the top wall face
+        vs = np.zeros_like(v)
+        vs[:, 1:] = vn[:, :-1]            # the bottom wall face below row 0 carries 0
+        out = out + (vn - vs) / dy
+    else:
+        out = out + (v - np.roll(v, 1, axis=1)) / dy
     top = np.zeros_like(u)
     bot = np.zeros_like(u)
     top[:-1] = w            # face k+1 for cells 0..nz-2; the top wall carries 0
@@ -41,7 +54,7 @@ def divergence(u, v, w, zf, lx, ly):
     return out + (top - bot) / dzf[:, None, None]
 
 
-def gradient(phi, zf, lx, ly):
+def gradient(phi, zf, lx, ly, ybc=grid.Y_PERIODIC):
     """G phi on the faces: (gx, gy) of shape (nz, ny, nx), gz of shape
     (nz - 1, ny, nx) on the interior z faces."""
     dt = phi.dtype.type
@@ -50,6 +63,8 @@ def gradient(phi, zf, lx, ly):
     _, _, dzc = grid.z_metrics(zf, dt)
     gx = (np.roll(phi, -1, axis=2) - phi) / dx
     gy = (np.roll(phi, -1, axis=1) - phi) / dy
+    if ybc == grid.Y_WALLS:
+        gy[:, ny - 1] = 0                 # no gradient across the top wall face
     gz = (phi[1:] - phi[:-1]) / dzc[:, None, None]
     return gx, gy, gz
 
@@ -64,11 +79,11 @@ def lz_neumann(phi, zf):
     return out
 
 
-def project(u, v, w, p, zf, lx, ly, gdt, c=0.0):
+def project(u, v, w, p, zf, lx, ly, gdt, c=0.0, ybc=grid.Y_PERIODIC):
     """One projection: returns (u_new, v_new, w_new, p_new, phi)."""
     dt = u.dtype.type
-    f = divergence(u, v, w, zf, lx, ly) / dt(gdt)
-    phi = poisson.solve_poisson(f, zf, lx, ly)
-    gx, gy, gz = gradient(phi, zf, lx, ly)
+    f = divergence(u, v, w, zf, lx, ly, ybc) / dt(gdt)
+    phi = poisson.solve_poisson(f, zf, lx, ly, ybc)
+    gx, gy, gz = gradient(phi, zf, lx, ly, ybc)
     g = dt(gdt)
     return (u - g * gx, v - g * gy, w - g * gz, p + phi - dt(c) * lz_neumann(phi, zf), phi)

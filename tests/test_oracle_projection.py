@@ -126,3 +126,35 @@ def test_neumann_lz_cosine_eigenvectors_and_pressure_update():
     assert np.max(np.abs(phi - phi_e)) <= 1e-12
     assert np.max(np.abs((p1 - p) - (1 + c * lam) * phi_e)) <= 1e-12 * (1 + c * lam)
     assert np.max(np.abs(w1)) <= 1e-12 * np.max(np.abs(w))
+
+
+# zero-gradient walls at both y ends (v[:, ny-1] is the top wall face)
+
+@pytest.mark.parametrize("beta", [0.0, 1.5])
+def test_y_walls_div_of_grad_is_the_seven_point_operator(beta):
+    nx, ny, nz = 12, 10, 9
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    phi = synth.uniform_pm1(55, (nz, ny, nx))
+    gx, gy, gz = projection.gradient(phi, zf, LX, LY, grid.Y_WALLS)
+    dg = projection.divergence(gx, gy, gz, zf, LX, LY, grid.Y_WALLS)
+    ref = poisson.apply_L7(phi, zf, LX, LY, grid.Y_WALLS)
+    assert np.max(np.abs(dg - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_y_walls_divergence_theorem_and_projection():
+    nx, ny, nz = 8, 6, 11
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    _, dzf, _ = grid.z_metrics(zf)
+    u, v, w = _fields(57, nx, ny, nz)
+    d = projection.divergence(u, v, w, zf, LX, LY, grid.Y_WALLS)
+    total = np.dot(dzf, d.reshape(nz, -1).sum(axis=1))
+    assert abs(total) <= 1e-14 * np.dot(dzf, np.abs(d).reshape(nz, -1).sum(axis=1))
+    # the top wall face is ignored
+    v2 = v.copy()
+    v2[:, ny - 1] += 3.0
+    assert np.array_equal(projection.divergence(u, v2, w, zf, LX, LY, grid.Y_WALLS), d)
+    u1, v1, w1, _, _ = projection.project(u, v, w, np.zeros_like(u), zf, LX, LY, gdt=0.2,
+                                          ybc=grid.Y_WALLS)
+    d1 = projection.divergence(u1, v1, w1, zf, LX, LY, grid.Y_WALLS)
+    assert np.sqrt(np.sum(d1 ** 2)) <= 1e-12 * np.sqrt(np.sum(d ** 2))
+    assert np.array_equal(v1[:, ny - 1], v[:, ny - 1])
