@@ -88,8 +88,10 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * wavenumbers 4 sin^2(pi (q + 1) / 2 ny) / dy^2, a nonsingular operator (f is
  * not projected and p is not pinned). Walls are implemented for
  * poisson_plan / poisson_solve and for helmholtz3d_plan / helmholtz3d_solve
- * (a field at cell-centre y positions); poisson_project returns
- * PF_ERR_UNSUPPORTED for a plan with y walls. */
+ * (a field at cell-centre y positions); poisson_project takes PF_Y_WALLS
+ * (v[:, ny-1, :] is then the top wall face: no flux through it enters the
+ * divergence and it is left unchanged) and returns PF_ERR_UNSUPPORTED for
+ * PF_Y_DIRICHLET. */
 enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;

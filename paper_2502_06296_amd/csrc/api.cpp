@@ -773,7 +773,8 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
                           double gdt, double c) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "poisson_project needs a Poisson plan");
-  if (pl->ybc != PF_Y_PERIODIC) return fail(PF_ERR_UNSUPPORTED, "poisson_project: y walls are not built");
+  if (pl->ybc == PF_Y_DIRICHLET)
+    return fail(PF_ERR_UNSUPPORTED, "poisson_project: the pressure takes periodic or zero-gradient y ends");
   if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
   if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");
@@ -800,12 +801,13 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
   d.idy = pl->ny / pl->ly;
   d.igdt = 1.0 / gdt;
   d.stash = nullptr;
+  d.ywalls = pl->ybc == PF_Y_WALLS ? 1 : 0;
   pf_status s = poisson_enqueue(pl, nullptr, phi, pl->st, &d);
   if (s) return s;
   return run_stage(pl->tm, pl->st, PF_STAGE_PROJECT, [&]() {
     return pf::launch_project(pl->nx, pl->ny, pl->nz, phi, u, v, w, p, A.at<double>(pl->o_zal),
                               A.at<double>(pl->o_zga), A.at<double>(pl->o_rdzc), gdt * d.idx,
-                              gdt * d.idy, gdt, c, pl->st);
+                              gdt * d.idy, gdt, c, d.ywalls != 0, pl->st);
   });
 }
 

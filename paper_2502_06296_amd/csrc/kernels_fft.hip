@@ -129,8 +129,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_div(DivArgs d, T *__restrict_
     if (!ok) return mkc<double>(0.0, 0.0);
     const int im = i == 0 ? N - 1 : i - 1;
     const double v0 = va[i];
-    double fa = (ua[i] - ua[im]) * d.idx + (v0 - vm[i]) * d.idy;
-    double fb = (ub[i] - ub[im]) * d.idx + (vb[i] - v0) * d.idy;
+    // with y walls the bottom wall face (below row 0) and the top one (row
+    // ny-1, the north face of line b of the last pair) carry no flux
+    const double vs = (d.ywalls && j == 0) ? 0.0 : vm[i];
+    const double vn = (d.ywalls && j + 2 == ny) ? 0.0 : vb[i];
+    double fa = (ua[i] - ua[im]) * d.idx + (v0 - vs) * d.idy;
+    double fb = (ub[i] - ub[im]) * d.idx + (vn - v0) * d.idy;
     if (top) {
       fa += wta[i] * rz;
       fb += wta[N + i] * rz;
@@ -183,10 +187,13 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
                                                  const double *__restrict__ zal,
                                                  const double *__restrict__ zga,
                                                  const double *__restrict__ rdzc, int nx, int ny,
-                                                 int nz, double gx, double gy, double gdt, double c) {
+                                                 int nz, double gx, double gy, double gdt, double c,
+                                                 int ywalls) {
   const int i = blockIdx.x * 64 + (int)(threadIdx.x % 64);
   const int j = blockIdx.y * 4 + (int)(threadIdx.x / 64);
   if (i >= nx || j >= ny) return;  // no barrier follows
+  // y walls: no gradient across the top wall face, v there stays as it is
+  const double gyj = (ywalls && j + 1 == ny) ? 0.0 : gy;
   const size_t plane = (size_t)nx * ny;
   const size_t o = (size_t)j * nx + i;
   const size_t ox = (size_t)j * nx + (i + 1 == nx ? 0 : i + 1);
@@ -199,7 +206,7 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
     const double fp = up ? phi[b + plane + o] : 0.0;
     const double fx = phi[b + ox], fy = phi[b + oy];
     u[b + o] -= gx * (fx - f0);
-    v[b + o] -= gy * (fy - f0);
+    v[b + o] -= gyj * (fy - f0);
     if (up) w[b + o] -= gdt * rdzc[k] * (fp - f0);  // w is (nz-1, ny, nx)
     double dp = f0;
     if (LZ) {
@@ -271,14 +278,15 @@ template hipError_t launch_xfwd_div<float>(int, int, int, const DivArgs &, float
 hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
                           double *w, double *p, const double *zal, const double *zga,
                           const double *rdzc, double gx, double gy, double gdt, double c,
-                          hipStream_t st) {
+                          bool ywalls, hipStream_t st) {
   dim3 g((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4));
+  const int yw = ywalls ? 1 : 0;
   if (c != 0.0)
     hipLaunchKernelGGL((k_project<true>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc, nx,
-                       ny, nz, gx, gy, gdt, c);
+                       ny, nz, gx, gy, gdt, c, yw);
   else
     hipLaunchKernelGGL((k_project<false>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc,
-                       nx, ny, nz, gx, gy, gdt, c);
+                       nx, ny, nz, gx, gy, gdt, c, yw);
   return hipGetLastError();
 }
 

@@ -153,17 +153,19 @@ struct DivArgs {
   const double *u, *v, *w, *rdzf;
   double idx, idy, igdt;
   double *stash;
+  int ywalls;  // 1: zero-gradient y walls, v[ny-1] is the top wall face (no flux)
 };
 template <typename T>
 hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
                            const cplx<double> *tw, double *sums, hipStream_t st);
 // u -= gx (phi[i+1] - phi[i]), v -= gy (phi[j+1] - phi[j]), w -= gdt rdzc[k]
 // (phi[k+1] - phi[k]) (gx = gdt/dx, gy = gdt/dy), p += phi - c L_z phi with
-// the Neumann rows zal, zga.
+// the Neumann rows zal, zga. ywalls: no v correction on the top wall face
+// j = ny-1.
 hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
                           double *w, double *p, const double *zal, const double *zga,
                           const double *rdzc, double gx, double gy, double gdt, double c,
-                          hipStream_t st);
+                          bool ywalls, hipStream_t st);
 
 // Poisson z solve on the doubly packed spectrum (in place), float64
 // elimination in registers; the (0,0) slot column is set to zero. `variant`

@@ -1,8 +1,8 @@
 """Poisson solve with walls at both y ends -- zero-gradient (the cosine
 transform of Sec. 2.2.1 along y) and value-zero (the sine transform) --
 through the C ABI against the CPU oracle, element by element, in the three
-precisions, for the Poisson solve and the 3-D Helmholtz; and the projection,
-which does not take y walls.
+precisions, for the Poisson solve, the 3-D Helmholtz and (zero-gradient
+walls) the projection.
 
 Bars (relative L2): float64 <= 1e-12, float32 with one float64-residual
 correction <= 1e-10, plain float32 <= 1e-5.
@@ -81,9 +81,9 @@ def test_ywalls_residual_at_512x256x64(ybc):
     assert err < 1e-10
 
 
-def test_projection_rejects_a_y_wall_plan():
+def test_projection_rejects_value_zero_y_walls():
     nx, ny, nz = 64, 64, 16
-    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, ybc="walls")
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, ybc="dirichlet")
     t = [torch.zeros((nz if i != 2 else nz - 1, ny, nx), dtype=torch.float64, device=_dev())
          for i in range(5)]
     with pytest.raises(N.PfError) as e:
@@ -146,3 +146,39 @@ def test_ywalls_graph_replays_equal_eager(ybc):
         stream.synchronize()
         torch.cuda.synchronize()
         assert torch.equal(p, pe), rep
+
+
+PROJ_CASES = [
+    (64, 64, 64, 1.5, 0.0, 0),
+    (128, 96, 40, 2.0, 1e-3, 1),   # radix-3 y, implicit z-diffusion pressure term
+    (96, 128, 9, 1.2, 0.0, 2),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,c,seed", PROJ_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+def test_ywalls_projection_matches_oracle(nx, ny, nz, beta, c, seed, prec):
+    from oracle import projection as oproj
+    print(f"projection y walls {prec} {nx}x{ny}x{nz} c={c}", flush=True)
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    u = synth.uniform_pm1(340 + seed, (nz, ny, nx))
+    v = synth.uniform_pm1(341 + seed, (nz, ny, nx))
+    w = synth.uniform_pm1(342 + seed, (nz - 1, ny, nx))
+    p = synth.uniform_pm1(343 + seed, (nz, ny, nx))
+    gdt = 0.37
+    ref = oproj.project(u, v, w, p, zf, LX, LY, gdt, c, ybc=ogrid.Y_WALLS)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, ybc="walls")
+    t = [torch.from_numpy(a).to(_dev()) for a in (u, v, w, p)]
+    phi = torch.empty_like(t[0])
+    pf.poisson_project(plan, *t, phi, gdt, c)
+    torch.cuda.synchronize()
+    got = [a.cpu().numpy() for a in t] + [phi.cpu().numpy()]
+    for name, g, r in zip(("u", "v", "w", "p", "phi"), got, ref):
+        err = op.rel_l2(g, r)
+        print(f"  {name}: rel L2 {err:.3e}", flush=True)
+        assert err < TOL[prec], name
+    if prec != "fp32":
+        # the projected field is divergence-free with the walls' fluxes
+        d1 = oproj.divergence(*got[:3], zf, LX, LY, ogrid.Y_WALLS)
+        d0 = oproj.divergence(u, v, w, zf, LX, LY, ogrid.Y_WALLS)
+        assert np.sqrt(np.sum(d1 ** 2)) <= TOL[prec] * np.sqrt(np.sum(d0 ** 2))

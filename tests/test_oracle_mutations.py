@@ -122,31 +122,31 @@ def test_unmutated_projection_passes():
 
 
 def _div_with_centre_distances(orig):
-    def f(u, v, w, zf, lx, ly):
+    def f(u, v, w, zf, lx, ly, *rest):
         zf = np.asarray(zf)
         zc = (zf[1:] + zf[:-1]) / 2
         fake = np.concatenate([[zf[0]], zc[:-1] + np.diff(zc) / 2, [zf[-1]]])
         fake[1:-1] = zf[1:-1] + 0.25 * (np.diff(zc))    # cell widths no longer dzf
-        return orig(u, v, w, fake, lx, ly)
+        return orig(u, v, w, fake, lx, ly, *rest)
     return f
 
 
 def _backward_x_gradient(orig):
-    def f(phi, zf, lx, ly):
-        gx, gy, gz = orig(phi, zf, lx, ly)
+    def f(phi, zf, lx, ly, *rest):
+        gx, gy, gz = orig(phi, zf, lx, ly, *rest)
         return np.roll(gx, 1, axis=2), gy, gz
     return f
 
 
 def _swapped_w_faces(orig):
-    def f(u, v, w, zf, lx, ly):
-        return orig(u, v, -w, zf, lx, ly)
+    def f(u, v, w, zf, lx, ly, *rest):
+        return orig(u, v, -w, zf, lx, ly, *rest)
     return f
 
 
 def _correction_without_gdt(orig):
-    def f(u, v, w, p, zf, lx, ly, gdt, c=0.0):
-        u1, v1, w1, p1, phi = orig(u, v, w, p, zf, lx, ly, gdt, c)
+    def f(u, v, w, p, zf, lx, ly, gdt, c=0.0, *rest):
+        u1, v1, w1, p1, phi = orig(u, v, w, p, zf, lx, ly, gdt, c, *rest)
         return u + (u1 - u) / gdt, v + (v1 - v) / gdt, w + (w1 - w) / gdt, p1, phi
     return f
 
