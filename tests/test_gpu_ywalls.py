@@ -182,3 +182,33 @@ def test_ywalls_projection_matches_oracle(nx, ny, nz, beta, c, seed, prec):
         d1 = oproj.divergence(*got[:3], zf, LX, LY, ogrid.Y_WALLS)
         d0 = oproj.divergence(u, v, w, zf, LX, LY, ogrid.Y_WALLS)
         assert np.sqrt(np.sum(d1 ** 2)) <= TOL[prec] * np.sqrt(np.sum(d0 ** 2))
+
+
+def test_mixed_y_boundaries_in_one_task_batch():
+    """Poisson problems with periodic y, zero-gradient and value-zero y walls
+    spread over internal streams give, bitwise, what each gives alone."""
+    stream = torch.cuda.Stream(device=_dev())
+    specs = [(128, 96, 40, "periodic"), (64, 64, 33, "walls"), (96, 128, 24, "dirichlet"),
+             (64, 192, 17, "walls"), (192, 64, 20, "dirichlet"), (64, 96, 48, "periodic")]
+    items = []
+    for t, (nx, ny, nz, ybc) in enumerate(specs):
+        zf = synth.tanh_faces(nz, 2.0, 1.5)
+        plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine",
+                               stream=stream, ybc=ybc)
+        rhs = torch.from_numpy(synth.uniform_pm1(360 + t, (nz, ny, nx))).to(_dev())
+        items.append((plan, rhs))
+    torch.cuda.synchronize()
+    ref = []
+    with torch.cuda.stream(stream):
+        for plan, rhs in items:
+            p = torch.empty_like(rhs)
+            pf.poisson_solve(plan, rhs, p)
+            ref.append(p)
+    stream.synchronize()
+    outs = [torch.full_like(rhs, -1.0) for _, rhs in items]
+    torch.cuda.synchronize()
+    tasks = [dict(poisson=plan, rhs=rhs, p=o) for (plan, rhs), o in zip(items, outs)]
+    pf.run_batched(tasks, lanes=4, stream=stream)
+    stream.synchronize()
+    for t, (o, r) in enumerate(zip(outs, ref)):
+        assert torch.equal(o, r), specs[t]
