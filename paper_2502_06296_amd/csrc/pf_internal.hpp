@@ -45,14 +45,16 @@ constexpr size_t kPlanePad = 64;
 // residual take more threads per line, the largest multiple of 32 up to 384
 // that divides n / div (div = 2 where every thread takes pairs of
 // positions), so that a CU still holds several waves per SIMD. The x
-// forward transforms keep 128 threads (more made them slower: 1.23 -> 1.38
-// ms at 3456 points).
-constexpr int long_tpl(int n, int div) {
-  for (int c = 384; c >= 64; c -= 32)
+// forward transforms stop at 192 (384 made them slower, 1.23 -> 1.38 ms at
+// 3456 points; 160-192 against 128 gains 1-2 %).
+constexpr int long_tpl(int n, int div, int cap = 384) {
+  for (int c = cap; c >= 64; c -= 32)
     if (n % (div * c) == 0) return c;
   return 0;
 }
-constexpr int xfwd_tpl(int n) { return n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16); }
+constexpr int xfwd_tpl(int n) {
+  return n > 2048 && long_tpl(n, 1, 192) ? long_tpl(n, 1, 192) : (n / 16 < 16 ? 16 : (n / 16 > 128 ? 128 : n / 16));
+}
 constexpr int x_tpl(int n) { return n > 2048 && long_tpl(n, 1) ? long_tpl(n, 1) : xfwd_tpl(n); }
 constexpr int x_lpw(int n) {
   const int by_threads = 256 / x_tpl(n);
