@@ -160,3 +160,71 @@ def _correction_without_gdt(orig):
 def test_planted_projection_mistake_is_caught(monkeypatch, attr, mut):
     monkeypatch.setattr(projection, attr, mut(getattr(projection, attr)))
     assert _projection_pin_errors() > 1e-6
+
+
+# ------------------------------------------------------------- y walls
+
+def _ywall_pin_errors():
+    """Largest error of the y-wall pins: the dense brute force of both wall
+    kinds and the even/odd-extension DFTs."""
+    errs = []
+    for ybc, dybc in ((grid.Y_WALLS, 1), (grid.Y_DIRICHLET, 2)):
+        for (nx, ny, nz, beta) in [(4, 5, 6, 1.5), (2, 6, 5, 0.5)]:
+            zf = synth.tanh_faces(nz, 2.0, beta)
+            f = synth.uniform_pm1(70 + ny, (nz, ny, nx))
+            errs.append(poisson.rel_l2(poisson.solve_poisson(f, zf, LX, LY, ybc=ybc),
+                                       dense.poisson_dense(f, zf, LX, LY, ybc=dybc)))
+    n = 7
+    x = synth.uniform_pm1(80, (n,))
+    q = np.arange(n)
+    E = transforms.dft_direct(np.concatenate([x, x[::-1]]))
+    errs.append(np.max(np.abs(transforms.dct2(x, axis=0) - E[:n] * np.exp(-1j * np.pi * q / (2 * n)))))
+    O = transforms.dft_direct(np.concatenate([x, -x[::-1]]))
+    errs.append(np.max(np.abs(transforms.dst2(x, axis=0)
+                              - 1j * np.exp(-1j * np.pi * (q + 1) / (2 * n)) * O[1:n + 1])))
+    return max(errs)
+
+
+def test_unmutated_ywall_oracle_passes():
+    assert _ywall_pin_errors() < 1e-12
+
+
+def _periodic_wavenumbers_for_walls(orig):
+    def f(n, length, dtype=np.float64):
+        q = np.arange(n, dtype=dtype)
+        dx = dtype(length) / n
+        return 4 * np.sin(np.pi * q / n) ** 2 / (dx * dx)     # pi q / n instead of pi q / 2n
+    return f
+
+
+def _cosine_phase_off_by_half(orig):
+    def f(x, axis):
+        x = np.moveaxis(np.asarray(x), axis, -1)
+        n = x.shape[-1]
+        t = np.arange(n)
+        M = 2.0 * np.cos(np.pi * np.outer(t, 2 * t) / (2 * n))   # 2t instead of 2t + 1
+        return np.moveaxis(x @ M.T, -1, axis)
+    return f
+
+
+def _sine_modes_from_zero(orig):
+    def f(n, length, dtype=np.float64):
+        return np.roll(orig(n, length, dtype), 1)                # sigma_{q-1} for mode q
+    return f
+
+
+def _wall_ghost_not_negated(orig):
+    def f(n, h, value_zero=False):
+        return orig(n, h, False)
+    return f
+
+
+@pytest.mark.parametrize("target,attr,mut", [
+    (grid, "wall_wavenumbers", _periodic_wavenumbers_for_walls),
+    (transforms, "dct2", _cosine_phase_off_by_half),
+    (grid, "dirichlet_wall_wavenumbers", _sine_modes_from_zero),
+    (dense, "wall_d2", _wall_ghost_not_negated),
+])
+def test_planted_ywall_mistake_is_caught(monkeypatch, target, attr, mut):
+    monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
+    assert _ywall_pin_errors() > 1e-6
