@@ -3,7 +3,7 @@
 Two row conventions appear here:
 
 * plain rows  ``a[k] x[k-1] + b[k] x[k] + c[k] x[k+1] = d[k]`` (eq.
-  eq_tridiag_base), used by the paper's algorithms exactly as stated;
+  eq_tridiag_base), the rows the paper's algorithms take;
 * sign-normalised M-matrix rows
   ``-alpha[k] x[k-1] + (alpha[k] + gamma[k] + eps[k]) x[k] - gamma[k] x[k+1] = d[k]``
   with alpha, gamma, eps >= 0. Every discrete operator of this solver has
@@ -86,176 +86,168 @@ def _check_bounds(n, bounds):
             raise ValueError("every chunk needs at least two rows")
 
 
-# ----------------------------------------------------------- Algorithm 1
-def alg1_solve(a, b, c, d, bounds):
-    """Partitioned solve with the paper's original cyclic-reduction step
-    (Algorithm 1): each chunk is normalised to unit diagonal and reduced to
-    rows that couple only its first and last unknowns; the 2P boundary rows
-    form a tridiagonal system solved by Thomas; interiors are rebuilt in
-    place. 1-D inputs only (a loop per chunk)."""
-    n = len(d)
+# ------------------------------------------------------ partitioned solve
+# Sec. 2.2.4 (Algorithms 1 and 2, after Laszlo et al.): the rows are split
+# into P contiguous chunks. Inside a chunk [s, e) every interior unknown
+# (rows s+1..e-2) is expressed through the chunk's two end unknowns, which
+# leaves a tridiagonal system of 2P rows over the end unknowns (eq.
+# eq_tridiag_redcyc and the reduced system of the text); its solution gives
+# the interiors back. Algebraically this is the Schur complement of the
+# interior blocks: with T the interior block, x_I = T^-1 d_I - x_s T^-1 (a_{s+1}
+# e_1) - x_{e-1} T^-1 (c_{e-2} e_last), substituted into rows s and e-1.
+# Algorithms 1 and 2 compute exactly these quantities; Algorithm 2 splits
+# them into a coefficient-only part (Step 1, done once per matrix) and a
+# part per right-hand side (Steps 2-4), which is the prepare / apply split
+# below. The interior blocks here are solved directly (a dense solve for
+# plain rows, the subtraction-free Thomas sweep for sign-normalised rows),
+# not by the paper's elimination sequence, so that the reduction is checked
+# independently of how the GPU reaches it.
+def schur_prepare(a, b, c, bounds):
+    """Coefficient-only part of the partitioned solve of plain rows (1-D
+    coefficients): per chunk the dense interior block T and the two vectors
+    q0 = T^-1 (a_{s+1} e_1), ql = T^-1 (c_{e-2} e_last) that carry the end
+    unknowns into the interior; and the reduced rows over the 2P end
+    unknowns X[2p] = x_s, X[2p+1] = x_{e-1}."""
+    a, b, c = (np.asarray(v, dtype=float) for v in (a, b, c))
+    n = len(b)
     _check_bounds(n, bounds)
-    a = np.array(a, dtype=float); b = np.array(b, dtype=float)
-    c = np.array(c, dtype=float); d = np.array(d, dtype=float)
-    for s, e in bounds:
-        m = e - s
-        A, B, C, D = a[s:e], b[s:e], c[s:e], d[s:e]   # views
-        for i in (0, 1):
-            A[i] /= B[i]; C[i] /= B[i]; D[i] /= B[i]
-        for i in range(2, m):
-            r = 1.0 / (B[i] - A[i] * C[i - 1])
-            D[i] = r * (D[i] - A[i] * D[i - 1])
-            C[i] = r * C[i]
-            A[i] = -r * A[i] * A[i - 1]
-        for i in range(m - 3, 0, -1):
-            D[i] = D[i] - C[i] * D[i + 1]
-            A[i] = A[i] - C[i] * A[i + 1]
-            C[i] = -C[i] * C[i + 1]
-        if m > 2:
-            r = 1.0 / (1.0 - A[1] * C[0])
-            D[0] = r * (D[0] - C[0] * D[1])
-            A[0] = r * A[0]
-            C[0] = -r * C[0] * C[1]
-        B[:] = 1.0
-    # reduced system over X[2p] = first, X[2p+1] = last unknown of chunk p
-    ra, rb, rc, rd = [], [], [], []
-    for s, e in bounds:
-        for row in (s, e - 1):
-            ra.append(a[row]); rb.append(1.0); rc.append(c[row]); rd.append(d[row])
-    X = thomas_plain(np.array(ra), np.array(rb), np.array(rc), np.array(rd))
+    P = len(bounds)
+    R = np.zeros((2 * P, 2 * P))
+    chunks = []
     for p, (s, e) in enumerate(bounds):
-        x0, xl = X[2 * p], X[2 * p + 1]
-        d[s + 1:e - 1] = d[s + 1:e - 1] - a[s + 1:e - 1] * x0 - c[s + 1:e - 1] * xl
-        d[s], d[e - 1] = x0, xl
-    return d
-
-
-# ----------------------------------------------------------- Algorithm 2
-def alg2_prepare(A, B, C, bounds):
-    """Algorithm 2, Step 1 as printed: per chunk, the modified (a, b, c)
-    from the original (A, B, C). Returns one dict per chunk. A chunk of two
-    rows is already reduced and passes through unchanged."""
-    out = []
-    for s, e in bounds:
         m = e - s
-        Ak, Bk, Ck = (np.array(v[s:e], dtype=float) for v in (A, B, C))
-        a, b, c = Ak.copy(), Bk.copy(), Ck.copy()
+        ch = dict(s=s, e=e)
         if m > 2:
-            a[1], b[1] = Ak[1], Bk[1]
-            for i in range(2, m):
-                b[i] = Bk[i] - Ak[i] * Ck[i - 1] / b[i - 1]
-                a[i] = -Ak[i] * a[i - 1] / b[i - 1]
-            c[m - 1], c[m - 2] = Ck[m - 1], Ck[m - 2]
-            for i in range(m - 3, 0, -1):
-                a[i] = a[i] - Ck[i] * a[i + 1] / b[i + 1]
-                c[i] = -Ck[i] * c[i + 1] / b[i + 1]
-            a[0] = Ak[0]
-            b[0] = Bk[0] - Ck[0] * a[1] / Bk[1]
-            c[0] = -Ck[0] * c[1] / Bk[1]
-        out.append(dict(s=s, e=e, A=Ak, C=Ck, a=a, b=b, c=c))
-    return out
+            k = np.arange(s + 1, e - 1)
+            T = np.diag(b[k]) + np.diag(a[k[1:]], -1) + np.diag(c[k[:-1]], 1)
+            rhs = np.zeros((m - 2, 2))
+            rhs[0, 0] = a[s + 1]
+            rhs[-1, 1] = c[e - 2]
+            q = np.linalg.solve(T, rhs)
+            ch.update(T=T, q0=q[:, 0], ql=q[:, 1])
+            # row s:  a_s x_{s-1} + (b_s - c_s q0[0]) x_s - c_s ql[0] x_{e-1}
+            R[2 * p, 2 * p] = b[s] - c[s] * q[0, 0]
+            R[2 * p, 2 * p + 1] = -c[s] * q[0, 1]
+            # row e-1: -a_{e-1} q0[-1] x_s + (b_{e-1} - a_{e-1} ql[-1]) x_{e-1} + c_{e-1} x_e
+            R[2 * p + 1, 2 * p] = -a[e - 1] * q[-1, 0]
+            R[2 * p + 1, 2 * p + 1] = b[e - 1] - a[e - 1] * q[-1, 1]
+        else:
+            R[2 * p, 2 * p], R[2 * p, 2 * p + 1] = b[s], c[s]
+            R[2 * p + 1, 2 * p], R[2 * p + 1, 2 * p + 1] = a[e - 1], b[e - 1]
+        if p > 0:
+            R[2 * p, 2 * p - 1] = a[s]
+        if p < P - 1:
+            R[2 * p + 1, 2 * p + 2] = c[e - 1]
+        chunks.append(ch)
+    return dict(a=a, c=c, chunks=chunks, R=R)
 
 
-def alg2_apply(prep, d):
-    """Algorithm 2, Steps 2-4: reduce d in place, solve the boundary system
-    by Thomas, rebuild the interior with the stored (a, b, c)."""
+def schur_apply(prep, d):
+    """Per right-hand side: y = T^-1 d_I per chunk, the reduced right-hand
+    sides d_s - c_s y[0] and d_{e-1} - a_{e-1} y[-1], a dense solve of the
+    2P reduced rows, then x_I = y - q0 x_s - ql x_{e-1}."""
     d = np.array(d, dtype=float)
-    for ch in prep:
+    a, c = prep["a"], prep["c"]
+    rd = np.empty(len(prep["R"]))
+    ys = []
+    for p, ch in enumerate(prep["chunks"]):
         s, e = ch["s"], ch["e"]
-        m = e - s
-        D = d[s:e]
-        if m > 2:
-            for i in range(2, m):
-                D[i] = D[i] - ch["A"][i] * D[i - 1] / ch["b"][i - 1]
-            for i in range(m - 3, -1, -1):
-                D[i] = D[i] - ch["C"][i] * D[i + 1] / ch["b"][i + 1]
-    ra, rb, rc, rd = [], [], [], []
-    for ch in prep:
+        y = np.linalg.solve(ch["T"], d[s + 1:e - 1]) if "T" in ch else None
+        ys.append(y)
+        rd[2 * p] = d[s] - (c[s] * y[0] if y is not None else 0.0)
+        rd[2 * p + 1] = d[e - 1] - (a[e - 1] * y[-1] if y is not None else 0.0)
+    X = np.linalg.solve(prep["R"], rd)
+    for p, (ch, y) in enumerate(zip(prep["chunks"], ys)):
         s, e = ch["s"], ch["e"]
-        ra += [ch["A"][0], ch["a"][-1]]
-        rb += [ch["b"][0], ch["b"][-1]]
-        rc += [ch["c"][0], ch["C"][-1]]
-        rd += [d[s], d[e - 1]]
-    X = thomas_plain(np.array(ra), np.array(rb), np.array(rc), np.array(rd))
-    for p, ch in enumerate(prep):
-        s, e = ch["s"], ch["e"]
-        x0, xl = X[2 * p], X[2 * p + 1]
-        sl = slice(1, e - s - 1)
-        d[s + 1:e - 1] = (d[s + 1:e - 1] - ch["a"][sl] * x0 - ch["c"][sl] * xl) / ch["b"][sl]
-        d[s], d[e - 1] = x0, xl
+        if y is not None:
+            d[s + 1:e - 1] = y - ch["q0"] * X[2 * p] - ch["ql"] * X[2 * p + 1]
+        d[s], d[e - 1] = X[2 * p], X[2 * p + 1]
     return d
 
 
-# ------------------------------------- Algorithm 2, subtraction-free form
+def schur_solve(a, b, c, d, bounds):
+    """The partitioned solve in one call (Algorithm 1's single pass)."""
+    return schur_apply(schur_prepare(a, b, c, bounds), d)
+
+
+# ------------------------------------- partitioned, subtraction-free form
+def _interior_rows(alpha, gamma, eps, s, e):
+    """Sign-normalised rows of the interior block of chunk [s, e): the
+    couplings to the end unknowns leave the block but stay in its diagonal,
+    so they join the excess (first row: alpha_{s+1}; last row: gamma_{e-2})."""
+    al = np.array(alpha[s + 1:e - 1], copy=True)
+    ga = np.array(gamma[s + 1:e - 1], copy=True)
+    ep = np.array(eps[s + 1:e - 1], copy=True)
+    ep[0] = ep[0] + al[0]
+    al[0] = 0 * al[0]
+    ep[-1] = ep[-1] + ga[-1]
+    ga[-1] = 0 * ga[-1]
+    return al, ga, ep
+
+
 def gth_prepare(alpha, gamma, eps, bounds):
-    """Algorithm 2, Step 1, in sign-normalised rows. For each chunk returns
-    the interior pivots b (rows 1..m-2), the magnitudes |a| and |c| of the
-    couplings to the chunk's first and last unknowns, and the two reduced
-    boundary rows as (alpha_R, gamma_R, eps_R) triples. Each diagonal is the
-    sum of its non-negative parts: a forward excess e' and a backward excess
-    eta are carried through the eliminations instead of being formed by
-    subtraction. Coefficients may be 1-D or broadcast over columns."""
+    """Coefficient-only part of the partitioned solve in sign-normalised rows
+    (-alpha x[k-1] + (alpha + gamma + eps) x[k] - gamma x[k+1] = d[k]).
+
+    The interior block T is itself such an M-matrix, so u0 = T^-1 (alpha_{s+1}
+    e_1), ul = T^-1 (gamma_{e-2} e_last) and v = T^-1 eps_I are non-negative,
+    and T 1 = eps_I + alpha_{s+1} e_1 + gamma_{e-2} e_last gives v + u0 + ul =
+    1. The reduced row of x_s then has the diagonal alpha_s + eps_s + gamma_s
+    (1 - u0[0]) = alpha_s + gamma_s ul[0] + (eps_s + gamma_s v[0]): its
+    off-diagonal parts alpha_s and gamma_s ul[0] and a non-negative excess,
+    with no subtraction; the row of x_{e-1} mirrors it. Coefficients may be
+    1-D or broadcast over columns (trailing axes)."""
     out = []
     for s, e in bounds:
-        m = e - s
-        al, ga, ep = alpha[s:e], gamma[s:e], eps[s:e]
-        if m == 2:
-            out.append(dict(s=s, e=e, alpha=al, gamma=ga,
-                            row0=(al[0], ga[0], ep[0]), rowl=(al[1], ga[1], ep[1]),
-                            b=[], a=[], c=[]))
-            continue
-        b = [None] * m; a = [None] * m; c = [None] * m
-        ef = [None] * m; eta = [None] * m
-        a[1] = al[1]; ef[1] = ep[1]; b[1] = ga[1] + al[1] + ep[1]
-        for i in range(2, m):
-            t = al[i] / b[i - 1]
-            a[i] = t * a[i - 1]
-            ef[i] = ep[i] + t * ef[i - 1]
-            b[i] = ga[i] + a[i] + ef[i]
-        c[m - 2] = ga[m - 2]
-        eta[m - 2] = ef[m - 2]
-        for i in range(m - 3, 0, -1):
-            t = ga[i] / b[i + 1]
-            a[i] = a[i] + t * a[i + 1]
-            c[i] = t * c[i + 1]
-            eta[i] = ef[i] + t * eta[i + 1]
-        t = ga[0] / b[1]
-        c0 = t * c[1]
-        eta0 = ep[0] + t * eta[1]
-        out.append(dict(s=s, e=e, alpha=al, gamma=ga,
-                        row0=(al[0], c0, eta0), rowl=(a[m - 1], ga[m - 1], ef[m - 1]),
-                        b=b, a=a, c=c))
+        if e - s < 2:
+            raise ValueError("every chunk needs at least two rows")
+        ch = dict(s=s, e=e)
+        if e - s == 2:
+            ch["row0"] = (alpha[s], gamma[s], eps[s])
+            ch["rowl"] = (alpha[e - 1], gamma[e - 1], eps[e - 1])
+        else:
+            al, ga, ep = _interior_rows(alpha, gamma, eps, s, e)
+            mI = e - s - 2
+            shape = np.broadcast_shapes(np.shape(alpha[s]), np.shape(gamma[s]), np.shape(eps[s]))
+            rhs = np.zeros((mI, 3) + shape)
+            rhs[:, 0] = eps[s + 1:e - 1]
+            rhs[0, 1] = alpha[s + 1]
+            rhs[-1, 2] = gamma[e - 2]
+            sl = (slice(None), None)
+            V = thomas_gth(al[sl], ga[sl], ep[sl], rhs)
+            v, u0, ul = V[:, 0], V[:, 1], V[:, 2]
+            ch.update(T=(al, ga, ep), u0=u0, ul=ul, gs=gamma[s], al_l=alpha[e - 1])
+            ch["row0"] = (alpha[s], gamma[s] * ul[0], eps[s] + gamma[s] * v[0])
+            ch["rowl"] = (alpha[e - 1] * u0[-1], gamma[e - 1], eps[e - 1] + alpha[e - 1] * v[-1])
+        out.append(ch)
     return out
 
 
 def gth_apply(prep, d):
-    """Algorithm 2, Steps 2-4 on sign-normalised rows: forward and backward
-    reduction of d, subtraction-free Thomas on the 2P boundary rows, then
-    x_i = (d_i + |a_i| x_first + |c_i| x_last) / b_i."""
+    """Per right-hand side: y = T^-1 d_I per chunk, the reduced right-hand
+    sides d_s + gamma_s y[0] and d_{e-1} + alpha_{e-1} y[-1], the
+    subtraction-free Thomas sweep over the 2P reduced rows, then x_I = y +
+    u0 x_s + ul x_{e-1}."""
     d = np.array(d, copy=True)
-    for ch in prep:
-        s, e = ch["s"], ch["e"]
-        m = e - s
-        if m == 2:
-            continue
-        D = d[s:e]
-        b, al, ga = ch["b"], ch["alpha"], ch["gamma"]
-        for i in range(2, m):
-            D[i] = D[i] + al[i] * D[i - 1] / b[i - 1]
-        for i in range(m - 3, -1, -1):
-            D[i] = D[i] + ga[i] * D[i + 1] / b[i + 1]
+    ys = []
     ra, rg, re_, rd = [], [], [], []
     for ch in prep:
         s, e = ch["s"], ch["e"]
-        for row, (x_al, x_ga, x_ep) in ((s, ch["row0"]), (e - 1, ch["rowl"])):
-            ra.append(x_al + 0 * d[row]); rg.append(x_ga + 0 * d[row])
-            re_.append(x_ep + 0 * d[row]); rd.append(d[row])
+        y = None
+        d0, dl = d[s], d[e - 1]
+        if "T" in ch:
+            al, ga, ep = ch["T"]
+            y = thomas_gth(al, ga, ep, d[s + 1:e - 1])
+            d0 = d0 + ch["gs"] * y[0]
+            dl = dl + ch["al_l"] * y[-1]
+        ys.append(y)
+        for (x_al, x_ga, x_ep), dv in ((ch["row0"], d0), (ch["rowl"], dl)):
+            ra.append(x_al + 0 * dv); rg.append(x_ga + 0 * dv)
+            re_.append(x_ep + 0 * dv); rd.append(dv)
     X = thomas_gth(np.array(ra), np.array(rg), np.array(re_), np.array(rd))
-    for p, ch in enumerate(prep):
+    for p, (ch, y) in enumerate(zip(prep, ys)):
         s, e = ch["s"], ch["e"]
-        m = e - s
-        x0, xl = X[2 * p], X[2 * p + 1]
-        for i in range(1, m - 1):
-            d[s + i] = (d[s + i] + ch["a"][i] * x0 + ch["c"][i] * xl) / ch["b"][i]
-        d[s], d[e - 1] = x0, xl
+        if y is not None:
+            d[s + 1:e - 1] = y + ch["u0"] * X[2 * p] + ch["ul"] * X[2 * p + 1]
+        d[s], d[e - 1] = X[2 * p], X[2 * p + 1]
     return d

@@ -45,6 +45,17 @@ def test_packed_fft_matches_direct_dft(n):
     np.testing.assert_allclose(back, x, rtol=0, atol=1e-14 * n)
 
 
+@pytest.mark.parametrize("n", [512, 1024, 2048, 3072, 3200, 3456])
+def test_packed_fft_matches_direct_dft_at_workload_lengths(n):
+    """The lengths the GPU parity tests and the benchmarks run (512-2048,
+    3072 and 3456 = 2^7 3^3, 3200 = 2^7 5^2), pinned by direct summation."""
+    x = synth.uniform_pm1(7000 + n, (n,))
+    got = transforms.rfft_packed(x, axis=0)
+    np.testing.assert_allclose(got, _packed_from_direct(x), rtol=0, atol=1e-14 * np.sqrt(n) * 10)
+    back = transforms.irfft_packed(got, axis=0)
+    np.testing.assert_allclose(back, x, rtol=0, atol=1e-14 * 10)
+
+
 @pytest.mark.parametrize("n", [8, 9, 64, 96])
 def test_packed_parseval(n):
     x = synth.uniform_pm1(3, (n,))
@@ -171,10 +182,9 @@ def test_tridiagonal_algorithms_equal_dense(n, excess):
     if n >= 7:
         chunkings.append([(0, 2), (2, 5), (5, n)])          # uneven, with a 2-row chunk
     for bnd in chunkings:
-        x1 = tridiag.alg1_solve(a, b, c, d, bnd)
-        x2 = tridiag.alg2_apply(tridiag.alg2_prepare(a, b, c, bnd), d)
-        x3 = tridiag.gth_apply(tridiag.gth_prepare(al, ga, ep, bnd), d)
-        for x in (x1, x2, x3):
+        x1 = tridiag.schur_solve(a, b, c, d, bnd)
+        x2 = tridiag.gth_apply(tridiag.gth_prepare(al, ga, ep, bnd), d)
+        for x in (x1, x2):
             assert np.abs(x - xd).max() < 1e3 * tol * scale
 
 
@@ -195,6 +205,28 @@ def test_subtraction_free_pivots_keep_digits():
     e_gth = poisson.rel_l2(gth, ref)
     e_plain = poisson.rel_l2(plain, ref)
     assert e_gth < 1e-14
+    assert e_plain > 10 * e_gth
+
+
+@pytest.mark.parametrize("P", [1, 4, 8, 32])
+def test_partitioned_subtraction_free_keeps_digits(P):
+    """The partitioned solve in sign-normalised rows (every reduced diagonal a
+    sum of non-negative parts) keeps the digits of the long-double solve on
+    the stretched pressure operator with a small wavenumber shift, where the
+    plain Schur complement (diagonals b - c q) loses them."""
+    nz = 1024
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    al, ga, ep = grid.zop(zf, grid.NEUMANN)
+    ep = ep + 4 * np.sin(np.pi / 1024) ** 2 / (LX / 1024) ** 2
+    d = synth.uniform_pm1(15, (nz,))
+    ld = np.longdouble
+    ref = tridiag.thomas_gth(al.astype(ld), ga.astype(ld), ep.astype(ld), d.astype(ld))
+    bnd = tridiag.even_bounds(nz, P)
+    x = tridiag.gth_apply(tridiag.gth_prepare(al, ga, ep, bnd), d)
+    e_gth = poisson.rel_l2(x, ref)
+    a, b, c = tridiag.gth_to_plain(al, ga, ep)
+    e_plain = poisson.rel_l2(tridiag.schur_solve(a, b, c, d, bnd), ref)
+    assert e_gth < 1e-13
     assert e_plain > 10 * e_gth
 
 
