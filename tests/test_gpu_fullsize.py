@@ -12,6 +12,19 @@ the device:
   ||r|| <= 1e-13 for float64 and <= 2e-10 for float32 + correction (1e-10
   relative error times the condition number, with margin).
 
+Sampled outputs are also compared with the oracle one by one, element-wise,
+in the launch configuration the benchmark times:
+
+- Helmholtz: the columns are independent, so the oracle solves a random
+  sample of columns of the full-size input;
+- Poisson: a right-hand side made of a few separable Fourier modes
+  cos(2 pi a x / lx + phase) cos(2 pi b y / ly + phase) g(z) (a, b not both
+  zero, Nyquist modes included). Each such mode is an eigenvector of the
+  periodic second differences, so the exact discrete solution is the same
+  mode times the profile h of one z system, (L_z - sigma_x(a) - sigma_y(b)) h
+  = g, which the oracle's subtraction-free Thomas solve gives; the solution
+  is evaluated by the oracle at sampled points.
+
 The stencils below are checked against sparse matrices built from the
 oracle's dense operators on small grids (CPU tests at the end).
 Inputs are seeded torch draws on the device (uniform[-1, 1], mean removed,
@@ -26,6 +39,9 @@ import paper_2502_06296_amd as pf
 import synth
 from oracle import dense
 from oracle import grid as ogrid
+from oracle import poisson as op
+from oracle import tridiag
+from parity import TOL, check
 
 LX, LY, LZ, BETA = 2 * np.pi, np.pi, 2.0, 1.5
 S_C3 = 0.5 * (1.0 / 5200.0) * 1e-4
@@ -123,7 +139,85 @@ def _normal(shape, seed, dev):
     return torch.randn(shape, generator=g, dtype=torch.float64, device=dev)
 
 
+def _sampled_columns_match_oracle(r, u, zf, s, bc, prec, seed, ncols=96):
+    """The oracle's Helmholtz solve of a random sample of (i, j) columns of
+    the device input r against the same columns of the device result u."""
+    n, ny, nx = r.shape
+    rng = np.random.default_rng(seed)
+    ii = torch.from_numpy(rng.integers(0, nx, ncols)).to(r.device)
+    jj = torch.from_numpy(rng.integers(0, ny, ncols)).to(r.device)
+    rc = r[:, jj, ii].cpu().numpy()
+    ref = op.solve_helmholtz(rc[:, None, :], zf, s, bc)[:, 0, :]
+    got = u[:, jj, ii].cpu().numpy()
+    check(got, ref, TOL[prec], f"{ncols} sampled columns {prec}")
+
+
+def _slot(n, q):
+    """Packed slot holding Fourier mode q (App. A layout)."""
+    return 0 if q == 0 else (1 if 2 * q == n else 2 * q)
+
+
+def _mode_set(nx, ny, nz, seed):
+    """Separable modes (cx over i, cy over j, g over k, profile h over k)
+    with the oracle's profile h solving (L_z - sigma) h = g."""
+    rng = np.random.default_rng(seed)
+    zf = synth.tanh_faces(nz, LZ, BETA)
+    al, ga, ex = ogrid.zop(zf, ogrid.NEUMANN)
+    sxs = ogrid.modified_wavenumbers(nx, LX)
+    sys_ = ogrid.modified_wavenumbers(ny, LY)
+    ab = [(1, 0), (0, 3), (5, 2), (nx // 2, 1), (nx // 4 + 1, ny // 2), (nx // 2 - 1, ny // 2 - 3),
+          (nx // 8 + 3, ny // 4 + 1)]
+    modes = []
+    for t, (a, b) in enumerate(ab):
+        phx, phy = rng.uniform(0, 2 * np.pi, 2)
+        cx = np.cos(2 * np.pi * a * np.arange(nx) / nx + phx)
+        cy = np.cos(2 * np.pi * b * np.arange(ny) / ny + phy)
+        g = synth.uniform_pm1(500 + t, (nz,))
+        sig = sxs[_slot(nx, a)] + sys_[_slot(ny, b)]
+        h = tridiag.thomas_gth(al, ga, ex + sig, -g)
+        modes.append((cx, cy, g, h))
+    return zf, modes
+
+
+def _mode_rhs(nx, ny, nz, modes, dev):
+    f = torch.zeros((nz, ny, nx), dtype=torch.float64, device=dev)
+    for cx, cy, g, _ in modes:
+        gy = torch.from_numpy(np.outer(g, cy)).to(dev)[:, :, None]
+        f.addcmul_(gy, torch.from_numpy(cx).to(dev)[None, None, :])
+    return f
+
+
 # ------------------------------------------------------------------ GPU
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(1024, 512, 512), (2048, 1024, 1024)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_poisson_full_size_fourier_modes_match_oracle(shape, prec):
+    """At the full workload sizes, with the plan the benchmark times: a
+    right-hand side of seven separable Fourier modes; 200k sampled solution
+    values against the oracle's value at each point."""
+    dev = torch.device("cuda", 0)
+    nx, ny, nz = shape
+    print(f"poisson modes {prec} {nx}x{ny}x{nz}", flush=True)
+    zf, modes = _mode_set(nx, ny, nz, nx + nz)
+    f = _mode_rhs(nx, ny, nz, modes, dev)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, LZ, BETA, precision=prec)
+    p = torch.empty_like(f)
+    pf.poisson_solve(plan, f, p)
+    torch.cuda.synchronize()
+    del f
+    rng = np.random.default_rng(3)
+    ns = 200_000
+    ii, jj, kk = rng.integers(0, nx, ns), rng.integers(0, ny, ns), rng.integers(0, nz, ns)
+    kk[:64] = 0
+    kk[64:128] = nz - 1
+    got = p[torch.from_numpy(kk).to(dev), torch.from_numpy(jj).to(dev),
+            torch.from_numpy(ii).to(dev)].cpu().numpy()
+    ref = np.zeros(ns)
+    for cx, cy, _, h in modes:
+        ref += h[kk] * cy[jj] * cx[ii]
+    check(got, ref, TOL[prec], f"{ns} sampled points")
+
+
 @pytest.mark.gpu
 def test_poisson_1024x512x512_fp64_residual_and_fp32_refine():
     dev = torch.device("cuda", 0)
@@ -250,6 +344,8 @@ def test_helmholtz_1024x1024x512_three_components():
         assert r64 < 1e-13
         assert r32 < 2e-10
         assert err < 1e-10
+        for prec in ("fp64", "fp32_refine"):
+            _sampled_columns_match_oracle(r3[c], out[prec][c], zf, S_C3, obc[c], prec, 7 + c)
 
 
 @pytest.mark.gpu
@@ -287,6 +383,7 @@ def test_projection_step_2048x1024x1024_in_one_graph():
         res = _helmholtz_residual(u[c], r3[c], zf, S_C3, obc[c])
         print(f"helmholtz component {c}: residual {res:.2e}", flush=True)
         assert res < 2e-10
+        _sampled_columns_match_oracle(r3[c], u[c], zf, S_C3, obc[c], "fp32_refine", 17 + c)
     del u, r3, g, plans
     torch.cuda.empty_cache()
     p64 = torch.empty_like(f)
@@ -337,3 +434,17 @@ def test_helmholtz_residual_matches_dense_operator(bc, dbc):
     r2 = r.clone()
     r2[3, 1, 2] += 1e-6
     assert _helmholtz_residual(u, r2, zf, s, bc) > 1e-8
+
+
+def test_fourier_mode_values_equal_the_oracle_solve():
+    """The sampled-mode construction above gives the oracle's full solve on a
+    small grid (every mode kind: x only, y only, both, Nyquist in x and y)."""
+    nx, ny, nz = 16, 12, 9
+    zf, modes = _mode_set(nx, ny, nz, 4)
+    f = np.zeros((nz, ny, nx))
+    want = np.zeros((nz, ny, nx))
+    for cx, cy, g, h in modes:
+        f += g[:, None, None] * cy[None, :, None] * cx[None, None, :]
+        want += h[:, None, None] * cy[None, :, None] * cx[None, None, :]
+    got = op.solve_poisson(f, zf, LX, LY)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
