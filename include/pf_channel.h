@@ -194,8 +194,11 @@ pf_status poisson_destroy(pf_poisson_plan *plan);
  * nz or nz-1 planes of the field); the plan is destroyed with
  * poisson_destroy and takes poisson_set_workspace, poisson_set_stream and
  * the stage timers. helmholtz3d_solve: r and u device (n, ny, nx) float64,
- * u must not overlap r or the workspace. helmholtz3d_update changes s for
- * the next substep (host recompute, upload enqueued on the plan's stream).
+ * u must not overlap r or the workspace. helmholtz3d_update changes s > 0
+ * for the solves enqueued after it: a kernel on the plan's stream rebuilds
+ * the shifted wavenumber table (no host staging, no synchronisation), and
+ * later solves take 1/s as a launch argument; capturable, and several
+ * updates with solves between them may be queued or captured in one graph.
  * Errors as poisson_solve; a Helmholtz plan is refused by poisson_solve and
  * poisson_project, and a Poisson plan by helmholtz3d_solve. */
 pf_status helmholtz3d_plan(pf_poisson_plan **out, const pf_grid *g, int32_t bc, double s,
@@ -210,17 +213,36 @@ pf_status helmholtz3d_update(pf_poisson_plan *plan, double s);
  * (I - s L_z) u = r, i.e. rows (s alpha, s gamma, 1 + s excess), s >= 0.
  * Rows are split into P chunks; chunk_rows is the
  * number of rows per chunk (0 picks it; otherwise 8, 16 or 32), at most 32
- * chunks; the last chunk is padded with identity rows. The chunk
- * coefficients, the reduced boundary system and its parallel cyclic
- * reduction are computed here in float64, subtraction-free, and uploaded.
+ * chunks; the last chunk is padded with identity rows. The rows are copied
+ * to the device; the chunk coefficients, the reduced boundary system's
+ * twisted elimination and its cyclic reduction are then computed there in
+ * float64, subtraction-free, by one kernel on `stream` (the plan call waits
+ * for it; pcr_update_coef reruns it).
  * precision: PF_FP64 (float64 field), PF_FP32 (float32 field), or
  * PF_FP32_REFINE (float64 field, float32 solves plus one float64-residual
  * correction in registers). n >= 4. */
 pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const double *gamma,
                       const double *excess, double s, int32_t precision, int32_t chunk_rows,
                       void *stream);
-/* Re-run Step 1 for a new s (per Runge-Kutta substep) on the host and
- * enqueue the upload on the plan's stream. */
+/* The same plan from the paper's form of the rows (the inputs A, B, C of
+ * Algorithm 2, here of L_z itself): lower[k] x[k-1] + diag[k] x[k] +
+ * upper[k] x[k+1] is row k of L_z, host arrays of length n, lower[0] =
+ * upper[n-1] = 0; the plan solves (I - s L_z) u = r. The rows are converted
+ * to the sign-normalised form (alpha = lower, gamma = upper, excess =
+ * -(lower + diag + upper), set to 0 when it is within 16 ulp of the three
+ * terms). PF_ERR_UNSUPPORTED when a row is not of M-matrix form (a negative
+ * off-diagonal, or a diagonal smaller in magnitude than the off-diagonal sum
+ * beyond rounding): the subtraction-free elimination needs it. Other
+ * arguments and errors as pcr_prepare. */
+pf_status pcr_prepare_rows(pf_pcr_plan **out, int32_t n, const double *lower, const double *diag,
+                           const double *upper, double s, int32_t precision, int32_t chunk_rows,
+                           void *stream);
+/* Re-run Step 1 for a new s >= 0 (one per Runge-Kutta substep, the paper's
+ * local recomputation of the chunk coefficients in Sec. 2.2.4): one kernel
+ * on the plan's stream recomputes every table from the stored rows of L_z.
+ * No host work, copy, allocation or synchronisation: stream-ordered with the
+ * plan's applies, and capturable, so a graph may hold several substeps with
+ * different s. */
 pf_status pcr_update_coef(pf_pcr_plan *plan, double s);
 /* In place, every column of a device (n, ny, nx) field; float64 or float32
  * per the plan's precision. nx must be a multiple of 64. */
@@ -253,8 +275,10 @@ pf_status pf_graph_destroy(pf_graph *graph);
  * launch (pcr[], field[], nx[], ny[] as for pcr_apply_batched: the plans of
  * a group share chunk rows and precision). Tasks are assigned largest first
  * to the least-loaded lane. Every task is ordered after the work already on
- * `stream`, and work enqueued on `stream` afterwards after every task; tasks
- * must not share plans or buffers. Inside pf_graph_begin/pf_graph_end on
+ * `stream`, and work enqueued on `stream` afterwards after every task. Tasks
+ * must not share Poisson plans, and nothing one task writes (p, workspace,
+ * Helmholtz fields) may overlap what another reads or writes: PF_ERR_ARG
+ * (Helmholtz plans, read only during an apply, may be shared). Inside pf_graph_begin/pf_graph_end on
  * `stream` the fork and join become graph edges. The lanes (default-priority
  * streams) and their events are created once per device by the first call,
  * which must not be inside a capture, and are kept until the process ends.

@@ -25,7 +25,7 @@ EXPORTS = [
     "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_project", "poisson_solve_batched",
     "helmholtz3d_plan", "helmholtz3d_solve", "helmholtz3d_update", "poisson_set_status",
     "poisson_set_stream", "poisson_destroy",
-    "pcr_prepare", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
+    "pcr_prepare", "pcr_prepare_rows", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
     "pcr_destroy",
     "pf_graph_begin", "pf_graph_end", "pf_graph_launch", "pf_graph_destroy",
     "poisson_timing", "poisson_timing_read", "pcr_timing", "pcr_timing_read",
@@ -86,6 +86,7 @@ def lib():
             "poisson_set_stream": (i32, [vp, vp]),
             "poisson_destroy": (i32, [vp]),
             "pcr_prepare": (i32, [C.POINTER(vp), i32, pd, pd, pd, dbl, i32, i32, vp]),
+            "pcr_prepare_rows": (i32, [C.POINTER(vp), i32, pd, pd, pd, dbl, i32, i32, vp]),
             "pcr_update_coef": (i32, [vp, dbl]),
             "pcr_apply": (i32, [vp, vp, i32, i32]),
             "pcr_apply_batched": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i32),

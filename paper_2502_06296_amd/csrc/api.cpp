@@ -230,12 +230,11 @@ struct pf_poisson_plan {
   double lx, ly;
   int bc = PF_BC_NEUMANN;  // NEUMANN: pressure Poisson; DIRICHLET_*: 3-D Helmholtz
   double kappa = 0.0;      // 1/s of the 3-D Helmholtz, folded into the sx table
-  std::vector<double> sx_host;  // modified wavenumbers of the x slots without kappa
   int prec, nref;
   hipStream_t st;
   int zchunk;
   DevArena ar;
-  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
+  size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sxb, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
       o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc, o_ctw;
   int ybc = PF_Y_PERIODIC;
   void *ws = nullptr;
@@ -255,7 +254,7 @@ struct pf_pcr_plan {
   hipStream_t st;
   std::vector<double> al, ga, ex;
   DevArena ar;
-  size_t o_d[11], o_f[11], o_m[4];  // double tables, float tables, M-matrix rows
+  size_t o_raw[3], o_d[11], o_f[11], o_m[4];  // rows of -L_z, double and float tables, M-matrix rows
   Timing tm;
 };
 
@@ -268,132 +267,57 @@ namespace {
 
 constexpr int kPcrTables = 11;
 
-// Algorithm 2, Step 1 (subtraction-free) for every chunk, then two solvers
-// of the reduced system. Fills 11 tables: fa, bg, ib, ra, rc (n each); the
-// cyclic-reduction multipliers k1, k2 (steps*2P) and invd (2P); the twisted
-// elimination's forward and backward multipliers tf, tb and reciprocal
-// twisted pivots ti (2P each).
-void pcr_tables(const pf_pcr_plan &pl, std::vector<std::vector<double>> &T) {
-  const int n = pl.n, P = pl.P, M = pl.M, np = P * M;
-  // rows past n are identity rows: they decouple because gamma[n-1] = 0
-  std::vector<double> A(np, 0.0), G(np, 0.0), E(np, 1.0);
-  for (int r = 0; r < n; ++r) {
-    A[r] = pl.s * pl.al[r];
-    G[r] = pl.s * pl.ga[r];
-    E[r] = 1.0 + pl.s * pl.ex[r];
-  }
-  T.assign(kPcrTables, {});
-  for (int t = 0; t < 5; ++t) T[t].assign(np, 0.0);
-  std::vector<double> RA(2 * P), RG(2 * P), RE(2 * P);
-  for (int p = 0; p < P; ++p) {
-    const int r0 = p * M, m = M;
-    const double *al = &A[r0], *ga = &G[r0], *ep = &E[r0];
-    std::vector<double> b(m), a(m), c(m), ef(m), eta(m);
-    a[1] = al[1]; ef[1] = ep[1]; b[1] = ga[1] + al[1] + ep[1];
-    for (int i = 2; i < m; ++i) {
-      const double t = al[i] / b[i - 1];
-      a[i] = t * a[i - 1];
-      ef[i] = ep[i] + t * ef[i - 1];
-      b[i] = ga[i] + a[i] + ef[i];
-    }
-    c[m - 2] = ga[m - 2];
-    eta[m - 2] = ef[m - 2];
-    for (int i = m - 3; i >= 1; --i) {
-      const double t = ga[i] / b[i + 1];
-      a[i] = a[i] + t * a[i + 1];
-      c[i] = t * c[i + 1];
-      eta[i] = ef[i] + t * eta[i + 1];
-    }
-    const double t0 = ga[0] / b[1];
-    RA[2 * p] = al[0]; RG[2 * p] = t0 * c[1]; RE[2 * p] = ep[0] + t0 * eta[1];
-    RA[2 * p + 1] = a[m - 1]; RG[2 * p + 1] = ga[m - 1]; RE[2 * p + 1] = ef[m - 1];
-    for (int i = 2; i < m; ++i) T[0][r0 + i] = al[i] / b[i - 1];
-    for (int i = 0; i <= m - 3; ++i) T[1][r0 + i] = ga[i] / b[i + 1];
-    for (int i = 1; i <= m - 2; ++i) {
-      T[2][r0 + i] = 1.0 / b[i];
-      T[3][r0 + i] = a[i];
-      T[4][r0 + i] = c[i];
-    }
-  }
-  const int nr = 2 * P;
-  // Twisted elimination of the reduced rows -RA x[r-1] + (RA+RG+RE) x[r] -
-  // RG x[r+1] = D[r]: a forward sweep y[r] = D[r] + tf[r] y[r-1] and a
-  // backward sweep z[r] = D[r] + tb[r] z[r+1] meet at any row r, where
-  // x[r] = (y[r] + tb[r] z[r+1]) ti[r]. Pivots are kept as off-diagonal plus
-  // excess (forward: RG + fe, backward: RA + be), and the twisted pivot is a
-  // sum of the excess and the two eliminated couplings' remainders, so no
-  // pivot is formed by subtraction.
-  {
-    std::vector<double> fe(nr), be(nr);
-    fe[0] = RA[0] + RE[0];
-    for (int r = 1; r < nr; ++r) fe[r] = RE[r] + RA[r] * fe[r - 1] / (RG[r - 1] + fe[r - 1]);
-    be[nr - 1] = RG[nr - 1] + RE[nr - 1];
-    for (int r = nr - 2; r >= 0; --r) be[r] = RE[r] + RG[r] * be[r + 1] / (RA[r + 1] + be[r + 1]);
-    for (int t = 8; t < 11; ++t) T[t].assign(nr, 0.0);
-    for (int r = 0; r < nr; ++r) {
-      const double fp = r > 0 ? RG[r - 1] + fe[r - 1] : 1.0;
-      const double bp = r < nr - 1 ? RA[r + 1] + be[r + 1] : 1.0;
-      const double lo = r > 0 ? RA[r] * fe[r - 1] / fp : RA[r];
-      const double hi = r < nr - 1 ? RG[r] * be[r + 1] / bp : RG[r];
-      T[8][r] = r > 0 ? RA[r] / fp : 0.0;
-      T[9][r] = r < nr - 1 ? RG[r] / bp : 0.0;
-      T[10][r] = 1.0 / (RE[r] + lo + hi);
-    }
-  }
-  T[5].assign((size_t)pl.steps * nr, 0.0);
-  T[6].assign((size_t)pl.steps * nr, 0.0);
-  for (int st = 0; st < pl.steps; ++st) {
-    const int s = 1 << st;
-    std::vector<double> nA(nr), nG(nr), nE(nr);
-    for (int r = 0; r < nr; ++r) {
-      double k1 = 0.0, k2 = 0.0, em = 0.0, ep2 = 0.0, am = 0.0, gp = 0.0;
-      if (r - s >= 0) { k1 = RA[r] / (RA[r - s] + RG[r - s] + RE[r - s]); am = RA[r - s]; em = RE[r - s]; }
-      if (r + s < nr) { k2 = RG[r] / (RA[r + s] + RG[r + s] + RE[r + s]); gp = RG[r + s]; ep2 = RE[r + s]; }
-      T[5][(size_t)st * nr + r] = k1;
-      T[6][(size_t)st * nr + r] = k2;
-      nA[r] = k1 * am;
-      nG[r] = k2 * gp;
-      nE[r] = RE[r] + k1 * em + k2 * ep2;
-    }
-    RA = nA; RG = nG; RE = nE;
-  }
-  T[7].assign(nr, 0.0);
-  for (int r = 0; r < nr; ++r) T[7][r] = 1.0 / (RA[r] + RG[r] + RE[r]);
+// lengths of the Step 1 tables (order of pf::HelmCoef): fa, bg, ib, ra, rc
+// (P*M each); the cyclic-reduction multipliers k1, k2 (steps*2P); invd and
+// the twisted elimination's tf, tb, ti (2P each)
+size_t pcr_table_len(const pf_pcr_plan &pl, int t) {
+  const size_t np = (size_t)pl.P * pl.M, nr = 2 * (size_t)pl.P;
+  return t < 5 ? np : (t < 7 ? (size_t)pl.steps * nr : nr);
 }
 
-pf_status pcr_upload(pf_pcr_plan *pl, bool first) {
-  std::vector<std::vector<double>> T;
-  pcr_tables(*pl, T);
-  if (first) {
-    for (int t = 0; t < kPcrTables; ++t) pl->o_d[t] = pl->ar.add(T[t].data(), T[t].size());
-    for (int t = 0; t < kPcrTables; ++t) pl->o_f[t] = pl->ar.add<float>(nullptr, T[t].size());
-    for (int t = 0; t < 4; ++t) pl->o_m[t] = pl->ar.add<double>(nullptr, (size_t)pl->P * pl->M);
-  } else {
-    for (int t = 0; t < kPcrTables; ++t)
-      std::memcpy(pl->ar.host.data() + pl->o_d[t], T[t].data(), T[t].size() * 8);
-  }
+// Lays out and allocates the plan's device tables: the rows of -L_z
+// (padded with zero rows, which become identity rows of I - s L_z), the
+// float64 and float32 Step 1 tables and the M-matrix rows; uploads the rows.
+pf_status pcr_alloc(pf_pcr_plan *pl) {
+  const size_t np = (size_t)pl->P * pl->M;
+  std::vector<double> al(np, 0.0), ga(np, 0.0), ex(np, 0.0);
+  std::copy(pl->al.begin(), pl->al.end(), al.begin());
+  std::copy(pl->ga.begin(), pl->ga.end(), ga.begin());
+  std::copy(pl->ex.begin(), pl->ex.end(), ex.begin());
+  pl->ar = DevArena();
+  pl->o_raw[0] = pl->ar.add(al.data(), np);
+  pl->o_raw[1] = pl->ar.add(ga.data(), np);
+  pl->o_raw[2] = pl->ar.add(ex.data(), np);
+  for (int t = 0; t < kPcrTables; ++t) pl->o_d[t] = pl->ar.add<double>(nullptr, pcr_table_len(*pl, t));
+  for (int t = 0; t < kPcrTables; ++t) pl->o_f[t] = pl->ar.add<float>(nullptr, pcr_table_len(*pl, t));
+  for (int t = 0; t < 4; ++t) pl->o_m[t] = pl->ar.add<double>(nullptr, np);
+  pl->ar.cap = pl->ar.used;
+  PF_HIP(hipMalloc((void **)&pl->ar.base, pl->ar.cap));
+  PF_HIP(hipMemcpy(pl->ar.base, pl->ar.host.data(), pl->ar.used, hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+// Algorithm 2, Step 1 for the plan's s, enqueued on stream st (a kernel:
+// no host work, no copy, capturable).
+pf_status pcr_recompute(pf_pcr_plan *pl, double s, hipStream_t st) {
+  pf::PcrPrep p;
+  p.al = pl->ar.at<double>(pl->o_raw[0]);
+  p.ga = pl->ar.at<double>(pl->o_raw[1]);
+  p.ex = pl->ar.at<double>(pl->o_raw[2]);
   for (int t = 0; t < kPcrTables; ++t) {
-    float *f = reinterpret_cast<float *>(pl->ar.host.data() + pl->o_f[t]);
-    for (size_t i = 0; i < T[t].size(); ++i) f[i] = (float)T[t][i];
+    p.d[t] = pl->ar.at<double>(pl->o_d[t]);
+    p.f[t] = pl->ar.at<float>(pl->o_f[t]);
   }
-  double *mA = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[0]);
-  double *mG = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[1]);
-  double *mE = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[2]);
-  double *mD = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_m[3]);
-  for (int r = 0; r < pl->P * pl->M; ++r) {
-    const bool real = r < pl->n;
-    mA[r] = real ? pl->s * pl->al[r] : 0.0;
-    mG[r] = real ? pl->s * pl->ga[r] : 0.0;
-    mE[r] = real ? 1.0 + pl->s * pl->ex[r] : 1.0;
-    mD[r] = mA[r] + mG[r] + mE[r];
-  }
-  if (first) {
-    pl->ar.cap = pl->ar.used;
-    PF_HIP(hipMalloc((void **)&pl->ar.base, pl->ar.cap));
-    PF_HIP(hipMemcpy(pl->ar.base, pl->ar.host.data(), pl->ar.used, hipMemcpyHostToDevice));
-  } else {
-    PF_HIP(hipMemcpyAsync(pl->ar.base, pl->ar.host.data(), pl->ar.used, hipMemcpyHostToDevice, pl->st));
-  }
+  p.mA = pl->ar.at<double>(pl->o_m[0]);
+  p.mG = pl->ar.at<double>(pl->o_m[1]);
+  p.mE = pl->ar.at<double>(pl->o_m[2]);
+  p.mD = pl->ar.at<double>(pl->o_m[3]);
+  p.n = pl->n;
+  p.P = pl->P;
+  p.M = pl->M;
+  p.steps = pl->steps;
+  hipError_t e = pf::launch_pcr_prepare(p, s, st);
+  if (e != hipSuccess) return fail(PF_ERR_DEVICE, "Step 1 kernel: %s", hipGetErrorString(e));
   return PF_OK;
 }
 
@@ -505,7 +429,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   // (zero-gradient walls), or the sine modes, 4 sin^2(pi (q + 1) / 2 ny) / dy^2
   // (value-zero walls); ctw[q] = exp(-i pi q / 2 ny) serves both transforms.
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
-  pl->sx_host = sx;
+  const std::vector<double> sxb = sx;  // without the Helmholtz shift kappa
   for (double &v : sx) v += pl->kappa;
   std::vector<double2> ctw;
   {
@@ -531,6 +455,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   pl->o_zex = A.add(ex.data(), ex.size());
   pl->o_dzf = A.add(dzf.data(), dzf.size());
   pl->o_sx = A.add(sx.data(), sx.size());
+  pl->o_sxb = A.add(sxb.data(), sxb.size());
   pl->o_sy = A.add(sy.data(), sy.size());
   pl->o_twx_d = A.add(twxd.data(), twxd.size());
   pl->o_twy_d = A.add(twyd.data(), twyd.size());
@@ -580,11 +505,14 @@ pf_status helmholtz3d_update(pf_poisson_plan *pl, double s) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   if (pl->bc == PF_BC_NEUMANN) return fail(PF_ERR_ARG, "not a Helmholtz plan");
   if (!(s > 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and > 0");
-  pl->kappa = 1.0 / s;
-  double *h = reinterpret_cast<double *>(pl->ar.host.data() + pl->o_sx);
-  for (size_t i = 0; i < pl->sx_host.size(); ++i) h[i] = pl->sx_host[i] + pl->kappa;
-  PF_HIP(hipMemcpyAsync(pl->ar.base + pl->o_sx, h, pl->sx_host.size() * sizeof(double),
-                        hipMemcpyHostToDevice, pl->st));
+  // the shifted x-slot table is rebuilt by a kernel on the plan's stream
+  // from the unshifted one (no host staging: capturable, and several
+  // updates may be queued); later solves take kappa as a launch argument
+  const double kappa = 1.0 / s;
+  hipError_t e = pf::launch_shift_add(pl->ar.at<double>(pl->o_sxb), pl->ar.at<double>(pl->o_sx), pl->nx,
+                                      kappa, pl->st);
+  if (e != hipSuccess) return fail(PF_ERR_DEVICE, "helmholtz3d_update: %s", hipGetErrorString(e));
+  pl->kappa = kappa;
   return PF_OK;
 }
 
@@ -904,7 +832,9 @@ pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const d
   pl->al.assign(alpha, alpha + n);
   pl->ga.assign(gamma, gamma + n);
   pl->ex.assign(excess, excess + n);
-  pf_status st = pcr_upload(pl, true);
+  pf_status st = pcr_alloc(pl);
+  if (!st) st = pcr_recompute(pl, s, pl->st);
+  if (!st && hipStreamSynchronize(pl->st) != hipSuccess) st = fail(PF_ERR_DEVICE, "Step 1 kernel failed");
   if (st) {
     if (pl->ar.base) (void)hipFree(pl->ar.base);
     delete pl;
@@ -914,12 +844,39 @@ pf_status pcr_prepare(pf_pcr_plan **out, int32_t n, const double *alpha, const d
   return PF_OK;
 }
 
+pf_status pcr_prepare_rows(pf_pcr_plan **out, int32_t n, const double *lower, const double *diag,
+                           const double *upper, double s, int32_t precision, int32_t chunk_rows, void *stream) {
+  if (!out) return fail(PF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 4) return fail(PF_ERR_ARG, "n must be >= 4 (got %d)", n);
+  if (!lower || !diag || !upper) return fail(PF_ERR_ARG, "row arrays must be host pointers");
+  if (lower[0] != 0.0 || upper[n - 1] != 0.0) return fail(PF_ERR_ARG, "lower[0] and upper[n-1] must be 0");
+  // rows of L_z: lower, upper >= 0 and a diagonal no larger than -(lower +
+  // upper); the excess -(lower + diag + upper) is clamped at zero within
+  // rounding of the three terms
+  std::vector<double> al(n), ga(n), ex(n);
+  for (int r = 0; r < n; ++r) {
+    const double A = lower[r], B = diag[r], C = upper[r];
+    if (!std::isfinite(A) || !std::isfinite(B) || !std::isfinite(C))
+      return fail(PF_ERR_ARG, "row %d is not finite", r);
+    if (A < 0.0 || C < 0.0)
+      return fail(PF_ERR_UNSUPPORTED, "row %d: negative off-diagonal of L_z (not an M-matrix form)", r);
+    const double e = -(A + B + C);
+    const double tol = 16.0 * 2.220446049250313e-16 * (A + std::fabs(B) + C);
+    if (e < -tol)
+      return fail(PF_ERR_UNSUPPORTED, "row %d: diagonal of -L_z below the off-diagonal sum (not an M-matrix)", r);
+    al[r] = A;
+    ga[r] = C;
+    ex[r] = e > tol ? e : 0.0;
+  }
+  return pcr_prepare(out, n, al.data(), ga.data(), ex.data(), s, precision, chunk_rows, stream);
+}
+
 pf_status pcr_update_coef(pf_pcr_plan *pl, double s) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   if (!(s >= 0.0) || !std::isfinite(s)) return fail(PF_ERR_ARG, "s must be finite and >= 0");
-  PF_HIP(hipStreamSynchronize(pl->st));  // the host staging copy is reused
   pl->s = s;
-  return pcr_upload(pl, false);
+  return pcr_recompute(pl, s, pl->st);
 }
 
 pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw_in) {
@@ -940,8 +897,9 @@ pf_status pcr_set_shape(pf_pcr_plan *pl, int32_t chunk_rows, int32_t cw_in) {
   pl->cw = cw;
   pl->steps = 0;
   while ((1 << pl->steps) < 2 * P) ++pl->steps;
-  pl->ar = DevArena();
-  pf_status st = pcr_upload(pl, true);
+  pf_status st = pcr_alloc(pl);
+  if (!st) st = pcr_recompute(pl, pl->s, pl->st);
+  if (!st && hipStreamSynchronize(pl->st) != hipSuccess) st = fail(PF_ERR_DEVICE, "Step 1 kernel failed");
   if (old) (void)hipFree(old);
   return st;
 }
@@ -1093,6 +1051,31 @@ pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, voi
       for (int c = 0; c < T.ncomp; ++c) cost[t] += (double)T.pcr[c]->n * T.nx[c] * T.ny[c] / 3.0;
     }
   }
+  // tasks run concurrently: no Poisson plan (its workspace and scratch
+  // tables) may serve two tasks, and nothing a task writes may overlap what
+  // another task reads or writes
+  struct Range { const void *p; size_t n; int task; bool write; };
+  std::vector<Range> rg;
+  for (int t = 0; t < count; ++t) {
+    const pf_task &T = tasks[t];
+    if (T.poisson) {
+      const size_t nb = T.poisson->npts() * sizeof(double);
+      rg.push_back({T.rhs, nb, t, false});
+      rg.push_back({T.p, nb, t, true});
+      if (T.poisson->ws_need) rg.push_back({T.poisson->ws, T.poisson->ws_need, t, true});
+      for (int u = 0; u < t; ++u)
+        if (tasks[u].poisson == T.poisson) return fail(PF_ERR_ARG, "tasks %d and %d share a Poisson plan", u, t);
+    }
+    for (int c = 0; c < T.ncomp; ++c) {
+      const size_t esz = T.pcr[c]->prec == PF_FP32 ? 4 : 8;
+      rg.push_back({T.field[c], (size_t)T.pcr[c]->n * T.nx[c] * T.ny[c] * esz, t, true});
+    }
+  }
+  for (size_t a = 0; a < rg.size(); ++a)
+    for (size_t b = a + 1; b < rg.size(); ++b)
+      if (rg[a].task != rg[b].task && (rg[a].write || rg[b].write) &&
+          overlaps(rg[a].p, rg[a].n, rg[b].p, rg[b].n))
+        return fail(PF_ERR_ARG, "tasks %d and %d overlap in device memory", rg[a].task, rg[b].task);
   if (count == 0) return PF_OK;
   int dev = 0;
   PF_HIP(hipGetDevice(&dev));

@@ -1183,6 +1183,155 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
   return hipGetLastError();
 }
 
+// ------------------------------------------- Algorithm 2, Step 1 on the device
+// The Step 1 coefficients of (I - s L_z) for every chunk, the reduced
+// system's twisted-elimination multipliers and its cyclic-reduction
+// multipliers, recomputed from the rows of -L_z and s by one workgroup, so
+// that a new s (one per Runge-Kutta substep) needs no host work, no copy and
+// no synchronisation. Rows in sign-normalised form: row r of I - s L_z is
+// -A x[r-1] + (A + G + E) x[r] - G x[r+1] with A = s alpha, G = s gamma,
+// E = 1 + s excess; the padding rows (alpha = gamma = excess = 0) are
+// identity rows.
+//
+// Per chunk of m rows (one thread each), eliminating the interior onto the
+// two end rows keeps every pivot as a sum of non-negative parts: the forward
+// elimination's pivot b = G + a + ef (a the coupling to the chunk's first
+// row, ef the carried excess), the backward pass's couplings a, c and excess
+// eta. The reduced 2P rows couple chunk ends; they are factored from both
+// ends (twisted elimination) and by cyclic reduction, each with the excess
+// carried instead of a diagonal formed by subtraction.
+constexpr int kPrepRows = 32 * 32;  // P * M at most
+__global__ __launch_bounds__(64) void k_pcr_prepare(PcrPrep t, double s) {
+  __shared__ double sb[kPrepRows], sa[kPrepRows], sc[kPrepRows], sef[kPrepRows], seta[kPrepRows];
+  __shared__ double RA[64], RG[64], RE[64], fe[64], be[64];
+  const int tid = threadIdx.x, P = t.P, m = t.M, nr = 2 * P, np = P * m;
+  double *T0 = t.d[0], *T1 = t.d[1], *T2 = t.d[2], *T3 = t.d[3], *T4 = t.d[4];
+  if (tid < P) {
+    const int r0 = tid * m;
+    double *b = sb + r0, *a = sa + r0, *c = sc + r0, *ef = sef + r0, *eta = seta + r0;
+    auto A = [&](int i) { return s * t.al[r0 + i]; };
+    auto G = [&](int i) { return s * t.ga[r0 + i]; };
+    auto E = [&](int i) { return 1.0 + s * t.ex[r0 + i]; };
+    a[1] = A(1);
+    ef[1] = E(1);
+    b[1] = G(1) + A(1) + E(1);
+    for (int i = 2; i < m; ++i) {
+      const double q = A(i) / b[i - 1];
+      a[i] = q * a[i - 1];
+      ef[i] = E(i) + q * ef[i - 1];
+      b[i] = G(i) + a[i] + ef[i];
+    }
+    c[m - 2] = G(m - 2);
+    eta[m - 2] = ef[m - 2];
+    for (int i = m - 3; i >= 1; --i) {
+      const double q = G(i) / b[i + 1];
+      a[i] = a[i] + q * a[i + 1];
+      c[i] = q * c[i + 1];
+      eta[i] = ef[i] + q * eta[i + 1];
+    }
+    const double q0 = G(0) / b[1];
+    RA[2 * tid] = A(0);
+    RG[2 * tid] = q0 * c[1];
+    RE[2 * tid] = E(0) + q0 * eta[1];
+    RA[2 * tid + 1] = a[m - 1];
+    RG[2 * tid + 1] = G(m - 1);
+    RE[2 * tid + 1] = ef[m - 1];
+    for (int i = 0; i < m; ++i) {
+      T0[r0 + i] = i >= 2 ? A(i) / b[i - 1] : 0.0;
+      T1[r0 + i] = i <= m - 3 ? G(i) / b[i + 1] : 0.0;
+      const bool in = i >= 1 && i <= m - 2;
+      T2[r0 + i] = in ? 1.0 / b[i] : 0.0;
+      T3[r0 + i] = in ? a[i] : 0.0;
+      T4[r0 + i] = in ? c[i] : 0.0;
+    }
+  }
+  __syncthreads();
+  // twisted elimination of the reduced rows: forward pivots G + fe,
+  // backward pivots A + be, both sums of non-negative parts
+  if (tid == 0) {
+    fe[0] = RA[0] + RE[0];
+    for (int r = 1; r < nr; ++r) fe[r] = RE[r] + RA[r] * fe[r - 1] / (RG[r - 1] + fe[r - 1]);
+    be[nr - 1] = RG[nr - 1] + RE[nr - 1];
+    for (int r = nr - 2; r >= 0; --r) be[r] = RE[r] + RG[r] * be[r + 1] / (RA[r + 1] + be[r + 1]);
+  }
+  __syncthreads();
+  if (tid < nr) {
+    const int r = tid;
+    const double fp = r > 0 ? RG[r - 1] + fe[r - 1] : 1.0;
+    const double bp = r < nr - 1 ? RA[r + 1] + be[r + 1] : 1.0;
+    const double lo = r > 0 ? RA[r] * fe[r - 1] / fp : RA[r];
+    const double hi = r < nr - 1 ? RG[r] * be[r + 1] / bp : RG[r];
+    t.d[8][r] = r > 0 ? RA[r] / fp : 0.0;
+    t.d[9][r] = r < nr - 1 ? RG[r] / bp : 0.0;
+    t.d[10][r] = 1.0 / (RE[r] + lo + hi);
+  }
+  // cyclic reduction of the reduced rows: step st couples rows 2^st apart;
+  // the new excess is the old one plus the eliminated neighbours' excesses
+  for (int st = 0; st < t.steps; ++st) {
+    const int h = 1 << st;
+    double nA = 0.0, nG = 0.0, nE = 0.0;
+    if (tid < nr) {
+      const int r = tid;
+      double k1 = 0.0, k2 = 0.0, em = 0.0, ep2 = 0.0, am = 0.0, gp = 0.0;
+      if (r - h >= 0) {
+        k1 = RA[r] / (RA[r - h] + RG[r - h] + RE[r - h]);
+        am = RA[r - h];
+        em = RE[r - h];
+      }
+      if (r + h < nr) {
+        k2 = RG[r] / (RA[r + h] + RG[r + h] + RE[r + h]);
+        gp = RG[r + h];
+        ep2 = RE[r + h];
+      }
+      t.d[5][st * nr + r] = k1;
+      t.d[6][st * nr + r] = k2;
+      nA = k1 * am;
+      nG = k2 * gp;
+      nE = RE[r] + k1 * em + k2 * ep2;
+    }
+    __syncthreads();
+    if (tid < nr) {
+      RA[tid] = nA;
+      RG[tid] = nG;
+      RE[tid] = nE;
+    }
+    __syncthreads();
+  }
+  if (tid < nr) t.d[7][tid] = 1.0 / (RA[tid] + RG[tid] + RE[tid]);
+  // the float32 copies and the M-matrix rows of the refinement's residual
+  __syncthreads();
+  const int len[11] = {np, np, np, np, np, t.steps * nr, t.steps * nr, nr, nr, nr, nr};
+  for (int k = 0; k < 11; ++k)
+    for (int i = tid; i < len[k]; i += 64) t.f[k][i] = (float)t.d[k][i];
+  for (int r = tid; r < np; r += 64) {
+    const double a = s * t.al[r], g = s * t.ga[r], e = 1.0 + s * t.ex[r];
+    t.mA[r] = a;
+    t.mG[r] = g;
+    t.mE[r] = e;
+    t.mD[r] = a + g + e;
+  }
+}
+
+hipError_t launch_pcr_prepare(const PcrPrep &p, double s, hipStream_t st) {
+  if (p.P < 1 || p.P > 32 || p.P * p.M > kPrepRows || p.M < 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pcr_prepare, dim3(1), dim3(64), 0, st, p, s);
+  return hipGetLastError();
+}
+
+// dst[i] = src[i] + kappa: the x-slot shifts of a 3-D Helmholtz plan for a
+// new s (kappa = 1/s)
+__global__ __launch_bounds__(256) void k_shift_add(const double *__restrict__ src, double *__restrict__ dst,
+                                                   int n, double kappa) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i] + kappa;
+}
+
+hipError_t launch_shift_add(const double *src, double *dst, int n, double kappa, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_add, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, kappa);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ plain copy
 __global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                               size_t n) {

@@ -216,6 +216,23 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
                        const HelmJob *jobs, hipStream_t st);
 int helm_default_cw(int P);
 
+// Algorithm 2, Step 1 on the device: from the rows (alpha, gamma, excess)
+// of -L_z (padded to P*M rows with zeros) and s, the 11 float64 tables of a
+// Helmholtz plan in HelmCoef order (fa, bg, ib, ra, rc: P*M each; k1, k2:
+// steps*2P; invd, tf, tb, ti: 2P), their float32 copies, and the M-matrix
+// rows s alpha, s gamma, 1 + s excess and their sum. One workgroup; P <= 32,
+// P*M <= 1024, M >= 3.
+struct PcrPrep {
+  const double *al, *ga, *ex;
+  double *d[11];
+  float *f[11];
+  double *mA, *mG, *mE, *mD;
+  int n, P, M, steps;
+};
+hipError_t launch_pcr_prepare(const PcrPrep &p, double s, hipStream_t st);
+// dst[i] = src[i] + kappa for i < n
+hipError_t launch_shift_add(const double *src, double *dst, int n, double kappa, hipStream_t st);
+
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 }  // namespace pf

@@ -214,6 +214,19 @@ def pcr_prepare(alpha, gamma, excess, s, precision="fp64", chunk_rows=0, stream=
     return PcrPlan(h, n, _prec(precision), stream)
 
 
+def pcr_prepare_rows(lower, diag, upper, s, precision="fp64", chunk_rows=0, stream=None):
+    """The same plan from the rows (lower, diag, upper) of L_z itself."""
+    import numpy as np
+    a, b, c = (np.ascontiguousarray(v, dtype=np.float64) for v in (lower, diag, upper))
+    n = a.size
+    pd = C.POINTER(C.c_double)
+    h = C.c_void_p()
+    N.check(N.lib().pcr_prepare_rows(C.byref(h), n, a.ctypes.data_as(pd), b.ctypes.data_as(pd),
+                                     c.ctypes.data_as(pd), float(s), _prec(precision), int(chunk_rows),
+                                     N.stream_handle(stream)))
+    return PcrPlan(h, n, _prec(precision), stream)
+
+
 def pcr_update_coef(plan, s):
     N.check(N.lib().pcr_update_coef(plan.handle, float(s)))
 

@@ -165,3 +165,31 @@ def test_autotune_cache_ignores_corrupt_file(tmp_path):
     assert autotune.load_cache(str(p)) == {}
     autotune.save_cache({"k": {"zsolve_variant": 3}}, str(p))
     assert autotune.load_cache(str(p)) == {"k": {"zsolve_variant": 3}}
+
+
+def test_pcr_prepare_rows_rejects_rows_outside_the_m_matrix_form():
+    """The (lower, diag, upper) form of L_z is validated and converted on the
+    host before anything reaches the device."""
+    L = N.lib()
+    pd = C.POINTER(C.c_double)
+    n = 8
+    lo = np.full(n, 2.0); up = np.full(n, 3.0)
+    lo[0] = 0.0; up[-1] = 0.0
+    di = -(lo + up)
+    h = C.c_void_p()
+
+    def call(lo, di, up, s=1e-3):
+        return L.pcr_prepare_rows(C.byref(h), n, lo.ctypes.data_as(pd), di.ctypes.data_as(pd),
+                                  up.ctypes.data_as(pd), s, 0, 0, None)
+    bad = lo.copy(); bad[0] = 1.0                     # coupling below the first row
+    assert call(bad, di, up) == N.PF_ERR_ARG
+    bad = up.copy(); bad[3] = -1.0                    # negative off-diagonal
+    assert call(lo, di, bad) == N.PF_ERR_UNSUPPORTED
+    bad = di.copy(); bad[4] = -4.0                    # |diag| below lower + upper = 5
+    assert call(lo, bad, up) == N.PF_ERR_UNSUPPORTED
+    bad = di.copy(); bad[2] = np.nan
+    assert call(lo, bad, up) == N.PF_ERR_ARG
+    assert call(lo, di, up, s=-1.0) == N.PF_ERR_ARG
+    assert L.pcr_prepare_rows(C.byref(h), 3, lo.ctypes.data_as(pd), di.ctypes.data_as(pd),
+                              up.ctypes.data_as(pd), 1e-3, 0, 0, None) == N.PF_ERR_ARG
+    assert b"M-matrix" in L.pf_last_error() or L.pf_last_error()
