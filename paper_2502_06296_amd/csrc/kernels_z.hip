@@ -586,11 +586,12 @@ int zsolve_default_variant(int nx, int nz, bool fp64) {
   // separator form, 16 rows, 32 columns), 10 (1.12); float32 storage (padded
   // planes) 18 (0.86 ms: separator form, 8 rows, 8 columns), 19 (0.87), 16
   // (0.95); the unpaired 4 and 3 as fall-backs where the LDS or thread
-  // budget excludes the paired shapes
-  // fall-backs. Short columns (few chunks) would leave those shapes with
+  // budget excludes the paired shapes; at 1024 rows (where only 4, 18 and
+  // 20 fit) float64 storage takes 20 (11.4 ms at 2048x1024x1024 against
+  // 22.2 ms for 4). Short columns (few chunks) would leave those shapes with
   // tiny workgroups, so the first fitting shape with at least 128 threads
   // wins, widened by the 64- and 128-column shapes.
-  static const int f64[] = {21, 10, 19, 26, 25, 24, 23, 8, 4, 3},
+  static const int f64[] = {21, 10, 19, 26, 25, 24, 23, 20, 8, 4, 3},
                    f32[] = {18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
   const int *list = fp64 ? f64 : f32;
   const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
@@ -792,6 +793,33 @@ __device__ __forceinline__ cptr<T> as_const(const void *p) {
   return (cptr<T>)p;
 }
 
+// The rows of a Step 1 table that a lane's chunk uses, from row r0 on. With
+// 64-column chunks r0 is wave-uniform and the tables are read through the
+// constant address space as scalar loads (GRow); narrower chunks put two or
+// four chunks in a wave, and their tables are read from a copy in LDS
+// (LRow): per-lane vector loads of the tables in global memory spilled the
+// 32-row shapes, and wave-uniform loads of every chunk of the wave with a
+// per-lane select ran out of scalar registers.
+// A compiler memory fence every fourth row of an unrolled sweep: the
+// compiler would otherwise issue every table and field read of the sweep up
+// front and run out of registers. It emits no instruction.
+__device__ __forceinline__ void sched_fence(int q) {
+  if ((q & 3) == 3) asm volatile("" ::: "memory");
+}
+
+template <typename T>
+struct GRow {
+  cptr<T> t;
+  int r0;
+  __device__ __forceinline__ T operator[](int q) const { return t[r0 + q]; }
+};
+template <typename T>
+struct LRow {
+  const T *t;
+  int r0;
+  __device__ __forceinline__ T operator[](int q) const { return t[r0 + q]; }
+};
+
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -806,17 +834,22 @@ __device__ __forceinline__ float fmad(float a, float b, float c) { return __buil
 // stored), so every sweep step is an explicit fused multiply-add: each
 // y[r] and z[r] is then the same chain of roundings in every wave. RD holds
 // 2P rows of CW values and is written once per call.
-template <typename TC, int M, bool NBR, typename CP>
-__device__ __forceinline__ void helm_solve_regs(TC (&d)[M], int r0, CP fa, CP bg, CP ib, CP ra,
-                                                CP rc, CP tf, CP tb, CP ti, int P, TC *RD, int w,
-                                                int lane, bool active, int CW, TC &below,
-                                                TC &above) {
+template <typename TC, int M, bool NBR, typename RW, typename CP>
+__device__ __forceinline__ void helm_solve_regs(TC (&d)[M], RW fa, RW bg, RW ib, RW ra, RW rc, CP tf,
+                                                CP tb, CP ti, int P, TC *RD, int w, int lane,
+                                                bool active, int CW, TC &below, TC &above) {
   if (active) {
     // Step 2: forward and backward reduction of d
 #pragma unroll
-    for (int q = 2; q < M; ++q) d[q] = d[q] + fa[r0 + q] * d[q - 1];
+    for (int q = 2; q < M; ++q) {
+      d[q] = d[q] + fa[q] * d[q - 1];
+      sched_fence(q);
+    }
 #pragma unroll
-    for (int q = M - 3; q >= 0; --q) d[q] = d[q] + bg[r0 + q] * d[q + 1];
+    for (int q = M - 3; q >= 0; --q) {
+      d[q] = d[q] + bg[q] * d[q + 1];
+      sched_fence(q);
+    }
     RD[(2 * w) * CW + lane] = d[0];
     RD[(2 * w + 1) * CW + lane] = d[M - 1];
   }
@@ -861,7 +894,10 @@ __device__ __forceinline__ void helm_solve_regs(TC (&d)[M], int r0, CP fa, CP bg
   }
   // Step 4: rebuild the interior in place
 #pragma unroll
-  for (int q = 1; q < M - 1; ++q) d[q] = (d[q] + ra[r0 + q] * x0 + rc[r0 + q] * xl) * ib[r0 + q];
+  for (int q = 1; q < M - 1; ++q) {
+    d[q] = (d[q] + ra[q] * x0 + rc[q] * xl) * ib[q];
+    sched_fence(q);
+  }
   d[0] = x0;
   d[M - 1] = xl;
 }
@@ -877,70 +913,157 @@ struct HelmArgs {
 // CW columns per chunk: 64 (one wave per chunk, wave-uniform coefficient
 // addresses), 32 or 16 (two or four chunks per wave: smaller workgroups, so
 // that several fit on a compute unit).
+// Steps 2-4 for the chunk of one lane (see k_helm), with the Step 1 rows
+// from RW sources (GRow or LRow) and the reduced system's multipliers from
+// constant memory.
+// Hides a per-lane column pointer from common-subexpression elimination:
+// with chunks narrower than a wave the row addresses are per-lane 64-bit
+// values, and keeping all of them from the loads to the stores of a sweep
+// took as many registers as the column itself; they are recomputed instead.
+template <typename TS>
+__device__ __forceinline__ TS *fresh(TS *p) {
+  uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  asm volatile("" : "+v"(a));
+  return reinterpret_cast<TS *>(a);
+}
+
+template <typename TS, typename TC, int M, bool REFINE, int CW, typename RW, typename DW>
+__device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n, RW fa, RW bg,
+                                            RW ibv, RW ra, RW rc, DW mal, DW mga, DW mdg,
+                                            cptr<TC> tf, cptr<TC> tb, cptr<TC> ti, int P, TC *RD,
+                                            int w, int lane, bool active) {
+  TC below, above;
+  if constexpr (!REFINE) {
+    TC d[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      d[q] = (active && r0 + q < n) ? (TC)cp[(size_t)q * plane] : TC(0);
+      if constexpr (CW < 64) sched_fence(q);
+    }
+    helm_solve_regs<TC, M, false>(d, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD, w, lane, active, CW,
+                                  below, above);
+    if constexpr (CW < 64) cp = fresh(cp);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (r0 + q < n) cp[(size_t)q * plane] = (TS)d[q];
+        if constexpr (CW < 64) sched_fence(q);
+      }
+    }
+  } else {
+    // Narrow chunks (CW < 64) put two or four chunks in a wave and need the
+    // registers for the two float32 solves: the float64 right-hand side is
+    // read again for the residual instead of being held (the field is only
+    // written at the end, and the second read is served by the caches)
+    constexpr bool kHold = CW == 64;
+    double r[M];
+    TC u[M], dd[M];
+    // every read of the column is issued before the first is used
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
+      if constexpr (!kHold) sched_fence(q);
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) u[q] = (TC)r[q];
+    // the first solve also gives the neighbours across the chunk ends
+    helm_solve_regs<TC, M, true>(u, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD, w, lane, active, CW,
+                                 below, above);
+    if constexpr (!kHold) cp = fresh(cp);
+    // the residual, in two halves of the chunk when the right-hand side is
+    // read again: all reads of a half are issued before the first is used
+    constexpr int kHalf = kHold ? M : M / 2;
+#pragma unroll
+    for (int h = 0; h < M; h += kHalf) {
+      if constexpr (!kHold) {
+#pragma unroll
+        for (int q = h; q < h + kHalf; ++q) {
+          r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
+          sched_fence(q);
+        }
+      }
+      if (!active) continue;
+#pragma unroll
+      for (int q = h; q < h + kHalf; ++q) {
+        const double al = mal[q], ga = mga[q], dg = mdg[q];
+        const double um = q == 0 ? (double)below : (double)u[q == 0 ? 0 : q - 1];
+        const double up = q == M - 1 ? (double)above : (double)u[q == M - 1 ? q : q + 1];
+        dd[q] = (TC)(r[q] - (dg * (double)u[q] - al * um - ga * up));
+        if constexpr (!kHold) {
+          // row by row: left to itself the compiler reads every table row
+          // of the loop first and spills them
+          asm volatile("" : "+v"(dd[q]));
+          sched_fence(q);
+        }
+      }
+    }
+    helm_solve_regs<TC, M, false>(dd, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD + 2 * P * CW, w, lane,
+                                  active, CW, below, above);
+    if constexpr (!kHold) cp = fresh(cp);
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (r0 + q < n) cp[(size_t)q * plane] = (TS)((double)u[q] + (double)dd[q]);
+        if constexpr (!kHold) sched_fence(q);
+      }
+    }
+  }
+}
+
+// TS = TC = double (float64), TS = TC = float (float32 storage), or TS =
+// double, TC = float with REFINE: a float32 solve, the float64 residual
+// r - (I - s L_z) u in registers, a float32 solve for the correction.
+// CW columns per chunk: 64 (one wave per chunk, wave-uniform coefficient
+// addresses), 32 or 16 (two or four chunks per wave, so that a column of 32
+// chunks fits a workgroup; the Step 1 tables are then copied to LDS after
+// the reduced rows: 5 P M values of TC, and for REFINE 3 P M float64 rows).
 template <typename TS, typename TC, int M, int CW, bool REFINE>
 __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
-  extern __shared__ unsigned char shraw[];
+  extern __shared__ double shd[];
   const HelmJob &J = args.job[blockIdx.y];
   const HelmCoef &C = J.c;
   const int nib = J.nx / CW;
   const long nblk = (long)nib * J.ny;
   if ((long)blockIdx.x >= nblk) return;  // uniform per block
-  // one array of 2P reduced rows per solve
-  TC *RD = reinterpret_cast<TC *>(shraw);
+  // the 2P reduced rows of each solve (two solves with REFINE)
+  TC *RD = reinterpret_cast<TC *>(shd);
   const int w = CW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / CW;
   const int lane = threadIdx.x % CW;
   const bool active = w < C.P;
   const int ib = blockIdx.x % nib;
   const int j = blockIdx.x / nib;
-  const int n = C.n;
   const int r0 = active ? w * M : 0;
   const size_t plane = (size_t)J.nx * J.ny;
   TS *cp = reinterpret_cast<TS *>(J.field) + (size_t)j * J.nx + ib * CW + lane + (size_t)r0 * plane;
-  const cptr<TC> fa = as_const<TC>(C.fa), bg = as_const<TC>(C.bg), ibv = as_const<TC>(C.ib);
-  const cptr<TC> ra = as_const<TC>(C.ra), rc = as_const<TC>(C.rc);
   const cptr<TC> tf = as_const<TC>(C.tf), tb = as_const<TC>(C.tb), ti = as_const<TC>(C.ti);
-  TC below, above;
-
-  if constexpr (!REFINE) {
-    TC d[M];
-#pragma unroll
-    for (int q = 0; q < M; ++q) d[q] = (active && r0 + q < n) ? (TC)cp[(size_t)q * plane] : TC(0);
-    helm_solve_regs<TC, M, false>(d, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD, w, lane, active,
-                                  CW, below, above);
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < M; ++q)
-        if (r0 + q < n) cp[(size_t)q * plane] = (TS)d[q];
-    }
+  if constexpr (CW == 64) {
+    using R = GRow<TC>;
+    using D = GRow<double>;
+    helm_column<TS, TC, M, REFINE, CW>(
+        cp, plane, r0, C.n, R{as_const<TC>(C.fa), r0}, R{as_const<TC>(C.bg), r0},
+        R{as_const<TC>(C.ib), r0}, R{as_const<TC>(C.ra), r0}, R{as_const<TC>(C.rc), r0},
+        D{as_const<double>(C.al), r0}, D{as_const<double>(C.ga), r0}, D{as_const<double>(C.dg), r0},
+        tf, tb, ti, C.P, RD, w, lane, active);
   } else {
-    const cptr<double> mal = as_const<double>(C.al), mga = as_const<double>(C.ga);
-    const cptr<double> mdg = as_const<double>(C.dg);
-    double r[M];
-    TC u[M], dd[M];
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-      r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
-      u[q] = (TC)r[q];
-    }
-    // the first solve also gives the neighbours across the chunk ends
-    helm_solve_regs<TC, M, true>(u, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD, w, lane, active,
-                                 CW, below, above);
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const double al = mal[r0 + q], ga = mga[r0 + q], dg = mdg[r0 + q];
-        const double um = q == 0 ? (double)below : (double)u[q == 0 ? 0 : q - 1];
-        const double up = q == M - 1 ? (double)above : (double)u[q == M - 1 ? q : q + 1];
-        dd[q] = (TC)(r[q] - (dg * (double)u[q] - al * um - ga * up));
+    const int npad = C.P * M;
+    double *D0 = shd + 2 * C.P * CW;  // past the reduced rows
+    double *mal = D0, *mga = D0 + npad, *mdg = D0 + 2 * npad;
+    TC *T0 = reinterpret_cast<TC *>(REFINE ? D0 + 3 * npad : D0);
+    TC *fa = T0, *bg = T0 + npad, *ibv = T0 + 2 * npad, *ra = T0 + 3 * npad, *rc = T0 + 4 * npad;
+    {
+      const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
+      const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
+      for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+        fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
+        if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mdg[r] = C.dg[r]; }
       }
     }
-    helm_solve_regs<TC, M, false>(dd, r0, fa, bg, ibv, ra, rc, tf, tb, ti, C.P, RD + 2 * C.P * CW,
-                                  w, lane, active, CW, below, above);
-    if (active) {
-#pragma unroll
-      for (int q = 0; q < M; ++q)
-        if (r0 + q < n) cp[(size_t)q * plane] = (TS)((double)u[q] + (double)dd[q]);
-    }
+    __syncthreads();
+    using R = LRow<TC>;
+    using D = LRow<double>;
+    helm_column<TS, TC, M, REFINE, CW>(cp, plane, r0, C.n, R{fa, r0}, R{bg, r0}, R{ibv, r0},
+                                       R{ra, r0}, R{rc, r0}, D{mal, r0}, D{mga, r0}, D{mdg, r0},
+                                       tf, tb, ti, C.P, RD, w, lane, active);
   }
 }
 
@@ -1152,8 +1275,14 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
     return hipGetLastError();
   }
   dim3 g((unsigned)maxblk, (unsigned)count), b(CW * maxP);
-  // the reduced rows: one float64 array, or two float32 arrays (refinement)
-  const size_t shm = (size_t)2 * maxP * CW * sizeof(double);
+  // the reduced rows: one float64 array, or two float32 arrays (refinement);
+  // chunks narrower than a wave add the Step 1 tables (see k_helm)
+  size_t shm = (size_t)2 * maxP * CW * sizeof(double);
+  if (CW < 64) {
+    const size_t npad = (size_t)maxP * chunk_rows;
+    shm += npad * (5 * (precision == 0 ? 8 : 4) + (precision == 2 ? 24 : 0));
+  }
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
 #define PF_HELM_CW(M, CWV)                                                                      \
   if (precision == 0)                                                                           \
     hipLaunchKernelGGL((k_helm<double, double, M, CWV, false>), g, b, shm, st, a);              \
