@@ -136,6 +136,20 @@ pf_status poisson_set_workspace(pf_poisson_plan *plan, void *workspace, size_t b
 /* p <- L7^{-1} f. rhs: device (nz,ny,nx) float64, read only. p: device
  * (nz,ny,nx) float64, must not overlap rhs or the workspace. */
 pf_status poisson_solve(pf_poisson_plan *plan, const double *rhs, double *p);
+/* poisson_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the float32 work arrays come from a static device array of the library,
+ * 320 MiB per GPU, held from the library's load until the process ends,
+ * instead of the plan's workspace (which need not be set). The call itself
+ * allocates nothing; its first call on a device looks up that device's
+ * array address once. Every call on one GPU shares the array, so calls that
+ * overlap in time on one GPU (several streams, or several host threads)
+ * race: order them on one stream. Nothing in the array needs to start at
+ * zero. PF_ERR_UNSUPPORTED when the plan needs more than 320 MiB of scratch
+ * (PF_FP32_REFINE: 8 nz (nx ny + 64) bytes, about 41 M points; PF_FP32
+ * half that); a PF_FP64 plan needs none. Other arguments and errors as
+ * poisson_solve. */
+pf_status poisson_solve_noalloc(pf_poisson_plan *plan, const double *rhs, double *p);
 /* A-posteriori status of the solves of a plan (device memory, written by
  * every later poisson_solve, poisson_project and helmholtz3d_solve on the
  * plan's stream; no host readback, so it is graph-capturable). For

@@ -13,4 +13,4 @@ from .solver import (  # noqa: F401
     pcr_prepare, pcr_prepare_rows, pcr_set_stream, pcr_timing, pcr_timing_read, pcr_update_coef, pf_copy_kernel,
     pf_graph_begin, pf_graph_end, poisson_plan, poisson_project, poisson_set_status, poisson_set_stream,
     read_status,
-    poisson_solve, poisson_solve_batched, poisson_timing, poisson_timing_read, run_batched, zop_rows)
+    poisson_solve, poisson_solve_batched, poisson_solve_noalloc, poisson_timing, poisson_timing_read, run_batched, zop_rows)

@@ -22,7 +22,8 @@ PF_STAGE_COUNT = len(STAGES)
 # every symbol include/pf_channel.h declares
 EXPORTS = [
     "pf_last_error", "pf_abi_version", "pf_zop_rows", "pf_grid_faces",
-    "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_project", "poisson_solve_batched",
+    "poisson_plan", "poisson_set_workspace", "poisson_solve", "poisson_solve_noalloc", "poisson_project",
+    "poisson_solve_batched",
     "helmholtz3d_plan", "helmholtz3d_solve", "helmholtz3d_update", "poisson_set_status",
     "poisson_set_stream", "poisson_destroy",
     "pcr_prepare", "pcr_prepare_rows", "pcr_update_coef", "pcr_apply", "pcr_apply_batched", "pcr_set_stream",
@@ -76,6 +77,7 @@ def lib():
             "poisson_plan": (i32, [C.POINTER(vp), C.POINTER(PfGrid), i32, i32, vp, C.POINTER(sz)]),
             "poisson_set_workspace": (i32, [vp, vp, sz]),
             "poisson_solve": (i32, [vp, vp, vp]),
+            "poisson_solve_noalloc": (i32, [vp, vp, vp]),
             "poisson_project": (i32, [vp, vp, vp, vp, vp, vp, C.c_double, C.c_double]),
             "helmholtz3d_plan": (i32, [C.POINTER(vp), C.POINTER(PfGrid), i32, C.c_double, i32, i32, vp,
                                        C.POINTER(sz)]),

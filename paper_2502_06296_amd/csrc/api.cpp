@@ -551,16 +551,19 @@ static pf_status poisson_check_solve(pf_poisson_plan *pl, const double *rhs, dou
 // (rhs unused); for the float32 refinement f is stashed in p, which the
 // residual reads before the last pass overwrites it.
 static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                       const pf::DivArgs *div, bool helm, double oscale);
+                                       const pf::DivArgs *div, bool helm, double oscale, void *ws);
 static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                         const pf::DivArgs *div, bool helm, double oscale);
+                                         const pf::DivArgs *div, bool helm, double oscale, void *ws);
 
 #define STAGE(id, expr)                                      \
   if ((s = run_stage(tm, st, id, [&]() { return (expr); }))) \
     return s;
 
+// ws: the float32 work arrays (the plan's workspace, or the static scratch
+// of poisson_solve_noalloc)
 static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                 const pf::DivArgs *div = nullptr) {
+                                 const pf::DivArgs *div = nullptr, void *ws = nullptr) {
+  if (!ws) ws = pl->ws;
   // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
   // and the chain solves (L - kappa) u' = r, so u = -kappa u'. Value-zero y
   // walls: no singular mode either (nothing projected, no pin)
@@ -570,16 +573,16 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET;
   if (pl->stat) PF_HIP(pf::launch_status_reset(pl->stat, st));
   if (pl->prec != PF_FP32_REFINE) {
-    pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, nozero, oscale);
+    pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, nozero, oscale, ws);
     if (!s && pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, false, st));
     return s;
   }
-  return poisson_enqueue_refined(pl, rhs, p, st, div, nozero, oscale);
+  return poisson_enqueue_refined(pl, rhs, p, st, div, nozero, oscale, ws);
 }
 
 // float64, or float32 without a correction
 static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                       const pf::DivArgs *div, bool helm, double oscale) {
+                                       const pf::DivArgs *div, bool helm, double oscale, void *ws) {
   const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
   const long lines = (long)ny * nz;
   const DevArena &A = pl->ar;
@@ -608,7 +611,7 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
   const int yw = pl->ybc;
-  float *W0 = (float *)pl->ws;
+  float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
@@ -626,7 +629,7 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
 
 // float32 with one float64-residual correction
 static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs, double *p, hipStream_t st,
-                                         const pf::DivArgs *div, bool helm, double oscale) {
+                                         const pf::DivArgs *div, bool helm, double oscale, void *ws) {
   const int nx = pl->nx, ny = pl->ny, nz = pl->nz;
   const long lines = (long)ny * nz;
   const DevArena &A = pl->ar;
@@ -639,7 +642,7 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
   const int yw = pl->ybc;
-  float *W0 = (float *)pl->ws;
+  float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
   // y inverse; the float64 residual of the plane-mean-free problem formed in
@@ -688,6 +691,57 @@ pf_status poisson_solve(pf_poisson_plan *pl, const double *rhs, double *p) {
   if (s) return s;
   if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "a 3-D Helmholtz plan: use helmholtz3d_solve");
   return poisson_enqueue(pl, rhs, p, pl->st);
+}
+
+// ------------------------------------------------- allocation-free solve
+// Device scratch for callers that cannot allocate: one static array per GPU,
+// reached through its device address (hipGetSymbolAddress, taken once per
+// device on the first call there with that device current; the array's name
+// in host code is only a host-side stand-in). It serves as the float32 work
+// arrays of the solve; every call on a device shares it.
+constexpr size_t kNoAllocScratch = size_t(320) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+static pf_status scratch_of_device(void **out) {
+  int dev = 0;
+  PF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(PF_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PF_ERR_DEVICE, "device scratch address: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PF_OK;
+}
+
+pf_status poisson_solve_noalloc(pf_poisson_plan *pl, const double *rhs, double *p) {
+  if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "a 3-D Helmholtz plan: use helmholtz3d_solve");
+  if (!rhs || !p) return fail(PF_ERR_ARG, "rhs and p must be device pointers");
+  const size_t nb = pl->npts() * sizeof(double);
+  if (overlaps(rhs, nb, p, nb)) return fail(PF_ERR_ARG, "p must not overlap rhs");
+  if (((uintptr_t)rhs & 15) || ((uintptr_t)p & 15)) return fail(PF_ERR_ARG, "rhs and p must be 16-byte aligned");
+  if (pl->ws_need > kNoAllocScratch)
+    return fail(PF_ERR_UNSUPPORTED, "the solve needs %zu bytes of scratch; the static scratch holds %zu",
+                pl->ws_need, kNoAllocScratch);
+  void *ws = nullptr;
+  if (pl->ws_need) {
+    pf_status s = scratch_of_device(&ws);
+    if (s) return s;
+    if (overlaps(ws, pl->ws_need, p, nb) || overlaps(ws, pl->ws_need, rhs, nb))
+      return fail(PF_ERR_ARG, "rhs or p overlaps the static scratch");
+  }
+  return poisson_enqueue(pl, rhs, p, pl->st, nullptr, ws);
 }
 
 pf_status helmholtz3d_solve(pf_poisson_plan *pl, const double *r, double *u) {

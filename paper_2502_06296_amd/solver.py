@@ -138,6 +138,16 @@ def poisson_solve(plan, rhs, p):
     return p
 
 
+def poisson_solve_noalloc(plan, rhs, p):
+    """poisson_solve with the library's static device scratch as the work
+    arrays (no allocation; calls on one GPU must not overlap in time)."""
+    import torch
+    _check_field(rhs, plan.shape, torch.float64)
+    _check_field(p, plan.shape, torch.float64)
+    N.check(N.lib().poisson_solve_noalloc(plan.handle, _ptr(rhs), _ptr(p)))
+    return p
+
+
 def poisson_set_status(plan, status, tol=1e-10):
     """Record the a-posteriori status of the plan's solves into `status`, a
     device int64 tensor of 4 elements (None stops recording)."""
