@@ -244,7 +244,7 @@ def roofline(prec, stages, traffic):
 # the oracle's sample of the workload: its z grid on a reduced plane, two
 # samples per worker process
 CPU_PLANE = (512, 256)
-CPU_SAMPLES_PER_WORKER = 2
+CPU_SAMPLES_PER_WORKER = 1
 
 
 def _oracle_sample(args):
@@ -280,7 +280,7 @@ def host_workers():
 
 def cpu_baseline(nz):
     """The float64 oracle (numpy, as written) on a bounded sample of the
-    workload, on the host's cores: two samples per worker process (each the
+    workload, on the host's cores: one sample per worker process (the
     Poisson solve plus the three Helmholtz solves on a 512 x 256 plane with
     the workload's z grid and stretching), all workers at once; the rate is
     the sampled points over the span from the first solve's start to the

@@ -43,6 +43,13 @@ __device__ __forceinline__ double rcp64(double b) {
   e = __builtin_fma(-b, r, 1.0);
   return __builtin_fma(r, e, r);
 }
+// A compiler memory fence every fourth row of an unrolled sweep: the
+// compiler would otherwise issue every table and field read of the sweep up
+// front and run out of registers. It emits no instruction.
+__device__ __forceinline__ void sched_fence(int q) {
+  if ((q & 3) == 3) asm volatile("" ::: "memory");
+}
+
 template <bool FAST>
 __device__ __forceinline__ double qdiv(double a, double b) {
   if constexpr (FAST) return a * rcp64(b);
@@ -378,8 +385,8 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
 //   SA = fa, SG = t ug', SE = fe + t ue', SD = D + t U', t = gamma / C',
 // with (fa, fe, D) from the downward sweep and (ug', ue', U', C') the next
 // chunk's reduced first row.
-template <typename TS, int M, int TP, int NR, int WAVES>
-__global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
+template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512>
+__global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
                                                       const double *sy, size_t sp) {
@@ -429,6 +436,9 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
     const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
 
     double d0[M], d1[M], ib_[M];
+    // the 1024-thread shapes have half the registers: compiler fences keep
+    // their unrolled sweeps from issuing every read up front
+    constexpr bool kFence = MAXT > 512;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       V v = V{};
@@ -449,6 +459,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
         u0 = d0[q] + t * u0;
         u1 = d1[q] + t * u1;
         cb = al(q) + ug + ue;
+        if constexpr (kFence) sched_fence(q);
       }
       X1[me] = mkc<double>(ug, ue);
       X2[me] = mkc<double>(u0, u1);
@@ -464,6 +475,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
       d0[q] = d0[q] + t * d0[q - 1];
       d1[q] = d1[q] + t * d1[q - 1];
       if (q < M - 1) ib_[q] = rcpn<NR>(fa + ga(q) + fe);
+      if constexpr (kFence) sched_fence(q);
     }
     __syncthreads();
     double A, G, E, S0, S1;
@@ -503,6 +515,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
       if (q >= 1) a = al(q) * ib_[q - 1] * a;
       d0[q] = (d0[q] + a * xl.x) * ib_[q];
       d1[q] = (d1[q] + a * xl.y) * ib_[q];
+      if constexpr (kFence) sched_fence(q);
     }
     d0[M - 1] = S0;
     d1[M - 1] = S1;
@@ -511,6 +524,7 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve3(TS *data, int nx, int ny
       const double c = ga(q) * ib_[q];
       d0[q] = d0[q] + c * d0[q + 1];
       d1[q] = d1[q] + c * d1[q + 1];
+      if constexpr (kFence) sched_fence(q);
     }
     if (st0 || st1) {
 #pragma unroll
@@ -542,6 +556,7 @@ struct ZVariant {
   int nr;
   bool skew = true;  // paired: gaps between reduced row pairs in LDS
   bool sep = false;  // paired: separator form, P reduced rows
+  int maxt = 512;    // threads per workgroup at most
 };
 static const ZVariant kZVariants[] = {
     {16, 16, 0, false, false, 2}, {16, 16, 4, true, false, 2}, {16, 16, 0, true, false, 2},
@@ -557,6 +572,9 @@ static const ZVariant kZVariants[] = {
     // wide separator shapes for short columns (few chunks per column)
     {8, 64, 4, true, true, 1, false, true},  {8, 128, 4, true, true, 1, false, true},
     {16, 64, 1, true, true, 1, false, true}, {16, 128, 1, true, true, 1, false, true},
+    // separator form in 1024-thread workgroups: wider rows for the long
+    // columns (8 rows per thread; 16 spilled)
+    {8, 32, 1, true, true, 1, false, true, 1024}, {8, 16, 1, true, true, 1, false, true, 1024},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
@@ -577,8 +595,8 @@ bool zsolve_variant_fits(int v, int nx, int nz) {
   const ZVariant &z = kZVariants[v];
   const int P = (nz + z.M - 1) / z.M;
   const int threads = z.paired ? P * z.TI / 2 : P * z.TI;
-  return threads <= 512 && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16 &&
-         zsolve_lds(z, P) <= 65536;
+  return threads <= z.maxt && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16 &&
+         zsolve_lds(z, P) <= (z.maxt > 512 ? 160 * 1024 : 65536);
 }
 
 int zsolve_default_variant(int nx, int nz, bool fp64) {
@@ -660,6 +678,14 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
     PF_ZS(24, 8, 128, 4)
     PF_ZS(25, 16, 64, 1)
     PF_ZS(26, 16, 128, 1)
+#define PF_ZW(ID, M_, TI_)                                                                       \
+  case ID:                                                                                       \
+    hipLaunchKernelGGL((k_zsolve3<TS, M_, TI_ / 2, 1, 1, 1024>), g, b, shm, st, data, nx, ny, nz, \
+                       P, zal, zga, zex, sx, sy, sp);                                            \
+    break;
+    PF_ZW(27, 8, 32)
+    PF_ZW(28, 8, 16)
+#undef PF_ZW
 #undef PF_ZS
 #undef PF_ZP
     default:
@@ -800,13 +826,6 @@ __device__ __forceinline__ cptr<T> as_const(const void *p) {
 // (LRow): per-lane vector loads of the tables in global memory spilled the
 // 32-row shapes, and wave-uniform loads of every chunk of the wave with a
 // per-lane select ran out of scalar registers.
-// A compiler memory fence every fourth row of an unrolled sweep: the
-// compiler would otherwise issue every table and field read of the sweep up
-// front and run out of registers. It emits no instruction.
-__device__ __forceinline__ void sched_fence(int q) {
-  if ((q & 3) == 3) asm volatile("" ::: "memory");
-}
-
 template <typename T>
 struct GRow {
   cptr<T> t;
