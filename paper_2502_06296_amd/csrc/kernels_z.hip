@@ -946,11 +946,18 @@ __device__ __forceinline__ TS *fresh(TS *p) {
   return reinterpret_cast<TS *>(a);
 }
 
+// Rows of the float64 right-hand side that the refinement of a 32-row chunk
+// narrower than a wave parks in LDS (the rest stay in registers): all 32 in
+// registers spill, and reading them again from global memory doubled the
+// HBM reads (the caches did not keep them).
+template <int M, int CW>
+constexpr int helm_parked_rows() { return CW < 64 && M > 16 ? 12 : 0; }
+
 template <typename TS, typename TC, int M, bool REFINE, int CW, typename RW, typename DW>
 __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n, RW fa, RW bg,
                                             RW ibv, RW ra, RW rc, DW mal, DW mga, DW mdg,
                                             cptr<TC> tf, cptr<TC> tb, cptr<TC> ti, int P, TC *RD,
-                                            int w, int lane, bool active) {
+                                            int w, int lane, bool active, double *park) {
   TC below, above;
   if constexpr (!REFINE) {
     TC d[M];
@@ -970,45 +977,33 @@ __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n,
       }
     }
   } else {
-    // Narrow chunks (CW < 64) put two or four chunks in a wave and need the
-    // registers for the two float32 solves: the float64 right-hand side is
-    // read again for the residual instead of being held (the field is only
-    // written at the end, and the second read is served by the caches)
-    constexpr bool kHold = CW == 64;
-    double r[M];
+    // The float64 right-hand side is held for the residual: in registers,
+    // except KL rows parked in LDS (one slot per thread and row) when the
+    // chunk is 32 rows and narrower than a wave
+    constexpr int KL = helm_parked_rows<M, CW>();
+    double r[M - KL];
     TC u[M], dd[M];
-    // every read of the column is issued before the first is used
+    const int tid = threadIdx.x, nt = blockDim.x;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
-      if constexpr (!kHold) sched_fence(q);
+      const double v = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
+      if (q < KL) park[q * nt + tid] = v;
+      else r[q < KL ? 0 : q - KL] = v;
+      u[q] = (TC)v;
+      if constexpr (KL > 0) sched_fence(q);
     }
-#pragma unroll
-    for (int q = 0; q < M; ++q) u[q] = (TC)r[q];
     // the first solve also gives the neighbours across the chunk ends
     helm_solve_regs<TC, M, true>(u, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD, w, lane, active, CW,
                                  below, above);
-    if constexpr (!kHold) cp = fresh(cp);
-    // the residual, in two halves of the chunk when the right-hand side is
-    // read again: all reads of a half are issued before the first is used
-    constexpr int kHalf = kHold ? M : M / 2;
+    if (active) {
 #pragma unroll
-    for (int h = 0; h < M; h += kHalf) {
-      if constexpr (!kHold) {
-#pragma unroll
-        for (int q = h; q < h + kHalf; ++q) {
-          r[q] = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
-          sched_fence(q);
-        }
-      }
-      if (!active) continue;
-#pragma unroll
-      for (int q = h; q < h + kHalf; ++q) {
+      for (int q = 0; q < M; ++q) {
         const double al = mal[q], ga = mga[q], dg = mdg[q];
         const double um = q == 0 ? (double)below : (double)u[q == 0 ? 0 : q - 1];
         const double up = q == M - 1 ? (double)above : (double)u[q == M - 1 ? q : q + 1];
-        dd[q] = (TC)(r[q] - (dg * (double)u[q] - al * um - ga * up));
-        if constexpr (!kHold) {
+        const double rq = q < KL ? park[q * nt + tid] : r[q < KL ? 0 : q - KL];
+        dd[q] = (TC)(rq - (dg * (double)u[q] - al * um - ga * up));
+        if constexpr (KL > 0) {
           // row by row: left to itself the compiler reads every table row
           // of the loop first and spills them
           asm volatile("" : "+v"(dd[q]));
@@ -1018,12 +1013,12 @@ __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n,
     }
     helm_solve_regs<TC, M, false>(dd, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD + 2 * P * CW, w, lane,
                                   active, CW, below, above);
-    if constexpr (!kHold) cp = fresh(cp);
+    if constexpr (CW < 64) cp = fresh(cp);
     if (active) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         if (r0 + q < n) cp[(size_t)q * plane] = (TS)((double)u[q] + (double)dd[q]);
-        if constexpr (!kHold) sched_fence(q);
+        if constexpr (CW < 64) sched_fence(q);
       }
     }
   }
@@ -1062,13 +1057,15 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
         cp, plane, r0, C.n, R{as_const<TC>(C.fa), r0}, R{as_const<TC>(C.bg), r0},
         R{as_const<TC>(C.ib), r0}, R{as_const<TC>(C.ra), r0}, R{as_const<TC>(C.rc), r0},
         D{as_const<double>(C.al), r0}, D{as_const<double>(C.ga), r0}, D{as_const<double>(C.dg), r0},
-        tf, tb, ti, C.P, RD, w, lane, active);
+        tf, tb, ti, C.P, RD, w, lane, active, nullptr);
   } else {
     const int npad = C.P * M;
     double *D0 = shd + 2 * C.P * CW;  // past the reduced rows
     double *mal = D0, *mga = D0 + npad, *mdg = D0 + 2 * npad;
     TC *T0 = reinterpret_cast<TC *>(REFINE ? D0 + 3 * npad : D0);
     TC *fa = T0, *bg = T0 + npad, *ibv = T0 + 2 * npad, *ra = T0 + 3 * npad, *rc = T0 + 4 * npad;
+    // the refinement's parked right-hand side rows, 8-byte aligned
+    double *park = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(rc + npad) + 7) & ~uintptr_t(7));
     {
       const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
       const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
@@ -1082,7 +1079,7 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
     using D = LRow<double>;
     helm_column<TS, TC, M, REFINE, CW>(cp, plane, r0, C.n, R{fa, r0}, R{bg, r0}, R{ibv, r0},
                                        R{ra, r0}, R{rc, r0}, D{mal, r0}, D{mga, r0}, D{mdg, r0},
-                                       tf, tb, ti, C.P, RD, w, lane, active);
+                                       tf, tb, ti, C.P, RD, w, lane, active, park);
   }
 }
 
@@ -1300,6 +1297,7 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
   if (CW < 64) {
     const size_t npad = (size_t)maxP * chunk_rows;
     shm += npad * (5 * (precision == 0 ? 8 : 4) + (precision == 2 ? 24 : 0));
+    if (precision == 2 && chunk_rows > 16) shm = ((shm + 7) & ~size_t(7)) + (size_t)12 * CW * maxP * 8;
   }
   if (shm > 160 * 1024) return hipErrorInvalidValue;
 #define PF_HELM_CW(M, CWV)                                                                      \
