@@ -832,6 +832,24 @@ struct GRow {
   int r0;
   __device__ __forceinline__ T operator[](int q) const { return t[r0 + q]; }
 };
+// The rows of a global table for the CPW chunks that share a wave: one
+// wave-uniform scalar load per chunk and a per-lane select (the sweeps that
+// use it are fenced, so the scalar loads are not all issued at once).
+template <typename T, int CPW>
+struct SRow {
+  cptr<T> t;
+  int base[CPW];  // first row of each chunk of the wave (uniform)
+  int slot;       // the lane's chunk within the wave
+  __device__ __forceinline__ T operator[](int q) const {
+    T v = t[base[0] + q];
+#pragma unroll
+    for (int k = 1; k < CPW; ++k) {
+      const T o = t[base[k] + q];
+      v = slot == k ? o : v;
+    }
+    return v;
+  }
+};
 template <typename T>
 struct LRow {
   const T *t;
@@ -949,15 +967,17 @@ __device__ __forceinline__ TS *fresh(TS *p) {
 // Rows of the float64 right-hand side that the refinement of a 32-row chunk
 // narrower than a wave parks in LDS (the rest stay in registers): all 32 in
 // registers spill, and reading them again from global memory doubled the
-// HBM reads (the caches did not keep them).
+// HBM reads (the caches did not keep them). To make room, such a launch
+// keeps one reduced-row array for both solves and reads the float64
+// M-matrix rows from global memory.
 template <int M, int CW>
-constexpr int helm_parked_rows() { return CW < 64 && M > 16 ? 12 : 0; }
+constexpr int helm_parked_rows() { return CW < 64 && M > 16 ? 16 : 0; }
 
 template <typename TS, typename TC, int M, bool REFINE, int CW, typename RW, typename DW>
 __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n, RW fa, RW bg,
                                             RW ibv, RW ra, RW rc, DW mal, DW mga, DW mdg,
                                             cptr<TC> tf, cptr<TC> tb, cptr<TC> ti, int P, TC *RD,
-                                            int w, int lane, bool active, double *park) {
+                                            int w, int lane, bool active, double *park, TC *RD2) {
   TC below, above;
   if constexpr (!REFINE) {
     TC d[M];
@@ -984,14 +1004,23 @@ __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n,
     double r[M - KL];
     TC u[M], dd[M];
     const int tid = threadIdx.x, nt = blockDim.x;
+    // every read of the column in flight before the first is used; then the
+    // parked rows go to LDS
+    double t[KL > 0 ? KL : 1];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       const double v = (active && r0 + q < n) ? (double)cp[(size_t)q * plane] : 0.0;
-      if (q < KL) park[q * nt + tid] = v;
+      if (q < KL) t[q < KL ? q : 0] = v;
       else r[q < KL ? 0 : q - KL] = v;
-      u[q] = (TC)v;
-      if constexpr (KL > 0) sched_fence(q);
     }
+#pragma unroll
+    for (int q = 0; q < KL; ++q) {
+      park[q * nt + tid] = t[q];
+      u[q] = (TC)t[q];
+    }
+#pragma unroll
+    for (int q = KL; q < M; ++q) u[q] = (TC)r[q - KL];
+    if constexpr (KL > 0) cp = fresh(cp);
     // the first solve also gives the neighbours across the chunk ends
     helm_solve_regs<TC, M, true>(u, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD, w, lane, active, CW,
                                  below, above);
@@ -1011,7 +1040,8 @@ __device__ __forceinline__ void helm_column(TS *cp, size_t plane, int r0, int n,
         }
       }
     }
-    helm_solve_regs<TC, M, false>(dd, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD + 2 * P * CW, w, lane,
+    if (RD2 == RD) __syncthreads();  // every wave is done reading the first solve's rows
+    helm_solve_regs<TC, M, false>(dd, fa, bg, ibv, ra, rc, tf, tb, ti, P, RD2, w, lane,
                                   active, CW, below, above);
     if constexpr (CW < 64) cp = fresh(cp);
     if (active) {
@@ -1044,8 +1074,13 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
   const int w = CW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / 64) : threadIdx.x / CW;
   const int lane = threadIdx.x % CW;
   const bool active = w < C.P;
-  const int ib = blockIdx.x % nib;
-  const int j = blockIdx.x / nib;
+  // narrow chunks (the long columns): every XCD walks a contiguous range of
+  // column blocks (2048x1024x1024, three components: float64 27.4 -> 24.1 ms,
+  // FP32+refine 34.9 -> 31.2 ms; the 64-column shapes lost up to 8 %). Only
+  // when the launch has no spare blocks beyond this job's count.
+  const unsigned bk = CW < 64 && gridDim.x == nblk ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int ib = bk % nib;
+  const int j = bk / nib;
   const int r0 = active ? w * M : 0;
   const size_t plane = (size_t)J.nx * J.ny;
   TS *cp = reinterpret_cast<TS *>(J.field) + (size_t)j * J.nx + ib * CW + lane + (size_t)r0 * plane;
@@ -1057,29 +1092,62 @@ __global__ __launch_bounds__(1024) void k_helm(HelmArgs args) {
         cp, plane, r0, C.n, R{as_const<TC>(C.fa), r0}, R{as_const<TC>(C.bg), r0},
         R{as_const<TC>(C.ib), r0}, R{as_const<TC>(C.ra), r0}, R{as_const<TC>(C.rc), r0},
         D{as_const<double>(C.al), r0}, D{as_const<double>(C.ga), r0}, D{as_const<double>(C.dg), r0},
-        tf, tb, ti, C.P, RD, w, lane, active, nullptr);
+        tf, tb, ti, C.P, RD, w, lane, active, nullptr, RD + 2 * C.P * CW);
   } else {
     const int npad = C.P * M;
-    double *D0 = shd + 2 * C.P * CW;  // past the reduced rows
-    double *mal = D0, *mga = D0 + npad, *mdg = D0 + 2 * npad;
-    TC *T0 = reinterpret_cast<TC *>(REFINE ? D0 + 3 * npad : D0);
-    TC *fa = T0, *bg = T0 + npad, *ibv = T0 + 2 * npad, *ra = T0 + 3 * npad, *rc = T0 + 4 * npad;
-    // the refinement's parked right-hand side rows, 8-byte aligned
-    double *park = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(rc + npad) + 7) & ~uintptr_t(7));
-    {
-      const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
-      const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
-      for (int r = threadIdx.x; r < npad; r += blockDim.x) {
-        fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
-        if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mdg[r] = C.dg[r]; }
+    constexpr bool kPark = REFINE && helm_parked_rows<M, CW>() > 0;
+    if constexpr (kPark) {
+      // one reduced-row array, then the five Step 1 tables, then the parked
+      // rows of the right-hand side
+      TC *T0 = RD + 2 * C.P * CW;
+      TC *fa = T0, *bg = T0 + npad, *ibv = T0 + 2 * npad, *ra = T0 + 3 * npad, *rc = T0 + 4 * npad;
+      // 8-byte aligned: 2 P CW and 5 P M float32 values are even counts;
+      // plain pointer arithmetic from the LDS array keeps the stores in LDS
+      // address space (through an integer the compiler lost it and used
+      // flat stores with 64-bit addresses)
+      double *park = reinterpret_cast<double *>(rc + npad);
+      {
+        const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
+        const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
+        for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+          fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
+        }
       }
+      __syncthreads();
+      using R = LRow<TC>;
+      constexpr int CPW = 64 / CW;
+      using D = SRow<double, CPW>;
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+      D dal{as_const<double>(C.al), {}, (int)(threadIdx.x % 64) / CW};
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) dal.base[k] = (wave * CPW + k < C.P ? wave * CPW + k : 0) * M;
+      D dga = dal, ddg = dal;
+      dga.t = as_const<double>(C.ga);
+      ddg.t = as_const<double>(C.dg);
+      helm_column<TS, TC, M, REFINE, CW>(cp, plane, r0, C.n, R{fa, r0}, R{bg, r0}, R{ibv, r0},
+                                         R{ra, r0}, R{rc, r0}, dal, dga, ddg, tf, tb, ti, C.P, RD, w,
+                                         lane, active, park, RD);
+    } else {
+      double *D0 = shd + 2 * C.P * CW;  // past the reduced rows
+      double *mal = D0, *mga = D0 + npad, *mdg = D0 + 2 * npad;
+      TC *T0 = reinterpret_cast<TC *>(REFINE ? D0 + 3 * npad : D0);
+      TC *fa = T0, *bg = T0 + npad, *ibv = T0 + 2 * npad, *ra = T0 + 3 * npad, *rc = T0 + 4 * npad;
+      {
+        const TC *sfa = (const TC *)C.fa, *sbg = (const TC *)C.bg, *sib = (const TC *)C.ib;
+        const TC *sra = (const TC *)C.ra, *src = (const TC *)C.rc;
+        for (int r = threadIdx.x; r < npad; r += blockDim.x) {
+          fa[r] = sfa[r]; bg[r] = sbg[r]; ibv[r] = sib[r]; ra[r] = sra[r]; rc[r] = src[r];
+          if (REFINE) { mal[r] = C.al[r]; mga[r] = C.ga[r]; mdg[r] = C.dg[r]; }
+        }
+      }
+      __syncthreads();
+      using R = LRow<TC>;
+      using D = LRow<double>;
+      helm_column<TS, TC, M, REFINE, CW>(cp, plane, r0, C.n, R{fa, r0}, R{bg, r0}, R{ibv, r0},
+                                         R{ra, r0}, R{rc, r0}, D{mal, r0}, D{mga, r0}, D{mdg, r0},
+                                         tf, tb, ti, C.P, RD, w, lane, active, nullptr,
+                                         RD + 2 * C.P * CW);
     }
-    __syncthreads();
-    using R = LRow<TC>;
-    using D = LRow<double>;
-    helm_column<TS, TC, M, REFINE, CW>(cp, plane, r0, C.n, R{fa, r0}, R{bg, r0}, R{ibv, r0},
-                                       R{ra, r0}, R{rc, r0}, D{mal, r0}, D{mga, r0}, D{mdg, r0},
-                                       tf, tb, ti, C.P, RD, w, lane, active, park);
   }
 }
 
@@ -1296,8 +1364,13 @@ hipError_t launch_helm(int precision, int chunk_rows, int cw, bool staged, int c
   size_t shm = (size_t)2 * maxP * CW * sizeof(double);
   if (CW < 64) {
     const size_t npad = (size_t)maxP * chunk_rows;
-    shm += npad * (5 * (precision == 0 ? 8 : 4) + (precision == 2 ? 24 : 0));
-    if (precision == 2 && chunk_rows > 16) shm = ((shm + 7) & ~size_t(7)) + (size_t)12 * CW * maxP * 8;
+    if (precision == 2 && chunk_rows > 16) {
+      // one float32 reduced-row array, the five float32 tables, 16 parked rows
+      shm = (size_t)2 * maxP * CW * 4 + npad * 5 * 4;
+      shm = ((shm + 7) & ~size_t(7)) + (size_t)16 * CW * maxP * 8;
+    } else {
+      shm += npad * (5 * (precision == 0 ? 8 : 4) + (precision == 2 ? 24 : 0));
+    }
   }
   if (shm > 160 * 1024) return hipErrorInvalidValue;
 #define PF_HELM_CW(M, CWV)                                                                      \
