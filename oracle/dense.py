@@ -80,24 +80,31 @@ def wall_d2(n, h, value_zero=False):
     return M / (h * h)
 
 
-def l7_dense(nx, ny, zf, lx, ly, ybc=0):
-    """Dense 7-point operator for C-order (nz, ny, nx) flattening (ybc = 1:
-    zero-gradient walls at both y ends)."""
+def _d2(n, length, bc):
+    """Second difference of one wall-parallel direction: periodic (bc 0),
+    between zero-gradient (1) or value-zero (2) walls."""
+    return wall_d2(n, length / n, bc == 2) if bc in (1, 2) else periodic_d2(n, length / n)
+
+
+def l7_dense(nx, ny, zf, lx, ly, ybc=0, xbc=0):
+    """Dense 7-point operator for C-order (nz, ny, nx) flattening; ybc and
+    xbc: periodic (0), zero-gradient walls (1) or value-zero walls (2) at
+    both ends of y and of x."""
     nz = len(zf) - 1
     Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
-    Dx = periodic_d2(nx, lx / nx)
-    Dy = wall_d2(ny, ly / ny, ybc == 2) if ybc in (1, 2) else periodic_d2(ny, ly / ny)
+    Dx = _d2(nx, lx, xbc)
+    Dy = _d2(ny, ly, ybc)
     Dz = lz_dense(zf, NEUMANN)
     return (np.kron(Iz, np.kron(Iy, Dx)) + np.kron(Iz, np.kron(Dy, Ix))
             + np.kron(Dz, np.kron(Iy, Ix)))
 
 
-def poisson_dense(f, zf, lx, ly, ybc=0):
+def poisson_dense(f, zf, lx, ly, ybc=0, xbc=0):
     """Least-squares solution of L7 p = f with the row sum_ijk dzf[k] p = 0
     appended (the solution of the projected problem when f is compatible)."""
     nz, ny, nx = f.shape
-    L = l7_dense(nx, ny, zf, lx, ly, ybc)
-    if ybc == 2:                     # value-zero y walls: nonsingular
+    L = l7_dense(nx, ny, zf, lx, ly, ybc, xbc)
+    if ybc == 2 or xbc == 2:         # value-zero walls: nonsingular
         return np.linalg.solve(L, f.reshape(-1)).reshape(f.shape)
     w = np.repeat(np.diff(np.asarray(zf, float)), nx * ny)
     # project f onto the range of L (orthogonal to the weights' null vector)
@@ -116,17 +123,17 @@ def helmholtz_dense(r, zf, s, bc):
     return np.linalg.solve(M, r.reshape(shp[0], -1)).reshape(shp)
 
 
-def helmholtz3d_dense(r, zf, s, bc, lx, ly, ybc=0):
+def helmholtz3d_dense(r, zf, s, bc, lx, ly, ybc=0, xbc=0):
     """Dense solve of (I - s L) u = r, L the 3-D operator of the staggered
-    grid: periodic second differences in x, in y periodic (ybc 0) or between
+    grid: second differences in x and y, each periodic (0) or between
     zero-gradient (1) or value-zero (2) walls, plus L_z of family bc (C-order
     (n, ny, nx) flattening, n = nz or nz - 1)."""
     n, ny, nx = r.shape
     Ix, Iy = np.eye(nx), np.eye(ny)
     Dz = lz_dense(zf, bc)
     Iz = np.eye(Dz.shape[0])
-    Dy = wall_d2(ny, ly / ny, ybc == 2) if ybc in (1, 2) else periodic_d2(ny, ly / ny)
-    L = (np.kron(Iz, np.kron(Iy, periodic_d2(nx, lx / nx))) + np.kron(Iz, np.kron(Dy, Ix))
+    Dy = _d2(ny, ly, ybc)
+    L = (np.kron(Iz, np.kron(Iy, _d2(nx, lx, xbc))) + np.kron(Iz, np.kron(Dy, Ix))
          + np.kron(Dz, np.kron(Iy, Ix)))
     M = np.eye(L.shape[0]) - s * L
     return np.linalg.solve(M, r.reshape(-1)).reshape(r.shape)

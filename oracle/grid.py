@@ -25,6 +25,10 @@ Y_PERIODIC = 0         # y periodic (the channel)
 Y_WALLS = 1            # zero-gradient (Neumann) walls at both y ends, cell centres
 Y_DIRICHLET = 2        # value-zero (Dirichlet) walls at both y ends, cell centres
 
+X_PERIODIC = 0         # x periodic (the channel)
+X_WALLS = 1            # zero-gradient walls at both x ends, cell centres
+X_DIRICHLET = 2        # value-zero walls at both x ends, cell centres
+
 
 def z_metrics(zf, dtype=np.float64):
     """Centres zc, cell widths dzf (nz), centre distances dzc (nz-1)."""

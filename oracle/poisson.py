@@ -50,62 +50,74 @@ def zero_mode_solve(fhat00, zf):
     return m - np.dot(dzf, m) / dzf.sum()
 
 
-def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC):
+def _y_transform(ybc):
+    """(forward, inverse, wavenumbers) of the y direction for ybc."""
+    if ybc == grid.Y_WALLS:
+        return transforms.dct2, transforms.idct2, grid.wall_wavenumbers
+    if ybc == grid.Y_DIRICHLET:
+        return transforms.dst2, transforms.idst2, grid.dirichlet_wall_wavenumbers
+    return transforms.rfft_packed, transforms.irfft_packed, grid.modified_wavenumbers
+
+
+def _x_transform(xbc):
+    """(forward, inverse, wavenumbers) of the x direction for xbc: the same
+    three members of the Fourier-based transforms as along y."""
+    return _y_transform({grid.X_WALLS: grid.Y_WALLS, grid.X_DIRICHLET: grid.Y_DIRICHLET}.get(
+        xbc, grid.Y_PERIODIC))
+
+
+def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     """p with L7 p = f (projected), zero dzf-weighted mean. f is (nz, ny, nx),
     float64 or longdouble; the result has f's dtype. ybc = grid.Y_WALLS puts
     zero-gradient walls at both y ends (cell-centred unknowns): the y
     transform is then the cosine transform and its wavenumbers those of the
     mirrored second difference (Sec. 2.2.1). ybc = grid.Y_DIRICHLET puts walls
-    where the value vanishes: the sine transform; L7 is then nonsingular, so f
-    is not projected and p carries no pin."""
+    where the value vanishes: the sine transform. xbc does the same for the x
+    ends (grid.X_WALLS, grid.X_DIRICHLET). With value-zero walls in x or y, L7
+    is nonsingular, so f is not projected and p carries no pin."""
     dt = f.dtype.type
     nz, ny, nx = f.shape
-    if ybc == grid.Y_DIRICHLET:
-        Fx = transforms.rfft_packed(f, axis=2)
-        F = transforms.dst2(Fx, axis=1)
-        sy = grid.dirichlet_wall_wavenumbers(ny, ly, dt)
-        sx = grid.modified_wavenumbers(nx, lx, dt)
-        alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
-        eps3 = eps[:, None, None] + (sy[:, None] + sx[None, :])[None, :, :]
-        P = tridiag.thomas_gth(alpha[:, None, None], gamma[:, None, None], eps3, -F)
-        return transforms.irfft_packed(transforms.idst2(P, axis=1), axis=2)
-    f = project_rhs(f, zf)
-    Fx = transforms.rfft_packed(f, axis=2)
-    if ybc == grid.Y_WALLS:
-        F = transforms.dct2(Fx, axis=1)
-        sy = grid.wall_wavenumbers(ny, ly, dt)
-    else:
-        F = transforms.rfft_packed(Fx, axis=1)
-        sy = grid.modified_wavenumbers(ny, ly, dt)
-    sx = grid.modified_wavenumbers(nx, lx, dt)
+    singular = ybc != grid.Y_DIRICHLET and xbc != grid.X_DIRICHLET
+    if singular:
+        f = project_rhs(f, zf)
+    xf, xi, xw = _x_transform(xbc)
+    yf, yi, yw = _y_transform(ybc)
+    F = yf(xf(f, axis=2), axis=1)
+    sx = xw(nx, lx, dt)
+    sy = yw(ny, ly, dt)
     alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
     shift = sy[:, None] + sx[None, :]                  # (ny, nx) >= 0
-    shift[0, 0] = 1                                    # placeholder, redone below
+    if singular:
+        shift[0, 0] = 1                                # placeholder, redone below
     eps3 = eps[:, None, None] + shift[None, :, :]
     # -(L_z - shift) phi = -fhat in sign-normalised rows
     P = tridiag.thomas_gth(alpha[:, None, None], gamma[:, None, None], eps3, -F)
-    P[:, 0, 0] = zero_mode_solve(F[:, 0, 0].copy(), zf)
-    Py = transforms.idct2(P, axis=1) if ybc == grid.Y_WALLS else transforms.irfft_packed(P, axis=1)
-    return transforms.irfft_packed(Py, axis=2)
+    if singular:
+        P[:, 0, 0] = zero_mode_solve(F[:, 0, 0].copy(), zf)
+    return xi(yi(P, axis=1), axis=2)
 
 
-def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC):
-    """L7 p in the arithmetic of p's dtype (periodic x; periodic y or, with
-    ybc = grid.Y_WALLS, zero-gradient y walls, whose ghost values mirror the
-    end rows; Neumann z)."""
+def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
+    """L7 p in the arithmetic of p's dtype (x and y each periodic or between
+    walls, whose ghost values mirror (zero gradient) or negate (value zero)
+    the end values; Neumann z)."""
     dt = p.dtype.type
     nz, ny, nx = p.shape
     dx, dy = dt(lx) / nx, dt(ly) / ny
-    out = (np.roll(p, -1, 2) - 2 * p + np.roll(p, 1, 2)) / (dx * dx)
-    if ybc in (grid.Y_WALLS, grid.Y_DIRICHLET):
-        # ghost rows beyond the walls: the end rows mirrored (zero gradient)
-        # or negated (value zero on the wall)
-        sg = -1 if ybc == grid.Y_DIRICHLET else 1
-        pm = np.concatenate([sg * p[:, :1], p[:, :-1]], axis=1)     # p[j-1]
-        pp = np.concatenate([p[:, 1:], sg * p[:, -1:]], axis=1)     # p[j+1]
-        out += (pp - 2 * p + pm) / (dy * dy)
-    else:
-        out += (np.roll(p, -1, 1) - 2 * p + np.roll(p, 1, 1)) / (dy * dy)
+
+    def d2(a, axis, bc, walls, value_zero, h):
+        if bc in walls:
+            sg = -1 if bc == value_zero else 1
+            first = np.take(a, [0], axis=axis)
+            last = np.take(a, [a.shape[axis] - 1], axis=axis)
+            am = np.concatenate([sg * first, np.take(a, range(a.shape[axis] - 1), axis=axis)], axis=axis)
+            ap = np.concatenate([np.take(a, range(1, a.shape[axis]), axis=axis), sg * last], axis=axis)
+        else:
+            am, ap = np.roll(a, 1, axis), np.roll(a, -1, axis)
+        return (ap - 2 * a + am) / (h * h)
+
+    out = d2(p, 2, xbc, (grid.X_WALLS, grid.X_DIRICHLET), grid.X_DIRICHLET, dx)
+    out += d2(p, 1, ybc, (grid.Y_WALLS, grid.Y_DIRICHLET), grid.Y_DIRICHLET, dy)
     alpha, gamma, eps = grid.zop(zf, grid.NEUMANN, dt)
     lz = -(alpha + gamma + eps)[:, None, None] * p
     lz[1:] += alpha[1:, None, None] * p[:-1]
@@ -113,10 +125,11 @@ def apply_L7(p, zf, lx, ly, ybc=grid.Y_PERIODIC):
     return out + lz
 
 
-def residual7(p, f, zf, lx, ly, ybc=grid.Y_PERIODIC):
+def residual7(p, f, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     """f - L7 p (f projected first where L7 is singular)."""
-    fp = f if ybc == grid.Y_DIRICHLET else project_rhs(f, zf)
-    return fp - apply_L7(p, zf, lx, ly, ybc)
+    singular = ybc != grid.Y_DIRICHLET and xbc != grid.X_DIRICHLET
+    fp = project_rhs(f, zf) if singular else f
+    return fp - apply_L7(p, zf, lx, ly, ybc, xbc)
 
 
 def solve_helmholtz(r, zf, s, bc):
@@ -129,35 +142,27 @@ def solve_helmholtz(r, zf, s, bc):
     return tridiag.thomas_gth((s * alpha)[shp], (s * gamma)[shp], (1 + s * eps)[shp], r)
 
 
-def _y_transform(ybc):
-    """(forward, inverse, wavenumbers) of the y direction for ybc."""
-    if ybc == grid.Y_WALLS:
-        return transforms.dct2, transforms.idct2, grid.wall_wavenumbers
-    if ybc == grid.Y_DIRICHLET:
-        return transforms.dst2, transforms.idst2, grid.dirichlet_wall_wavenumbers
-    return transforms.rfft_packed, transforms.irfft_packed, grid.modified_wavenumbers
-
-
-def solve_helmholtz3d(r, zf, s, bc, lx, ly, ybc=grid.Y_PERIODIC):
-    """u with (I - s L) u = r, L the 3-D second-order operator: periodic in x,
-    periodic in y or with y walls (ybc, as for the Poisson solve: a field
-    at cell-centre y positions), L_z of family bc in z (eq. proj2_ustar, the
-    fully implicit diffusion of a Runge-Kutta substep with s = gamma_k nu dt /
-    2). Same route as the Poisson solve: transforms in x and y, then per slot
-    pair the z rows (s alpha, s gamma, 1 + s excess + s (sigma_x + sigma_y)),
-    all non-negative, so there is no singular column."""
+def solve_helmholtz3d(r, zf, s, bc, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
+    """u with (I - s L) u = r, L the 3-D second-order operator: x and y each
+    periodic or with walls (xbc, ybc as for the Poisson solve: a field at
+    cell-centre x and y positions), L_z of family bc in z (eq. proj2_ustar,
+    the fully implicit diffusion of a Runge-Kutta substep with s = gamma_k nu
+    dt / 2). Same route as the Poisson solve: transforms in x and y, then per
+    slot pair the z rows (s alpha, s gamma, 1 + s excess + s (sigma_x +
+    sigma_y)), all non-negative, so there is no singular column."""
     dt = r.dtype.type
     n, ny, nx = r.shape
     s = dt(s)
-    fwd, inv, wavenumbers = _y_transform(ybc)
-    R = fwd(transforms.rfft_packed(r, axis=2), axis=1)
-    sx = grid.modified_wavenumbers(nx, lx, dt)
-    sy = wavenumbers(ny, ly, dt)
+    xf, xi, xw = _x_transform(xbc)
+    yf, yi, yw = _y_transform(ybc)
+    R = yf(xf(r, axis=2), axis=1)
+    sx = xw(nx, lx, dt)
+    sy = yw(ny, ly, dt)
     alpha, gamma, eps = grid.zop(zf, bc, dt)
     shift = sy[:, None] + sx[None, :]
     diag = (1 + s * eps)[:, None, None] + s * shift[None, :, :]
     U = tridiag.thomas_gth((s * alpha)[:, None, None], (s * gamma)[:, None, None], diag, R)
-    return transforms.irfft_packed(inv(U, axis=1), axis=2)
+    return xi(yi(U, axis=1), axis=2)
 
 
 def rel_l2(x, ref):
