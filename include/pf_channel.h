@@ -91,14 +91,22 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * (a field at cell-centre y positions); poisson_project takes PF_Y_WALLS
  * (v[:, ny-1, :] is then the top wall face: no flux through it enters the
  * divergence and it is left unchanged) and returns PF_ERR_UNSUPPORTED for
- * PF_Y_DIRICHLET. */
+ * PF_Y_DIRICHLET.
+ * xbc: the same choice at both x ends (PF_X_PERIODIC, PF_X_WALLS: the cosine
+ * transform along x, wavenumbers 4 sin^2(pi q / 2 nx) / dx^2; PF_X_DIRICHLET:
+ * the sine transform, 4 sin^2(pi (q + 1) / 2 nx) / dx^2, nonsingular), with
+ * nx cell-centred unknowns, alone or with y walls; built for poisson_plan /
+ * poisson_solve and helmholtz3d_plan / helmholtz3d_solve (poisson_project
+ * returns PF_ERR_UNSUPPORTED for x walls). */
 enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2 };
+enum { PF_X_PERIODIC = 0, PF_X_WALLS = 1, PF_X_DIRICHLET = 2 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;
   double lx, ly, lz;
   double beta;
   const double *zf;
   int32_t ybc;
+  int32_t xbc;
 } pf_grid;
 
 typedef struct pf_poisson_plan pf_poisson_plan;
@@ -106,7 +114,7 @@ typedef struct pf_pcr_plan pf_pcr_plan;
 typedef struct pf_graph pf_graph;
 
 const char *pf_last_error(void);
-int32_t pf_abi_version(void); /* 2: pf_grid carries ybc */
+int32_t pf_abi_version(void); /* 3: pf_grid carries ybc and xbc */
 
 /* Host helper: the sign-normalised rows of -L_z for boundary family bc,
  * row k = -alpha[k] x[k-1] + (alpha[k]+gamma[k]+excess[k]) x[k]

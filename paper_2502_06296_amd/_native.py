@@ -40,7 +40,8 @@ EXPORTS = [
 class PfGrid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
-                ("beta", C.c_double), ("zf", C.POINTER(C.c_double)), ("ybc", C.c_int32)]
+                ("beta", C.c_double), ("zf", C.POINTER(C.c_double)), ("ybc", C.c_int32),
+                ("xbc", C.c_int32)]
 
 
 class PfTask(C.Structure):
@@ -125,9 +126,9 @@ def check(code):
 
 
 def make_grid(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5, zf=None,
-              ybc=0):
+              ybc=0, xbc=0):
     """(PfGrid, keep-alive) for the C ABI; zf is an optional host array of nz+1 faces;
-    ybc 0 (periodic y) or 1 (zero-gradient y walls)."""
+    ybc and xbc: 0 periodic, 1 zero-gradient walls, 2 value-zero walls."""
     keep = None
     zp = None
     if zf is not None:
@@ -136,7 +137,7 @@ def make_grid(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, be
         if keep.shape != (nz + 1,):
             raise ValueError("zf must have nz+1 entries")
         zp = keep.ctypes.data_as(C.POINTER(C.c_double))
-    return PfGrid(nx, ny, nz, lx, ly, lz, beta, zp, ybc), keep
+    return PfGrid(nx, ny, nz, lx, ly, lz, beta, zp, ybc, xbc), keep
 
 
 def stream_handle(stream=None):

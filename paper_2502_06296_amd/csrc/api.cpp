@@ -47,6 +47,8 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
   if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS && g->ybc != PF_Y_DIRICHLET)
     return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC, PF_Y_WALLS or PF_Y_DIRICHLET (got %d)", g->ybc);
+  if (g->xbc != PF_X_PERIODIC && g->xbc != PF_X_WALLS && g->xbc != PF_X_DIRICHLET)
+    return fail(PF_ERR_ARG, "xbc must be PF_X_PERIODIC, PF_X_WALLS or PF_X_DIRICHLET (got %d)", g->xbc);
   if (need_fft) {
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
 #define PF_LEN_STR(N) " " #N
@@ -235,8 +237,8 @@ struct pf_poisson_plan {
   int zchunk;
   DevArena ar;
   size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sxb, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
-      o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc, o_ctw;
-  int ybc = PF_Y_PERIODIC;
+      o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc, o_ctw, o_ctwx;
+  int ybc = PF_Y_PERIODIC, xbc = PF_X_PERIODIC;
   void *ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   unsigned long long *stat = nullptr;  // caller's pf_solve_status (device) or null
@@ -355,7 +357,7 @@ int zpad(int nz) { return (nz + kZChunk - 1) / kZChunk * kZChunk; }
 extern "C" {
 
 const char *pf_last_error(void) { return g_err.c_str(); }
-int32_t pf_abi_version(void) { return 2; }
+int32_t pf_abi_version(void) { return 3; }
 
 pf_status pf_grid_faces(const pf_grid *g, double *zf_out) {
   pf_status s = check_grid(g, false);
@@ -406,6 +408,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   pl->lx = g->lx; pl->ly = g->ly;
   pl->bc = bc;
   pl->ybc = g->ybc;
+  pl->xbc = g->xbc;
   pl->kappa = bc == PF_BC_NEUMANN ? 0.0 : 1.0 / hs;
   pl->prec = precision;
   pl->nref = precision == PF_FP32_REFINE ? n_refine : 0;
@@ -429,6 +432,19 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   // (zero-gradient walls), or the sine modes, 4 sin^2(pi (q + 1) / 2 ny) / dy^2
   // (value-zero walls); ctw[q] = exp(-i pi q / 2 ny) serves both transforms.
   auto sx = sigma_slots(g->nx, g->lx), sy = sigma_slots(g->ny, g->ly);
+  // x walls: one real cosine (sine) mode per slot in natural order, the
+  // wavenumbers 4 sin^2(pi (q + q0) / 2 nx) / dx^2; ctwx[q] = exp(-i pi q / 2 nx)
+  std::vector<double2> ctwx;
+  if (g->xbc != PF_X_PERIODIC) {
+    const double dx = g->lx / g->nx;
+    const int q0 = g->xbc == PF_X_DIRICHLET ? 1 : 0;
+    for (int q = 0; q < g->nx; ++q) {
+      const long double v = std::sin((long double)M_PI * (q + q0) / (2.0L * g->nx));
+      sx[q] = (double)(4.0L * v * v / ((long double)dx * dx));
+      const long double a = (long double)M_PI * q / (2.0L * g->nx);
+      ctwx.push_back(double2{(double)std::cos(a), (double)(-std::sin(a))});
+    }
+  }
   const std::vector<double> sxb = sx;  // without the Helmholtz shift kappa
   for (double &v : sx) v += pl->kappa;
   std::vector<double2> ctw;
@@ -447,6 +463,11 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
         const long double a = (long double)M_PI * q / (2.0L * g->ny);
         ctw.push_back(double2{(double)std::cos(a), (double)(-std::sin(a))});
       }
+    // x walls with periodic y: every x slot is a real column whose y
+    // spectrum is packed, so the z solve's second table (complex modes of
+    // the other slot pairs) holds the packed wavenumbers as well
+    if (!walls && g->xbc != PF_X_PERIODIC)
+      for (int m = 0; m < g->ny; ++m) sy[g->ny + m] = sy[m];
   }
   auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
   DevArena &A = pl->ar;
@@ -460,6 +481,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   pl->o_twx_d = A.add(twxd.data(), twxd.size());
   pl->o_twy_d = A.add(twyd.data(), twyd.size());
   pl->o_ctw = ctw.empty() ? 0 : A.add(ctw.data(), ctw.size());
+  pl->o_ctwx = ctwx.empty() ? 0 : A.add(ctwx.data(), ctwx.size());
   // per-plane buffers; fbar and zm stay zero for the Helmholtz (no zero mode)
   pl->o_sums = A.add<double>(nullptr, (size_t)g->ny * nzu);
   pl->o_sump = A.add<double>(nullptr, (size_t)g->ny * nzu);
@@ -570,7 +592,7 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   const double scale = 1.0 / ((double)pl->nx * pl->ny);
   const bool helm = pl->bc != PF_BC_NEUMANN;
   const double oscale = helm ? -pl->kappa * scale : scale;
-  const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET;
+  const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET || pl->xbc == PF_X_DIRICHLET;
   if (pl->stat) PF_HIP(pf::launch_status_reset(pl->stat, st));
   if (pl->prec != PF_FP32_REFINE) {
     pf_status s = poisson_enqueue_plain(pl, rhs, p, st, div, nozero, oscale, ws);
@@ -594,34 +616,38 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
   pf_status s;
   if (pl->prec == PF_FP64) {
     const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
-  const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
-  const int yw = pl->ybc;
+    const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
+    const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
+    const int yw = pl->ybc, xw = pl->xbc;
+    const bool xr = xw != PF_X_PERIODIC;
     // the spectrum lives in p itself, dense
     const size_t sd = (size_t)nx * ny;
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
-                             : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st));
+                             : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st, xw, ctwx));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, yw, st));
-    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, yw, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr));
     STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, helm ? zm : mm, nullptr, oscale,
-                                                          lines, st)));
+                                                          lines, st, nullptr, xw, ctwx)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
-  const int yw = pl->ybc;
+  const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
+  const int yw = pl->ybc, xw = pl->xbc;
+  const bool xr = xw != PF_X_PERIODIC;
   float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
-                             : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
+                             : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
-    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
     STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, helm ? zm : mm, nullptr,
-                                                               oscale, lines, st)));
+                                                               oscale, lines, st, nullptr, xw, ctwx)));
     return PF_OK;
   }
   return fail(PF_ERR_ARG, "unexpected precision");
@@ -641,7 +667,9 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
   pf_status s;
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
   const double2 *ctw = pl->ybc != PF_Y_PERIODIC ? A.at<double2>(pl->o_ctw) : nullptr;
-  const int yw = pl->ybc;
+  const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
+  const int yw = pl->ybc, xw = pl->xbc;
+  const bool xr = xw != PF_X_PERIODIC;
   float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
@@ -656,22 +684,23 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd_div<float>(nx, ny, nz, d, W0, sp, twx, sums, st));
     rhs = p;
   } else {
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st));
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx));
   }
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
-  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
   const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
   STAGE(PF_STAGE_XFWD_RESID,
         pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2,
-                             pl->ybc, st));
+                             pl->ybc, st, xw, ctwx));
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st));
-  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr));
   STAGE(PF_STAGE_XINV_FINAL,
-        (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat)));
+        (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat, xw,
+                                        ctwx)));
   if (pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, true, st));
 #undef STAGE
   return PF_OK;
@@ -757,6 +786,8 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
   if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "poisson_project needs a Poisson plan");
   if (pl->ybc == PF_Y_DIRICHLET)
     return fail(PF_ERR_UNSUPPORTED, "poisson_project: the pressure takes periodic or zero-gradient y ends");
+  if (pl->xbc != PF_X_PERIODIC)
+    return fail(PF_ERR_UNSUPPORTED, "poisson_project: x walls are built for the Poisson and 3-D Helmholtz solves only");
   if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
   if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");

@@ -53,9 +53,23 @@ __device__ __forceinline__ void st2(T *p, double x, double y) {
 }
 
 // ----------------------------------------------------------- x forward
-template <typename T, int N, int TPL, int LPW, bool SUMS>
+// XW = 0: periodic x, the packed real layout (App. A).
+// XW = 1 (2): zero-gradient (value-zero) walls at both x ends: the cosine
+// (sine) transform of every line, X_q = 2 sum_i x_i cos(pi q (2i + 1) / 2N)
+// (Y_q = 2 sum_i x_i sin(pi (q + 1) (2i + 1) / 2N)), one real coefficient
+// per slot in natural order (slot q holds mode q). Computed as along y for y
+// walls: the line pair a + ib in Makhoul's order (even positions ascending,
+// odd descending; for the sine the odd positions negated) through one
+// complex FFT, then X_q = c_q Z_q + conj(c_q) Z_{N-q} (c_q = ctw[q] =
+// exp(-i pi q / 2N), Z_N = Z_0) gives the two lines' coefficients as its
+// real and imaginary parts (the transform has real coefficients); the sine
+// takes the cosine coefficient of index N-1-q as its mode q. Z_0 is the sum
+// of each line, as in the periodic case.
+__device__ __forceinline__ int xw_src(int n, int N) { return n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n; }
+template <typename T, int N, int TPL, int LPW, bool SUMS, int XW>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
                                                    const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw,
                                                    double *__restrict__ sums, long ncl, int ny,
                                                    size_t sp) {
   using C = cplx<double>;
@@ -68,11 +82,34 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
   // the first pass reads the line pair straight from global memory
   const double *a = in + (ok ? (size_t)(2 * c) * N : 0);
   const double *b = a + N;
-  auto src = [&](int i) { return ok ? mkc<double>(a[i], b[i]) : mkc<double>(0.0, 0.0); };
+  auto src = [&](int i) {
+    if constexpr (XW == 0) {
+      return ok ? mkc<double>(a[i], b[i]) : mkc<double>(0.0, 0.0);
+    } else {
+      const int x = xw_src(i, N);
+      const double sg = (XW == 2 && (x & 1)) ? -1.0 : 1.0;
+      return ok ? mkc<double>(sg * a[x], sg * b[x]) : mkc<double>(0.0, 0.0);
+    }
+  };
   fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
   if (!ok) return;
   T *oa = out + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
   T *ob = oa + N;
+  if constexpr (XW != 0) {
+#pragma unroll
+    for (int q = t; q < N; q += TPL) {
+      const C v1 = buf[lds_idx(q)], v2 = buf[lds_idx(q == 0 ? 0 : N - q)], cq = ctw[q];
+      const int slot = XW == 2 ? N - 1 - q : q;
+      oa[slot] = (T)(cq.x * v1.x - cq.y * v1.y + cq.x * v2.x + cq.y * v2.y);
+      ob[slot] = (T)(cq.x * v1.y + cq.y * v1.x + cq.x * v2.y - cq.y * v2.x);
+      if (SUMS && q == 0) {
+        // the sum of each line (a sign-alternated sum for the sine, unused)
+        sums[2 * c] = v1.x;
+        sums[2 * c + 1] = v1.y;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
@@ -309,13 +346,17 @@ hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, 
 // iterate disappears: the final pass transforms W + (correction) at once.
 // Shape of k_xfwd; a workgroup takes LPW line pairs of one plane (2*LPW
 // divides ny), planes fastest so that the neighbour planes' W is in L2.
-template <int N, int TPL, int LPW>
+// XW = 1 (2): walls at both x ends: X(f) is k_xfwd's cosine (sine)
+// transform, one real coefficient per slot, so a slot pair holds two x
+// modes of the same line; the x second difference is still -sx[slot], and
+// the cosine's zero mode of a constant f is 2 N f.
+template <int N, int TPL, int LPW, int XW>
 __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
-    float *__restrict__ out, const cplx<double> *__restrict__ tw, double *__restrict__ sums_p,
-    const double *__restrict__ sx, const double *__restrict__ zal, const double *__restrict__ zga,
-    const double *__restrict__ zex, int ny, int nz, double idy2, double inv_ny, int ywalls,
-    size_t sp) {
+    float *__restrict__ out, const cplx<double> *__restrict__ tw, const cplx<double> *__restrict__ ctw,
+    double *__restrict__ sums_p, const double *__restrict__ sx, const double *__restrict__ zal,
+    const double *__restrict__ zga, const double *__restrict__ zex, int ny, int nz, double idy2,
+    double inv_ny, int ywalls, size_t sp) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
@@ -327,10 +368,19 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     // the first pass reads the line pair of f straight from global memory
     const double *fa = f + ((size_t)k * ny + j) * N;
     const double *fb = fa + N;
-    auto src = [&](int i) { return mkc<double>(fa[i], fb[i]); };
+    auto src = [&](int i) {
+      if constexpr (XW == 0) {
+        return mkc<double>(fa[i], fb[i]);
+      } else {
+        const int x = xw_src(i, N);
+        const double sg = (XW == 2 && (x & 1)) ? -1.0 : 1.0;
+        return mkc<double>(sg * fa[x], sg * fb[x]);
+      }
+    };
     fft_line_io<double, N, TPL, false, true, false>(buf, tw, t, src, [](int, const C &) {});
   }
-  const double ak = zal[k], gk = zga[k], dk = ak + gk + zex[k], fk = (double)N * fbar[k];
+  const double ak = zal[k], gk = zga[k], dk = ak + gk + zex[k];
+  const double fk = (XW == 1 ? 2.0 : 1.0) * (double)N * fbar[k];
   const bool lo = k > 0, hi = k < nz - 1;
   // y neighbours of the line pair: periodic wrap, or the end row itself as
   // the ghost value beyond a wall, mirrored (ywalls 1, zero gradient) or
@@ -347,7 +397,19 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
-    if (q == 0) {
+    if constexpr (XW != 0) {
+      // slots 2q and 2q+1 of lines a (real parts) and b (imaginary parts)
+      C v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int qc = XW == 2 ? N - 1 - (2 * q + h) : 2 * q + h;
+        const C v1 = buf[lds_idx(qc)], v2 = buf[lds_idx(qc == 0 ? 0 : N - qc)], cq = ctw[qc];
+        v[h] = mkc<double>(cq.x * v1.x - cq.y * v1.y + cq.x * v2.x + cq.y * v2.y,
+                           cq.x * v1.y + cq.y * v1.x + cq.x * v2.y - cq.y * v2.x);
+      }
+      A = mkc<double>(v[0].x - (q == 0 ? fk : 0.0), v[1].x);
+      B = mkc<double>(v[0].y - (q == 0 ? fk : 0.0), v[1].y);
+    } else if (q == 0) {
       const C z0 = buf[lds_idx(0)], zh = buf[lds_idx(N / 2)];
       A = mkc<double>(z0.x - fk, zh.x);
       B = mkc<double>(z0.y - fk, zh.y);
@@ -379,8 +441,10 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     *reinterpret_cast<cplx<float> *>(ob + 2 * q) =
         mkc<float>((float)(B.x - inv_ny * lb0), (float)(B.y - inv_ny * lb1));
     if (q == 0) {
-      sums_p[(size_t)k * ny + j] = c0.x * inv_ny;
-      sums_p[(size_t)k * ny + j + 1] = c1.x * inv_ny;
+      // the iterate's line sums (the cosine's slot 0 holds twice the sum)
+      const double sc = XW == 1 ? 0.5 * inv_ny : inv_ny;
+      sums_p[(size_t)k * ny + j] = c0.x * sc;
+      sums_p[(size_t)k * ny + j + 1] = c1.x * sc;
     }
   }
 }
@@ -399,7 +463,10 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 // Y_q = 2 sum_y x_y sin(pi (q + 1) (2y + 1) / 2N), which is the cosine
 // transform of (-1)^y x_y read backwards (Y_q = X'_{N-1-q}): the odd rows are
 // negated as they are read and mode q is written to row N-1-q.
-template <typename T, int N, int TPL, int LPW, int YW>
+// XR (periodic y only): the x slots are real coefficients of x walls'
+// cosine or sine transforms, so every slot pair is two real columns and takes
+// the split into packed real y spectra that slots 0 and 1 take otherwise.
+template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
@@ -437,7 +504,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
     }
     return;
   }
-  if (ib != 0) {
+  if (ib != 0 && !XR) {
     // slot pairs (2m, 2m+1), m >= 1, are the real and imaginary parts of x
     // mode m: their y transform is the complex spectrum itself, written in
     // natural order (row ky) by the last pass
@@ -455,7 +522,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
     const int e = tid + s * NT;
     const int l2 = e % LPW, y = e / LPW;
     const C *b2 = lds + l2 * y_stride(N);
-    if (l2 != 0) {
+    if (l2 != 0 && !XR) {
       const C v = b2[lds_idx(y)];
       st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
     } else if (y < N / 2) {
@@ -470,8 +537,8 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
         r0 = mkc<double>(A.x, B.x);
         r1 = mkc<double>(A.y, B.y);
       }
-      st2<T>(base + (size_t)(2 * q) * nx, r0.x, r0.y);
-      st2<T>(base + (size_t)(2 * q + 1) * nx, r1.x, r1.y);
+      st2<T>(base + (size_t)(2 * q) * nx + 2 * l2, r0.x, r0.y);
+      st2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2, r1.x, r1.y);
     }
   }
 }
@@ -484,7 +551,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
 // 2n+1 from v_n and v_{N-1-n} (sine: X_q is read from row N-1-q and the odd
 // rows negated); the 1/N is left to the x inverse's scale, as for the
 // periodic transform.
-template <typename T, int N, int TPL, int LPW, int YW>
+template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
 __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
@@ -535,7 +602,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
     fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dstw);
     return;
   }
-  if (ib != 0) {
+  if (ib != 0 && !XR) {
     // the first pass reads the complex spectrum straight from row ky
     auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
     fft_line_io<double, N, TPL, true, true, true>(buf, tw, t, src, dst);
@@ -546,12 +613,12 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
     const int e = tid + s * NT;
     const int l2 = e % LPW, y = e / LPW;
     C *b2 = lds + l2 * y_stride(N);
-    if (l2 != 0) {
+    if (l2 != 0 && !XR) {
       b2[lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l2);
     } else if (y < N / 2) {
       const int q = y;
-      const C r0 = ld2<T>(base + (size_t)(2 * q) * nx);
-      const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx);
+      const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
+      const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
       if (q == 0) {
         b2[lds_idx(0)] = r0;
         b2[lds_idx(N / 2)] = r1;
@@ -572,9 +639,15 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
 // LDS before writing it), so they are not marked restrict.
 // SUM2: the transform of in + in2 (two spectra of the same layout, summed
 // in float64 before the inverse).
-template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool SUM2>
+// XW = 1 (2): inverse of k_xfwd's cosine (sine) transform, as along y for y
+// walls: V_q = conj(c_q) (X_q - i X_{N-q}) / 2 (X_N = 0) from the two lines'
+// coefficients X = a + ib, the inverse FFT, and the positions 2n and 2n+1
+// from v_n and v_{N-1-n} (sine: mode q read from slot q as the cosine index
+// N-1-q, odd positions negated); the 1/N is in `scale`.
+template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool SUM2, int XW>
 __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
                                                    const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw,
                                                    const double *__restrict__ zm,
                                                    const TS *__restrict__ in2, double scale,
                                                    int ny, long ncl, size_t sp,
@@ -587,7 +660,44 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
   double m0 = 0.0, m1 = 0.0;  // largest |iterate| and |correction| seen (SUM2)
-  if (ok) {
+  if (XW != 0 && ok) {
+    const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
+    const TS *a = in + o;
+    const TS *b = a + N;
+#pragma unroll
+    for (int s = t; s < N; s += TPL) {
+      double xa = (double)a[s], xb = (double)b[s];
+      if (SUM2) {
+        const double ya = (double)in2[o + s], yb = (double)in2[o + N + s];
+        m0 = fmax(m0, fmax(fabs(xa), fabs(xb)));
+        m1 = fmax(m1, fmax(fabs(ya), fabs(yb)));
+        xa += ya;
+        xb += yb;
+      }
+      // cosine index of the stored coefficient
+      buf[lds_idx(XW == 2 ? N - 1 - s : s)] = mkc<double>(xa, xb);
+    }
+  }
+  if (XW != 0) {
+    __syncthreads();
+    // one thread per index pair (q, N - q), q = 0..N/2: both read before
+    // either is overwritten
+    if (ok) {
+      for (int q = t; q <= N / 2; q += TPL) {
+        const C xq = buf[lds_idx(q)];
+        const C xn = q == 0 ? mkc<double>(0.0, 0.0) : buf[lds_idx(N - q)];
+        const C cq = ctw[q];
+        const double ur = 0.5 * (xq.x + xn.y), ui = 0.5 * (xq.y - xn.x);
+        buf[lds_idx(q)] = mkc<double>(cq.x * ur + cq.y * ui, cq.x * ui - cq.y * ur);
+        if (q != 0 && 2 * q != N) {
+          const C cn = ctw[N - q];
+          const double wr = 0.5 * (xn.x + xq.y), wi = 0.5 * (xn.y - xq.x);
+          buf[lds_idx(N - q)] = mkc<double>(cn.x * wr + cn.y * wi, cn.x * wi - cn.y * wr);
+        }
+      }
+    }
+  }
+  if (XW == 0 && ok) {
     const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
     const TS *a = in + o;
     const TS *b = a + N;
@@ -633,8 +743,15 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
   TO *ob = oa + N;
   auto dst = [&](int pos, const C &z) {
     if (ok) {
-      oa[pos] = (TO)(z.x * scale + add);
-      ob[pos] = (TO)(z.y * scale + add);
+      if constexpr (XW == 0) {
+        oa[pos] = (TO)(z.x * scale + add);
+        ob[pos] = (TO)(z.y * scale + add);
+      } else {
+        const int x = xw_src(pos, N);
+        const double sg = (XW == 2 && (x & 1)) ? -scale : scale;
+        oa[x] = (TO)(z.x * sg + add);
+        ob[x] = (TO)(z.y * sg + add);
+      }
     }
   };
   fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dst);
@@ -643,19 +760,27 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
 // ------------------------------------------------------------- launchers
 template <typename T>
 hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
-                       const cplx<double> *tw, double *sums, long lines, hipStream_t st) {
+                       const cplx<double> *tw, double *sums, long lines, hipStream_t st, int xw,
+                       const cplx<double> *ctwx) {
   const long ncl = lines / 2;
+  if (xw != 0 && (!sums || !ctwx)) return hipErrorInvalidValue;
   switch (nx) {
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
     constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                            \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
-    if (sums)                                                                                   \
-      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, in, out, tw, \
-                         sums, ncl, ny, sp);                                                    \
+    if (xw == 1)                                                                                \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true, 1>), g, dim3(TPL * LPW), 0, st, in, out,  \
+                         tw, ctwx, sums, ncl, ny, sp);                                          \
+    else if (xw == 2)                                                                           \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true, 2>), g, dim3(TPL * LPW), 0, st, in, out,  \
+                         tw, ctwx, sums, ncl, ny, sp);                                          \
+    else if (sums)                                                                              \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true, 0>), g, dim3(TPL * LPW), 0, st, in, out,  \
+                         tw, ctwx, sums, ncl, ny, sp);                                          \
     else                                                                                        \
-      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, false>), g, dim3(TPL * LPW), 0, st, in, out,    \
-                         tw, sums, ncl, ny, sp);                                                \
+      hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, false, 0>), g, dim3(TPL * LPW), 0, st, in, out, \
+                         tw, ctwx, sums, ncl, ny, sp);                                          \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
@@ -669,20 +794,29 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
                              const double *zga, const double *zex, double idy2, int ywalls,
-                             hipStream_t st) {
+                             hipStream_t st, int xw, const cplx<double> *ctwx) {
+  if (xw != 0 && !ctwx) return hipErrorInvalidValue;
   switch (nx) {
+#define PF_RESID(N, XW)                                                                          \
+  hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW, XW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,  \
+                     st, f, fbar, W, out, tw, ctwx, sums_p, sx, zal, zga, zex, ny, nz, idy2,      \
+                     1.0 / ny, ywalls, sp)
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
     constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                        \
     if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
     const long nblk = (long)ny * nz / (2 * LPW);                                                 \
-    hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,    \
-                       st, f, fbar, W, out, tw, sums_p, sx, zal, zga, zex, ny, nz, idy2, 1.0 / ny,  \
-                       ywalls, sp);                                                              \
+    if (xw == 1)                                                                                 \
+      PF_RESID(N, 1);                                                                            \
+    else if (xw == 2)                                                                            \
+      PF_RESID(N, 2);                                                                            \
+    else                                                                                         \
+      PF_RESID(N, 0);                                                                            \
     return hipGetLastError();                                                                    \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
 #undef PF_CASE
+#undef PF_RESID
     default:
       return hipErrorInvalidValue;
   }
@@ -690,7 +824,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st) {
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -705,6 +839,9 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
     else if (yw == 2)                                                                         \
       hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 2>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
+    else if (xr)                                                                              \
+      hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 0, true>), g, b, 0, st, data, tw, ctw, nx,   \
+                         nib, sp);                                                            \
     else                                                                                      \
       hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 0>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
@@ -719,7 +856,7 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st) {
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr) {
   switch (ny) {
 #define PF_CASE(N)                                                                            \
   case N: {                                                                                   \
@@ -734,6 +871,9 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
     else if (yw == 2)                                                                         \
       hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 2>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
+    else if (xr)                                                                              \
+      hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 0, true>), g, b, 0, st, data, tw, ctw, nx,   \
+                         nib, sp);                                                            \
     else                                                                                      \
       hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 0>), g, b, 0, st, data, tw, ctw, nx, nib,    \
                          sp);                                                                 \
@@ -749,54 +889,65 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const TS *in2, double scale, long lines,
-                       hipStream_t st, unsigned long long *stat) {
+                       hipStream_t st, unsigned long long *stat, int xw,
+                       const cplx<double> *ctwx) {
   const long ncl = lines / 2;
+  // the walls' inverses are built for the solves' uses (with the zero-mode
+  // profile, with or without a second spectrum)
+  if (xw != 0 && (!zm || !ctwx)) return hipErrorInvalidValue;
   switch (nx) {
+#define PF_XINV(N, ADDZ, SUM2, XW, STAT)                                                         \
+  hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, ADDZ, SUM2, XW>), g, b, 0, st, in, out, tw,    \
+                     ctwx, zm, in2, scale, ny, ncl, sp, STAT)
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
     constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
-    if (zm && in2)                                                                              \
-      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, true>), g, b, 0, st, in, out, tw,  \
-                         zm, in2, scale, ny, ncl, sp, stat);                                         \
+    if (xw == 1 && in2)                                                                         \
+      PF_XINV(N, true, true, 1, stat);                                                             \
+    else if (xw == 1)                                                                           \
+      PF_XINV(N, true, false, 1, nullptr);                                                         \
+    else if (xw == 2 && in2)                                                                    \
+      PF_XINV(N, true, true, 2, stat);                                                             \
+    else if (xw == 2)                                                                           \
+      PF_XINV(N, true, false, 2, nullptr);                                                         \
+    else if (zm && in2)                                                                         \
+      PF_XINV(N, true, true, 0, stat);                                                             \
     else if (zm)                                                                                \
-      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, true, false>), g, b, 0, st, in, out, tw, \
-                         zm, in2, scale, ny, ncl, sp, nullptr);                                      \
+      PF_XINV(N, true, false, 0, nullptr);                                                         \
     else                                                                                        \
-      hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, false, false>), g, b, 0, st, in, out,    \
-                         tw, zm, in2, scale, ny, ncl, sp, nullptr);                                  \
+      PF_XINV(N, false, false, 0, nullptr);                                                        \
     return hipGetLastError();                                                                   \
   }
     PF_FOR_FFT_SIZES(PF_CASE)
 #undef PF_CASE
+#undef PF_XINV
     default:
       return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_xfwd<double>(int, int, const double *, double *, size_t,
-                                        const cplx<double> *, double *, long, hipStream_t);
+                                        const cplx<double> *, double *, long, hipStream_t, int,
+                                        const cplx<double> *);
 template hipError_t launch_xfwd<float>(int, int, const double *, float *, size_t,
-                                       const cplx<double> *, double *, long, hipStream_t);
+                                       const cplx<double> *, double *, long, hipStream_t, int,
+                                       const cplx<double> *);
 template hipError_t launch_yfwd<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        const cplx<double> *, int, hipStream_t);
+                                        const cplx<double> *, int, hipStream_t, bool);
 template hipError_t launch_yfwd<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       const cplx<double> *, int, hipStream_t);
+                                       const cplx<double> *, int, hipStream_t, bool);
 template hipError_t launch_yinv<double>(int, int, int, double *, size_t, const cplx<double> *,
-                                        const cplx<double> *, int, hipStream_t);
+                                        const cplx<double> *, int, hipStream_t, bool);
 template hipError_t launch_yinv<float>(int, int, int, float *, size_t, const cplx<double> *,
-                                       const cplx<double> *, int, hipStream_t);
+                                       const cplx<double> *, int, hipStream_t, bool);
 template hipError_t launch_xinv<double, double>(int, int, const double *, size_t, double *,
                                                 const cplx<double> *, const double *,
                                                 const double *, double, long, hipStream_t,
-                                                unsigned long long *);
-template hipError_t launch_xinv<float, float>(int, int, const float *, size_t, float *,
-                                              const cplx<double> *, const double *, const float *,
-                                              double, long, hipStream_t,
-                                                unsigned long long *);
+                                                unsigned long long *, int, const cplx<double> *);
 template hipError_t launch_xinv<float, double>(int, int, const float *, size_t, double *,
                                                const cplx<double> *, const double *, const float *,
-                                               double, long, hipStream_t,
-                                                unsigned long long *);
+                                               double, long, hipStream_t, unsigned long long *,
+                                               int, const cplx<double> *);
 
 }  // namespace pf

@@ -206,7 +206,7 @@ template <typename TS, int M, int TP, int NR, int WAVES, bool SK>
 __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny, int nz, int P,
                                                const double *zal, const double *zga,
                                                const double *zex, const double *sx,
-                                               const double *sy, size_t sp) {
+                                               const double *sy, size_t sp, int xr) {
   using V = cplx<TS>;  // the pair (column i, column i+1) of one row
   // LDS: the z tables of the column, (alpha, gamma) and eps of row
   // ch*M + q at [q*P + ch] (the chunks of one wave read consecutive
@@ -238,7 +238,9 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
   auto ga = [&](int q) { return agc[q * P].y; };
   auto ex = [&](int q) { return exc[q * P]; };
   __syncthreads();
-  const int npass = ib == 0 ? 2 : 1;  // uniform per workgroup
+  // xr (x walls): every slot is its own real x mode, so the two columns of
+  // a pair have different shifts and every pair takes both passes
+  const int npass = ib == 0 || xr ? 2 : 1;  // uniform per workgroup
   for (int pass = 0; pass < npass; ++pass) {
     // pass 1 exists only for the pair of slots 0 and 1; other lanes redo
     // pass 0's work on already solved data and store nothing
@@ -247,9 +249,11 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
     const bool zero_col = lam0 == 0.0;  // Poisson's (0,0) only
     const double lam = zero_col ? 1.0 : lam0;
     // pass 0 stores both columns of every pair except column 1 of the pair
-    // (0, 1); pass 1 stores only that column
+    // (0, 1); pass 1 stores only that column (with xr: pass 0 column 0 and
+    // pass 1 column 1 of every pair)
     const bool st0 = pass == 0;
-    const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
+    const bool st1 = xr ? pass == 1
+                        : (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
 
     double d0[M], d1[M], ib_[M];
 #pragma unroll
@@ -389,7 +393,7 @@ template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512>
 __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
-                                                      const double *sy, size_t sp) {
+                                                      const double *sy, size_t sp, int xr) {
   static_assert(M >= 3, "a chunk needs interior rows");
   using V = cplx<TS>;
   using D2 = cplx<double>;
@@ -425,15 +429,17 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
   const int nch = ch + 1 < P ? ch + 1 : ch;  // the last chunk's gamma is 0
   const int nb = nch * TP + pc;
   __syncthreads();
-  const int npass = ib == 0 ? 2 : 1;  // uniform per workgroup
+  const int npass = ib == 0 || xr ? 2 : 1;  // uniform per workgroup
   for (int pass = 0; pass < npass; ++pass) {
-    // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1
+    // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1,
+    // or (xr) for column 1 of every pair
     const int ci = i + pass;
     const double lam0 = sx[ci] + sy[(ci >= 2 ? ny : 0) + j];
     const bool zero_col = lam0 == 0.0;  // Poisson's (0,0) only
     const double lam = zero_col ? 1.0 : lam0;
     const bool st0 = pass == 0;
-    const bool st1 = (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
+    const bool st1 = xr ? pass == 1
+                        : (pass == 0 && (npass == 1 || i != 0)) || (pass == 1 && i == 0);
 
     double d0[M], d1[M], ib_[M];
     // the 1024-thread shapes have half the registers: compiler fences keep
@@ -628,7 +634,7 @@ int zsolve_default_variant(int nx, int nz, bool fp64) {
 template <typename TS>
 hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const double *zal,
                          const double *zga, const double *zex, const double *sx, const double *sy,
-                         int variant, hipStream_t st) {
+                         int variant, hipStream_t st, bool xr) {
   // the z tables hold whole 16-row chunks (identity padding past nz)
   if (!zsolve_variant_fits(variant, nx, nz)) return hipErrorInvalidValue;
   const ZVariant &z = kZVariants[variant];
@@ -652,7 +658,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #define PF_ZP(ID, M_, TI_, NR_, W_, SK_)                                                         \
   case ID:                                                                                       \
     hipLaunchKernelGGL((k_zsolve2<TS, M_, TI_ / 2, NR_, W_, SK_>), g, b, shm, st, data, nx, ny,  \
-                       nz, P, zal, zga, zex, sx, sy, sp);                                            \
+                       nz, P, zal, zga, zex, sx, sy, sp, (int)xr);                                   \
     break;
     PF_ZP(8, 16, 16, 1, 1, true)
     PF_ZP(9, 8, 16, 1, 1, true)
@@ -667,7 +673,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #define PF_ZS(ID, M_, TI_, W_)                                                                   \
   case ID:                                                                                       \
     hipLaunchKernelGGL((k_zsolve3<TS, M_, TI_ / 2, 1, W_>), g, b, shm, st, data, nx, ny, nz, P,  \
-                       zal, zga, zex, sx, sy, sp);                                                   \
+                       zal, zga, zex, sx, sy, sp, (int)xr);                                          \
     break;
     PF_ZS(18, 8, 8, 4)
     PF_ZS(19, 8, 16, 4)
@@ -681,7 +687,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #define PF_ZW(ID, M_, TI_)                                                                       \
   case ID:                                                                                       \
     hipLaunchKernelGGL((k_zsolve3<TS, M_, TI_ / 2, 1, 1, 1024>), g, b, shm, st, data, nx, ny, nz, \
-                       P, zal, zga, zex, sx, sy, sp);                                            \
+                       P, zal, zga, zex, sx, sy, sp, (int)xr);                                   \
     break;
     PF_ZW(27, 8, 32)
     PF_ZW(28, 8, 16)
@@ -696,10 +702,10 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 }
 template hipError_t launch_zsolve<double>(int, int, int, double *, size_t, const double *, const double *,
                                           const double *, const double *, const double *, int,
-                                          hipStream_t);
+                                          hipStream_t, bool);
 template hipError_t launch_zsolve<float>(int, int, int, float *, size_t, const double *, const double *,
                                          const double *, const double *, const double *, int,
-                                         hipStream_t);
+                                         hipStream_t, bool);
 
 // ----------------------------------------------------------- zero mode
 // The (0,0) slot of the transformed problem is the plane-mean profile of p.

@@ -105,10 +105,13 @@ constexpr int y_lpw(int n) {
 // float32 work arrays are padded so that the z columns do not all fall on
 // the same memory channels); real-space arrays are dense.
 // x forward: rhs (float64 lines of nx) -> packed spectrum (T). Optional
-// float64 sums of every input line (sums may be null).
+// float64 sums of every input line (sums may be null). xw = 1 (2): walls at
+// both x ends, the cosine (sine) transform, one real coefficient per slot in
+// natural order; needs sums and ctwx = exp(-i pi q / 2 nx), q = 0..nx-1.
 template <typename T>
 hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
-                       const cplx<double> *tw, double *sums, long lines, hipStream_t st);
+                       const cplx<double> *tw, double *sums, long lines, hipStream_t st,
+                       int xw = 0, const cplx<double> *ctwx = nullptr);
 // x spectrum of the float64 7-point residual of the plane-mean-free
 // problem, R = X(f - fbar[k]) - L7 of the iterate whose x spectrum (times ny)
 // is W (float32, after the y inverse); the x operator is -sx per packed
@@ -120,26 +123,30 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
                              const double *zga, const double *zex, double idy2, int ywalls,
-                             hipStream_t st);
+                             hipStream_t st, int xw = 0, const cplx<double> *ctwx = nullptr);
 // y forward / inverse, in place on the packed (T) data. yw = 1 (2) selects
 // the cosine (sine) transform of zero-gradient (value-zero) y walls, in
 // natural order for every slot pair; it needs ctw = exp(-i pi q / 2 ny),
 // q = 0..ny-1.
+// xr (periodic y): the x slots are real coefficients of x walls' transforms,
+// so every slot pair is split into two packed real y spectra.
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st);
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false);
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st);
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k]; with in2 (requires zm) the inverse of
 // in + in2, summed in float64.
 // With in2, a non-null stat (4 unsigned 64-bit words) receives the largest
 // |in| and |in2| values by atomic max (see launch_status_final).
+// xw = 1 (2): the inverse cosine (sine) transform (requires zm and ctwx).
 template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const TS *in2, double scale, long lines,
-                       hipStream_t st, unsigned long long *stat = nullptr);
+                       hipStream_t st, unsigned long long *stat = nullptr, int xw = 0,
+                       const cplx<double> *ctwx = nullptr);
 // a-posteriori status of a solve: zero the 4 words; then the estimate
 // (max|in2| / max|in|)^2 into word 2 (-1 unless refined) and flag word 3
 // when it exceeds tol
@@ -173,11 +180,12 @@ hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, 
 // elimination in registers; the (0,0) slot column is set to zero. `variant`
 // indexes a table of launch shapes (rows per thread, columns per workgroup,
 // occupancy bound, reciprocal flavour); the z tables must be padded to a
-// multiple of 16 rows.
+// multiple of 16 rows. xr: x walls, every x slot its own real mode (the
+// paired shapes then solve the two columns of a pair one after the other).
 template <typename TS>
 hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const double *zal,
                          const double *zga, const double *zex, const double *sx, const double *sy,
-                         int variant, hipStream_t st);
+                         int variant, hipStream_t st, bool xr = false);
 int zsolve_variant_count();
 bool zsolve_variant_fits(int variant, int nx, int nz);
 int zsolve_default_variant(int nx, int nz, bool fp64);

@@ -64,15 +64,18 @@ YBCS = {"periodic": 0, "walls": 1, "dirichlet": 2}
 
 
 def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
-                 zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic"):
+                 zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic",
+                 xbc="periodic"):
     """Plan the channel Poisson solve; allocates the workspace as a torch tensor.
     ybc "walls": zero-gradient walls at both y ends (cosine transform in y);
-    "dirichlet": value-zero walls at both y ends (sine transform in y)."""
+    "dirichlet": value-zero walls at both y ends (sine transform in y); xbc
+    the same at both x ends."""
     import torch
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     yb = YBCS[ybc] if isinstance(ybc, str) else int(ybc)
+    xb = YBCS[xbc] if isinstance(xbc, str) else int(xbc)
     with torch.cuda.device(dev):
-        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf, yb)
+        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf, yb, xb)
         h = C.c_void_p()
         ws = C.c_size_t(0)
         s = N.stream_handle(stream)
@@ -86,16 +89,19 @@ def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0,
 
 
 def helmholtz3d_plan(nx, ny, nz, bc, s, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
-                     zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic"):
+                     zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic",
+                     xbc="periodic"):
     """Plan the 3-D implicit Helmholtz (I - s L) u = r (bc "dirichlet_centre":
-    fields of nz planes; "dirichlet_face": nz - 1; ybc as for poisson_plan, for
-    a field at cell-centre y positions); allocates the workspace."""
+    fields of nz planes; "dirichlet_face": nz - 1; ybc and xbc as for
+    poisson_plan, for a field at cell-centre x and y positions); allocates the
+    workspace."""
     import torch
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     b = BCS[bc] if isinstance(bc, str) else int(bc)
     yb = YBCS[ybc] if isinstance(ybc, str) else int(ybc)
+    xb = YBCS[xbc] if isinstance(xbc, str) else int(xbc)
     with torch.cuda.device(dev):
-        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf, yb)
+        g, keep = N.make_grid(nx, ny, nz, lx, ly, lz, beta, zf, yb, xb)
         h = C.c_void_p()
         ws = C.c_size_t(0)
         N.check(N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), b, float(s), _prec(precision),

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     L = N.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.pf_abi_version() == 2
+    assert L.pf_abi_version() == 3
 
 
 @pytest.mark.parametrize("bc", [0, 1, 2])
@@ -193,3 +193,13 @@ def test_pcr_prepare_rows_rejects_rows_outside_the_m_matrix_form():
     assert L.pcr_prepare_rows(C.byref(h), 3, lo.ctypes.data_as(pd), di.ctypes.data_as(pd),
                               up.ctypes.data_as(pd), 1e-3, 0, 0, None) == N.PF_ERR_ARG
     assert b"M-matrix" in L.pf_last_error() or L.pf_last_error()
+
+
+def test_plan_validates_the_x_boundary_before_any_device_call():
+    L = N.lib()
+    h = C.c_void_p()
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 3)
+    assert L.poisson_plan(C.byref(h), C.byref(g), 0, 1, None, None) == N.PF_ERR_ARG
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, -1)
+    assert L.poisson_plan(C.byref(h), C.byref(g), 0, 1, None, None) == N.PF_ERR_ARG
+    assert L.pf_abi_version() == 3

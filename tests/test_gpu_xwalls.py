@@ -1,0 +1,139 @@
+"""Walls at both x ends -- zero-gradient (the cosine transform of Sec. 2.2.1
+along x) and value-zero (the sine transform) -- alone and with every y
+boundary, through the C ABI against the CPU oracle, element by element, in
+the three precisions: the Poisson solve and the 3-D Helmholtz. Also graph
+replays, the float64 7-point residual at a larger size, and the projection's
+refusal of x walls.
+
+Bars: float64 1e-12, float32 with one float64-residual correction 1e-10,
+plain float32 1e-5, each for the relative L2 error and for the largest
+element-wise error against the largest reference value.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2502_06296_amd as pf
+import synth
+from oracle import grid as ogrid
+from oracle import poisson as op
+from paper_2502_06296_amd import _native as N
+from parity import TOL, check
+
+pytestmark = pytest.mark.gpu
+LX, LY = 2 * np.pi, np.pi
+XBC = {"walls": ogrid.X_WALLS, "dirichlet": ogrid.X_DIRICHLET}
+YBC = {"periodic": ogrid.Y_PERIODIC, "walls": ogrid.Y_WALLS, "dirichlet": ogrid.Y_DIRICHLET}
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+def _solve_gpu(f, zf, beta, prec, xbc, ybc):
+    nz, ny, nx = f.shape
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, ybc=ybc, xbc=xbc)
+    rhs = torch.from_numpy(f).to(_dev())
+    p = torch.empty_like(rhs)
+    pf.poisson_solve(plan, rhs, p)
+    torch.cuda.synchronize()
+    return p.cpu().numpy()
+
+
+CASES = [
+    (64, 64, 32, 1.5, 0),       # the smallest lengths
+    (96, 128, 20, 2.0, 1),      # radix-3 x, ragged z chunks
+    (256, 192, 17, 0.0, 2),     # radix-3 y, uniform z
+    (1024, 64, 12, 1.5, 3),     # the workloads' x length
+    (3200, 64, 6, 1.5, 4),      # radix-5 x lines (3200 = 2^7 5^2)
+    (3456, 96, 5, 1.2, 5),      # the longest x lines
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,seed", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+@pytest.mark.parametrize("ybc", ["periodic", "walls", "dirichlet"])
+@pytest.mark.parametrize("xbc", ["walls", "dirichlet"])
+def test_xwalls_poisson_matches_oracle(nx, ny, nz, beta, seed, prec, ybc, xbc):
+    print(f"x {xbc} y {ybc} {prec} {nx}x{ny}x{nz} beta={beta} seed={seed}", flush=True)
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    f = synth.uniform_pm1(700 + seed, (nz, ny, nx))
+    ref = op.solve_poisson(f, zf, LX, LY, ybc=YBC[ybc], xbc=XBC[xbc])
+    got = _solve_gpu(f, zf, beta, prec, xbc, ybc)
+    check(got, ref, TOL[prec], prec)
+
+
+H3D_CASES = [
+    (64, 64, 32, 1.5, ogrid.DIRICHLET_CENTRE, 1e-3, 0),
+    (96, 128, 20, 2.0, ogrid.DIRICHLET_FACE, 0.05, 1),
+    (1024, 64, 9, 1.5, ogrid.DIRICHLET_CENTRE, 9.615e-9, 2),
+]
+H3D_BC = {ogrid.DIRICHLET_CENTRE: "dirichlet_centre", ogrid.DIRICHLET_FACE: "dirichlet_face"}
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,bc,s,seed", H3D_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+@pytest.mark.parametrize("ybc", ["periodic", "walls"])
+@pytest.mark.parametrize("xbc", ["walls", "dirichlet"])
+def test_xwalls_helmholtz3d_matches_oracle(nx, ny, nz, beta, bc, s, seed, prec, ybc, xbc):
+    print(f"helmholtz3d x {xbc} y {ybc} {prec} {nx}x{ny}x{nz} bc={bc} s={s}", flush=True)
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    n = nz if bc == ogrid.DIRICHLET_CENTRE else nz - 1
+    r = synth.normal01(720 + seed, (n, ny, nx))
+    ref = op.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=YBC[ybc], xbc=XBC[xbc])
+    plan = pf.helmholtz3d_plan(nx, ny, nz, H3D_BC[bc], s, LX, LY, 2.0, beta, zf=zf, precision=prec,
+                               ybc=ybc, xbc=xbc)
+    rt = torch.from_numpy(r).to(_dev())
+    u = torch.empty_like(rt)
+    pf.helmholtz3d_solve(plan, rt, u)
+    torch.cuda.synchronize()
+    check(u.cpu().numpy(), ref, TOL[prec], prec)
+
+
+@pytest.mark.parametrize("xbc", ["walls", "dirichlet"])
+def test_xwalls_residual_at_512x256x64(xbc):
+    nx, ny, nz, beta = 512, 256, 64, 1.5
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    f = synth.uniform_pm1(730, (nz, ny, nx))
+    p64 = _solve_gpu(f, zf, beta, "fp64", xbc, "periodic")
+    r = op.residual7(p64, f, zf, LX, LY, xbc=XBC[xbc])
+    res = np.max(np.abs(r)) / np.max(np.abs(f))
+    print(f"fp64 7-point residual {res:.2e}", flush=True)
+    assert res < 1e-12
+    p32 = _solve_gpu(f, zf, beta, "fp32_refine", xbc, "periodic")
+    check(p32, p64, 1e-10, "fp32_refine vs fp64")
+
+
+@pytest.mark.parametrize("xbc", ["walls", "dirichlet"])
+def test_xwalls_graph_replays_equal_eager(xbc):
+    nx, ny, nz = 128, 96, 40
+    stream = torch.cuda.Stream(device=_dev())
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine",
+                           stream=stream, xbc=xbc)
+    rhs = torch.from_numpy(synth.uniform_pm1(740, (nz, ny, nx))).to(_dev())
+    pe = torch.empty_like(rhs)
+    p = torch.empty_like(rhs)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        pf.poisson_solve(plan, rhs, pe)
+    stream.synchronize()
+    pf.pf_graph_begin(stream)
+    pf.poisson_solve(plan, rhs, p)
+    g = pf.pf_graph_end(stream)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            p.fill_(-1.0)
+        g.launch(stream)
+        stream.synchronize()
+        assert torch.equal(p, pe), rep
+
+
+def test_projection_rejects_x_walls():
+    nx, ny, nz = 64, 64, 16
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, xbc="walls")
+    t = [torch.zeros((nz if i != 2 else nz - 1, ny, nx), dtype=torch.float64, device=_dev())
+         for i in range(5)]
+    with pytest.raises(N.PfError) as e:
+        pf.poisson_project(plan, t[0], t[1], t[2], t[3], t[4], 0.1, 0.0)
+    assert e.value.code == N.PF_ERR_UNSUPPORTED
