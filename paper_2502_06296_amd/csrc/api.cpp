@@ -400,7 +400,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   int zc = pf::zsolve_default_variant(g->nx, nzu, precision == PF_FP64);
   if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
     const int v = std::atoi(ev);
-    if (pf::zsolve_variant_fits(v, g->nx, nzu)) zc = v;
+    if (pf::zsolve_variant_fits(v, g->nx, nzu, precision == PF_FP64 ? 8 : 4)) zc = v;
   }
   if (zc < 0) return fail(PF_ERR_UNSUPPORTED, "no z-solve shape fits nx=%d nz=%d", g->nx, nzu);
   auto *pl = new pf_poisson_plan();
@@ -856,7 +856,7 @@ pf_status poisson_variant_count(pf_poisson_plan *pl, int32_t stage, int32_t *cou
 pf_status poisson_set_variant(pf_poisson_plan *pl, int32_t stage, int32_t variant) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
   if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
-  if (!pf::zsolve_variant_fits(variant, pl->nx, pl->nz))
+  if (!pf::zsolve_variant_fits(variant, pl->nx, pl->nz, pl->prec == PF_FP64 ? 8 : 4))
     return fail(PF_ERR_UNSUPPORTED, "z-solve variant %d does not fit nx=%d nz=%d", variant, pl->nx, pl->nz);
   pl->zchunk = variant;
   return PF_OK;

@@ -16,6 +16,9 @@
 // ever formed by subtraction.
 #include "pf_internal.hpp"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace pf {
 
 // ------------------------------------------------------- Poisson z solve
@@ -389,15 +392,29 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
 //   SA = fa, SG = t ug', SE = fe + t ue', SD = D + t U', t = gamma / C',
 // with (fa, fe, D) from the downward sweep and (ug', ue', U', C') the next
 // chunk's reduced first row.
-template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512>
+//
+// TILE: the workgroup's R*2*TP columns (128 bytes of every row) are staged
+// through LDS: the whole column tile is read row by row with 16-byte loads
+// (whole 128-byte lines, instead of 2*TP*sizeof(TS) bytes per row and
+// thread group), every thread takes its rows from LDS, and the results go
+// back the same way, after the last round. The threads take the tile's
+// columns in R rounds of 2*TP; each round's columns are a region of their
+// own, [P*M rows][2*TP], whose first bytes the reduced-row arrays share
+// once every thread holds its rows. Only single-pass workgroups tile; the
+// two-pass ones (the pair of slots 0 and 1, x walls) read and write their
+// columns directly.
+template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1>
 __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
                                                       const double *sy, size_t sp, int xr) {
   static_assert(M >= 3, "a chunk needs interior rows");
+  static_assert(TILE || R == 1, "rounds need the tile");
   using V = cplx<TS>;
   using D2 = cplx<double>;
   // LDS: the z tables as in k_zsolve2, then three double2 arrays [P][TP]
+  // (TILE: then R tile regions, the first bytes of the current one shared
+  // with the three arrays)
   extern __shared__ double red[];
   D2 *tag = reinterpret_cast<D2 *>(red);
   double *tex = reinterpret_cast<double *>(tag + P * M);
@@ -406,16 +423,23 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
     tag[o] = mkc<double>(zal[e], zga[e]);
     tex[o] = zex[e];
   }
-  D2 *X1 = reinterpret_cast<D2 *>(tex + P * M);
+  constexpr int TC = 2 * TP;  // columns of one round
+  // one tile region: P*M rows of TC values, at least the three arrays
+  const size_t region = ((size_t)P * M * TC * sizeof(TS) > (size_t)3 * P * TP * sizeof(D2)
+                             ? (size_t)P * M * TC * sizeof(TS)
+                             : (size_t)3 * P * TP * sizeof(D2)) / sizeof(double);
+  double *const reg0 = tex + P * M;
+  D2 *X1 = reinterpret_cast<D2 *>(reg0);
   D2 *X2 = X1 + P * TP;
   D2 *X3 = X2 + P * TP;
-  const int nib = nx / (2 * TP);
+  TS *tile = reinterpret_cast<TS *>(reg0);
+  const int nib = nx / (R * TC);
   const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
   const int ib = blk % nib;
   const int j = blk / nib;
   const int pc = threadIdx.x % TP;
   const int ch = threadIdx.x / TP;
-  const int i = 2 * (ib * TP + pc);
+  int i = 2 * (ib * R * TP + pc);
   const int r0 = ch * M;
   const size_t plane = sp;
   V *cp = reinterpret_cast<V *>(data + (size_t)j * nx + i + (size_t)r0 * plane);
@@ -428,8 +452,32 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
   const int me = ch * TP + pc;
   const int nch = ch + 1 < P ? ch + 1 : ch;  // the last chunk's gamma is 0
   const int nb = nch * TP + pc;
-  __syncthreads();
   const int npass = ib == 0 || xr ? 2 : 1;  // uniform per workgroup
+  // 16-byte vectors of a round's row segment and of a tile row, and the
+  // tile's first row in global memory
+  constexpr int EPV = 16 / (int)sizeof(TS);
+  constexpr int VPR = TC / EPV;
+  static_assert(!TILE || TC % EPV == 0, "tile rows are whole 16-byte vectors");
+  TS *const gt = data + (size_t)j * nx + (size_t)ib * R * TC;
+  const bool tiled = TILE && npass == 1;
+  auto tile_io = [&](bool load) {
+    for (int e = threadIdx.x; e < nz * R * VPR; e += blockDim.x) {
+      const int r = e / (R * VPR), c = e % (R * VPR);
+      uint4 *l = reinterpret_cast<uint4 *>(reinterpret_cast<TS *>(reg0 + (c / VPR) * region) + r * TC +
+                                           (c % VPR) * EPV);
+      uint4 *g = reinterpret_cast<uint4 *>(gt + (size_t)r * plane + c * EPV);
+      if (load)
+        *l = *g;
+      else
+        *g = *l;
+    }
+  };
+  if (tiled) tile_io(true);
+  __syncthreads();
+  // the tiled and the direct path as separate instances of the pass loop,
+  // so that neither keeps the other's addresses live
+  auto passes = [&](auto tl) {
+  constexpr bool TL = decltype(tl)::value;
   for (int pass = 0; pass < npass; ++pass) {
     // as in k_zsolve2: pass 1 only for column 1 of the pair of slots 0, 1,
     // or (xr) for column 1 of every pair
@@ -444,14 +492,17 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
     double d0[M], d1[M], ib_[M];
     // the 1024-thread shapes have half the registers: compiler fences keep
     // their unrolled sweeps from issuing every read up front
-    constexpr bool kFence = MAXT > 512;
+    constexpr bool kFence = MAXT > 512 || M >= 32;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       V v = V{};
-      if (r0 + q < nz) v = cp[(size_t)q * vplane];
+      if (r0 + q < nz)
+        v = TL ? *reinterpret_cast<const V *>(tile + (r0 + q) * TC + 2 * pc) : cp[(size_t)q * vplane];
       d0[q] = -(double)v.x;
       d1[q] = -(double)v.y;
     }
+    // every thread holds its rows before the reduced-row arrays reuse the tile
+    if constexpr (TL) __syncthreads();
     // upward sweep over the interior: the chunk's first row in terms of the
     // previous separator (alpha_0) and the own separator (ug)
     {
@@ -532,7 +583,16 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
       d1[q] = d1[q] + c * d1[q + 1];
       if constexpr (kFence) sched_fence(q);
     }
-    if (st0 || st1) {
+    if constexpr (TL) {
+      // single pass: both columns, into the round's region (its reduced-row
+      // arrays are read by now); the tile goes out after the last round
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (r0 + q < nz)
+          *reinterpret_cast<V *>(tile + (r0 + q) * TC + 2 * pc) = V{(TS)d0[q], (TS)d1[q]};
+      __syncthreads();
+    } else if (st0 || st1) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         if (r0 + q < nz) {
@@ -548,6 +608,24 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
       }
     }
   }
+  };
+  for (int rd = 0; rd < R; ++rd) {
+    if (rd > 0) {
+      // the next round: its columns, its tile region (which the three
+      // arrays share now)
+      i += 2 * TP;
+      cp += TP;
+      X1 = reinterpret_cast<D2 *>(reg0 + rd * region);
+      X2 = X1 + P * TP;
+      X3 = X2 + P * TP;
+      tile = reinterpret_cast<TS *>(reg0 + rd * region);
+    }
+    if (tiled)
+      passes(std::true_type{});
+    else
+      passes(std::false_type{});
+  }
+  if (tiled) tile_io(false);
 }
 
 // Launch shapes of the z solve: rows per thread M, columns per workgroup
@@ -563,6 +641,8 @@ struct ZVariant {
   bool skew = true;  // paired: gaps between reduced row pairs in LDS
   bool sep = false;  // paired: separator form, P reduced rows
   int maxt = 512;    // threads per workgroup at most
+  bool tile = false; // separator form with the column tile staged through LDS
+  int rounds = 1;    // tiled: the threads take the TI columns in rounds of TI/rounds
 };
 static const ZVariant kZVariants[] = {
     {16, 16, 0, false, false, 2}, {16, 16, 4, true, false, 2}, {16, 16, 0, true, false, 2},
@@ -581,53 +661,72 @@ static const ZVariant kZVariants[] = {
     // separator form in 1024-thread workgroups: wider rows for the long
     // columns (8 rows per thread; 16 spilled)
     {8, 32, 1, true, true, 1, false, true, 1024}, {8, 16, 1, true, true, 1, false, true, 1024},
+    // separator form with 128-byte row tiles through LDS (32 float32 or 16
+    // float64 columns), the 32 float32 columns of 1024-row tiles in two
+    // rounds of 16: one workgroup per compute unit at 1024 rows
+    {8, 32, 1, true, true, 1, false, true, 1024, true, 2},  {16, 32, 1, true, true, 1, false, true, 512, true, 2},
+    {8, 16, 1, true, true, 1, false, true, 1024, true, 1},  {16, 16, 1, true, true, 1, false, true, 512, true, 1},
+    {16, 32, 1, true, true, 1, false, true, 512, true, 1},  {8, 32, 1, true, true, 1, false, true, 1024, true, 1},
+    {8, 16, 1, true, true, 1, false, true, 512, true, 1},   {8, 32, 1, true, true, 1, false, true, 512, true, 2},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
 int zsolve_variant_count() { return kZVariantCount; }
 
 // LDS bytes of a launch: paired variants hold the column's z tables and
-// three double2 arrays of the reduced rows, unpaired ones four double arrays.
-static size_t zsolve_lds(const ZVariant &z, int P) {
+// three double2 arrays of the reduced rows, unpaired ones four double arrays;
+// tiled ones the tables and the larger of the reduced-row arrays and the
+// column tile (elements of esize bytes).
+static size_t zsolve_lds(const ZVariant &z, int P, int esize) {
   const int tp = z.TI / 2;
   const size_t tables = (size_t)3 * P * z.M * sizeof(double);
+  if (z.tile) {
+    const int tpr = tp / z.rounds;  // thread pairs of a round
+    return tables + z.rounds * std::max((size_t)3 * P * tpr * 2 * sizeof(double),
+                                        (size_t)P * z.M * 2 * tpr * esize);
+  }
   if (z.paired && z.sep) return tables + (size_t)3 * P * tp * 2 * sizeof(double);
   return z.paired ? (size_t)3 * P * (2 * tp + zskew(tp, z.skew)) * 2 * sizeof(double) + tables
                   : (size_t)4 * 2 * P * z.TI * sizeof(double);
 }
 
-bool zsolve_variant_fits(int v, int nx, int nz) {
+bool zsolve_variant_fits(int v, int nx, int nz, int esize) {
   if (v < 0 || v >= kZVariantCount) return false;
   const ZVariant &z = kZVariants[v];
   const int P = (nz + z.M - 1) / z.M;
-  const int threads = z.paired ? P * z.TI / 2 : P * z.TI;
+  const int threads = z.paired ? P * z.TI / 2 / z.rounds : P * z.TI;
+  // a tiled launch needs whole 16-byte vectors per round's row segment and
+  // at least two chunks
+  if (z.tile && (z.TI / z.rounds * esize % 16 != 0 || P < 2)) return false;
   return threads <= z.maxt && nx % z.TI == 0 && P * z.M <= (nz + 15) / 16 * 16 &&
-         zsolve_lds(z, P) <= (z.maxt > 512 ? 160 * 1024 : 65536);
+         zsolve_lds(z, P, esize) <= (z.maxt > 512 || z.tile ? 160 * 1024 : 65536);
 }
 
 int zsolve_default_variant(int nx, int nz, bool fp64) {
-  // fastest measured on MI355X at 1024x512x512: float64 storage 21 (1.05 ms:
-  // separator form, 16 rows, 32 columns), 10 (1.12); float32 storage (padded
-  // planes) 18 (0.86 ms: separator form, 8 rows, 8 columns), 19 (0.87), 16
-  // (0.95); the unpaired 4 and 3 as fall-backs where the LDS or thread
-  // budget excludes the paired shapes; at 1024 rows (where only 4, 18 and
-  // 20 fit) float64 storage takes 20 (11.4 ms at 2048x1024x1024 against
-  // 22.2 ms for 4). Short columns (few chunks) would leave those shapes with
-  // tiny workgroups, so the first fitting shape with at least 128 threads
-  // wins, widened by the 64- and 128-column shapes.
+  // fastest measured on MI355X at 1024x512x512: float64 storage 21 (1.06 ms:
+  // separator form, 16 rows, 32 columns), 10 (1.11); float32 storage (padded
+  // planes) 35 (0.71 ms: separator form, 8 rows, 16-column tiles through
+  // LDS), 31 (0.72), 18 (0.84: 8 rows, 8 columns, direct); the unpaired 4
+  // and 3 as fall-backs where the LDS or thread budget excludes the paired
+  // shapes. At 1024 rows float64 storage takes 20 (11.5 ms at
+  // 2048x1024x1024; 28 11.3, the tiled 31 12.8, 4 22.2) and float32 storage
+  // the tiled 29 (8.2 ms: 32-column tiles in two rounds; 18 8.9). Short
+  // columns (few chunks) would leave those shapes with tiny workgroups, so
+  // the first fitting shape with at least 128 threads wins, widened by the
+  // 64- and 128-column shapes.
   static const int f64[] = {21, 10, 19, 26, 25, 24, 23, 20, 8, 4, 3},
-                   f32[] = {18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
+                   f32[] = {35, 29, 31, 18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
   const int *list = fp64 ? f64 : f32;
   const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
   auto threads = [&](int v) {
     const ZVariant &z = kZVariants[v];
     const int P = (nz + z.M - 1) / z.M;
-    return z.paired ? P * z.TI / 2 : P * z.TI;
+    return z.paired ? P * z.TI / 2 / z.rounds : P * z.TI;
   };
   for (int k = 0; k < len; ++k)
-    if (zsolve_variant_fits(list[k], nx, nz) && threads(list[k]) >= 128) return list[k];
+    if (zsolve_variant_fits(list[k], nx, nz, fp64 ? 8 : 4) && threads(list[k]) >= 128) return list[k];
   for (int k = 0; k < len; ++k)
-    if (zsolve_variant_fits(list[k], nx, nz)) return list[k];
+    if (zsolve_variant_fits(list[k], nx, nz, fp64 ? 8 : 4)) return list[k];
   return -1;
 }
 
@@ -636,11 +735,11 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
                          const double *zga, const double *zex, const double *sx, const double *sy,
                          int variant, hipStream_t st, bool xr) {
   // the z tables hold whole 16-row chunks (identity padding past nz)
-  if (!zsolve_variant_fits(variant, nx, nz)) return hipErrorInvalidValue;
+  if (!zsolve_variant_fits(variant, nx, nz, (int)sizeof(TS))) return hipErrorInvalidValue;
   const ZVariant &z = kZVariants[variant];
   const int P = (nz + z.M - 1) / z.M;
-  const size_t shm = zsolve_lds(z, P);
-  dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(z.paired ? P * z.TI / 2 : P * z.TI);
+  const size_t shm = zsolve_lds(z, P, (int)sizeof(TS));
+  dim3 g((unsigned)((long)(nx / z.TI) * ny)), b(z.paired ? P * z.TI / 2 / z.rounds : P * z.TI);
 #define PF_ZV(ID, M_, TI_, W_, F_)                                                                \
   case ID:                                                                                        \
     hipLaunchKernelGGL((k_zsolve<TS, M_, TI_, W_, F_>), g, b, shm, st, data, nx, ny, nz, P, zal, \
@@ -691,6 +790,20 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
     break;
     PF_ZW(27, 8, 32)
     PF_ZW(28, 8, 16)
+#define PF_ZT(ID, M_, TI_, MAXT_, R_)                                                            \
+  case ID:                                                                                       \
+    hipLaunchKernelGGL((k_zsolve3<TS, M_, TI_ / 2 / R_, 1, 1, MAXT_, true, R_>), g, b, shm, st,   \
+                       data, nx, ny, nz, P, zal, zga, zex, sx, sy, sp, (int)xr);                 \
+    break;
+    PF_ZT(29, 8, 32, 1024, 2)
+    PF_ZT(30, 16, 32, 512, 2)
+    PF_ZT(31, 8, 16, 1024, 1)
+    PF_ZT(32, 16, 16, 512, 1)
+    PF_ZT(33, 16, 32, 512, 1)
+    PF_ZT(34, 8, 32, 1024, 1)
+    PF_ZT(35, 8, 16, 512, 1)
+    PF_ZT(36, 8, 32, 512, 2)
+#undef PF_ZT
 #undef PF_ZW
 #undef PF_ZS
 #undef PF_ZP
@@ -1558,19 +1671,34 @@ hipError_t launch_shift_add(const double *src, double *dst, int n, double kappa,
 }
 
 // ------------------------------------------------------------ plain copy
-__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+// The fastest copy measured on MI355X (4 GiB: 5.6 TB/s, against 4.9 TB/s for
+// one 16-byte element per thread and grid stride): four 16-byte nontemporal
+// loads in flight per thread over a 16 KiB block tile, 16384 workgroups
+// striding over the tiles, then the tail one element per thread.
+typedef unsigned int pf_v4u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const pf_v4u *__restrict__ src, pf_v4u *__restrict__ dst,
                                               size_t n) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+  constexpr int U = 4;
+  constexpr size_t kTile = (size_t)256 * U;
+  const size_t full = n / kTile * kTile;
+  for (size_t b = (size_t)blockIdx.x * kTile; b < full; b += (size_t)gridDim.x * kTile) {
+    pf_v4u v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + b + u * 256 + threadIdx.x);
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], dst + b + u * 256 + threadIdx.x);
+  }
+  for (size_t i = full + (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     dst[i] = src[i];
 }
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 16;
-  size_t blocks = (n + 255) / 256;
+  size_t blocks = (n + 1023) / 1024;
   if (blocks > 16384) blocks = 16384;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4 *)src,
-                     (uint4 *)dst, n);
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const pf_v4u *)src,
+                     (pf_v4u *)dst, n);
   return hipGetLastError();
 }
 

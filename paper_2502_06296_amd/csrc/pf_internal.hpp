@@ -187,7 +187,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
                          const double *zga, const double *zex, const double *sx, const double *sy,
                          int variant, hipStream_t st, bool xr = false);
 int zsolve_variant_count();
-bool zsolve_variant_fits(int variant, int nx, int nz);
+bool zsolve_variant_fits(int variant, int nx, int nz, int esize);  // esize: bytes per stored value
 int zsolve_default_variant(int nx, int nz, bool fp64);
 // Singular (0,0) mode: plane means fbar[nz] of the right-hand side from its
 // line sums, projection, pinned Neumann solve for the plane-mean profile

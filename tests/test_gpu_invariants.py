@@ -64,3 +64,16 @@ def test_translation_invariance_and_linearity(prec):
     pg = solve(g)
     comb = solve(0.75 * f - 2.5 * g)
     assert op.rel_l2(comb, 0.75 * pf_ - 2.5 * pg) < TOL[prec]
+
+
+@pytest.mark.parametrize("nbytes", [16, 16 * 1023, 16 * 1024, 16 * 1024 * 37 + 16 * 5, (64 << 20) + 48])
+def test_calibration_copy_copies_every_byte(nbytes):
+    """The byte-counter calibration copy: whole 16 KiB tiles plus a ragged
+    tail, every byte copied and nothing past the end written."""
+    g = torch.Generator(device="cpu").manual_seed(nbytes % 1000)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).to(_dev())
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device=_dev())
+    pf.pf_copy_kernel(dst[:nbytes], src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert torch.all(dst[nbytes:] == 0)
