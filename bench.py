@@ -392,6 +392,7 @@ def uneven_batch(args):
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows = []
     for lanes in (1, 2, 4, 8):
+        log(f"bench: uneven batch, task batch on {lanes} lanes")
         for _ in range(args.warmup):
             pf.run_batched(tasks, lanes=lanes, stream=stream)
         stream.synchronize()
@@ -414,9 +415,55 @@ def uneven_batch(args):
         gms = a.elapsed_time(b) / args.steps
         rows.append({"lanes": lanes, "ms": round(ms, 3), "graph_ms": round(gms, 3),
                      "gpoints_per_s": round(pts / ms / 1e6, 2), "graph_gpoints_per_s": round(pts / gms / 1e6, 2)})
+    # grouped launches on the caller's stream: the 48 Helmholtz fields in
+    # launches of up to 16 fields of one chunk height (pcr_apply_batched),
+    # then the 16 Poisson solves stage by stage, one launch per transform
+    # length, z-solve shape and chunk count (poisson_solve_batched)
+    from paper_2502_06296_amd import autotune
+    log("bench: uneven batch, grouped launches")
+    by_m = {}
+    for tk in tasks:
+        for pl, fl in zip(tk["pcr"], tk["fields"]):
+            by_m.setdefault(autotune.pcr_shape(pl)[0], []).append((pl, fl))
+    hgroups = []
+    for items in by_m.values():
+        for k in range(0, len(items), 16):
+            hgroups.append(([pl for pl, _ in items[k:k + 16]], [fl for _, fl in items[k:k + 16]]))
+    pplans = [tk["poisson"] for tk in tasks]
+    prhs = [tk["rhs"] for tk in tasks]
+    pout = [tk["p"] for tk in tasks]
+
+    def grouped():
+        with torch.cuda.stream(stream):
+            for pls, fls in hgroups:
+                pf.pcr_apply_batched(pls, fls)
+            pf.poisson_solve_batched(pplans, prhs, pout)
+
+    for _ in range(args.warmup):
+        grouped()
+    stream.synchronize()
+    a.record(stream)
+    for _ in range(args.steps):
+        grouped()
+    b.record(stream)
+    stream.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    pf.pf_graph_begin(stream)
+    grouped()
+    gr = pf.pf_graph_end(stream)
+    gr.launch(stream)
+    stream.synchronize()
+    a.record(stream)
+    for _ in range(args.steps):
+        gr.launch(stream)
+    b.record(stream)
+    stream.synchronize()
+    gms = a.elapsed_time(b) / args.steps
+    grow = {"helmholtz_launches": len(hgroups), "ms": round(ms, 3), "graph_ms": round(gms, 3),
+            "gpoints_per_s": round(pts / ms / 1e6, 2), "graph_gpoints_per_s": round(pts / gms / 1e6, 2)}
     print(json.dumps({"workload": f"16 uneven problems ({pts} points): Poisson + 3 Helmholtz each, FP32+refine",
                       "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                      "by_lanes": rows}), flush=True)
+                      "by_lanes": rows, "grouped_one_stream": grow}), flush=True)
 
 
 SHARES = {

@@ -196,8 +196,20 @@ pf_status poisson_set_status(pf_poisson_plan *plan, void *dev_status, double tol
  * the workspace; the workspace rules of poisson_solve apply. */
 pf_status poisson_project(pf_poisson_plan *plan, double *u, double *v, double *w, double *p,
                           double *phi, double gdt, double c);
-/* The same solve for several plans, launched back to back on the first
- * plan's stream. */
+/* The same solve for several independent problems on the first plan's
+ * stream (the batches of uneven problems of the paper's use, Sec. 3: one
+ * pressure solve or 3-D Helmholtz per grid). Plans in float32 with one
+ * float64-residual correction (PF_FP32_REFINE), periodic in x and y, whose
+ * z solve takes a separator-form shape (the default for every supported
+ * size), run grouped: each stage of all of them is one launch per kernel
+ * instance (one per transform length; per z-solve shape and chunk count),
+ * at most 16 problems a launch; the other plans run one after another
+ * afterwards. Results equal poisson_solve's bitwise. Stage timing, when
+ * enabled on the first grouped plan, records the grouped launches there.
+ * PF_ERR_ARG: a plan given twice, an output overlapping another entry's
+ * input or output, overlapping workspaces; the per-solve checks of
+ * poisson_solve apply to each entry; all checks run before anything is
+ * enqueued. */
 pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans,
                                 const double *const *rhs, double *const *p);
 pf_status poisson_set_stream(pf_poisson_plan *plan, void *stream);
@@ -269,8 +281,9 @@ pf_status pcr_update_coef(pf_pcr_plan *plan, double s);
 /* In place, every column of a device (n, ny, nx) field; float64 or float32
  * per the plan's precision. nx must be a multiple of 64. */
 pf_status pcr_apply(pf_pcr_plan *plan, void *field, int32_t nx, int32_t ny);
-/* Several fields (for example the three velocity components) in one
- * launch; all plans must share precision and stream. */
+/* Several fields (1..16: for example the three velocity components, or
+ * those of several independent problems) in one launch; all plans must
+ * share precision, chunk rows and stream. */
 pf_status pcr_apply_batched(int32_t count, pf_pcr_plan *const *plans, void *const *fields,
                             const int32_t *nx, const int32_t *ny);
 pf_status pcr_set_stream(pf_pcr_plan *plan, void *stream);

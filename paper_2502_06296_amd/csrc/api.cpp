@@ -824,15 +824,219 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
   });
 }
 
+}  // extern "C"
+
+// Grouped batch: the plans that can share launches (float32 with one
+// float64-residual correction, periodic x and y, a separator-form z solve)
+// run stage by stage; each stage of all plans with the same kernel instance
+// (transform length; z-solve shape and chunk count) is one launch of up to
+// kMaxGroupJobs jobs. The per-plan zero-mode and status kernels run between.
+namespace {
+struct GroupKey {
+  int a, b;
+  bool operator==(const GroupKey &o) const { return a == o.a && b == o.b; }
+};
+// launches fn(key, jobs) for every group of the plans' jobs, in first-seen
+// key order, splitting groups larger than kMaxGroupJobs
+template <typename KeyFn, typename JobFn, typename LaunchFn>
+hipError_t run_groups(const std::vector<int> &ids, KeyFn key, JobFn job, LaunchFn launch) {
+  std::vector<GroupKey> keys;
+  for (int t : ids) {
+    const GroupKey k = key(t);
+    bool seen = false;
+    for (const GroupKey &q : keys) seen = seen || q == k;
+    if (!seen) keys.push_back(k);
+  }
+  for (const GroupKey &k : keys) {
+    pf::GJobs g{};
+    for (int t : ids) {
+      if (!(key(t) == k)) continue;
+      g.j[g.count++] = job(t);
+      if (g.count == pf::kMaxGroupJobs) {
+        const hipError_t e = launch(k, g);
+        if (e != hipSuccess) return e;
+        g = pf::GJobs{};
+      }
+    }
+    if (g.count) {
+      const hipError_t e = launch(k, g);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+static bool poisson_groupable(const pf_poisson_plan *pl) {
+  return pl->prec == PF_FP32_REFINE && pl->ybc == PF_Y_PERIODIC && pl->xbc == PF_X_PERIODIC &&
+         pf::zsolve_variant_groups(pl->zchunk);
+}
+
+#define STAGE(id, expr)                                      \
+  if ((s = run_stage(tm, st, id, [&]() { return (expr); }))) \
+    return s;
+static pf_status poisson_enqueue_grouped(pf_poisson_plan *const *plans, const double *const *rhs,
+                                         double *const *p, const std::vector<int> &ids, hipStream_t st) {
+  Timing &tm = plans[ids[0]]->tm;
+  pf_status s;
+  auto helm = [&](int t) { return plans[t]->bc != PF_BC_NEUMANN; };
+  // the fields of job t: its tables and its two float32 work arrays
+  auto base = [&](int t) {
+    const pf_poisson_plan *pl = plans[t];
+    const DevArena &A = pl->ar;
+    pf::GJob J{};
+    J.tw = A.at<double2>(pl->o_twx_d);
+    J.zal = A.at<double>(pl->o_zal);
+    J.zga = A.at<double>(pl->o_zga);
+    J.zex = A.at<double>(pl->o_zex);
+    J.sx = A.at<double>(pl->o_sx);
+    J.sy = A.at<double>(pl->o_sy);
+    J.sp = pl->sp32();
+    J.nx = pl->nx;
+    J.ny = pl->ny;
+    J.nz = pl->nz;
+    return J;
+  };
+  auto W0 = [&](int t) { return (float *)plans[t]->ws; };
+  auto W1 = [&](int t) { return (float *)plans[t]->ws + plans[t]->sp32() * (size_t)plans[t]->nz; };
+  auto kx = [&](int t) { return GroupKey{plans[t]->nx, 0}; };
+  auto ky = [&](int t) { return GroupKey{plans[t]->ny, 0}; };
+  auto kz = [&](int t) {
+    const pf_poisson_plan *pl = plans[t];
+    return GroupKey{pl->zchunk, pl->nz};
+  };
+  for (int t : ids)
+    if (plans[t]->stat) PF_HIP(pf::launch_status_reset(plans[t]->stat, st));
+  // x forward of f into W0, with the float64 line sums
+  STAGE(PF_STAGE_XFWD, run_groups(ids, kx, [&](int t) {
+          pf::GJob J = base(t);
+          J.in = rhs[t];
+          J.out = W0(t);
+          J.sums = plans[t]->ar.at<double>(plans[t]->o_sums);
+          return J;
+        }, [&](GroupKey k, pf::GJobs &g) { return pf::launch_xfwd_grp(k.a, g, st); }));
+  // the zero modes of the Poisson plans (the 3-D Helmholtz has none)
+  std::vector<int> pois;
+  for (int t : ids)
+    if (!helm(t)) pois.push_back(t);
+  auto kone = [&](int) { return GroupKey{0, 0}; };
+  if (!pois.empty())
+    STAGE(PF_STAGE_ZERO_MODE, run_groups(pois, kone, [&](int t) {
+            pf::GJob J = base(t);
+            const pf_poisson_plan *pl = plans[t];
+            J.sums = pl->ar.at<double>(pl->o_sums);
+            J.out = pl->ar.at<double>(pl->o_fbar);
+            J.in2 = pl->ar.at<double>(pl->o_m);
+            J.aux = pl->ar.at<double>(pl->o_dzf);
+            return J;
+          }, [&](GroupKey, pf::GJobs &g) { return pf::launch_zero_mode_grp(g, st); }));
+  // y forward, z solve, y inverse of one work array
+  auto yzy = [&](bool second) -> pf_status {
+    auto wj = [&](int t) {
+      pf::GJob J = base(t);
+      J.tw = plans[t]->ar.at<double2>(plans[t]->o_twy_d);
+      J.out = second ? W1(t) : W0(t);
+      return J;
+    };
+    auto zj = [&](int t) {
+      pf::GJob J = base(t);
+      J.out = second ? W1(t) : W0(t);
+      J.P = pf::zsolve_chunks(plans[t]->zchunk, plans[t]->nz);
+      return J;
+    };
+    pf_status s2;
+    if ((s2 = run_stage(tm, st, PF_STAGE_YFWD, [&]() {
+           return run_groups(ids, ky, wj, [&](GroupKey k, pf::GJobs &g) { return pf::launch_yfwd_grp(k.a, g, st); });
+         })))
+      return s2;
+    if ((s2 = run_stage(tm, st, PF_STAGE_ZSOLVE, [&]() {
+           return run_groups(ids, kz, zj, [&](GroupKey k, pf::GJobs &g) { return pf::launch_zsolve_grp(k.a, g, st); });
+         })))
+      return s2;
+    return run_stage(tm, st, PF_STAGE_YINV, [&]() {
+      return run_groups(ids, ky, wj, [&](GroupKey k, pf::GJobs &g) { return pf::launch_yinv_grp(k.a, g, st); });
+    });
+  };
+  if ((s = yzy(false))) return s;
+  // the float64 residual of the iterate W0 into W1
+  STAGE(PF_STAGE_XFWD_RESID, run_groups(ids, kx, [&](int t) {
+          pf::GJob J = base(t);
+          const pf_poisson_plan *pl = plans[t];
+          J.in = rhs[t];
+          J.in2 = W0(t);
+          J.out = W1(t);
+          J.zm = pl->ar.at<double>(pl->o_fbar);
+          J.sums = pl->ar.at<double>(pl->o_sump);
+          J.idy2 = (double)pl->ny * pl->ny / (pl->ly * pl->ly);
+          return J;
+        }, [&](GroupKey k, pf::GJobs &g) { return pf::launch_resid_grp(k.a, g, st); }));
+  if (!pois.empty())
+    STAGE(PF_STAGE_ZERO_MODE, run_groups(pois, kone, [&](int t) {
+            pf::GJob J = base(t);
+            const pf_poisson_plan *pl = plans[t];
+            J.sums = pl->ar.at<double>(pl->o_sump);
+            J.out = pl->ar.at<double>(pl->o_p0m);
+            J.in2 = pl->ar.at<double>(pl->o_m);
+            J.zm = pl->ar.at<double>(pl->o_zm);
+            return J;
+          }, [&](GroupKey, pf::GJobs &g) { return pf::launch_zero_shift_grp(g, st); }));
+  if ((s = yzy(true))) return s;
+  // one x inverse of W0 + W1 with the zero-mode profile
+  STAGE(PF_STAGE_XINV_FINAL, run_groups(ids, kx, [&](int t) {
+          pf::GJob J = base(t);
+          const pf_poisson_plan *pl = plans[t];
+          const double scale = 1.0 / ((double)pl->nx * pl->ny);
+          J.in = W0(t);
+          J.in2 = W1(t);
+          J.out = p[t];
+          J.zm = pl->ar.at<double>(pl->o_zm);
+          J.scale = helm(t) ? -pl->kappa * scale : scale;
+          J.stat = pl->stat;
+          return J;
+        }, [&](GroupKey k, pf::GJobs &g) { return pf::launch_xinv_grp(k.a, g, st); }));
+  for (int t : ids)
+    if (plans[t]->stat) PF_HIP(pf::launch_status_final(plans[t]->stat, plans[t]->stat_tol, true, st));
+  return PF_OK;
+}
+
+#undef STAGE
+
+extern "C" {
+
 pf_status poisson_solve_batched(int32_t count, pf_poisson_plan *const *plans, const double *const *rhs,
                                 double *const *p) {
   if (count < 0 || (count > 0 && (!plans || !rhs || !p))) return fail(PF_ERR_ARG, "bad batch arguments");
   for (int t = 0; t < count; ++t) {
     pf_status s = poisson_check_solve(plans[t], rhs[t], p[t]);
     if (s) return s;
+    for (int u = 0; u < t; ++u)
+      if (plans[u] == plans[t]) return fail(PF_ERR_ARG, "entries %d and %d share a plan", u, t);
+  }
+  if (count == 0) return PF_OK;
+  // the batch runs in one stream: a problem's output may not feed another
+  for (int a = 0; a < count; ++a)
+    for (int b = 0; b < count; ++b) {
+      const size_t na = plans[a]->npts() * sizeof(double), nb = plans[b]->npts() * sizeof(double);
+      if (a != b && overlaps(p[a], na, p[b], nb)) return fail(PF_ERR_ARG, "outputs %d and %d overlap", a, b);
+      if (a != b && overlaps(p[a], na, rhs[b], nb)) return fail(PF_ERR_ARG, "output %d overlaps input %d", a, b);
+      if (a != b && plans[a]->ws_need && plans[b]->ws_need &&
+          overlaps(plans[a]->ws, plans[a]->ws_need, plans[b]->ws, plans[b]->ws_need))
+        return fail(PF_ERR_ARG, "workspaces %d and %d overlap", a, b);
+      if (a != b && plans[a]->ws_need &&
+          (overlaps(plans[a]->ws, plans[a]->ws_need, rhs[b], nb) || overlaps(plans[a]->ws, plans[a]->ws_need, p[b], nb)))
+        return fail(PF_ERR_ARG, "workspace %d overlaps the fields of entry %d", a, b);
+    }
+  const hipStream_t st = plans[0]->st;
+  std::vector<int> grouped;
+  for (int t = 0; t < count; ++t)
+    if (poisson_groupable(plans[t])) grouped.push_back(t);
+  if (!grouped.empty()) {
+    pf_status s = poisson_enqueue_grouped(plans, rhs, p, grouped, st);
+    if (s) return s;
   }
   for (int t = 0; t < count; ++t) {
-    pf_status s = poisson_enqueue(plans[t], rhs[t], p[t], plans[0]->st);
+    if (poisson_groupable(plans[t])) continue;
+    pf_status s = poisson_enqueue(plans[t], rhs[t], p[t], st);
     if (s) return s;
   }
   return PF_OK;
@@ -1093,6 +1297,7 @@ pf_status pcr_timing_read(pf_pcr_plan *pl, double *ms, int32_t *count) {
 // device, created on first use and kept until the process ends.
 namespace {
 constexpr int kMaxLanes = 8;
+constexpr int kMaxTaskComps = 4;  // Helmholtz fields of one pf_task
 struct Lanes {
   bool ready = false;
   hipStream_t s[kMaxLanes] = {};
@@ -1116,11 +1321,14 @@ static pf_status lanes_ready(int dev, Lanes *&L) {
   return PF_OK;
 }
 
-pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, void *stream) {
+// Every task of a batch checked before anything is enqueued: its Poisson
+// solve, its Helmholtz group (filled into groups[t]) and its footprint
+// against every other task's (cost[t]: its points, for the lane balance).
+static pf_status validate_tasks(int32_t count, const pf_task *tasks, std::vector<HelmGroup> &groups,
+                                std::vector<double> &cost) {
   if (count < 0 || (count > 0 && !tasks)) return fail(PF_ERR_ARG, "bad batch arguments");
-  if (lanes < 1 || lanes > kMaxLanes) return fail(PF_ERR_ARG, "lanes must be 1..%d", kMaxLanes);
-  std::vector<HelmGroup> groups((size_t)count);
-  std::vector<double> cost((size_t)count, 0.0);
+  groups.assign((size_t)count, HelmGroup{});
+  cost.assign((size_t)count, 0.0);
   for (int t = 0; t < count; ++t) {
     const pf_task &T = tasks[t];
     if (T.poisson) {
@@ -1128,7 +1336,7 @@ pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, voi
       if (s) return s;
       cost[t] += (double)T.poisson->npts();
     }
-    if (T.ncomp < 0 || T.ncomp > pf::kMaxHelmJobs) return fail(PF_ERR_ARG, "task %d: ncomp must be 0..%d", t, pf::kMaxHelmJobs);
+    if (T.ncomp < 0 || T.ncomp > kMaxTaskComps) return fail(PF_ERR_ARG, "task %d: ncomp must be 0..%d", t, kMaxTaskComps);
     if (!T.poisson && T.ncomp == 0) return fail(PF_ERR_ARG, "task %d is empty", t);
     if (T.ncomp) {
       pf_status s = pcr_group(T.ncomp, T.pcr, T.field, T.nx, T.ny, groups[t]);
@@ -1161,6 +1369,15 @@ pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, voi
       if (rg[a].task != rg[b].task && (rg[a].write || rg[b].write) &&
           overlaps(rg[a].p, rg[a].n, rg[b].p, rg[b].n))
         return fail(PF_ERR_ARG, "tasks %d and %d overlap in device memory", rg[a].task, rg[b].task);
+  return PF_OK;
+}
+
+pf_status pf_run_batched(int32_t count, const pf_task *tasks, int32_t lanes, void *stream) {
+  if (lanes < 1 || lanes > kMaxLanes) return fail(PF_ERR_ARG, "lanes must be 1..%d", kMaxLanes);
+  std::vector<HelmGroup> groups;
+  std::vector<double> cost;
+  pf_status vs = validate_tasks(count, tasks, groups, cost);
+  if (vs) return vs;
   if (count == 0) return PF_OK;
   int dev = 0;
   PF_HIP(hipGetDevice(&dev));

@@ -67,16 +67,17 @@ __device__ __forceinline__ void st2(T *p, double x, double y) {
 // of each line, as in the periodic case.
 __device__ __forceinline__ int xw_src(int n, int N) { return n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n; }
 template <typename T, int N, int TPL, int LPW, bool SUMS, int XW>
-__global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
+__device__ __forceinline__ void xfwd_body(const double *__restrict__ in, T *__restrict__ out,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw,
                                                    double *__restrict__ sums, long ncl, int ny,
-                                                   size_t sp) {
+                                                   size_t sp,
+                                          unsigned bx_, unsigned gx_) {
   using C = cplx<double>;
   __shared__ C lds[LPW * lds_len(N)];
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
-  const long c = (long)blockIdx.x * LPW + l;
+  const long c = (long)bx_ * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
   // the first pass reads the line pair straight from global memory
@@ -129,6 +130,14 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
     *reinterpret_cast<cplx<T> *>(oa + 2 * q) = mkc<T>((T)A.x, (T)A.y);
     *reinterpret_cast<cplx<T> *>(ob + 2 * q) = mkc<T>((T)B.x, (T)B.y);
   }
+}
+template <typename T, int N, int TPL, int LPW, bool SUMS, int XW>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in, T *__restrict__ out,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw,
+                                                   double *__restrict__ sums, long ncl, int ny,
+                                                   size_t sp) {
+  xfwd_body<T, N, TPL, LPW, SUMS, XW>(in, out, tw, ctw, sums, ncl, ny, sp, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------- x forward of the divergence
@@ -351,17 +360,18 @@ hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, 
 // modes of the same line; the x second difference is still -sx[slot], and
 // the cosine's zero mode of a constant f is 2 N f.
 template <int N, int TPL, int LPW, int XW>
-__global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
+__device__ __forceinline__ void resid_spec_body(
     const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
     float *__restrict__ out, const cplx<double> *__restrict__ tw, const cplx<double> *__restrict__ ctw,
     double *__restrict__ sums_p, const double *__restrict__ sx, const double *__restrict__ zal,
     const double *__restrict__ zga, const double *__restrict__ zex, int ny, int nz, double idy2,
-    double inv_ny, int ywalls, size_t sp) {
+    double inv_ny, int ywalls, size_t sp,
+                                                unsigned bx_, unsigned gx_) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned b = xcd_block(bx_, gx_);
   const int k = (int)(b % nz), j = (int)(b / nz) * 2 * LPW + 2 * l;  // lines j, j+1
   C *buf = lds + l * lds_len(N);
   {
@@ -448,6 +458,15 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
     }
   }
 }
+template <int N, int TPL, int LPW, int XW>
+__global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
+    const double *__restrict__ f, const double *__restrict__ fbar, const float *__restrict__ W,
+    float *__restrict__ out, const cplx<double> *__restrict__ tw, const cplx<double> *__restrict__ ctw,
+    double *__restrict__ sums_p, const double *__restrict__ sx, const double *__restrict__ zal,
+    const double *__restrict__ zga, const double *__restrict__ zex, int ny, int nz, double idy2,
+    double inv_ny, int ywalls, size_t sp) {
+  resid_spec_body<N, TPL, LPW, XW>(f, fbar, W, out, tw, ctw, sums_p, sx, zal, zga, zex, ny, nz, idy2, inv_ny, ywalls, sp, blockIdx.x, gridDim.x);
+}
 
 // ------------------------------------------------------------- y forward
 
@@ -467,16 +486,17 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 // cosine or sine transforms, so every slot pair is two real columns and takes
 // the split into packed real y spectra that slots 0 and 1 take otherwise.
 template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
-__global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
+__device__ __forceinline__ void yfwd_body(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
-                                                   int nib, size_t sp) {
+                                                   int nib, size_t sp,
+                                          unsigned bx_, unsigned gx_) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * y_stride(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned blk = xcd_block(bx_, gx_);
   const int ib = blk % nib;
   const long k = blk / nib;
   T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
@@ -542,6 +562,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
     }
   }
 }
+template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
+__global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw, int nx,
+                                                   int nib, size_t sp) {
+  yfwd_body<T, N, TPL, LPW, YW, XR>(data, tw, ctw, nx, nib, sp, blockIdx.x, gridDim.x);
+}
 
 // ------------------------------------------------------------- y inverse
 // Inverse of k_yfwd's layout: complex spectra in natural order for slot
@@ -552,16 +579,17 @@ __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
 // rows negated); the 1/N is left to the x inverse's scale, as for the
 // periodic transform.
 template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
-__global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
+__device__ __forceinline__ void yinv_body(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw, int nx,
-                                                   int nib, size_t sp) {
+                                                   int nib, size_t sp,
+                                          unsigned bx_, unsigned gx_) {
   using C = cplx<double>;
   static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * y_stride(N)];
   constexpr int NT = TPL * LPW;
   const int tid = threadIdx.x;
-  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned blk = xcd_block(bx_, gx_);
   const int ib = blk % nib;
   const long k = blk / nib;
   T *base = data + (size_t)k * sp + (size_t)ib * 2 * LPW;
@@ -633,6 +661,13 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
   __syncthreads();
   fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dst);
 }
+template <typename T, int N, int TPL, int LPW, int YW, bool XR = false>
+__global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw, int nx,
+                                                   int nib, size_t sp) {
+  yinv_body<T, N, TPL, LPW, YW, XR>(data, tw, ctw, nx, nib, sp, blockIdx.x, gridDim.x);
+}
 
 // ------------------------------------------------------------- x inverse
 // in and out may be the same array (each workgroup reads its line pair into
@@ -645,18 +680,19 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
 // from v_n and v_{N-1-n} (sine: mode q read from slot q as the cosine index
 // N-1-q, odd positions negated); the 1/N is in `scale`.
 template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool SUM2, int XW>
-__global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
+__device__ __forceinline__ void xinv_body(const TS *in, TO *out,
                                                    const cplx<double> *__restrict__ tw,
                                                    const cplx<double> *__restrict__ ctw,
                                                    const double *__restrict__ zm,
                                                    const TS *__restrict__ in2, double scale,
                                                    int ny, long ncl, size_t sp,
-                                                   unsigned long long *__restrict__ stat) {
+                                                   unsigned long long *__restrict__ stat,
+                                          unsigned bx_, unsigned gx_) {
   using C = cplx<double>;
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
-  const long c = (long)blockIdx.x * LPW + l;
+  const long c = (long)bx_ * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
   double m0 = 0.0, m1 = 0.0;  // largest |iterate| and |correction| seen (SUM2)
@@ -755,6 +791,60 @@ __global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
     }
   };
   fft_line_io<double, N, TPL, true, false, true>(buf, tw, t, [](int) { return C{}; }, dst);
+}
+template <typename TS, typename TO, int N, int TPL, int LPW, bool ADDZ, bool SUM2, int XW>
+__global__ __launch_bounds__(TPL *LPW) void k_xinv(const TS *in, TO *out,
+                                                   const cplx<double> *__restrict__ tw,
+                                                   const cplx<double> *__restrict__ ctw,
+                                                   const double *__restrict__ zm,
+                                                   const TS *__restrict__ in2, double scale,
+                                                   int ny, long ncl, size_t sp,
+                                                   unsigned long long *__restrict__ stat) {
+  xinv_body<TS, TO, N, TPL, LPW, ADDZ, SUM2, XW>(in, out, tw, ctw, zm, in2, scale, ny, ncl, sp, stat, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------------ grouped kernels
+// One stage of several problems of one transform length per launch (float32
+// storage with one float64-residual correction, periodic x and y); the job
+// table is a kernel argument, read with scalar loads.
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_xfwd_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;  // uniform per block
+  xfwd_body<float, N, TPL, LPW, true, 0>(static_cast<const double *>(J.in), static_cast<float *>(J.out),
+                                         J.tw, nullptr, J.sums, (long)J.ny * J.nz / 2, J.ny, J.sp,
+                                         blockIdx.x, J.nblk);
+}
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_yfwd_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;
+  yfwd_body<float, N, TPL, LPW, 0, false>(static_cast<float *>(J.out), J.tw, nullptr, J.nx,
+                                          J.nx / (2 * LPW), J.sp, blockIdx.x, J.nblk);
+}
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_yinv_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;
+  yinv_body<float, N, TPL, LPW, 0, false>(static_cast<float *>(J.out), J.tw, nullptr, J.nx,
+                                          J.nx / (2 * LPW), J.sp, blockIdx.x, J.nblk);
+}
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_resid_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;
+  resid_spec_body<N, TPL, LPW, 0>(static_cast<const double *>(J.in), J.zm, static_cast<const float *>(J.in2),
+                                  static_cast<float *>(J.out), J.tw, nullptr, J.sums, J.sx, J.zal, J.zga,
+                                  J.zex, J.ny, J.nz, J.idy2, 1.0 / J.ny, 0, J.sp, blockIdx.x, J.nblk);
+}
+template <int N, int TPL, int LPW>
+__global__ __launch_bounds__(TPL *LPW) void k_xinv_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;
+  xinv_body<float, double, N, TPL, LPW, true, true, 0>(
+      static_cast<const float *>(J.in), static_cast<double *>(J.out), J.tw, nullptr, J.zm,
+      static_cast<const float *>(J.in2), J.scale, J.ny, (long)J.ny * J.nz / 2, J.sp, J.stat, blockIdx.x,
+      J.nblk);
 }
 
 // ------------------------------------------------------------- launchers
@@ -922,6 +1012,101 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const c
     PF_FOR_FFT_SIZES(PF_CASE)
 #undef PF_CASE
 #undef PF_XINV
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// grouped launchers: the grid spans the widest job; every job of a group
+// has the length of the switch
+static dim3 grp_grid(const GJobs &g) {
+  unsigned m = 1;
+  for (int k = 0; k < g.count; ++k) m = g.j[k].nblk > m ? g.j[k].nblk : m;
+  return dim3(m, (unsigned)g.count);
+}
+static bool grp_ok(const GJobs &g) { return g.count >= 1 && g.count <= kMaxGroupJobs; }
+
+hipError_t launch_xfwd_grp(int nx, GJobs &g, hipStream_t st) {
+  if (!grp_ok(g)) return hipErrorInvalidValue;
+  switch (nx) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                          \
+    for (int k = 0; k < g.count; ++k) {                                                       \
+      if (g.j[k].nx != N || g.j[k].ny % 2) return hipErrorInvalidValue;                       \
+      g.j[k].nblk = (unsigned)(((long)g.j[k].ny * g.j[k].nz / 2 + LPW - 1) / LPW);            \
+    }                                                                                         \
+    hipLaunchKernelGGL((k_xfwd_grp<N, TPL, LPW>), grp_grid(g), dim3(TPL * LPW), 0, st, g);    \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <bool INV>
+static hipError_t launch_y_grp(int ny, GJobs &g, hipStream_t st) {
+  if (!grp_ok(g)) return hipErrorInvalidValue;
+  switch (ny) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = y_tpl(N), LPW = y_lpw<float>(N);                                      \
+    for (int k = 0; k < g.count; ++k) {                                                       \
+      if (g.j[k].ny != N || g.j[k].nx % (2 * LPW)) return hipErrorInvalidValue;               \
+      g.j[k].nblk = (unsigned)(g.j[k].nx / (2 * LPW) * g.j[k].nz);                            \
+    }                                                                                         \
+    if (INV)                                                                                  \
+      hipLaunchKernelGGL((k_yinv_grp<N, TPL, LPW>), grp_grid(g), dim3(TPL * LPW), 0, st, g);  \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_yfwd_grp<N, TPL, LPW>), grp_grid(g), dim3(TPL * LPW), 0, st, g);  \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES_Y(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_yfwd_grp(int ny, GJobs &g, hipStream_t st) { return launch_y_grp<false>(ny, g, st); }
+hipError_t launch_yinv_grp(int ny, GJobs &g, hipStream_t st) { return launch_y_grp<true>(ny, g, st); }
+
+hipError_t launch_resid_grp(int nx, GJobs &g, hipStream_t st) {
+  if (!grp_ok(g)) return hipErrorInvalidValue;
+  switch (nx) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                     \
+    for (int k = 0; k < g.count; ++k) {                                                       \
+      if (g.j[k].nx != N || g.j[k].ny % (2 * LPW)) return hipErrorInvalidValue;               \
+      g.j[k].nblk = (unsigned)((long)g.j[k].ny * g.j[k].nz / (2 * LPW));                      \
+    }                                                                                         \
+    hipLaunchKernelGGL((k_resid_grp<N, TPL, LPW>), grp_grid(g), dim3(TPL * LPW), 0, st, g);   \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_xinv_grp(int nx, GJobs &g, hipStream_t st) {
+  if (!grp_ok(g)) return hipErrorInvalidValue;
+  switch (nx) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                             \
+    for (int k = 0; k < g.count; ++k) {                                                       \
+      if (g.j[k].nx != N || g.j[k].ny % 2 || !g.j[k].zm) return hipErrorInvalidValue;         \
+      g.j[k].nblk = (unsigned)(((long)g.j[k].ny * g.j[k].nz / 2 + LPW - 1) / LPW);            \
+    }                                                                                         \
+    hipLaunchKernelGGL((k_xinv_grp<N, TPL, LPW>), grp_grid(g), dim3(TPL * LPW), 0, st, g);    \
+    return hipGetLastError();                                                                 \
+  }
+    PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
     default:
       return hipErrorInvalidValue;
   }

@@ -404,10 +404,11 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
 // two-pass ones (the pair of slots 0 and 1, x walls) read and write their
 // columns directly.
 template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1>
-__global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
+__device__ __forceinline__ void zsolve3_body(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
-                                                      const double *sy, size_t sp, int xr) {
+                                                      const double *sy, size_t sp, int xr,
+                                             unsigned bx_, unsigned gx_) {
   static_assert(M >= 3, "a chunk needs interior rows");
   static_assert(TILE || R == 1, "rounds need the tile");
   using V = cplx<TS>;
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
   D2 *X3 = X2 + P * TP;
   TS *tile = reinterpret_cast<TS *>(reg0);
   const int nib = nx / (R * TC);
-  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int blk = (int)xcd_block(bx_, gx_);
   const int ib = blk % nib;
   const int j = blk / nib;
   const int pc = threadIdx.x % TP;
@@ -627,6 +628,24 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
   }
   if (tiled) tile_io(false);
 }
+template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1>
+__global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
+                                                      const double *zal, const double *zga,
+                                                      const double *zex, const double *sx,
+                                                      const double *sy, size_t sp, int xr) {
+  zsolve3_body<TS, M, TP, NR, WAVES, MAXT, TILE, R>(data, nx, ny, nz, P, zal, zga, zex, sx, sy, sp, xr, blockIdx.x, gridDim.x);
+}
+
+// one z-solve shape for several problems with the same chunk count (see
+// GJobs): float32 storage, periodic x
+template <int M, int TP, int NR, int WAVES, int MAXT, bool TILE, int R>
+__global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if (blockIdx.x >= J.nblk) return;  // uniform per block
+  zsolve3_body<float, M, TP, NR, WAVES, MAXT, TILE, R>(static_cast<float *>(J.out), J.nx, J.ny, J.nz, J.P,
+                                                       J.zal, J.zga, J.zex, J.sx, J.sy, J.sp, 0, blockIdx.x,
+                                                       J.nblk);
+}
 
 // Launch shapes of the z solve: rows per thread M, columns per workgroup
 // TI, minimum waves per SIMD (0: none), fast reciprocals.
@@ -813,6 +832,54 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #undef PF_ZV
   return hipGetLastError();
 }
+bool zsolve_variant_groups(int variant) { return variant >= 18 && variant < kZVariantCount; }
+int zsolve_chunks(int variant, int nz) { return (nz + kZVariants[variant].M - 1) / kZVariants[variant].M; }
+
+hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st) {
+  if (!zsolve_variant_groups(variant) || g.count < 1 || g.count > kMaxGroupJobs) return hipErrorInvalidValue;
+  const ZVariant &z = kZVariants[variant];
+  const int P = (g.j[0].nz + z.M - 1) / z.M;
+  unsigned mb = 1;
+  for (int k = 0; k < g.count; ++k) {
+    GJob &J = g.j[k];
+    if ((J.nz + z.M - 1) / z.M != P || J.P != P || !zsolve_variant_fits(variant, J.nx, J.nz, 4))
+      return hipErrorInvalidValue;
+    J.nblk = (unsigned)((long)(J.nx / z.TI) * J.ny);
+    mb = J.nblk > mb ? J.nblk : mb;
+  }
+  const size_t shm = zsolve_lds(z, P, 4);
+  const dim3 gr(mb, (unsigned)g.count), b(P * z.TI / 2 / z.rounds);
+#define PF_G(ID, M_, TI_, W_, MAXT_, TILE_, R_)                                                     \
+  case ID:                                                                                         \
+    hipLaunchKernelGGL((k_zsolve3_grp<M_, TI_ / 2 / R_, 1, W_, MAXT_, TILE_, R_>), gr, b, shm, st, g); \
+    break;
+  switch (variant) {
+    PF_G(18, 8, 8, 4, 512, false, 1)
+    PF_G(19, 8, 16, 4, 512, false, 1)
+    PF_G(20, 16, 16, 1, 512, false, 1)
+    PF_G(21, 16, 32, 1, 512, false, 1)
+    PF_G(22, 8, 32, 4, 512, false, 1)
+    PF_G(23, 8, 64, 4, 512, false, 1)
+    PF_G(24, 8, 128, 4, 512, false, 1)
+    PF_G(25, 16, 64, 1, 512, false, 1)
+    PF_G(26, 16, 128, 1, 512, false, 1)
+    PF_G(27, 8, 32, 1, 1024, false, 1)
+    PF_G(28, 8, 16, 1, 1024, false, 1)
+    PF_G(29, 8, 32, 1, 1024, true, 2)
+    PF_G(30, 16, 32, 1, 512, true, 2)
+    PF_G(31, 8, 16, 1, 1024, true, 1)
+    PF_G(32, 16, 16, 1, 512, true, 1)
+    PF_G(33, 16, 32, 1, 512, true, 1)
+    PF_G(34, 8, 32, 1, 1024, true, 1)
+    PF_G(35, 8, 16, 1, 512, true, 1)
+    PF_G(36, 8, 32, 1, 512, true, 2)
+#undef PF_G
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template hipError_t launch_zsolve<double>(int, int, int, double *, size_t, const double *, const double *,
                                           const double *, const double *, const double *, int,
                                           hipStream_t, bool);
@@ -824,11 +891,10 @@ template hipError_t launch_zsolve<float>(int, int, int, float *, size_t, const d
 // The (0,0) slot of the transformed problem is the plane-mean profile of p.
 // Plane means come from the float64 line sums, one workgroup per plane with
 // a fixed-order tree reduction (bitwise reproducible).
-__global__ __launch_bounds__(256) void k_plane_means(const double *__restrict__ sums,
-                                                     double *__restrict__ mean, int ny,
-                                                     double inv_nxny) {
+__device__ __forceinline__ void plane_means_body(const double *__restrict__ sums, double *__restrict__ mean,
+                                                 int ny, double inv_nxny, int k) {
   __shared__ double red[256];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const double *s = sums + (size_t)k * ny;
   double a = 0.0;
   for (int j = tid; j < ny; j += 256) a += s[j];
@@ -840,16 +906,19 @@ __global__ __launch_bounds__(256) void k_plane_means(const double *__restrict__ 
   }
   if (tid == 0) mean[k] = red[0] * inv_nxny;
 }
+__global__ __launch_bounds__(256) void k_plane_means(const double *__restrict__ sums,
+                                                     double *__restrict__ mean, int ny,
+                                                     double inv_nxny) {
+  plane_means_body(sums, mean, ny, inv_nxny, blockIdx.x);
+}
 
 // One thread: projection of the plane means fbar onto the range of L_z (zero
 // dzf-weighted mean), the singular Neumann system solved with its last
 // equation replaced by m[nz-1] = 0, then the shift to zero dzf-weighted mean.
 // With p0mean (the iterate's plane means) it writes zm = m - p0mean instead.
-__global__ __launch_bounds__(256) void k_zero_solve(const double *__restrict__ fbar,
-                                                    const double *__restrict__ dzf,
-                                                    const double *__restrict__ zal,
-                                                    const double *__restrict__ zga,
-                                                    double *__restrict__ m, int nz) {
+__device__ __forceinline__ void zero_solve_body(const double *__restrict__ fbar, const double *__restrict__ dzf,
+                                                const double *__restrict__ zal, const double *__restrict__ zga,
+                                                double *__restrict__ m, int nz) {
   extern __shared__ double sh[];  // F, W, A, G, Y, RT: nz each
   double *F = sh, *W = sh + nz, *A = sh + 2 * nz, *G = sh + 3 * nz, *Y = sh + 4 * nz,
          *RT = sh + 5 * nz;
@@ -890,12 +959,57 @@ __global__ __launch_bounds__(256) void k_zero_solve(const double *__restrict__ f
   const double shift = wm / w;
   for (int k = 0; k < nz; ++k) m[k] = Y[k] - shift;
 }
+__global__ __launch_bounds__(256) void k_zero_solve(const double *__restrict__ fbar,
+                                                    const double *__restrict__ dzf,
+                                                    const double *__restrict__ zal,
+                                                    const double *__restrict__ zga,
+                                                    double *__restrict__ m, int nz) {
+  zero_solve_body(fbar, dzf, zal, zga, m, nz);
+}
 
 __global__ __launch_bounds__(256) void k_sub(const double *__restrict__ a,
                                              const double *__restrict__ b, double *__restrict__ out,
                                              int n) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < n) out[k] = a[k] - b[k];
+}
+
+// grouped: blockIdx.y (means) or blockIdx.x (solve, difference) is the job
+__global__ __launch_bounds__(256) void k_plane_means_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  if ((int)blockIdx.x >= J.nz) return;  // uniform per block
+  plane_means_body(J.sums, static_cast<double *>(J.out), J.ny, 1.0 / ((double)J.nx * J.ny), blockIdx.x);
+}
+__global__ __launch_bounds__(256) void k_zero_solve_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.x];
+  zero_solve_body(static_cast<const double *>(J.out), J.aux, J.zal, J.zga,
+                  const_cast<double *>(static_cast<const double *>(J.in2)), J.nz);
+}
+__global__ __launch_bounds__(256) void k_sub_grp(const GJobs g) {
+  const GJob &J = g.j[blockIdx.y];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < J.nz)
+    const_cast<double *>(J.zm)[k] = static_cast<const double *>(J.in2)[k] - static_cast<const double *>(J.out)[k];
+}
+hipError_t launch_zero_mode_grp(GJobs &g, hipStream_t st) {
+  if (g.count < 1 || g.count > kMaxGroupJobs) return hipErrorInvalidValue;
+  int mz = 1;
+  for (int k = 0; k < g.count; ++k) mz = g.j[k].nz > mz ? g.j[k].nz : mz;
+  hipLaunchKernelGGL(k_plane_means_grp, dim3(mz, g.count), dim3(256), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_solve_grp, dim3(g.count), dim3(256), (size_t)6 * mz * sizeof(double), st, g);
+  return hipGetLastError();
+}
+hipError_t launch_zero_shift_grp(GJobs &g, hipStream_t st) {
+  if (g.count < 1 || g.count > kMaxGroupJobs) return hipErrorInvalidValue;
+  int mz = 1;
+  for (int k = 0; k < g.count; ++k) mz = g.j[k].nz > mz ? g.j[k].nz : mz;
+  hipLaunchKernelGGL(k_plane_means_grp, dim3(mz, g.count), dim3(256), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sub_grp, dim3((mz + 255) / 256, g.count), dim3(256), 0, st, g);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_mode(int nx, int ny, int nz, const double *sums, const double *dzf,

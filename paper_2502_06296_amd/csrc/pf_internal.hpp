@@ -189,6 +189,57 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 int zsolve_variant_count();
 bool zsolve_variant_fits(int variant, int nx, int nz, int esize);  // esize: bytes per stored value
 int zsolve_default_variant(int nx, int nz, bool fp64);
+
+// ----------------------------------------------------- grouped launches
+// One launch runs one stage of several independent problems that share the
+// kernel instance (transform length; z-solve shape and chunk count):
+// blockIdx.y selects the job, blockIdx.x runs over the widest job's blocks,
+// and a job's blocks past its own count exit at once. Float32 storage with
+// one float64-residual correction, periodic x and y. The fields a stage
+// reads and writes:
+//   x forward:  in = f (float64), out = W (float32), sums = line sums
+//   y forward / inverse, z solve: out = W in place
+//   residual:   in = f, in2 = W (iterate), out = correction's right-hand
+//               side (float32), zm = fbar, sums = the iterate's line sums
+//   x inverse:  in = W, in2 = correction, out = p (float64), zm = zero-mode
+//               profile, scale, stat (nullable)
+// nblk is set by the launcher.
+constexpr int kMaxGroupJobs = 16;
+struct GJob {
+  const void *in;
+  void *out;
+  const void *in2;
+  const cplx<double> *tw;
+  double *sums;
+  const double *zm;
+  const double *zal, *zga, *zex, *sx, *sy;
+  unsigned long long *stat;
+  const double *aux;  // zero mode: dzf
+  double scale, idy2;
+  size_t sp;
+  int nx, ny, nz, P;
+  unsigned nblk;
+};
+struct GJobs {
+  GJob j[kMaxGroupJobs];
+  int count;
+};
+hipError_t launch_xfwd_grp(int nx, GJobs &g, hipStream_t st);
+hipError_t launch_yfwd_grp(int ny, GJobs &g, hipStream_t st);
+hipError_t launch_yinv_grp(int ny, GJobs &g, hipStream_t st);
+hipError_t launch_resid_grp(int nx, GJobs &g, hipStream_t st);
+hipError_t launch_xinv_grp(int nx, GJobs &g, hipStream_t st);
+// the zero mode of every job: plane means fbar (out) of its line sums
+// (sums), then the pinned solve for the profile m (in2 -> written) from
+// fbar, dzf (aux), zal, zga; zero shift: plane means p0m (out) of the
+// iterate's sums, then zm (zm, written) = m (in2) - p0m
+hipError_t launch_zero_mode_grp(GJobs &g, hipStream_t st);
+hipError_t launch_zero_shift_grp(GJobs &g, hipStream_t st);
+// every job of the group runs z-solve `variant` (a separator-form shape)
+// with the same chunk count
+hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st);
+bool zsolve_variant_groups(int variant);
+int zsolve_chunks(int variant, int nz);  // P of a variant for nz rows
 // Singular (0,0) mode: plane means fbar[nz] of the right-hand side from its
 // line sums, projection, pinned Neumann solve for the plane-mean profile
 // m[nz] of p.
@@ -215,7 +266,7 @@ struct HelmJob {
   int nx, ny;
   HelmCoef c;
 };
-constexpr int kMaxHelmJobs = 4;
+constexpr int kMaxHelmJobs = 16;  // fields of one grouped Helmholtz launch
 // precision: 0 float64, 1 float32 storage, 2 float64 I/O with a float32
 // solve and one float64-residual correction.
 // cw: columns per chunk, 16, 32 or 64, with P*cw <= 1024 (<= 512 staged).

@@ -282,11 +282,8 @@ def pcr_set_stream(plan, stream):
 
 
 # -------------------------------------------------------------- task batch
-def run_batched(tasks, lanes=4, stream=None):
-    """Independent tasks spread over `lanes` internal streams forked from and
-    joined back into `stream` (pf_run_batched). Each task is a dict with an
-    optional Poisson solve (``poisson``, ``rhs``, ``p``) and an optional group
-    of up to 4 Helmholtz fields (``pcr``: plans, ``fields``: tensors)."""
+def _task_array(tasks):
+    """The pf_task array of a list of task dicts (see run_batched)."""
     import torch
     arr = (N.PfTask * max(1, len(tasks)))()
     for t, task in enumerate(tasks):
@@ -306,6 +303,15 @@ def run_batched(tasks, lanes=4, stream=None):
             _check_field(f, f.shape, _pcr_dtype(hp))
             T.pcr[c], T.field[c] = hp.handle, f.data_ptr()
             T.nx[c], T.ny[c] = f.shape[2], f.shape[1]
+    return arr
+
+
+def run_batched(tasks, lanes=4, stream=None):
+    """Independent tasks spread over `lanes` internal streams forked from and
+    joined back into `stream` (pf_run_batched). Each task is a dict with an
+    optional Poisson solve (``poisson``, ``rhs``, ``p``) and an optional group
+    of up to 4 Helmholtz fields (``pcr``: plans, ``fields``: tensors)."""
+    arr = _task_array(tasks)
     N.check(N.lib().pf_run_batched(len(tasks), arr, int(lanes), N.stream_handle(stream)))
 
 

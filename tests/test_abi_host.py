@@ -203,3 +203,15 @@ def test_plan_validates_the_x_boundary_before_any_device_call():
     g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, -1)
     assert L.poisson_plan(C.byref(h), C.byref(g), 0, 1, None, None) == N.PF_ERR_ARG
     assert L.pf_abi_version() == 3
+
+
+def test_batched_calls_check_their_counts_before_any_device_call():
+    L = N.lib()
+    arr = (C.c_void_p * 17)()
+    i32 = (C.c_int32 * 17)()
+    assert L.pcr_apply_batched(0, arr, arr, i32, i32) == N.PF_ERR_ARG
+    assert L.pcr_apply_batched(17, arr, arr, i32, i32) == N.PF_ERR_ARG      # 1..16 fields
+    assert L.poisson_solve_batched(-1, arr, arr, arr) == N.PF_ERR_ARG
+    assert L.poisson_solve_batched(0, arr, arr, arr) == N.PF_OK            # nothing to do
+    assert L.poisson_solve_batched(1, arr, arr, arr) == N.PF_ERR_ARG       # NULL plan
+
