@@ -28,6 +28,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -102,12 +103,13 @@ class Step:
     velocity components are N(0, 1) draws of fixed seeds, redrawn by
     reset_fields()."""
 
-    def __init__(self, pf, torch, dev, prec, f):
+    def __init__(self, pf, torch, dev, prec, f, tune=False):
         self.pf, self.torch, self.prec = pf, torch, prec
         self.stream = torch.cuda.Stream(device=dev)
+        self.tuned = None
         with torch.cuda.stream(self.stream):
             self.poisson = pf.poisson_plan(NX, NY, NZ, LX, LY, LZ, BETA, precision=prec, n_refine=1,
-                                           stream=self.stream, device=dev)
+                                           stream=self.stream, device=dev, tuned=False)
             self.pcr = []
             for bc in ("dirichlet_centre", "dirichlet_centre", "dirichlet_face"):
                 al, ga, ex = pf.zop_rows(NZ, bc, LZ, BETA)
@@ -117,6 +119,15 @@ class Step:
             self.u = [torch.empty((NZ if c < 2 else NZ - 1, NY, NX), dtype=torch.float64, device=dev)
                       for c in range(3)]
         self.reset_fields()
+        if tune:
+            # the autotuner's choice of z-solve shape and transform shapes for
+            # this grid, timed on the plan's own buffers (a cache in the
+            # temporary directory keeps it between runs on one machine)
+            from paper_2502_06296_amd import autotune
+            with torch.cuda.stream(self.stream):
+                res = autotune.apply_or_tune_poisson(self.poisson, f, self.p, prec, reps=2, path=TUNE_CACHE)
+            self.stream.synchronize()
+            self.tuned = {k: res[k] for k in ("zsolve_variant", "xshape", "yshape", "cached")}
 
     def reset_fields(self):
         with self.torch.cuda.stream(self.stream):
@@ -557,6 +568,9 @@ def helmholtz_c3(torch, pf, dev, steps, warmup):
     return out
 
 
+TUNE_CACHE = os.path.join(tempfile.gettempdir(), "pf_channel_bench_tune.json")
+
+
 def headline(args):
     """The projection step at the workload's grid, FP32+refine then FP64 (one
     precision's plans and fields freed before the other's are built)."""
@@ -575,7 +589,9 @@ def headline(args):
     results, kept = {}, {}
     for prec in (["fp32_refine"] if args.no_fp64 else ["fp32_refine", "fp64"]):
         log(f"bench: {prec} plans")
-        st = Step(pf, torch, dev, prec, f)
+        st = Step(pf, torch, dev, prec, f, tune=not args.no_tune)
+        if st.tuned:
+            log(f"bench: {prec} autotuned shapes {st.tuned}")
         ms, wall, stages = time_steps(st, args.steps, args.warmup)
         log(f"bench: {prec} {ms:.3f} ms/step")
         gms = graph_ms(st, max(3, args.steps // 2))
@@ -584,7 +600,7 @@ def headline(args):
         st.run()
         st.stream.synchronize()
         kept[prec] = (st.p, st.u)
-        results[prec] = dict(ms=ms, wall=wall, stages=stages, graph_ms=gms)
+        results[prec] = dict(ms=ms, wall=wall, stages=stages, graph_ms=gms, tuned=st.tuned)
         del st
         torch.cuda.empty_cache()
 
@@ -616,6 +632,7 @@ def headline(args):
         "roofline": roofline("fp32_refine", main["stages"], traffic),
         "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in main["stages"].items()},
         "graph_ms_per_step": round(main["graph_ms"], 4),
+        "autotuned": main["tuned"],
         "accuracy": acc,
     }
     if "fp64" in results:
@@ -624,6 +641,7 @@ def headline(args):
                         "ms_per_step": round(r64["ms"], 4),
                         "graph_ms_per_step": round(r64["graph_ms"], 4),
                         "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in r64["stages"].items()},
+                        "autotuned": r64["tuned"],
                         "roofline": roofline("fp64", r64["stages"], traffic)}
         line["speedup_fp32_refine_vs_fp64"] = round(r64["ms"] / main["ms"], 4)
     return line, torch, pf, dev
@@ -692,6 +710,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes instead of the autotuner's")
     ap.add_argument("--no-coupled", action="store_true",
                     help="channel workload: skip the coupled substep and the 3-D Helmholtz")
     ap.add_argument("--no-helmholtz", action="store_true",

@@ -356,10 +356,17 @@ pf_status pcr_timing_read(pf_pcr_plan *plan, double *ms, int32_t *count);
 /* ------------------------------------------------------------ tuning
  * Launch-shape variants that an autotuner may choose between. For
  * PF_STAGE_ZSOLVE the variants are table entries of (rows per thread,
- * columns per workgroup, occupancy bound, reciprocal flavour); every variant
- * computes the same solution (to rounding). *count receives the number of
- * table entries; pf_poisson_set_variant returns PF_ERR_UNSUPPORTED for a
- * variant that does not fit the plan's grid. Set variants only while no
+ * columns per workgroup, occupancy bound, reciprocal flavour). For
+ * PF_STAGE_XFWD (the x forward, the x inverse and the refinement's residual)
+ * and PF_STAGE_YFWD (both y transforms) of a direction without walls they
+ * are 4 transform shapes: 0 the default, 1 half the threads per line, 2
+ * twice the threads per line (x) or the lines per workgroup (y), 3 the
+ * radix capped at 8; shapes 1-3 exist for the lengths 256, 512, 1024 and
+ * 2048. Every variant computes the same solution to rounding. *count
+ * receives the number of
+ * variants; poisson_set_variant returns PF_ERR_UNSUPPORTED for a variant
+ * that does not fit the plan's grid. Plans with non-default transform
+ * shapes run one by one in poisson_solve_batched. Set variants only while no
  * solve of the plan is in flight. */
 pf_status poisson_variant_count(pf_poisson_plan *plan, int32_t stage, int32_t *count);
 pf_status poisson_set_variant(pf_poisson_plan *plan, int32_t stage, int32_t variant);

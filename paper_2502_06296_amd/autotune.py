@@ -5,13 +5,16 @@ variants for the stages that have more than one:
 
 * the Poisson z solve (rows per thread, columns per workgroup, occupancy
   bound, reciprocal flavour), timed on the plan's own buffers;
+* the x and y transforms of the Poisson solve (threads per line, lines per
+  workgroup, radix order: four shapes per direction);
 * the Helmholtz apply (rows per chunk, columns per chunk).
 
 Winners are kept in a JSON cache keyed by GPU architecture, HIP runtime
 version, shape and precision (path: $PF_TUNE_CACHE, else
 ~/.cache/pf_channel/tune.json). A corrupt or unreadable cache is ignored.
-Tuning runs kernels and may allocate; do it at set-up, not inside a graph
-capture.
+poisson_plan applies a cached entry for its shape and precision by default
+(apply_cached_poisson). Tuning runs kernels and may allocate; do it at
+set-up, not inside a graph capture.
 """
 from __future__ import annotations
 
@@ -22,6 +25,8 @@ import os
 from . import _native as N
 from . import solver
 
+STAGE_XFWD = 0
+STAGE_YFWD = 1
 STAGE_ZSOLVE = 2
 
 
@@ -81,6 +86,47 @@ def get_zsolve_variant(plan):
     v = C.c_int32()
     N.check(N.lib().poisson_get_variant(plan.handle, STAGE_ZSOLVE, C.byref(v)))
     return v.value
+
+
+def set_variant(plan, stage, v):
+    return N.lib().poisson_set_variant(plan.handle, int(stage), int(v)) == N.PF_OK
+
+
+def get_variant(plan, stage):
+    v = C.c_int32()
+    N.check(N.lib().poisson_get_variant(plan.handle, int(stage), C.byref(v)))
+    return v.value
+
+
+def tune_transforms(plan, rhs, p, reps=3):
+    """Time every transform shape that fits the plan, x and y direction
+    separately (the x shape by the x forward, x inverse and residual stages,
+    the y shape by both y stages); keep the fastest of each. Returns
+    {"x": {shape: ms}, "y": {shape: ms}}."""
+    cnt = C.c_int32()
+    N.check(N.lib().poisson_variant_count(plan.handle, STAGE_XFWD, C.byref(cnt)))
+    stages = {"x": (STAGE_XFWD, ("xfwd", "xinv", "xinv_final", "xfwd_resid")),
+              "y": (STAGE_YFWD, ("yfwd", "yinv"))}
+    out = {}
+    solver.poisson_timing(plan, True)
+    try:
+        for d, (stage, names) in stages.items():
+            times = {}
+            for v in range(cnt.value):
+                if not set_variant(plan, stage, v):
+                    continue
+                solver.poisson_solve(plan, rhs, p)
+                solver.poisson_timing_read(plan)
+                for _ in range(reps):
+                    solver.poisson_solve(plan, rhs, p)
+                t = solver.poisson_timing_read(plan)
+                times[v] = sum(t[n][0] for n in names if n in t) / reps
+            best = min(times, key=times.get)
+            set_variant(plan, stage, best)
+            out[d] = times
+    finally:
+        solver.poisson_timing(plan, False)
+    return out
 
 
 def tune_poisson(plan, rhs, p, reps=3):
@@ -147,22 +193,47 @@ def pcr_key(n, nx, ny, precision, count):
     return f"{_arch_key()}|pcr|{count}x{n}x{ny}x{nx}|{precision}"
 
 
+def apply_cached_poisson(plan, nx, ny, nz, precision, path=None):
+    """Apply the cached variants (z solve, x and y transform shapes) for this
+    shape and precision if the cache holds an entry that fits the plan.
+    Returns the applied entry or None."""
+    try:
+        ent = load_cache(path).get(poisson_key(nx, ny, nz, precision))
+    except Exception:  # no device properties (or no torch): nothing to apply
+        return None
+    if not isinstance(ent, dict):
+        return None
+    done = {}
+    for name, stage in (("zsolve_variant", STAGE_ZSOLVE), ("xshape", STAGE_XFWD), ("yshape", STAGE_YFWD)):
+        v = ent.get(name)
+        if isinstance(v, int) and set_variant(plan, stage, v):
+            done[name] = v
+    return done or None
+
+
 def apply_or_tune_poisson(plan, rhs, p, precision, reps=3, path=None):
-    """Use the cached z-solve variant for this shape, or tune and cache it."""
+    """Use the cached variants for this shape, or tune the z solve and the
+    transform shapes and cache them."""
     nz, ny, nx = plan.shape
     key = poisson_key(nx, ny, nz, precision)
     cache = load_cache(path)
-    v = cache.get(key, {}).get("zsolve_variant") if isinstance(cache.get(key), dict) else None
-    if v is not None and set_zsolve_variant(plan, v):
-        return {"zsolve_variant": v, "cached": True}
+    ent = cache.get(key) if isinstance(cache.get(key), dict) else {}
+    if "zsolve_variant" in ent and "xshape" in ent and "yshape" in ent:
+        done = apply_cached_poisson(plan, nx, ny, nz, precision, path)
+        if done and len(done) == 3:
+            return {**done, "cached": True}
     times = tune_poisson(plan, rhs, p, reps)
-    best = get_zsolve_variant(plan)
-    cache[key] = {"zsolve_variant": best, "ms": {str(k): v for k, v in times.items()}}
+    tt = tune_transforms(plan, rhs, p, reps)
+    best = {"zsolve_variant": get_zsolve_variant(plan), "xshape": get_variant(plan, STAGE_XFWD),
+            "yshape": get_variant(plan, STAGE_YFWD)}
+    cache[key] = {**best, "ms": {str(k): v for k, v in times.items()},
+                  "x_ms": {str(k): v for k, v in tt["x"].items()},
+                  "y_ms": {str(k): v for k, v in tt["y"].items()}}
     try:
         save_cache(cache, path)
     except OSError:
         pass
-    return {"zsolve_variant": best, "cached": False, "ms": times}
+    return {**best, "cached": False, "ms": times, "transform_ms": tt}
 
 
 def apply_or_tune_pcr(plans, fields, precision, reps=3, path=None):

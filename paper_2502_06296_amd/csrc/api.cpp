@@ -235,6 +235,7 @@ struct pf_poisson_plan {
   int prec, nref;
   hipStream_t st;
   int zchunk;
+  int xshape = 0, yshape = 0;  // launch shapes of the periodic x and y transforms
   DevArena ar;
   size_t o_zal, o_zga, o_zex, o_dzf, o_sx, o_sxb, o_sy, o_twx_d, o_twy_d, o_sums, o_sump,
       o_fbar, o_m, o_zm, o_p0m, o_rdzf, o_rdzc, o_ctw, o_ctwx;
@@ -620,16 +621,17 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
     const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
     const int yw = pl->ybc, xw = pl->xbc;
     const bool xr = xw != PF_X_PERIODIC;
+    const int xs = xw == PF_X_PERIODIC ? pl->xshape : 0, ys = yw == PF_Y_PERIODIC && !xr ? pl->yshape : 0;
     // the spectrum lives in p itself, dense
     const size_t sd = (size_t)nx * ny;
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<double>(nx, ny, nz, *div, p, sd, twx, sums, st)
-                             : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st, xw, ctwx));
+                             : pf::launch_xfwd<double>(nx, ny, rhs, p, sd, twx, sums, lines, st, xw, ctwx, xs));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr, ys));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<double>(nx, ny, nz, p, sd, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<double>(nx, ny, nz, p, sd, twy, ctw, yw, st, xr, ys));
     STAGE(PF_STAGE_XINV, (pf::launch_xinv<double, double>(nx, ny, p, sd, p, twx, helm ? zm : mm, nullptr, oscale,
-                                                          lines, st, nullptr, xw, ctwx)));
+                                                          lines, st, nullptr, xw, ctwx, xs)));
     return PF_OK;
   }
   const double2 *twx = A.at<double2>(pl->o_twx_d), *twy = A.at<double2>(pl->o_twy_d);
@@ -637,17 +639,18 @@ static pf_status poisson_enqueue_plain(pf_poisson_plan *pl, const double *rhs, d
   const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
   const int yw = pl->ybc, xw = pl->xbc;
   const bool xr = xw != PF_X_PERIODIC;
+  const int xs = xw == PF_X_PERIODIC ? pl->xshape : 0, ys = yw == PF_Y_PERIODIC && !xr ? pl->yshape : 0;
   float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   if (pl->prec == PF_FP32) {
     STAGE(PF_STAGE_XFWD, div ? pf::launch_xfwd_div<float>(nx, ny, nz, *div, W0, sp, twx, sums, st)
-                             : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx));
+                             : pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx, xs));
     if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr, ys));
     STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
-    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+    STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr, ys));
     STAGE(PF_STAGE_XINV_FINAL, (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, helm ? zm : mm, nullptr,
-                                                               oscale, lines, st, nullptr, xw, ctwx)));
+                                                               oscale, lines, st, nullptr, xw, ctwx, xs)));
     return PF_OK;
   }
   return fail(PF_ERR_ARG, "unexpected precision");
@@ -670,6 +673,7 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
   const double2 *ctwx = pl->xbc != PF_X_PERIODIC ? A.at<double2>(pl->o_ctwx) : nullptr;
   const int yw = pl->ybc, xw = pl->xbc;
   const bool xr = xw != PF_X_PERIODIC;
+  const int xs = xw == PF_X_PERIODIC ? pl->xshape : 0, ys = yw == PF_Y_PERIODIC && !xr ? pl->yshape : 0;
   float *W0 = (float *)ws;
   const size_t sp = pl->sp32();
   // float32 solve without the zero mode, kept as its x spectrum W0 after the
@@ -684,23 +688,23 @@ static pf_status poisson_enqueue_refined(pf_poisson_plan *pl, const double *rhs,
     STAGE(PF_STAGE_XFWD, pf::launch_xfwd_div<float>(nx, ny, nz, d, W0, sp, twx, sums, st));
     rhs = p;
   } else {
-    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx));
+    STAGE(PF_STAGE_XFWD, pf::launch_xfwd<float>(nx, ny, rhs, W0, sp, twx, sums, lines, st, xw, ctwx, xs));
   }
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_mode(nx, ny, nz, sums, dzf, zal, zga, fbar, mm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr, ys));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W0, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W0, sp, twy, ctw, yw, st, xr, ys));
   const double idy2 = (double)ny * ny / (pl->ly * pl->ly);
   STAGE(PF_STAGE_XFWD_RESID,
         pf::launch_resid_spec(nx, ny, nz, rhs, fbar, W0, W1, sp, twx, sump, sx, zal, zga, zex, idy2,
-                             pl->ybc, st, xw, ctwx));
+                             pl->ybc, st, xw, ctwx, xs));
   if (!helm) STAGE(PF_STAGE_ZERO_MODE, pf::launch_zero_shift(nx, ny, nz, sump, mm, A.at<double>(pl->o_p0m), zm, st));
-  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_YFWD, pf::launch_yfwd<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr, ys));
   STAGE(PF_STAGE_ZSOLVE, pf::launch_zsolve<float>(nx, ny, nz, W1, sp, zal, zga, zex, sx, sy, pl->zchunk, st, xr));
-  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr));
+  STAGE(PF_STAGE_YINV, pf::launch_yinv<float>(nx, ny, nz, W1, sp, twy, ctw, yw, st, xr, ys));
   STAGE(PF_STAGE_XINV_FINAL,
         (pf::launch_xinv<float, double>(nx, ny, W0, sp, p, twx, zm, W1, oscale, lines, st, pl->stat, xw,
-                                        ctwx)));
+                                        ctwx, xs)));
   if (pl->stat) PF_HIP(pf::launch_status_final(pl->stat, pl->stat_tol, true, st));
 #undef STAGE
   return PF_OK;
@@ -869,7 +873,7 @@ hipError_t run_groups(const std::vector<int> &ids, KeyFn key, JobFn job, LaunchF
 
 static bool poisson_groupable(const pf_poisson_plan *pl) {
   return pl->prec == PF_FP32_REFINE && pl->ybc == PF_Y_PERIODIC && pl->xbc == PF_X_PERIODIC &&
-         pf::zsolve_variant_groups(pl->zchunk);
+         pf::zsolve_variant_groups(pl->zchunk) && pl->xshape == 0 && pl->yshape == 0;
 }
 
 #define STAGE(id, expr)                                      \
@@ -1050,8 +1054,25 @@ pf_status poisson_destroy(pf_poisson_plan *pl) {
   return PF_OK;
 }
 
+// the transform shapes a plan can take: periodic directions only; the x
+// shape covers the x forward, the x inverse and the residual, the y shape
+// both y transforms
+static bool transform_shape_fits(const pf_poisson_plan *pl, int stage, int v) {
+  if (v < 0 || v >= pf::kTransformShapes) return false;
+  if (v == 0) return true;
+  if (stage == PF_STAGE_XFWD)
+    return pl->xbc == PF_X_PERIODIC && pf::xfwd_shape(pl->nx, v).ok && pf::xinv_shape(pl->nx, v).ok &&
+           pf::resid_shape(pl->nx, v).ok && pl->ny % (2 * pf::resid_shape(pl->nx, v).lpw) == 0;
+  const pf::TShape h = pl->prec == PF_FP64 ? pf::y_shape<double>(pl->ny, v) : pf::y_shape<float>(pl->ny, v);
+  return pl->xbc == PF_X_PERIODIC && pl->ybc == PF_Y_PERIODIC && h.ok && pl->nx % (2 * h.lpw) == 0;
+}
+
 pf_status poisson_variant_count(pf_poisson_plan *pl, int32_t stage, int32_t *count) {
   if (!pl || !count) return fail(PF_ERR_ARG, "NULL argument");
+  if (stage == PF_STAGE_XFWD || stage == PF_STAGE_YFWD) {
+    *count = pf::kTransformShapes;
+    return PF_OK;
+  }
   if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
   *count = pf::zsolve_variant_count();
   return PF_OK;
@@ -1059,6 +1080,12 @@ pf_status poisson_variant_count(pf_poisson_plan *pl, int32_t stage, int32_t *cou
 
 pf_status poisson_set_variant(pf_poisson_plan *pl, int32_t stage, int32_t variant) {
   if (!pl) return fail(PF_ERR_ARG, "plan is NULL");
+  if (stage == PF_STAGE_XFWD || stage == PF_STAGE_YFWD) {
+    if (!transform_shape_fits(pl, stage, variant))
+      return fail(PF_ERR_UNSUPPORTED, "transform shape %d does not fit stage %d of this plan", variant, stage);
+    (stage == PF_STAGE_XFWD ? pl->xshape : pl->yshape) = variant;
+    return PF_OK;
+  }
   if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
   if (!pf::zsolve_variant_fits(variant, pl->nx, pl->nz, pl->prec == PF_FP64 ? 8 : 4))
     return fail(PF_ERR_UNSUPPORTED, "z-solve variant %d does not fit nx=%d nz=%d", variant, pl->nx, pl->nz);
@@ -1068,6 +1095,10 @@ pf_status poisson_set_variant(pf_poisson_plan *pl, int32_t stage, int32_t varian
 
 pf_status poisson_get_variant(pf_poisson_plan *pl, int32_t stage, int32_t *variant) {
   if (!pl || !variant) return fail(PF_ERR_ARG, "NULL argument");
+  if (stage == PF_STAGE_XFWD || stage == PF_STAGE_YFWD) {
+    *variant = stage == PF_STAGE_XFWD ? pl->xshape : pl->yshape;
+    return PF_OK;
+  }
   if (stage != PF_STAGE_ZSOLVE) return fail(PF_ERR_UNSUPPORTED, "stage %d has no variants", stage);
   *variant = pl->zchunk;
   return PF_OK;

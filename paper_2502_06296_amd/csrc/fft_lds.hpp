@@ -188,10 +188,11 @@ __device__ __forceinline__ void dft_r(cplx<T> *v) {
   else if constexpr (R == 16) dft16<T, INV>(v);
 }
 
-// radix of the next pass for the remaining length REM
-template <int REM>
+// radix of the next pass for the remaining length REM; radix order RO = 1
+// caps the radix at 8 (more passes, fewer values per thread)
+template <int REM, int RO = 0>
 __host__ __device__ constexpr int pick_radix() {
-  return (REM % 16 == 0 && REM != 32) ? 16
+  return (RO == 0 && REM % 16 == 0 && REM != 32) ? 16
          : (REM % 8 == 0)             ? 8
          : (REM % 4 == 0)             ? 4
          : (REM % 2 == 0)             ? 2
@@ -273,11 +274,11 @@ __device__ __forceinline__ void stockham_pass_io(const cplx<T> *__restrict__ tw,
 // pass writes the result through dst instead of LDS (the LDS line is left
 // partly stale). Otherwise the line must be in LDS, published by a barrier,
 // and the result is left there, published by a barrier.
-template <typename T, int N, int NS, int TPL, bool INV, bool GIN, bool GOUT, class Src, class Dst>
+template <typename T, int N, int NS, int TPL, bool INV, bool GIN, bool GOUT, int RO, class Src, class Dst>
 __device__ __forceinline__ void fft_passes_io(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t,
                                               Src src, Dst dst) {
   if constexpr (NS < N) {
-    constexpr int R = pick_radix<N / NS>();
+    constexpr int R = pick_radix<N / NS, RO>();
     static_assert(R != 0, "transform length must be 2^a 3^b 5^c");
     constexpr bool gin = GIN && NS == 1, gout = GOUT && NS * R == N;
     auto lrd = [buf](int i) { return buf[lds_idx(i)]; };
@@ -286,14 +287,14 @@ __device__ __forceinline__ void fft_passes_io(cplx<T> *buf, const cplx<T> *__res
     else if constexpr (gin) stockham_pass_io<T, N, R, NS, TPL, INV, false, true>(tw, t, src, lwr);
     else if constexpr (gout) stockham_pass_io<T, N, R, NS, TPL, INV, true, false>(tw, t, lrd, dst);
     else stockham_pass_io<T, N, R, NS, TPL, INV, true, true>(tw, t, lrd, lwr);
-    fft_passes_io<T, N, NS * R, TPL, INV, GIN, GOUT>(buf, tw, t, src, dst);
+    fft_passes_io<T, N, NS * R, TPL, INV, GIN, GOUT, RO>(buf, tw, t, src, dst);
   }
 }
 
-template <typename T, int N, int TPL, bool INV, bool GIN, bool GOUT, class Src, class Dst>
+template <typename T, int N, int TPL, bool INV, bool GIN, bool GOUT, int RO = 0, class Src, class Dst>
 __device__ __forceinline__ void fft_line_io(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t,
                                             Src src, Dst dst) {
-  fft_passes_io<T, N, 1, TPL, INV, GIN, GOUT>(buf, tw, t, src, dst);
+  fft_passes_io<T, N, 1, TPL, INV, GIN, GOUT, RO>(buf, tw, t, src, dst);
 }
 
 // Full complex transform of one LDS line, in place (unnormalised). Every

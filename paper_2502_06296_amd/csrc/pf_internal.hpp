@@ -96,6 +96,39 @@ constexpr int y_lpw(int n) {
   return v;
 }
 
+// Launch shapes of the periodic transforms the autotuner chooses from, per
+// family: 0 the default above; 1 half the threads per line (twice the
+// values per thread); 2 twice the threads per line (x transforms and the
+// residual) or twice the lines per workgroup (y transforms); 3 the default
+// threads and lines with the radix capped at 8. Shapes 1-3 exist for the
+// lengths 256, 512, 1024 and 2048 where the length, the 1024-thread and the
+// LDS limits allow them; shapes 0-2 compute the same butterflies (up to the
+// compiler's fusion of multiply-adds), shape 3 in a different order of
+// passes.
+constexpr int kTransformShapes = 4;
+constexpr bool tuned_len(int n) { return n == 256 || n == 512 || n == 1024 || n == 2048; }
+struct TShape {
+  int tpl, lpw, ro;
+  bool ok;
+};
+constexpr TShape alt_shape(int n, int s, int t, int l, bool y, int lds_line_bytes, int tmin) {
+  if (s == 0) return {t, l, 0, true};
+  if (!tuned_len(n)) return {t, l, 0, false};
+  if (s == 1) return {t / 2, l, 0, t / 2 >= tmin && n % (y ? t : t / 2) == 0};
+  if (s == 2 && !y) return {2 * t, l, 0, 2 * t <= 256 && n % (2 * t) == 0 && 2 * t * l <= 1024};
+  if (s == 2 && y)
+    return {t, 2 * l, 0, 2 * l <= 16 && (long)2 * l * lds_line_bytes <= 160 * 1024 && t * 2 * l <= 1024};
+  if (s == 3) return {t, l, 1, true};
+  return {t, l, 0, false};
+}
+constexpr TShape xfwd_shape(int n, int s) { return alt_shape(n, s, xfwd_tpl(n), x_lpw(n), false, 0, 16); }
+constexpr TShape xinv_shape(int n, int s) { return alt_shape(n, s, x_tpl(n), x_lpw(n), false, 0, 16); }
+constexpr TShape resid_shape(int n, int s) { return alt_shape(n, s, resid_tpl(n), resid_lpw(n), false, 0, 16); }
+template <typename T>
+constexpr TShape y_shape(int n, int s) {
+  return alt_shape(n, s, y_tpl(n), y_lpw<T>(n), true, y_stride(n) * 16, 8);
+}
+
 // --------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error. Lengths are runtime checked by
 // the caller against fft_size_supported.
@@ -111,7 +144,7 @@ constexpr int y_lpw(int n) {
 template <typename T>
 hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
                        const cplx<double> *tw, double *sums, long lines, hipStream_t st,
-                       int xw = 0, const cplx<double> *ctwx = nullptr);
+                       int xw = 0, const cplx<double> *ctwx = nullptr, int shape = 0);
 // x spectrum of the float64 7-point residual of the plane-mean-free
 // problem, R = X(f - fbar[k]) - L7 of the iterate whose x spectrum (times ny)
 // is W (float32, after the y inverse); the x operator is -sx per packed
@@ -123,7 +156,8 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
                              const double *zga, const double *zex, double idy2, int ywalls,
-                             hipStream_t st, int xw = 0, const cplx<double> *ctwx = nullptr);
+                             hipStream_t st, int xw = 0, const cplx<double> *ctwx = nullptr,
+                             int shape = 0);
 // y forward / inverse, in place on the packed (T) data. yw = 1 (2) selects
 // the cosine (sine) transform of zero-gradient (value-zero) y walls, in
 // natural order for every slot pair; it needs ctw = exp(-i pi q / 2 ny),
@@ -132,10 +166,10 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 // so every slot pair is split into two packed real y spectra.
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false);
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false, int shape = 0);
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
-                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false);
+                       const cplx<double> *ctw, int yw, hipStream_t st, bool xr = false, int shape = 0);
 // x inverse: packed (TS) -> real lines (TO), scaled by `scale`; optional
 // per-plane float64 profile zm[k]; with in2 (requires zm) the inverse of
 // in + in2, summed in float64.
@@ -146,7 +180,23 @@ template <typename TS, typename TO>
 hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const cplx<double> *tw,
                        const double *zm, const TS *in2, double scale, long lines,
                        hipStream_t st, unsigned long long *stat = nullptr, int xw = 0,
-                       const cplx<double> *ctwx = nullptr);
+                       const cplx<double> *ctwx = nullptr, int shape = 0);
+// shapes 1..3 of the periodic transforms (kernels_fft_alt.hip); the
+// arguments as above, validated by the callers
+template <typename T>
+hipError_t launch_xfwd_alt(int shape, int nx, int ny, const double *in, T *out, size_t sp,
+                           const cplx<double> *tw, double *sums, long lines, hipStream_t st);
+hipError_t launch_resid_alt(int shape, int nx, int ny, int nz, const double *f, const double *fbar,
+                            const float *W, float *out, size_t sp, const cplx<double> *tw,
+                            double *sums_p, const double *sx, const double *zal, const double *zga,
+                            const double *zex, double idy2, int ywalls, hipStream_t st);
+template <typename T>
+hipError_t launch_y_alt(bool inv, int shape, int nx, int ny, int nz, T *data, size_t sp,
+                        const cplx<double> *tw, hipStream_t st);
+template <typename TS, typename TO>
+hipError_t launch_xinv_alt(int shape, int nx, int ny, const TS *in, size_t sp, TO *out,
+                           const cplx<double> *tw, const double *zm, const TS *in2, double scale,
+                           long lines, hipStream_t st, unsigned long long *stat);
 // a-posteriori status of a solve: zero the 4 words; then the estimate
 // (max|in2| / max|in|)^2 into word 2 (-1 unless refined) and flag word 3
 // when it exceeds tol

@@ -65,11 +65,12 @@ YBCS = {"periodic": 0, "walls": 1, "dirichlet": 2}
 
 def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
                  zf=None, precision="fp64", n_refine=1, stream=None, device=None, ybc="periodic",
-                 xbc="periodic"):
+                 xbc="periodic", tuned=True):
     """Plan the channel Poisson solve; allocates the workspace as a torch tensor.
     ybc "walls": zero-gradient walls at both y ends (cosine transform in y);
     "dirichlet": value-zero walls at both y ends (sine transform in y); xbc
-    the same at both x ends."""
+    the same at both x ends. tuned: apply the autotuner's cached launch
+    shapes for this grid and precision, if the cache holds them."""
     import torch
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     yb = YBCS[ybc] if isinstance(ybc, str) else int(ybc)
@@ -85,6 +86,9 @@ def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0,
         if ws.value:
             plan.workspace = torch.empty(ws.value, dtype=torch.uint8, device=dev)
             N.check(N.lib().poisson_set_workspace(h, _ptr(plan.workspace), ws.value))
+        if tuned:
+            from . import autotune
+            autotune.apply_cached_poisson(plan, nx, ny, nz, precision)
     return plan
 
 

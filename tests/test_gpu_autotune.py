@@ -60,3 +60,67 @@ def test_pcr_shapes_agree_and_tuner_keeps_fastest(tmp_path):
     assert autotune.pcr_shape(plan) == tuple(res["shape"])
     res2 = autotune.apply_or_tune_pcr([plan], [u], "fp64", reps=2, path=str(tmp_path / "t.json"))
     assert res2["cached"] and tuple(res2["shape"]) == tuple(res["shape"])
+
+
+TSHAPES = [(256, 512, 24, 3), (1024, 256, 12, 4), (2048, 64, 8, 5), (512, 1024, 8, 6)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,seed", TSHAPES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+def test_every_transform_shape_matches_oracle(nx, ny, nz, seed, prec):
+    """The four launch shapes of each periodic direction (threads per line,
+    lines per workgroup, radix at most 8) meet the oracle's bar; with
+    float32 storage the first three give the default's result bitwise (the
+    butterflies are the same; only the compiler's fusion of their
+    multiply-adds may differ, below float32 rounding)."""
+    from parity import TOL, check
+    print(f"transform shapes {prec} {nx}x{ny}x{nz}", flush=True)
+    f, zf = synth.channel_rhs(40 + seed, nx, ny, nz, beta=1.5)
+    ref = op.solve_poisson(f, zf, LX, LY)
+    dev = torch.device("cuda", 0)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision=prec, tuned=False)
+    rhs = torch.from_numpy(f).to(dev)
+    p0 = torch.empty_like(rhs)
+    pf.poisson_solve(plan, rhs, p0)
+    torch.cuda.synchronize()
+    tried = 0
+    for stage in (autotune.STAGE_XFWD, autotune.STAGE_YFWD):
+        for v in range(4):
+            if not autotune.set_variant(plan, stage, v):
+                continue
+            p = torch.empty_like(rhs)
+            pf.poisson_solve(plan, rhs, p)
+            torch.cuda.synchronize()
+            if v in (1, 2) and prec == "fp32":
+                assert torch.equal(p, p0), (stage, v)
+            check(p.cpu().numpy(), ref, TOL[prec], f"stage {stage} shape {v}")
+            tried += 1
+        autotune.set_variant(plan, stage, 0)
+    assert tried >= 4
+
+
+def test_transform_tuner_caches_and_plans_apply_the_cache(tmp_path, monkeypatch):
+    nx, ny, nz = 512, 256, 16
+    f, zf = synth.channel_rhs(47, nx, ny, nz, beta=1.5)
+    dev = torch.device("cuda", 0)
+    path = str(tmp_path / "tune.json")
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine", tuned=False)
+    rhs = torch.from_numpy(f).to(dev)
+    p = torch.empty_like(rhs)
+    res = autotune.apply_or_tune_poisson(plan, rhs, p, "fp32_refine", reps=2, path=path)
+    assert not res["cached"]
+    tx, ty = res["transform_ms"]["x"], res["transform_ms"]["y"]
+    assert autotune.get_variant(plan, autotune.STAGE_XFWD) == min(tx, key=tx.get)
+    assert autotune.get_variant(plan, autotune.STAGE_YFWD) == min(ty, key=ty.get)
+    monkeypatch.setenv("PF_TUNE_CACHE", path)
+    fresh = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine")
+    for st in (autotune.STAGE_ZSOLVE, autotune.STAGE_XFWD, autotune.STAGE_YFWD):
+        assert autotune.get_variant(fresh, st) == autotune.get_variant(plan, st)
+    # a tuned plan and a default one agree within the bar
+    q = torch.empty_like(rhs)
+    pf.poisson_solve(fresh, rhs, q)
+    d = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine", tuned=False)
+    r = torch.empty_like(rhs)
+    pf.poisson_solve(d, rhs, r)
+    torch.cuda.synchronize()
+    assert op.rel_l2(q.cpu().numpy(), r.cpu().numpy()) < 1e-10

@@ -187,3 +187,22 @@ def test_grouped_batch_rejects_shared_plans_and_overlaps():
         pf.poisson_solve_batched([p1, p2], [r1, a], [a, b])
     assert e.value.code == N.PF_ERR_ARG
 
+
+
+def test_plans_with_tuned_transform_shapes_run_one_by_one():
+    from paper_2502_06296_amd import autotune
+    specs = [(256, 64, 24, 1.5), (256, 64, 24, 1.3), (256, 64, 24, 1.1)]
+    plans, rhs = [], []
+    for t, sp in enumerate(specs):
+        plan, r = _problem(t, sp)
+        plans.append(plan)
+        rhs.append(r)
+    assert autotune.set_variant(plans[1], autotune.STAGE_XFWD, 3)
+    outs = [torch.empty_like(r) for r in rhs]
+    singles = [torch.empty_like(r) for r in rhs]
+    pf.poisson_solve_batched(plans, rhs, outs)
+    for pl, r, s1 in zip(plans, rhs, singles):
+        pf.poisson_solve(pl, r, s1)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, singles):
+        assert torch.equal(a, b)
