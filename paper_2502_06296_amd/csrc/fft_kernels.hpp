@@ -126,7 +126,7 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd(const double *__restrict__ in
 // iterate, W[slot 0] / ny, feed its plane means. The x inverse of the
 // iterate disappears: the final pass transforms W + (correction) at once.
 // Shape of k_xfwd; a workgroup takes LPW line pairs of one plane (2*LPW
-// divides ny), planes fastest so that the neighbour planes' W is in L2.
+// divides ny), in chunks of planes (see the block order below).
 // XW = 1 (2): walls at both x ends: X(f) is k_xfwd's cosine (sine)
 // transform, one real coefficient per slot, so a slot pair holds two x
 // modes of the same line; the x second difference is still -sx[slot], and
@@ -143,8 +143,17 @@ __device__ __forceinline__ void resid_spec_body(
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
   __shared__ C lds[LPW * lds_len(N)];
   const int tid = threadIdx.x, l = tid / TPL, t = tid % TPL;
+  // block order: chunks of kResidPlanes planes; within a chunk the planes
+  // run fastest, then the row groups, so that the rows j-1 and j+2 (read
+  // by the previous and the next row group of the same planes) and the
+  // planes k-1 and k+1 are read by blocks close in time and come from L2
   const unsigned b = xcd_block(bx_, gx_);
-  const int k = (int)(b % nz), j = (int)(b / nz) * 2 * LPW + 2 * l;  // lines j, j+1
+  const int njg = ny / (2 * LPW);  // row groups of a plane
+  const long per = (long)kResidPlanes * njg;
+  const int k0 = (int)(b / per) * kResidPlanes;
+  const int sz = nz - k0 < kResidPlanes ? nz - k0 : kResidPlanes;
+  const long rem = (long)b - (long)(k0 / kResidPlanes) * per;
+  const int k = k0 + (int)(rem % sz), j = (int)(rem / sz) * 2 * LPW + 2 * l;  // lines j, j+1
   C *buf = lds + l * lds_len(N);
   {
     // the first pass reads the line pair of f straight from global memory

@@ -66,6 +66,8 @@ constexpr int x_lpw(int n) {
 // the residual: twice the threads per line of the x transforms (its stencil
 // loads after the transform need the extra waves to hide their latency)
 constexpr int resid_tpl(int n) { return 2 * x_tpl(n) <= 256 && n % (2 * x_tpl(n)) == 0 ? 2 * x_tpl(n) : x_tpl(n); }
+// planes per chunk of the residual's block order
+constexpr int kResidPlanes = 8;
 constexpr int resid_lpw(int n) {
   const int by_threads = 256 / resid_tpl(n) < 1 ? 1 : 256 / resid_tpl(n);
   const int by_lds = 32768 / (n * 16);
