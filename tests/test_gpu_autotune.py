@@ -38,6 +38,31 @@ def test_every_zsolve_variant_matches_oracle(prec, tol):
     assert autotune.get_zsolve_variant(plan) == min(times, key=times.get)
 
 
+@pytest.mark.parametrize("xbc", ["walls", "dirichlet"])
+def test_every_zsolve_variant_matches_oracle_with_x_walls(xbc):
+    # x walls: every column pair carries two shifts, so each variant's
+    # two-pass path runs on every tile
+    nx, ny, nz = 128, 64, 120
+    f, zf = synth.channel_rhs(37, nx, ny, nz, beta=1.5)
+    xc = {"walls": ogrid.X_WALLS, "dirichlet": ogrid.X_DIRICHLET}[xbc]
+    ref = op.solve_poisson(f, zf, LX, LY, xbc=xc)
+    dev = torch.device("cuda", 0)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine", xbc=xbc)
+    rhs = torch.from_numpy(f).to(dev)
+    p = torch.empty_like(rhs)
+    tried = 0
+    for v in autotune.zsolve_variants(plan):
+        if not autotune.set_zsolve_variant(plan, v):
+            continue
+        pf.poisson_solve(plan, rhs, p)
+        torch.cuda.synchronize()
+        err = op.rel_l2(p.cpu().numpy(), ref)
+        print(f"x {xbc} variant {v}: {err:.2e}", flush=True)
+        assert err < 1e-10, v
+        tried += 1
+    assert tried >= 4
+
+
 def test_pcr_shapes_agree_and_tuner_keeps_fastest(tmp_path):
     nz, ny, nx = 300, 8, 128
     zf = synth.tanh_faces(nz)
