@@ -359,10 +359,12 @@ pf_status pcr_timing_read(pf_pcr_plan *plan, double *ms, int32_t *count);
  * columns per workgroup, occupancy bound, reciprocal flavour). For
  * PF_STAGE_XFWD (the x forward, the x inverse and the refinement's residual)
  * and PF_STAGE_YFWD (both y transforms) of a direction without walls they
- * are 4 transform shapes: 0 the default, 1 half the threads per line, 2
+ * are 5 transform shapes: 0 the default, 1 half the threads per line, 2
  * twice the threads per line (x) or the lines per workgroup (y), 3 the
- * radix capped at 8; shapes 1-3 exist for the lengths 256, 512, 1024 and
- * 2048. Every variant computes the same solution to rounding. *count
+ * radix capped at 8, 4 (y only, every length) the default shape in a
+ * persistent launch that loads each workgroup's next lines while it
+ * transforms the current ones; shapes 1-3 exist for the lengths 256, 512,
+ * 1024 and 2048. Every variant computes the same solution to rounding. *count
  * receives the number of
  * variants; poisson_set_variant returns PF_ERR_UNSUPPORTED for a variant
  * that does not fit the plan's grid. Plans with non-default transform

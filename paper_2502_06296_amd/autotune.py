@@ -98,6 +98,13 @@ def get_variant(plan, stage):
     return v.value
 
 
+def transform_shape_count(plan):
+    """Number of transform launch shapes (some fit only some plans)."""
+    cnt = C.c_int32()
+    N.check(N.lib().poisson_variant_count(plan.handle, STAGE_XFWD, C.byref(cnt)))
+    return cnt.value
+
+
 def tune_transforms(plan, rhs, p, reps=3):
     """Time every transform shape that fits the plan, x and y direction
     separately (the x shape by the x forward, x inverse and residual stages,

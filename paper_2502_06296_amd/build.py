@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libpf_channel.so")
-SOURCES = ["kernels_fft.hip", "kernels_fft_alt.hip", "kernels_z.hip", "api.cpp"]
+SOURCES = ["kernels_fft.hip", "kernels_fft_alt.hip", "kernels_fft_pf.hip", "kernels_z.hip", "api.cpp"]
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1063,7 +1063,8 @@ static bool transform_shape_fits(const pf_poisson_plan *pl, int stage, int v) {
   if (stage == PF_STAGE_XFWD)
     return pl->xbc == PF_X_PERIODIC && pf::xfwd_shape(pl->nx, v).ok && pf::xinv_shape(pl->nx, v).ok &&
            pf::resid_shape(pl->nx, v).ok && pl->ny % (2 * pf::resid_shape(pl->nx, v).lpw) == 0;
-  const pf::TShape h = pl->prec == PF_FP64 ? pf::y_shape<double>(pl->ny, v) : pf::y_shape<float>(pl->ny, v);
+  const pf::TShape h = pl->prec == PF_FP64 ? pf::y_shape<double>(pl->ny, v == pf::kYPersistShape ? 0 : v)
+                                            : pf::y_shape<float>(pl->ny, v == pf::kYPersistShape ? 0 : v);
   return pl->xbc == PF_X_PERIODIC && pl->ybc == PF_Y_PERIODIC && h.ok && pl->nx % (2 * h.lpw) == 0;
 }
 

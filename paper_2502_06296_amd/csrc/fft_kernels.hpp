@@ -266,6 +266,73 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 // XR (periodic y only): the x slots are real coefficients of x walls'
 // cosine or sine transforms, so every slot pair is two real columns and takes
 // the split into packed real y spectra that slots 0 and 1 take otherwise.
+// The y forward's store of the workgroup holding slots 0 and 1 (and, with x
+// walls, of every workgroup), from the transformed lines in LDS: slots 0
+// and 1 are two real columns (x modes 0 and nx/2), split into two packed
+// real y spectra (rows 2q, 2q+1 hold the real and imaginary parts of mode
+// q; rows 0 and 1 the modes 0 and ny/2) in float64 before rounding to the
+// storage type; the other slot pairs are stored as they are.
+template <typename T, int N, int TPL, int LPW, bool XR>
+__device__ __forceinline__ void yfwd_split_store(const cplx<double> *lds, T *base, int nx, int tid) {
+  using C = cplx<double>;
+  constexpr int NT = TPL * LPW;
+#pragma unroll
+  for (int s = 0; s < N / TPL; ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, y = e / LPW;
+    const C *b2 = lds + l2 * y_stride(N);
+    if (l2 != 0 && !XR) {
+      const C v = b2[lds_idx(y)];
+      st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
+    } else if (y < N / 2) {
+      const int q = y;
+      C r0, r1;
+      if (q == 0) {
+        r0 = b2[lds_idx(0)];
+        r1 = b2[lds_idx(N / 2)];
+      } else {
+        C A, B;
+        split_pair<double>(b2[lds_idx(q)], b2[lds_idx(N - q)], A, B);
+        r0 = mkc<double>(A.x, B.x);
+        r1 = mkc<double>(A.y, B.y);
+      }
+      st2<T>(base + (size_t)(2 * q) * nx + 2 * l2, r0.x, r0.y);
+      st2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2, r1.x, r1.y);
+    }
+  }
+}
+
+// Inverse of yfwd_split_store: the workgroup's lines into LDS, slots 0 and 1
+// (every slot pair with x walls) joined from their two packed real spectra.
+// The caller publishes the LDS lines with a barrier.
+template <typename T, int N, int TPL, int LPW, bool XR>
+__device__ __forceinline__ void yinv_join_load(cplx<double> *lds, const T *base, int nx, int tid) {
+  using C = cplx<double>;
+  constexpr int NT = TPL * LPW;
+#pragma unroll
+  for (int s = 0; s < N / TPL; ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, y = e / LPW;
+    C *b2 = lds + l2 * y_stride(N);
+    if (l2 != 0 && !XR) {
+      b2[lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l2);
+    } else if (y < N / 2) {
+      const int q = y;
+      const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
+      const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
+      if (q == 0) {
+        b2[lds_idx(0)] = r0;
+        b2[lds_idx(N / 2)] = r1;
+      } else {
+        C zq, zn;
+        join_pair<double>(mkc<double>(r0.x, r1.x), mkc<double>(r0.y, r1.y), zq, zn);
+        b2[lds_idx(q)] = zq;
+        b2[lds_idx(N - q)] = zn;
+      }
+    }
+  }
+}
+
 template <typename T, int N, int TPL, int LPW, int YW, bool XR = false, int RO = 0>
 __device__ __forceinline__ void yfwd_body(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ tw,
@@ -318,30 +385,7 @@ __device__ __forceinline__ void yfwd_body(T *__restrict__ data,
   // 2q+1 hold the real and imaginary parts of mode q; rows 0 and 1 the
   // modes 0 and ny/2) in float64 before rounding to the storage type
   fft_line_io<double, N, TPL, false, true, false, RO>(buf, tw, t, src, [](int, const C &) {});
-#pragma unroll
-  for (int s = 0; s < N / TPL; ++s) {
-    const int e = tid + s * NT;
-    const int l2 = e % LPW, y = e / LPW;
-    const C *b2 = lds + l2 * y_stride(N);
-    if (l2 != 0 && !XR) {
-      const C v = b2[lds_idx(y)];
-      st2<T>(base + (size_t)y * nx + 2 * l2, v.x, v.y);
-    } else if (y < N / 2) {
-      const int q = y;
-      C r0, r1;
-      if (q == 0) {
-        r0 = b2[lds_idx(0)];
-        r1 = b2[lds_idx(N / 2)];
-      } else {
-        C A, B;
-        split_pair<double>(b2[lds_idx(q)], b2[lds_idx(N - q)], A, B);
-        r0 = mkc<double>(A.x, B.x);
-        r1 = mkc<double>(A.y, B.y);
-      }
-      st2<T>(base + (size_t)(2 * q) * nx + 2 * l2, r0.x, r0.y);
-      st2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2, r1.x, r1.y);
-    }
-  }
+  yfwd_split_store<T, N, TPL, LPW, XR>(lds, base, nx, tid);
 }
 template <typename T, int N, int TPL, int LPW, int YW, bool XR = false, int RO = 0>
 __global__ __launch_bounds__(TPL *LPW) void k_yfwd(T *__restrict__ data,
@@ -417,28 +461,7 @@ __device__ __forceinline__ void yinv_body(T *__restrict__ data,
     fft_line_io<double, N, TPL, true, true, true, RO>(buf, tw, t, src, dst);
     return;
   }
-#pragma unroll
-  for (int s = 0; s < N / TPL; ++s) {
-    const int e = tid + s * NT;
-    const int l2 = e % LPW, y = e / LPW;
-    C *b2 = lds + l2 * y_stride(N);
-    if (l2 != 0 && !XR) {
-      b2[lds_idx(y)] = ld2<T>(base + (size_t)y * nx + 2 * l2);
-    } else if (y < N / 2) {
-      const int q = y;
-      const C r0 = ld2<T>(base + (size_t)(2 * q) * nx + 2 * l2);
-      const C r1 = ld2<T>(base + (size_t)(2 * q + 1) * nx + 2 * l2);
-      if (q == 0) {
-        b2[lds_idx(0)] = r0;
-        b2[lds_idx(N / 2)] = r1;
-      } else {
-        C zq, zn;
-        join_pair<double>(mkc<double>(r0.x, r1.x), mkc<double>(r0.y, r1.y), zq, zn);
-        b2[lds_idx(q)] = zq;
-        b2[lds_idx(N - q)] = zn;
-      }
-    }
-  }
+  yinv_join_load<T, N, TPL, LPW, XR>(lds, base, nx, tid);
   __syncthreads();
   fft_line_io<double, N, TPL, true, false, true, RO>(buf, tw, t, [](int) { return C{}; }, dst);
 }
@@ -448,6 +471,81 @@ __global__ __launch_bounds__(TPL *LPW) void k_yinv(T *__restrict__ data,
                                                    const cplx<double> *__restrict__ ctw, int nx,
                                                    int nib, size_t sp) {
   yinv_body<T, N, TPL, LPW, YW, XR, RO>(data, tw, ctw, nx, nib, sp, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------- persistent y transforms
+// The periodic y transforms of k_yfwd / k_yinv for a grid of at most one
+// round of resident workgroups: workgroup w takes the blocks i G + w' of
+// rounds i = 0, 1, ... (G workgroups; w' the XCD-contiguous renumbering of
+// w in full rounds), and loads the next block's rows into registers right
+// after the current block's first pass, so that those loads travel while
+// the current block's other passes and stores run. The y inverse of slots 0
+// and 1 joins its two packed real spectra while loading, so it takes its
+// rows itself (without the prefetch). Same arithmetic as k_yfwd / k_yinv.
+__device__ __forceinline__ long pf_round_block(long i, long G, long nblk) {
+  const long b0 = i * G;
+  return b0 + G <= nblk ? b0 + xcd_block(blockIdx.x, (unsigned)G) : b0 + blockIdx.x;
+}
+template <typename T, int N, int TPL, int LPW, bool INV>
+__global__ __launch_bounds__(TPL *LPW) void k_y_persist(T *__restrict__ data,
+                                                        const cplx<double> *__restrict__ tw, int nx,
+                                                        int nib, size_t sp, long nblk) {
+  using C = cplx<double>;
+  using F = FirstPass<N, TPL, 0>;
+  static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
+  __shared__ C lds[LPW * y_stride(N)];
+  const int tid = threadIdx.x;
+  const int l = tid % LPW, t = tid / LPW;
+  C *buf = lds + l * y_stride(N);
+  const long G = gridDim.x;
+  long blk = pf_round_block(0, G, nblk);
+  if (blk >= nblk) return;  // uniform
+  auto at = [&](long b) { return data + (size_t)(b / nib) * sp + (size_t)(b % nib) * 2 * LPW; };
+  // a block whose first pass starts from registers
+  auto from_regs = [&](long b) { return !INV || b % nib != 0; };
+  cplx<T> pre[F::IT][F::R];
+  auto load = [&](long b) {
+    const T *bb = at(b);
+    first_load<N, TPL, 0>(pre, t, [&](int y) { return *reinterpret_cast<const cplx<T> *>(bb + (size_t)y * nx + 2 * l); });
+  };
+  if (from_regs(blk)) load(blk);
+  for (long i = 0;; ++i) {
+    const int ib = (int)(blk % nib);
+    T *base = at(blk);
+    const long nb = pf_round_block(i + 1, G, nblk);
+    const bool more = nb < nblk;  // uniform
+    // the thread's positions as values the compiler cannot carry from one
+    // block to the next: otherwise it keeps every address of the passes
+    // live across the loop and runs out of registers
+    int tl = t, ll = l, tidl = tid;
+    asm volatile("" : "+v"(tl), "+v"(ll), "+v"(tidl));
+    C *bufl = lds + ll * y_stride(N);
+    // nothing reads the LDS lines of the previous block any more
+    if (i > 0) __syncthreads();
+    auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * ll, v.x, v.y); };
+    const bool regs = from_regs(blk);  // uniform
+    if (regs) {
+      fft_from_regs<double, N, TPL, INV, 0>(bufl, pre, tl);
+    } else {
+      yinv_join_load<T, N, TPL, LPW, false>(lds, base, nx, tidl);
+      __syncthreads();
+    }
+    if (more && from_regs(nb)) {
+      const T *bb = at(nb);
+      first_load<N, TPL, 0>(pre, tl, [&](int y) { return *reinterpret_cast<const cplx<T> *>(bb + (size_t)y * nx + 2 * ll); });
+    }
+    if (!regs) {
+      // the joined lines are in LDS: every pass from there
+      fft_line_io<double, N, TPL, true, false, true, 0>(bufl, tw, tl, [](int) { return C{}; }, dst);
+    } else if (INV || ib != 0) {
+      fft_rest<double, N, TPL, INV, true, 0>(bufl, tw, tl, dst);
+    } else {
+      fft_rest<double, N, TPL, INV, false, 0>(bufl, tw, tl, dst);
+      yfwd_split_store<T, N, TPL, LPW, false>(lds, base, nx, tidl);
+    }
+    if (!more) break;
+    blk = nb;
+  }
 }
 
 // ------------------------------------------------------------- x inverse

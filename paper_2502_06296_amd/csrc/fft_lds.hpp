@@ -297,6 +297,56 @@ __device__ __forceinline__ void fft_line_io(cplx<T> *buf, const cplx<T> *__restr
   fft_passes_io<T, N, 1, TPL, INV, GIN, GOUT, RO>(buf, tw, t, src, dst);
 }
 
+// The first pass of fft_line_io split in two, so that a line's inputs can
+// be loaded while the previous line is being transformed: first_load reads
+// the values the thread's first-pass butterflies take (radix R of the first
+// pass, no twiddles) into registers; fft_from_regs transforms them, writes
+// the first pass's output to the LDS line (ending with a barrier), and
+// fft_rest runs the remaining passes as fft_line_io does.
+template <int N, int TPL, int RO>
+struct FirstPass {
+  static constexpr int R = pick_radix<N, RO>();
+  static constexpr int NB = N / R;
+  static constexpr int IT = (NB + TPL - 1) / TPL;
+  static_assert(R != 0 && R < N, "a first pass of a longer transform");
+};
+template <int N, int TPL, int RO, class V, int IT, int R, class Src>
+__device__ __forceinline__ void first_load(V (&v)[IT][R], int t, Src src) {
+  using F = FirstPass<N, TPL, RO>;
+  static_assert(IT == F::IT && R == F::R, "registers of the first pass");
+#pragma unroll
+  for (int it = 0; it < F::IT; ++it) {
+    const int j = t + it * TPL;
+    if (F::NB % TPL == 0 || j < F::NB) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[it][r] = src(j + r * F::NB);
+    }
+  }
+}
+template <typename T, int N, int TPL, bool INV, int RO, class V, int IT, int R>
+__device__ __forceinline__ void fft_from_regs(cplx<T> *buf, const V (&in)[IT][R], int t) {
+  using F = FirstPass<N, TPL, RO>;
+  static_assert(IT == F::IT && R == F::R, "registers of the first pass");
+  cplx<T> v[F::IT][F::R];
+#pragma unroll
+  for (int it = 0; it < F::IT; ++it) {
+    const int j = t + it * TPL;
+    if (F::NB % TPL == 0 || j < F::NB) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[it][r] = mkc<T>((T)in[it][r].x, (T)in[it][r].y);
+      dft_r<T, F::R, INV>(v[it]);
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) buf[lds_idx(j * F::R + r)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+template <typename T, int N, int TPL, bool INV, bool GOUT, int RO, class Dst>
+__device__ __forceinline__ void fft_rest(cplx<T> *buf, const cplx<T> *__restrict__ tw, int t, Dst dst) {
+  fft_passes_io<T, N, FirstPass<N, TPL, RO>::R, TPL, INV, false, GOUT, RO>(
+      buf, tw, t, [](int) { return cplx<T>{}; }, dst);
+}
+
 // Full complex transform of one LDS line, in place (unnormalised). Every
 // thread of the workgroup must call it (it contains barriers).
 template <typename T, int N, int TPL, bool INV>

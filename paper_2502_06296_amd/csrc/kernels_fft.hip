@@ -361,6 +361,7 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
                        const cplx<double> *ctw, int yw, hipStream_t st, bool xr, int shape) {
   if (shape != 0) {
     if (yw != 0 || xr) return hipErrorInvalidValue;
+    if (shape == kYPersistShape) return launch_y_persist<T>(false, nx, ny, nz, data, sp, tw, st);
     return launch_y_alt<T>(false, shape, nx, ny, nz, data, sp, tw, st);
   }
   switch (ny) {
@@ -397,6 +398,7 @@ hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
                        const cplx<double> *ctw, int yw, hipStream_t st, bool xr, int shape) {
   if (shape != 0) {
     if (yw != 0 || xr) return hipErrorInvalidValue;
+    if (shape == kYPersistShape) return launch_y_persist<T>(true, nx, ny, nz, data, sp, tw, st);
     return launch_y_alt<T>(true, shape, nx, ny, nz, data, sp, tw, st);
   }
   switch (ny) {

@@ -107,7 +107,11 @@ constexpr int y_lpw(int n) {
 // LDS limits allow them; shapes 0-2 compute the same butterflies (up to the
 // compiler's fusion of multiply-adds), shape 3 in a different order of
 // passes.
-constexpr int kTransformShapes = 4;
+// Shape 4 (y transforms only, every length): the default threads and lines
+// in a persistent launch that prefetches each workgroup's next block
+// (k_y_persist).
+constexpr int kTransformShapes = 5;
+constexpr int kYPersistShape = 4;
 constexpr bool tuned_len(int n) { return n == 256 || n == 512 || n == 1024 || n == 2048; }
 struct TShape {
   int tpl, lpw, ro;
@@ -195,6 +199,10 @@ hipError_t launch_resid_alt(int shape, int nx, int ny, int nz, const double *f, 
 template <typename T>
 hipError_t launch_y_alt(bool inv, int shape, int nx, int ny, int nz, T *data, size_t sp,
                         const cplx<double> *tw, hipStream_t st);
+// the persistent y transforms (shape kYPersistShape, periodic x and y)
+template <typename T>
+hipError_t launch_y_persist(bool inv, int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
+                            hipStream_t st);
 template <typename TS, typename TO>
 hipError_t launch_xinv_alt(int shape, int nx, int ny, const TS *in, size_t sp, TO *out,
                            const cplx<double> *tw, const double *zm, const TS *in2, double scale,
