@@ -11,7 +11,9 @@ floor), slow and direct:
                     family, modified wavenumbers in the packed slot order.
 * ``transforms`` -- packed real Fourier transform of the paper's App. A
                     layout, on top of numpy's FFT (a library primitive); the
-                    cosine transform for walls in y, from its definition.
+                    cosine and sine transforms for walls in x or y and the
+                    type-I sine transform of a field on the y faces, from
+                    their definitions.
 * ``tridiag``    -- subtraction-free Thomas elimination, the paper's
                     Algorithm 1 and Algorithm 2 (plain and subtraction-free),
                     the reduced boundary system of the partition method.

@@ -80,6 +80,21 @@ def wall_d2(n, h, value_zero=False):
     return M / (h * h)
 
 
+def face_d2(n, h):
+    """Dense second difference on the n - 1 interior faces of n cells of
+    spacing h between two walls where the value vanishes: each face couples
+    to its two neighbours, a wall face counting as zero."""
+    m = n - 1
+    M = np.zeros((m, m))
+    for i in range(m):
+        M[i, i] = -2
+        if i > 0:
+            M[i, i - 1] = 1
+        if i < m - 1:
+            M[i, i + 1] = 1
+    return M / (h * h)
+
+
 def _d2(n, length, bc):
     """Second difference of one wall-parallel direction: periodic (bc 0),
     between zero-gradient (1) or value-zero (2) walls."""
@@ -127,12 +142,24 @@ def helmholtz3d_dense(r, zf, s, bc, lx, ly, ybc=0, xbc=0):
     """Dense solve of (I - s L) u = r, L the 3-D operator of the staggered
     grid: second differences in x and y, each periodic (0) or between
     zero-gradient (1) or value-zero (2) walls, plus L_z of family bc (C-order
-    (n, ny, nx) flattening, n = nz or nz - 1)."""
+    (n, ny, nx) flattening, n = nz or nz - 1). ybc = 3: a field on the y faces
+    between value-zero walls (row j the face j + 1, row ny - 1 the top wall
+    face, zero in the result)."""
     n, ny, nx = r.shape
-    Ix, Iy = np.eye(nx), np.eye(ny)
+    if ybc == 3:
+        # a field on the y faces: unknowns on the ny - 1 interior faces, the
+        # wall row (ny - 1) is zero
+        u = np.zeros(r.shape, dtype=np.result_type(r, np.float64))
+        u[:, : ny - 1, :] = _helm_dense(r[:, : ny - 1, :], zf, s, bc, lx, face_d2(ny, ly / ny), xbc)
+        return u
+    return _helm_dense(r, zf, s, bc, lx, _d2(ny, ly, ybc), xbc)
+
+
+def _helm_dense(r, zf, s, bc, lx, Dy, xbc):
+    n, my, nx = r.shape
+    Ix, Iy = np.eye(nx), np.eye(my)
     Dz = lz_dense(zf, bc)
     Iz = np.eye(Dz.shape[0])
-    Dy = _d2(ny, ly, ybc)
     L = (np.kron(Iz, np.kron(Iy, _d2(nx, lx, xbc))) + np.kron(Iz, np.kron(Dy, Ix))
          + np.kron(Dz, np.kron(Iy, Ix)))
     M = np.eye(L.shape[0]) - s * L

@@ -24,6 +24,8 @@ DIRICHLET_FACE = 2     # w at interior faces, w = 0 on the wall faces
 Y_PERIODIC = 0         # y periodic (the channel)
 Y_WALLS = 1            # zero-gradient (Neumann) walls at both y ends, cell centres
 Y_DIRICHLET = 2        # value-zero (Dirichlet) walls at both y ends, cell centres
+Y_FACES = 3            # value-zero walls at both y ends, unknowns on the y faces
+                       # (row j is face j + 1; row ny - 1 is the top wall face)
 
 X_PERIODIC = 0         # x periodic (the channel)
 X_WALLS = 1            # zero-gradient walls at both x ends, cell centres
@@ -99,6 +101,17 @@ def wall_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
     """sigma per cosine mode q = 0..n-1 (natural order) of the cell-centred
     second difference with zero-gradient walls: 4 sin^2(pi q / (2n)) / dx^2."""
     q = np.arange(n, dtype=dtype)
+    dx = dtype(length) / dtype(n)
+    s = np.sin(np.pi * q / (2 * dtype(n)))
+    return 4 * s * s / (dx * dx)
+
+
+def face_wall_wavenumbers(n: int, length, dtype=np.float64) -> np.ndarray:
+    """sigma per type-I sine mode of the second difference on the n - 1
+    interior y faces between two walls where the value vanishes: mode q =
+    1..n-1 in row q - 1, 4 sin^2(pi q / (2n)) / dy^2. Row n - 1 (the wall
+    face, no mode) gets the value of q = n, 4 / dy^2."""
+    q = np.arange(n, dtype=dtype) + 1
     dx = dtype(length) / dtype(n)
     s = np.sin(np.pi * q / (2 * dtype(n)))
     return 4 * s * s / (dx * dx)

@@ -56,6 +56,8 @@ def _y_transform(ybc):
         return transforms.dct2, transforms.idct2, grid.wall_wavenumbers
     if ybc == grid.Y_DIRICHLET:
         return transforms.dst2, transforms.idst2, grid.dirichlet_wall_wavenumbers
+    if ybc == grid.Y_FACES:
+        return transforms.dst1, transforms.idst1, grid.face_wall_wavenumbers
     return transforms.rfft_packed, transforms.irfft_packed, grid.modified_wavenumbers
 
 
@@ -75,6 +77,8 @@ def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     where the value vanishes: the sine transform. xbc does the same for the x
     ends (grid.X_WALLS, grid.X_DIRICHLET). With value-zero walls in x or y, L7
     is nonsingular, so f is not projected and p carries no pin."""
+    if ybc == grid.Y_FACES:
+        raise ValueError("the pressure lives at cell centres: y faces are for the 3-D Helmholtz")
     dt = f.dtype.type
     nz, ny, nx = f.shape
     singular = ybc != grid.Y_DIRICHLET and xbc != grid.X_DIRICHLET
@@ -153,6 +157,9 @@ def solve_helmholtz3d(r, zf, s, bc, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERI
     dt = r.dtype.type
     n, ny, nx = r.shape
     s = dt(s)
+    # ybc = grid.Y_FACES: a field on the y faces (the face-located velocity
+    # of a y-walled grid): the type-I sine transform over the ny - 1 interior
+    # faces; the wall row stays zero
     xf, xi, xw = _x_transform(xbc)
     yf, yi, yw = _y_transform(ybc)
     R = yf(xf(r, axis=2), axis=1)

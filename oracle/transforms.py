@@ -117,3 +117,30 @@ def idst2(Y: np.ndarray, axis: int) -> np.ndarray:
     M = np.sin(np.pi * np.outer(2 * t + 1, t + 1) / (2 * n))
     M[:, n - 1] *= 0.5
     return np.moveaxis((Y @ M.T) / n, -1, axis)
+
+
+def dst1(x: np.ndarray, axis: int) -> np.ndarray:
+    """Type-I sine transform along ``axis`` for a field on the y faces between
+    two walls where it vanishes (the face-located velocity of Sec. 2.2.1's
+    wall-bounded directions): n rows, row m - 1 holding face m = 1..n-1 (the
+    interior faces) and row n - 1 the top wall face. From the definition:
+    X_q = 2 sum_{m=1}^{n-1} x_m sin(pi q m / n), q = 1..n-1, written to row
+    q - 1; the wall row of x is not read and row n - 1 of X is zero. A dense
+    matrix product; ``x`` may be complex."""
+    x = np.moveaxis(np.asarray(x), axis, -1)
+    n = x.shape[-1]
+    m = np.arange(1, n)
+    M = np.zeros((n, n))
+    M[: n - 1, : n - 1] = 2.0 * np.sin(np.pi * np.outer(m, m) / n)
+    return np.moveaxis(x @ M.T, -1, axis)
+
+
+def idst1(X: np.ndarray, axis: int) -> np.ndarray:
+    """Inverse of ``dst1``: x_m = (1 / n) sum_{q=1}^{n-1} X_q sin(pi q m / n)
+    on the interior faces; the wall row is zero."""
+    X = np.moveaxis(np.asarray(X), axis, -1)
+    n = X.shape[-1]
+    m = np.arange(1, n)
+    M = np.zeros((n, n))
+    M[: n - 1, : n - 1] = np.sin(np.pi * np.outer(m, m) / n) / n
+    return np.moveaxis(X @ M.T, -1, axis)

@@ -228,3 +228,59 @@ def _wall_ghost_not_negated(orig):
 def test_planted_ywall_mistake_is_caught(monkeypatch, target, attr, mut):
     monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
     assert _ywall_pin_errors() > 1e-6
+
+
+# ------------------------------------------------------------- y faces
+
+def _yface_pin_errors():
+    """Largest error of the y-face pins: the dense brute force of the 3-D
+    Helmholtz on the faces and the odd-extension DFT of the type-I sine
+    transform."""
+    errs = []
+    for bc, n in ((grid.DIRICHLET_CENTRE, 5), (grid.DIRICHLET_FACE, 4)):
+        zf = synth.tanh_faces(5, 2.0, 1.5)
+        r = synth.uniform_pm1(90 + bc, (n, 6, 4))
+        errs.append(poisson.rel_l2(poisson.solve_helmholtz3d(r, zf, 0.05, bc, LX, LY, ybc=grid.Y_FACES),
+                                   dense.helmholtz3d_dense(r, zf, 0.05, bc, LX, LY, ybc=3)))
+    n = 7
+    x = synth.uniform_pm1(95, (n,))
+    E = transforms.dft_direct(np.concatenate([[0], x[: n - 1], [0], -x[: n - 1][::-1]]))
+    errs.append(np.max(np.abs(transforms.dst1(x, axis=0)[: n - 1] - 1j * E[1:n])))
+    return max(errs)
+
+
+def test_unmutated_yface_oracle_passes():
+    assert _yface_pin_errors() < 1e-12
+
+
+def _face_modes_from_zero(orig):
+    def f(n, length, dtype=np.float64):
+        return np.roll(orig(n, length, dtype), 1)                # sigma_{q-1} for mode q
+    return f
+
+
+def _face_sine_over_n_plus_one(orig):
+    def f(x, axis):
+        x = np.moveaxis(np.asarray(x), axis, -1)
+        n = x.shape[-1]
+        m = np.arange(1, n)
+        M = np.zeros((n, n))
+        M[: n - 1, : n - 1] = 2.0 * np.sin(np.pi * np.outer(m, m) / (n + 1))   # n + 1 for n
+        return np.moveaxis(x @ M.T, -1, axis)
+    return f
+
+
+def _face_inverse_without_scale(orig):
+    def f(X, axis):
+        return orig(X, axis) * X.shape[axis] / (X.shape[axis] - 1)            # 1/(n-1) for 1/n
+    return f
+
+
+@pytest.mark.parametrize("target,attr,mut", [
+    (grid, "face_wall_wavenumbers", _face_modes_from_zero),
+    (transforms, "dst1", _face_sine_over_n_plus_one),
+    (transforms, "idst1", _face_inverse_without_scale),
+])
+def test_planted_yface_mistake_is_caught(monkeypatch, target, attr, mut):
+    monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
+    assert _yface_pin_errors() > 1e-6

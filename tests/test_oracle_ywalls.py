@@ -133,3 +133,74 @@ def test_helmholtz3d_with_y_walls_matches_dense(ybc, dense_ybc, bc):
     got = poisson.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=ybc)
     ref = dense.helmholtz3d_dense(r, zf, s, bc, LX, LY, ybc=dense_ybc)
     assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+# a field on the y faces between value-zero walls (the face-located velocity
+# of a y-walled grid): the type-I sine transform
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 12])
+def test_type1_sine_transform_is_the_odd_extension_dft(n):
+    rng = np.random.default_rng(70 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)   # row n-1: the wall, not read
+    f = x[: n - 1]                                              # faces 1..n-1
+    e = np.concatenate([[0], f, [0], -f[::-1]])                # odd extension, length 2n
+    E = transforms.dft_direct(e)
+    # the odd extension's DFT at q is -2i sum_m x_m sin(pi q m / n) = -i X_q
+    ref = np.zeros(n, dtype=complex)
+    ref[: n - 1] = 1j * E[1:n]
+    X = transforms.dst1(x, axis=0)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    back = transforms.idst1(X, axis=0)
+    assert np.max(np.abs(back[: n - 1] - f)) <= 1e-13 * n
+    assert back[n - 1] == 0
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 13])
+def test_type1_sine_vectors_diagonalise_the_face_second_difference(n):
+    h = 0.31
+    D = dense.face_d2(n, h)
+    sig = grid.face_wall_wavenumbers(n, n * h)
+    m = np.arange(1, n)
+    for q in range(1, n):
+        e = np.sin(np.pi * q * m / n)
+        assert np.max(np.abs(D @ e + sig[q - 1] * e)) <= 1e-10 * max(1.0, sig[q - 1])
+
+
+@pytest.mark.parametrize("bc", [grid.DIRICHLET_CENTRE, grid.DIRICHLET_FACE])
+@pytest.mark.parametrize("xbc,dense_xbc", [(grid.X_PERIODIC, 0), (grid.X_WALLS, 1), (grid.X_DIRICHLET, 2)])
+def test_helmholtz3d_on_y_faces_matches_dense(bc, xbc, dense_xbc):
+    nx, ny, nz, s = 4, 6, 5, 0.05
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    n = nz if bc == grid.DIRICHLET_CENTRE else nz - 1
+    r = synth.uniform_pm1(80 + bc + 3 * dense_xbc, (n, ny, nx))
+    got = poisson.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=grid.Y_FACES, xbc=xbc)
+    ref = dense.helmholtz3d_dense(r, zf, s, bc, LX, LY, ybc=3, xbc=dense_xbc)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.all(got[:, ny - 1, :] == 0)
+
+
+def test_helmholtz3d_on_y_faces_residual_from_face_fluxes():
+    # (I - s L) u = r on the interior faces, L assembled from face-to-face
+    # differences with the wall faces at zero, independently of the dense
+    # matrices above
+    nx, ny, nz, s = 8, 10, 6, 0.03
+    zf = synth.tanh_faces(nz, 2.0, 1.2)
+    r = synth.uniform_pm1(91, (nz, ny, nx))
+    u = poisson.solve_helmholtz3d(r, zf, s, grid.DIRICHLET_CENTRE, LX, LY, ybc=grid.Y_FACES)
+    dx, dy = LX / nx, LY / ny
+    ui = u[:, : ny - 1, :]
+    pad = np.concatenate([np.zeros((nz, 1, nx)), ui, np.zeros((nz, 1, nx))], axis=1)
+    lyy = (pad[:, 2:, :] - 2 * ui + pad[:, :-2, :]) / dy ** 2
+    lxx = (np.roll(ui, -1, 2) - 2 * ui + np.roll(ui, 1, 2)) / dx ** 2
+    al, ga, ex = grid.zop(zf, grid.DIRICHLET_CENTRE)
+    lz = -(al + ga + ex)[:, None, None] * ui
+    lz[1:] += al[1:, None, None] * ui[:-1]
+    lz[:-1] += ga[:-1, None, None] * ui[1:]
+    res = r[:, : ny - 1, :] - (ui - s * (lxx + lyy + lz))
+    assert np.max(np.abs(res)) <= 1e-12 * np.max(np.abs(r))
+
+
+def test_poisson_rejects_y_faces():
+    zf = synth.tanh_faces(4, 2.0, 1.0)
+    with pytest.raises(ValueError):
+        poisson.solve_poisson(np.zeros((4, 4, 4)), zf, LX, LY, ybc=grid.Y_FACES)
