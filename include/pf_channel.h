@@ -92,13 +92,23 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * (v[:, ny-1, :] is then the top wall face: no flux through it enters the
  * divergence and it is left unchanged) and returns PF_ERR_UNSUPPORTED for
  * PF_Y_DIRICHLET.
+ * PF_Y_FACES (helmholtz3d_plan only; poisson_plan returns
+ * PF_ERR_UNSUPPORTED): a field on the y faces between walls where it
+ * vanishes, the face-located velocity v of a y-walled grid: row j of each
+ * plane holds the face j + 1 (j = 0..ny-2) and row ny - 1 the top wall face,
+ * where the solve leaves zero up to rounding (about 1e-16 of the field's
+ * largest value: the x inverse transforms it together with row ny - 2; r
+ * there is not read). The y transform is the
+ * type-I sine transform of the ny - 1 interior faces (the sine member of
+ * Sec. 2.2.1's transforms for face unknowns), wavenumbers
+ * 4 sin^2(pi q / 2 ny) / dy^2, q = 1..ny-1; 2 ny must be a built length.
  * xbc: the same choice at both x ends (PF_X_PERIODIC, PF_X_WALLS: the cosine
  * transform along x, wavenumbers 4 sin^2(pi q / 2 nx) / dx^2; PF_X_DIRICHLET:
  * the sine transform, 4 sin^2(pi (q + 1) / 2 nx) / dx^2, nonsingular), with
  * nx cell-centred unknowns, alone or with y walls; built for poisson_plan /
  * poisson_solve and helmholtz3d_plan / helmholtz3d_solve (poisson_project
  * returns PF_ERR_UNSUPPORTED for x walls). */
-enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2 };
+enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2, PF_Y_FACES = 3 };
 enum { PF_X_PERIODIC = 0, PF_X_WALLS = 1, PF_X_DIRICHLET = 2 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;

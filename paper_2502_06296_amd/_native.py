@@ -128,7 +128,8 @@ def check(code):
 def make_grid(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5, zf=None,
               ybc=0, xbc=0):
     """(PfGrid, keep-alive) for the C ABI; zf is an optional host array of nz+1 faces;
-    ybc and xbc: 0 periodic, 1 zero-gradient walls, 2 value-zero walls."""
+    ybc and xbc: 0 periodic, 1 zero-gradient walls, 2 value-zero walls; ybc 3:
+    a field on the y faces between value-zero walls."""
     keep = None
     zp = None
     if zf is not None:

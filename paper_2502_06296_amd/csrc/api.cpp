@@ -45,8 +45,9 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (g->nz < 4) return fail(PF_ERR_ARG, "nz must be >= 4 (got %d)", g->nz);
   if (!(g->lz > 0.0) && !g->zf) return fail(PF_ERR_ARG, "lz must be > 0");
   if (!(g->beta >= 0.0) || !std::isfinite(g->beta)) return fail(PF_ERR_ARG, "beta must be finite and >= 0");
-  if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS && g->ybc != PF_Y_DIRICHLET)
-    return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC, PF_Y_WALLS or PF_Y_DIRICHLET (got %d)", g->ybc);
+  if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS && g->ybc != PF_Y_DIRICHLET && g->ybc != PF_Y_FACES)
+    return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC, PF_Y_WALLS, PF_Y_DIRICHLET or PF_Y_FACES (got %d)",
+                g->ybc);
   if (g->xbc != PF_X_PERIODIC && g->xbc != PF_X_WALLS && g->xbc != PF_X_DIRICHLET)
     return fail(PF_ERR_ARG, "xbc must be PF_X_PERIODIC, PF_X_WALLS or PF_X_DIRICHLET (got %d)", g->xbc);
   if (need_fft) {
@@ -55,9 +56,11 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
     if (!pf::fft_size_supported(g->nx))
       return fail(PF_ERR_UNSUPPORTED, "x length %d not built (built:" PF_FOR_FFT_SIZES(PF_LEN_STR) ")",
                   g->nx);
-    if (!pf::fft_size_supported_y(g->ny))
-      return fail(PF_ERR_UNSUPPORTED, "y length %d not built (built:" PF_FOR_FFT_SIZES_Y(PF_LEN_STR) ")",
-                  g->ny);
+    // a field on the y faces takes one transform of twice its rows
+    if (g->ybc == PF_Y_FACES ? !pf::fft_size_supported_y(2 * g->ny) : !pf::fft_size_supported_y(g->ny))
+      return fail(PF_ERR_UNSUPPORTED,
+                  "y length %d%s not built (built:" PF_FOR_FFT_SIZES_Y(PF_LEN_STR) ")", g->ny,
+                  g->ybc == PF_Y_FACES ? " (faces: twice the rows)" : "");
 #undef PF_LEN_STR
   }
   if (g->zf) {
@@ -397,6 +400,9 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
     return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
   if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
+  if (g->ybc == PF_Y_FACES && bc == PF_BC_NEUMANN)
+    return fail(PF_ERR_UNSUPPORTED, "ybc PF_Y_FACES places a velocity component on the y faces: "
+                                    "helmholtz3d_plan only");
   const int nzu = bc == PF_BC_DIRICHLET_FACE ? g->nz - 1 : g->nz;  // planes of the field
   int zc = pf::zsolve_default_variant(g->nx, nzu, precision == PF_FP64);
   if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
@@ -452,7 +458,10 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   {
     const double dy = g->ly / g->ny;
     const bool walls = g->ybc != PF_Y_PERIODIC;
-    const int q0 = g->ybc == PF_Y_DIRICHLET ? 1 : 0;
+    // y faces: the type-I sine modes q = 1..ny-1 in rows 0..ny-2, the same
+    // formula as the value-zero walls' sine modes (row ny - 1, the wall face,
+    // holds no mode)
+    const int q0 = g->ybc == PF_Y_DIRICHLET || g->ybc == PF_Y_FACES ? 1 : 0;
     if (walls) sy.clear();
     for (int h = 0; h < (walls ? 2 : 1); ++h)
       for (int m = 0; m < g->ny; ++m) {
@@ -470,7 +479,7 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
     if (!walls && g->xbc != PF_X_PERIODIC)
       for (int m = 0; m < g->ny; ++m) sy[g->ny + m] = sy[m];
   }
-  auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ny);
+  auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ybc == PF_Y_FACES ? 2 * g->ny : g->ny);
   DevArena &A = pl->ar;
   pl->o_zal = A.add(al.data(), al.size());
   pl->o_zga = A.add(ga.data(), ga.size());
@@ -590,7 +599,9 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
   // and the chain solves (L - kappa) u' = r, so u = -kappa u'. Value-zero y
   // walls: no singular mode either (nothing projected, no pin)
-  const double scale = 1.0 / ((double)pl->nx * pl->ny);
+  // the y inverse leaves the factor ny (2 ny for the type-I sine transform
+  // of a field on the y faces)
+  const double scale = 1.0 / ((double)pl->nx * pl->ny * (pl->ybc == PF_Y_FACES ? 2 : 1));
   const bool helm = pl->bc != PF_BC_NEUMANN;
   const double oscale = helm ? -pl->kappa * scale : scale;
   const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET || pl->xbc == PF_X_DIRICHLET;
@@ -989,7 +1000,7 @@ static pf_status poisson_enqueue_grouped(pf_poisson_plan *const *plans, const do
   STAGE(PF_STAGE_XINV_FINAL, run_groups(ids, kx, [&](int t) {
           pf::GJob J = base(t);
           const pf_poisson_plan *pl = plans[t];
-          const double scale = 1.0 / ((double)pl->nx * pl->ny);
+          const double scale = 1.0 / ((double)pl->nx * pl->ny);  // periodic y only
           J.in = W0(t);
           J.in2 = W1(t);
           J.out = p[t];

@@ -176,10 +176,13 @@ __device__ __forceinline__ void resid_spec_body(
   // y neighbours of the line pair: periodic wrap, or the end row itself as
   // the ghost value beyond a wall, mirrored (ywalls 1, zero gradient) or
   // negated (ywalls 2, value zero on the wall)
+  // ywalls 3: a field on the y faces: the wall face below row 0 is zero, row
+  // ny - 1 is the top wall face (zero in the iterate; its residual row is
+  // never read)
   const int jm = j == 0 ? (ywalls ? 0 : ny - 1) : j - 1;
   const int jp2 = j + 2 == ny ? (ywalls ? ny - 1 : 0) : j + 2;
-  const double gm = (ywalls == 2 && j == 0) ? -1.0 : 1.0;
-  const double gp = (ywalls == 2 && j + 2 == ny) ? -1.0 : 1.0;
+  const double gm = j == 0 ? (ywalls == 2 ? -1.0 : ywalls == 3 ? 0.0 : 1.0) : 1.0;
+  const double gp = j + 2 == ny ? (ywalls == 2 ? -1.0 : ywalls == 3 ? 0.0 : 1.0) : 1.0;
   const float *Wk = W + (size_t)k * sp;
   const float *w0 = Wk + (size_t)j * N, *w1 = w0 + N;          // lines j, j+1
   const float *wm = Wk + (size_t)jm * N, *wp = Wk + (size_t)jp2 * N;
@@ -266,6 +269,48 @@ __global__ __launch_bounds__(TPL *LPW) void k_resid_spec(
 // XR (periodic y only): the x slots are real coefficients of x walls'
 // cosine or sine transforms, so every slot pair is two real columns and takes
 // the split into packed real y spectra that slots 0 and 1 take otherwise.
+// A field on the y faces between value-zero walls (YW = 3): the type-I sine
+// transform of each column's NR - 1 interior faces (rows 0..NR-2 hold the
+// faces 1..NR-1, row NR-1 the top wall face), N = 2 NR. The column is
+// extended oddly (e_m = x_m, e_{N-m} = -x_m, e_0 = e_NR = 0), transformed by
+// one complex FFT of length N, and X_q = i E_q (q = 1..NR-1) goes to row
+// q - 1, zero to the wall row. The transform has real coefficients, so the
+// two columns of a slot pair transform together as the real and imaginary
+// parts of one line, and it is its own inverse up to the factor 1 / N,
+// which the x inverse's scale carries: the y forward and y inverse are this
+// same function.
+template <typename T, int N, int TPL, int LPW, int RO>
+__device__ __forceinline__ void y_faces_body(T *base, const cplx<double> *__restrict__ tw, int nx,
+                                             cplx<double> *lds, int tid) {
+  using C = cplx<double>;
+  constexpr int NR = N / 2, NT = TPL * LPW;
+  static_assert(N % (2 * TPL) == 0, "every thread takes N / TPL positions");
+  const int l = tid % LPW, t = tid / LPW;
+  C *buf = lds + l * y_stride(N);
+#pragma unroll
+  for (int s = 0; s < N / (2 * TPL); ++s) {
+    const int e = tid + s * NT;
+    const int l2 = e % LPW, r = e / LPW;
+    C *b2 = lds + l2 * y_stride(N);
+    if (r < NR - 1) {
+      const C v = ld2<T>(base + (size_t)r * nx + 2 * l2);
+      b2[lds_idx(r + 1)] = v;
+      b2[lds_idx(N - 1 - r)] = mkc<double>(-v.x, -v.y);
+    } else {
+      b2[lds_idx(0)] = mkc<double>(0.0, 0.0);
+      b2[lds_idx(NR)] = mkc<double>(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  auto dst = [&](int q, const C &v) {
+    if (q >= 1 && q < NR)
+      st2<T>(base + (size_t)(q - 1) * nx + 2 * l, -v.y, v.x);
+    else if (q == NR)
+      st2<T>(base + (size_t)(NR - 1) * nx + 2 * l, 0.0, 0.0);
+  };
+  fft_line_io<double, N, TPL, false, false, true, RO>(buf, tw, t, [](int) { return C{}; }, dst);
+}
+
 // The y forward's store of the workgroup holding slots 0 and 1 (and, with x
 // walls, of every workgroup), from the transformed lines in LDS: slots 0
 // and 1 are two real columns (x modes 0 and nx/2), split into two packed
@@ -353,7 +398,10 @@ __device__ __forceinline__ void yfwd_body(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto src = [&](int y) { return ld2<T>(base + (size_t)y * nx + 2 * l); };
-  if constexpr (YW != 0) {
+  if constexpr (YW == 3) {
+    y_faces_body<T, N, TPL, LPW, RO>(base, tw, nx, lds, tid);
+    return;
+  } else if constexpr (YW != 0) {
     auto srcw = [&](int n) {
       const int y = n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n;
       const C v = src(y);
@@ -421,7 +469,10 @@ __device__ __forceinline__ void yinv_body(T *__restrict__ data,
   const int l = tid % LPW, t = tid / LPW;
   C *buf = lds + l * y_stride(N);
   auto dst = [&](int y, const C &v) { st2<T>(base + (size_t)y * nx + 2 * l, v.x, v.y); };
-  if constexpr (YW != 0) {
+  if constexpr (YW == 3) {
+    y_faces_body<T, N, TPL, LPW, RO>(base, tw, nx, lds, tid);
+    return;
+  } else if constexpr (YW != 0) {
 #pragma unroll
     for (int s = 0; s < N / TPL; ++s) {
       const int e = tid + s * NT;

@@ -334,7 +334,7 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 #define PF_RESID(N, XW)                                                                          \
   hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW, XW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,  \
                      st, f, fbar, W, out, tw, ctwx, sums_p, sx, zal, zga, zex, ny, nz, idy2,      \
-                     1.0 / ny, ywalls, sp)
+                     ywalls == 3 ? 0.5 / ny : 1.0 / ny, ywalls, sp)
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
     constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                        \
@@ -359,6 +359,25 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 template <typename T>
 hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
                        const cplx<double> *ctw, int yw, hipStream_t st, bool xr, int shape) {
+  if (yw == 3) {
+    // a field on the y faces: one FFT of twice the rows per column
+    if (shape != 0) return hipErrorInvalidValue;
+    switch (2 * ny) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
+    if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
+    const int nib = nx / (2 * LPW);                                                           \
+    hipLaunchKernelGGL((k_yfwd<T, N, TPL, LPW, 3>), dim3((unsigned)((long)nib * nz)),          \
+                       dim3(TPL * LPW), 0, st, data, tw, ctw, nx, nib, sp);                   \
+    return hipGetLastError();                                                                 \
+  }
+      PF_FOR_FFT_SIZES_Y(PF_CASE)
+#undef PF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   if (shape != 0) {
     if (yw != 0 || xr) return hipErrorInvalidValue;
     if (shape == kYPersistShape) return launch_y_persist<T>(false, nx, ny, nz, data, sp, tw, st);
@@ -396,6 +415,25 @@ hipError_t launch_yfwd(int nx, int ny, int nz, T *data, size_t sp, const cplx<do
 template <typename T>
 hipError_t launch_yinv(int nx, int ny, int nz, T *data, size_t sp, const cplx<double> *tw,
                        const cplx<double> *ctw, int yw, hipStream_t st, bool xr, int shape) {
+  if (yw == 3) {
+    // a field on the y faces: one FFT of twice the rows per column
+    if (shape != 0) return hipErrorInvalidValue;
+    switch (2 * ny) {
+#define PF_CASE(N)                                                                            \
+  case N: {                                                                                   \
+    constexpr int TPL = y_tpl(N), LPW = y_lpw<T>(N);                                          \
+    if (nx % (2 * LPW)) return hipErrorInvalidValue;                                          \
+    const int nib = nx / (2 * LPW);                                                           \
+    hipLaunchKernelGGL((k_yinv<T, N, TPL, LPW, 3>), dim3((unsigned)((long)nib * nz)),          \
+                       dim3(TPL * LPW), 0, st, data, tw, ctw, nx, nib, sp);                   \
+    return hipGetLastError();                                                                 \
+  }
+      PF_FOR_FFT_SIZES_Y(PF_CASE)
+#undef PF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   if (shape != 0) {
     if (yw != 0 || xr) return hipErrorInvalidValue;
     if (shape == kYPersistShape) return launch_y_persist<T>(true, nx, ny, nz, data, sp, tw, st);

@@ -34,7 +34,7 @@ hipError_t resid_one(int ny, int nz, const double *f, const double *fbar, const 
     if (ny % (2 * h.lpw)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_resid_spec<N, h.tpl, h.lpw, 0, h.ro>), dim3((unsigned)((long)ny * nz / (2 * h.lpw))),
                        dim3(h.tpl * h.lpw), 0, st, f, fbar, W, out, tw, nullptr, sums_p, sx, zal, zga, zex,
-                       ny, nz, idy2, 1.0 / ny, ywalls, sp);
+                       ny, nz, idy2, ywalls == 3 ? 0.5 / ny : 1.0 / ny, ywalls, sp);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

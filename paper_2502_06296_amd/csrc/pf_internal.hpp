@@ -157,7 +157,9 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
 // slot, the z rows (zal, zga, zex). Also the float64 line sums of the
 // iterate. R is float32. ywalls: the y second difference wraps (0), or takes
 // the end rows mirrored (1, zero-gradient walls) or negated (2, value-zero
-// walls) as the ghost values beyond the walls.
+// walls) as the ghost values beyond the walls, or (3, a field on the y
+// faces) zero beyond row 0 and in the wall row ny - 1; W then holds the
+// iterate's x spectrum times 2 ny.
 hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const double *fbar,
                              const float *W, float *out, size_t sp, const cplx<double> *tw,
                              double *sums_p, const double *sx, const double *zal,
@@ -167,7 +169,10 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
 // y forward / inverse, in place on the packed (T) data. yw = 1 (2) selects
 // the cosine (sine) transform of zero-gradient (value-zero) y walls, in
 // natural order for every slot pair; it needs ctw = exp(-i pi q / 2 ny),
-// q = 0..ny-1.
+// q = 0..ny-1. yw = 3: a field on the y faces between value-zero walls (row
+// j the face j + 1, row ny - 1 the top wall face): the type-I sine
+// transform, one FFT of length 2 ny per column (tw of that length), the
+// same function forward and inverse (the inverse leaves the factor 2 ny).
 // xr (periodic y): the x slots are real coefficients of x walls' transforms,
 // so every slot pair is split into two packed real y spectra.
 template <typename T>

@@ -60,7 +60,7 @@ class PoissonPlan:
             self.handle = None
 
 
-YBCS = {"periodic": 0, "walls": 1, "dirichlet": 2}
+YBCS = {"periodic": 0, "walls": 1, "dirichlet": 2, "faces": 3}
 
 
 def poisson_plan(nx, ny, nz, lx=6.283185307179586, ly=3.141592653589793, lz=2.0, beta=1.5,
@@ -97,8 +97,9 @@ def helmholtz3d_plan(nx, ny, nz, bc, s, lx=6.283185307179586, ly=3.1415926535897
                      xbc="periodic"):
     """Plan the 3-D implicit Helmholtz (I - s L) u = r (bc "dirichlet_centre":
     fields of nz planes; "dirichlet_face": nz - 1; ybc and xbc as for
-    poisson_plan, for a field at cell-centre x and y positions); allocates the
-    workspace."""
+    poisson_plan, for a field at cell-centre x and y positions; ybc "faces":
+    a field on the y faces between value-zero walls, row ny - 1 the top wall
+    face, zero in the result up to rounding); allocates the workspace."""
     import torch
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     b = BCS[bc] if isinstance(bc, str) else int(bc)

@@ -72,15 +72,30 @@ def test_plan_rejects_bad_grids_before_any_device_call(args, code):
 
 
 def test_plan_validates_the_y_boundary_before_any_device_call():
-    for ybc, code in ((3, N.PF_ERR_ARG), (-1, N.PF_ERR_ARG)):
+    for ybc, code in ((4, N.PF_ERR_ARG), (-1, N.PF_ERR_ARG)):
         g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, ybc)
         h, ws = C.c_void_p(), C.c_size_t(0)
         assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == code
         assert b"ybc" in N.lib().pf_last_error()
-    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 3)
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 4)
     h, ws = C.c_void_p(), C.c_size_t(0)
     assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
         N.PF_ERR_ARG
+
+
+def test_y_faces_are_for_the_helmholtz_and_need_twice_the_rows_built():
+    # a field on the y faces (ybc 3): the Poisson plan refuses it; the 3-D
+    # Helmholtz takes one transform of 2 ny points, so ny = 100 (200 points)
+    # and ny = 2048 (4096) are not built
+    g, keep = N.make_grid(64, 32, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 3)
+    h, ws = C.c_void_p(), C.c_size_t(0)
+    assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == N.PF_ERR_UNSUPPORTED
+    assert b"helmholtz3d_plan only" in N.lib().pf_last_error()
+    for ny in (100, 2048):
+        g, keep = N.make_grid(64, ny, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 3)
+        assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
+            N.PF_ERR_UNSUPPORTED
+        assert b"faces" in N.lib().pf_last_error()
 
 
 def test_plan_rejects_bad_precision_and_refinement():
