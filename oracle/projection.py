@@ -22,6 +22,11 @@ bottom wall face below row 0) as zero, the gradient across it is zero and
 the projection leaves it unchanged; D G is then L7 with zero-gradient y
 walls.
 
+With xbc = grid.X_WALLS the x ends are zero-gradient walls in the same way:
+u[:, :, nx-1] is the east wall face, the divergence takes it (and the west
+wall face of cell 0) as zero, the gradient across it is zero and the
+projection leaves it unchanged; D G is then L7 with zero-gradient x walls.
+
 Plain numpy in the dtype of the inputs; test infrastructure only.
 """
 from __future__ import annotations
@@ -31,14 +36,21 @@ import numpy as np
 from . import grid, poisson
 
 
-def divergence(u, v, w, zf, lx, ly, ybc=grid.Y_PERIODIC):
+def divergence(u, v, w, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     """D (u, v, w) at cell centres, shape (nz, ny, nx)."""
     dt = u.dtype.type
     nz, ny, nx = u.shape
     dx, dy = dt(lx) / nx, dt(ly) / ny
     _, dzf, _ = grid.z_metrics(zf, dt)
-    # west face of cell i is the east face of cell i-1 (periodic)
-    out = (u - np.roll(u, 1, axis=2)) / dx
+    if xbc == grid.X_WALLS:
+        ue = u.copy()
+        ue[:, :, nx - 1] = 0              # the east wall face
+        uw = np.zeros_like(u)
+        uw[:, :, 1:] = ue[:, :, :-1]      # the west wall face of cell 0 carries 0
+        out = (ue - uw) / dx
+    else:
+        # west face of cell i is the east face of cell i-1 (periodic)
+        out = (u - np.roll(u, 1, axis=2)) / dx
     if ybc == grid.Y_WALLS:
         vn = v.copy()
         vn[:, ny - 1] = 0                 # the top wall face
@@ -54,7 +66,7 @@ def divergence(u, v, w, zf, lx, ly, ybc=grid.Y_PERIODIC):
     return out + (top - bot) / dzf[:, None, None]
 
 
-def gradient(phi, zf, lx, ly, ybc=grid.Y_PERIODIC):
+def gradient(phi, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     """G phi on the faces: (gx, gy) of shape (nz, ny, nx), gz of shape
     (nz - 1, ny, nx) on the interior z faces."""
     dt = phi.dtype.type
@@ -62,6 +74,8 @@ def gradient(phi, zf, lx, ly, ybc=grid.Y_PERIODIC):
     dx, dy = dt(lx) / nx, dt(ly) / ny
     _, _, dzc = grid.z_metrics(zf, dt)
     gx = (np.roll(phi, -1, axis=2) - phi) / dx
+    if xbc == grid.X_WALLS:
+        gx[:, :, nx - 1] = 0              # no gradient across the east wall face
     gy = (np.roll(phi, -1, axis=1) - phi) / dy
     if ybc == grid.Y_WALLS:
         gy[:, ny - 1] = 0                 # no gradient across the top wall face
@@ -79,11 +93,11 @@ def lz_neumann(phi, zf):
     return out
 
 
-def project(u, v, w, p, zf, lx, ly, gdt, c=0.0, ybc=grid.Y_PERIODIC):
+def project(u, v, w, p, zf, lx, ly, gdt, c=0.0, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     """One projection: returns (u_new, v_new, w_new, p_new, phi)."""
     dt = u.dtype.type
-    f = divergence(u, v, w, zf, lx, ly, ybc) / dt(gdt)
-    phi = poisson.solve_poisson(f, zf, lx, ly, ybc)
-    gx, gy, gz = gradient(phi, zf, lx, ly, ybc)
+    f = divergence(u, v, w, zf, lx, ly, ybc, xbc) / dt(gdt)
+    phi = poisson.solve_poisson(f, zf, lx, ly, ybc, xbc)
+    gx, gy, gz = gradient(phi, zf, lx, ly, ybc, xbc)
     g = dt(gdt)
     return (u - g * gx, v - g * gy, w - g * gz, p + phi - dt(c) * lz_neumann(phi, zf), phi)

@@ -284,3 +284,55 @@ def _face_inverse_without_scale(orig):
 def test_planted_yface_mistake_is_caught(monkeypatch, target, attr, mut):
     monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
     assert _yface_pin_errors() > 1e-6
+
+
+# ------------------------------------------------- projection with x walls
+
+def _xwall_projection_pin_errors():
+    """D G = L7 with zero-gradient x walls, a divergence-free result, and the
+    east wall face's velocity left as it was."""
+    nx, ny, nz = 8, 6, 7
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    phi = synth.uniform_pm1(41, (nz, ny, nx))
+    gx, gy, gz = projection.gradient(phi, zf, LX, LY, grid.Y_PERIODIC, grid.X_WALLS)
+    ref = poisson.apply_L7(phi, zf, LX, LY, grid.Y_PERIODIC, grid.X_WALLS)
+    dg = projection.divergence(gx, gy, gz, zf, LX, LY, grid.Y_PERIODIC, grid.X_WALLS)
+    errs = [np.max(np.abs(dg - ref)) / np.max(np.abs(ref))]
+    u = synth.uniform_pm1(42, (nz, ny, nx))
+    v = synth.uniform_pm1(43, (nz, ny, nx))
+    w = synth.uniform_pm1(44, (nz - 1, ny, nx))
+    d0 = np.abs(projection.divergence(u, v, w, zf, LX, LY, grid.Y_PERIODIC, grid.X_WALLS)).max()
+    u1, v1, w1, _, _ = projection.project(u, v, w, np.zeros_like(u), zf, LX, LY, gdt=0.3,
+                                          xbc=grid.X_WALLS)
+    errs.append(np.abs(projection.divergence(u1, v1, w1, zf, LX, LY, grid.Y_PERIODIC,
+                                             grid.X_WALLS)).max() / d0)
+    errs.append(np.abs(u1[:, :, -1] - u[:, :, -1]).max())
+    return max(errs)
+
+
+def test_unmutated_xwall_projection_passes():
+    assert _xwall_projection_pin_errors() < 1e-10
+
+
+def _east_wall_flux_kept(orig):
+    def f(u, v, w, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
+        d = orig(u, v, w, zf, lx, ly, ybc, xbc)
+        if xbc == grid.X_WALLS:                        # the wall face's flux counted
+            d[:, :, -1] += u[:, :, -1] / (lx / u.shape[2])
+        return d
+    return f
+
+
+def _gradient_across_the_east_wall(orig):
+    def f(phi, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
+        return orig(phi, zf, lx, ly, ybc, grid.X_PERIODIC)
+    return f
+
+
+@pytest.mark.parametrize("attr,mut", [
+    ("divergence", _east_wall_flux_kept),
+    ("gradient", _gradient_across_the_east_wall),
+])
+def test_planted_xwall_projection_mistake_is_caught(monkeypatch, attr, mut):
+    monkeypatch.setattr(projection, attr, mut(getattr(projection, attr)))
+    assert _xwall_projection_pin_errors() > 1e-6

@@ -158,3 +158,38 @@ def test_y_walls_divergence_theorem_and_projection():
     d1 = projection.divergence(u1, v1, w1, zf, LX, LY, grid.Y_WALLS)
     assert np.sqrt(np.sum(d1 ** 2)) <= 1e-12 * np.sqrt(np.sum(d ** 2))
     assert np.array_equal(v1[:, ny - 1], v[:, ny - 1])
+
+
+# zero-gradient walls at both x ends (u[:, :, nx-1] is the east wall face),
+# alone and with y walls
+
+@pytest.mark.parametrize("ybc", [grid.Y_PERIODIC, grid.Y_WALLS])
+@pytest.mark.parametrize("beta", [0.0, 1.5])
+def test_x_walls_div_of_grad_is_the_seven_point_operator(beta, ybc):
+    nx, ny, nz = 10, 12, 9
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    phi = synth.uniform_pm1(58, (nz, ny, nx))
+    gx, gy, gz = projection.gradient(phi, zf, LX, LY, ybc, grid.X_WALLS)
+    dg = projection.divergence(gx, gy, gz, zf, LX, LY, ybc, grid.X_WALLS)
+    ref = poisson.apply_L7(phi, zf, LX, LY, ybc, grid.X_WALLS)
+    assert np.max(np.abs(dg - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("ybc", [grid.Y_PERIODIC, grid.Y_WALLS])
+def test_x_walls_divergence_theorem_and_projection(ybc):
+    nx, ny, nz = 6, 8, 11
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    _, dzf, _ = grid.z_metrics(zf)
+    u, v, w = _fields(59, nx, ny, nz)
+    d = projection.divergence(u, v, w, zf, LX, LY, ybc, grid.X_WALLS)
+    total = np.dot(dzf, d.reshape(nz, -1).sum(axis=1))
+    assert abs(total) <= 1e-14 * np.dot(dzf, np.abs(d).reshape(nz, -1).sum(axis=1))
+    # the east wall face is ignored
+    u2 = u.copy()
+    u2[:, :, nx - 1] += 3.0
+    assert np.array_equal(projection.divergence(u2, v, w, zf, LX, LY, ybc, grid.X_WALLS), d)
+    u1, v1, w1, _, _ = projection.project(u, v, w, np.zeros_like(u), zf, LX, LY, gdt=0.2,
+                                          ybc=ybc, xbc=grid.X_WALLS)
+    d1 = projection.divergence(u1, v1, w1, zf, LX, LY, ybc, grid.X_WALLS)
+    assert np.sqrt(np.sum(d1 ** 2)) <= 1e-12 * np.sqrt(np.sum(d ** 2))
+    assert np.array_equal(u1[:, :, nx - 1], u[:, :, nx - 1])
