@@ -106,8 +106,10 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * transform along x, wavenumbers 4 sin^2(pi q / 2 nx) / dx^2; PF_X_DIRICHLET:
  * the sine transform, 4 sin^2(pi (q + 1) / 2 nx) / dx^2, nonsingular), with
  * nx cell-centred unknowns, alone or with y walls; built for poisson_plan /
- * poisson_solve and helmholtz3d_plan / helmholtz3d_solve (poisson_project
- * returns PF_ERR_UNSUPPORTED for x walls). */
+ * poisson_solve and helmholtz3d_plan / helmholtz3d_solve; poisson_project
+ * takes PF_X_WALLS (u[:, :, nx-1] is then the east wall face: no flux
+ * through it or through the west wall face enters the divergence, and it is
+ * left unchanged) and returns PF_ERR_UNSUPPORTED for PF_X_DIRICHLET. */
 enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2, PF_Y_FACES = 3 };
 enum { PF_X_PERIODIC = 0, PF_X_WALLS = 1, PF_X_DIRICHLET = 2 };
 typedef struct pf_grid {
@@ -199,6 +201,10 @@ pf_status poisson_set_status(pf_poisson_plan *plan, void *dev_status, double tol
  * dzf), G the face gradient (over dx, dy and the centre distances), L_z the
  * zero-gradient z operator; D G = L7. gdt = gamma_k * dt > 0; c >= 0 (0 for
  * explicit diffusion, gamma_k * nu * dt / 2 with the z-implicit Helmholtz).
+ * Zero-gradient walls (PF_Y_WALLS, PF_X_WALLS) make v[:, ny-1, :] and
+ * u[:, :, nx-1] wall faces: no flux, no correction. Value-zero walls
+ * (PF_Y_DIRICHLET, PF_X_DIRICHLET) return PF_ERR_UNSUPPORTED: a correction
+ * pressure that vanishes on a wall would push fluid through it.
  * phi: device (nz,ny,nx) float64, receives the correction pressure (zero
  * dzf-weighted mean) and serves the solve as its spectral buffer (PF_FP64)
  * or as the stash of f (PF_FP32_REFINE). u, v, w, p are updated in place.

@@ -801,8 +801,8 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
   if (pl->bc != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "poisson_project needs a Poisson plan");
   if (pl->ybc == PF_Y_DIRICHLET)
     return fail(PF_ERR_UNSUPPORTED, "poisson_project: the pressure takes periodic or zero-gradient y ends");
-  if (pl->xbc != PF_X_PERIODIC)
-    return fail(PF_ERR_UNSUPPORTED, "poisson_project: x walls are built for the Poisson and 3-D Helmholtz solves only");
+  if (pl->xbc == PF_X_DIRICHLET)
+    return fail(PF_ERR_UNSUPPORTED, "poisson_project: the pressure takes periodic or zero-gradient x ends");
   if (!u || !v || !w || !p || !phi) return fail(PF_ERR_ARG, "u, v, w, p and phi must be device pointers");
   if (!(gdt > 0.0) || !std::isfinite(gdt)) return fail(PF_ERR_ARG, "gdt must be finite and > 0");
   if (!(c >= 0.0) || !std::isfinite(c)) return fail(PF_ERR_ARG, "c must be finite and >= 0");
@@ -830,12 +830,14 @@ pf_status poisson_project(pf_poisson_plan *pl, double *u, double *v, double *w, 
   d.igdt = 1.0 / gdt;
   d.stash = nullptr;
   d.ywalls = pl->ybc == PF_Y_WALLS ? 1 : 0;
+  d.xwalls = pl->xbc == PF_X_WALLS ? 1 : 0;
+  d.ctwx = d.xwalls ? A.at<double2>(pl->o_ctwx) : nullptr;
   pf_status s = poisson_enqueue(pl, nullptr, phi, pl->st, &d);
   if (s) return s;
   return run_stage(pl->tm, pl->st, PF_STAGE_PROJECT, [&]() {
     return pf::launch_project(pl->nx, pl->ny, pl->nz, phi, u, v, w, p, A.at<double>(pl->o_zal),
                               A.at<double>(pl->o_zga), A.at<double>(pl->o_rdzc), gdt * d.idx,
-                              gdt * d.idy, gdt, c, d.ywalls != 0, pl->st);
+                              gdt * d.idy, gdt, c, d.ywalls != 0, d.xwalls != 0, pl->st);
   });
 }
 

@@ -51,11 +51,15 @@ bool fft_size_supported_y(int n) {
 // even), so they share the v row j. With STASH, f itself is also written
 // (float64, real space) for the residual of a refinement; the first pass
 // reads every position exactly once. Otherwise as k_xfwd with line sums.
-template <typename T, int N, int TPL, int LPW, bool STASH>
+// XW = 1: zero-gradient walls at both x ends: u[nx-1] is the east wall face
+// and the west face of cell 0 a wall face, both without flux; the line then
+// goes through the cosine transform along x (as k_xfwd with XW = 1).
+template <typename T, int N, int TPL, int LPW, bool STASH, int XW = 0>
 __global__ __launch_bounds__(TPL *LPW) void k_xfwd_div(DivArgs d, T *__restrict__ out,
                                                        const cplx<double> *__restrict__ tw,
                                                        double *__restrict__ sums, long ncl, int ny,
                                                        int nz, size_t sp) {
+  static_assert(XW == 0 || XW == 1, "periodic x or zero-gradient x walls");
   using C = cplx<double>;
   __shared__ C lds[LPW * lds_len(N)];
   static_assert(N % TPL == 0, "every thread takes N / TPL positions");
@@ -73,16 +77,22 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_div(DivArgs d, T *__restrict_
   const double *wta = top ? d.w + o : d.w;                   // top faces of rows j, j+1
   const double *wba = bot ? d.w + (o - (size_t)ny * N) : d.w;  // bottom faces
   const double rz = d.rdzf[k];
-  auto src = [&](int i) {
+  auto src = [&](int n) {
     if (!ok) return mkc<double>(0.0, 0.0);
+    // the position the transform takes at n: natural order, or Makhoul's
+    // order for the cosine transform
+    const int i = XW ? xw_src(n, N) : n;
     const int im = i == 0 ? N - 1 : i - 1;
     const double v0 = va[i];
     // with y walls the bottom wall face (below row 0) and the top one (row
-    // ny-1, the north face of line b of the last pair) carry no flux
+    // ny-1, the north face of line b of the last pair) carry no flux; with
+    // x walls the east face of the last cell and the west face of the first
     const double vs = (d.ywalls && j == 0) ? 0.0 : vm[i];
     const double vn = (d.ywalls && j + 2 == ny) ? 0.0 : vb[i];
-    double fa = (ua[i] - ua[im]) * d.idx + (v0 - vs) * d.idy;
-    double fb = (ub[i] - ub[im]) * d.idx + (vn - v0) * d.idy;
+    const double uea = XW && i == N - 1 ? 0.0 : ua[i], ueb = XW && i == N - 1 ? 0.0 : ub[i];
+    const double uwa = XW && i == 0 ? 0.0 : ua[im], uwb = XW && i == 0 ? 0.0 : ub[im];
+    double fa = (uea - uwa) * d.idx + (v0 - vs) * d.idy;
+    double fb = (ueb - uwb) * d.idx + (vn - v0) * d.idy;
     if (top) {
       fa += wta[i] * rz;
       fb += wta[N + i] * rz;
@@ -103,6 +113,20 @@ __global__ __launch_bounds__(TPL *LPW) void k_xfwd_div(DivArgs d, T *__restrict_
   if (!ok) return;
   T *oa = out + (size_t)k * sp + (size_t)j * N;
   T *ob = oa + N;
+  if constexpr (XW == 1) {
+    // one real cosine coefficient per slot: X_q = c_q Z_q + conj(c_q) Z_{N-q}
+#pragma unroll
+    for (int q = t; q < N; q += TPL) {
+      const C v1 = buf[lds_idx(q)], v2 = buf[lds_idx(q == 0 ? 0 : N - q)], cq = d.ctwx[q];
+      oa[q] = (T)(cq.x * v1.x - cq.y * v1.y + cq.x * v2.x + cq.y * v2.y);
+      ob[q] = (T)(cq.x * v1.y + cq.y * v1.x + cq.x * v2.y - cq.y * v2.x);
+      if (q == 0) {
+        sums[2 * c] = v1.x;
+        sums[2 * c + 1] = v1.y;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
     C A, B;
@@ -136,12 +160,14 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
                                                  const double *__restrict__ zga,
                                                  const double *__restrict__ rdzc, int nx, int ny,
                                                  int nz, double gx, double gy, double gdt, double c,
-                                                 int ywalls) {
+                                                 int ywalls, int xwalls) {
   const int i = blockIdx.x * 64 + (int)(threadIdx.x % 64);
   const int j = blockIdx.y * 4 + (int)(threadIdx.x / 64);
   if (i >= nx || j >= ny) return;  // no barrier follows
-  // y walls: no gradient across the top wall face, v there stays as it is
+  // y (x) walls: no gradient across the top (east) wall face, v (u) there
+  // stays as it is
   const double gyj = (ywalls && j + 1 == ny) ? 0.0 : gy;
+  const double gxi = (xwalls && i + 1 == nx) ? 0.0 : gx;
   const size_t plane = (size_t)nx * ny;
   const size_t o = (size_t)j * nx + i;
   const size_t ox = (size_t)j * nx + (i + 1 == nx ? 0 : i + 1);
@@ -153,7 +179,7 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ phi,
     const bool up = k + 1 < nz;
     const double fp = up ? phi[b + plane + o] : 0.0;
     const double fx = phi[b + ox], fy = phi[b + oy];
-    u[b + o] -= gx * (fx - f0);
+    u[b + o] -= gxi * (fx - f0);
     v[b + o] -= gyj * (fy - f0);
     if (up) w[b + o] -= gdt * rdzc[k] * (fp - f0);  // w is (nz-1, ny, nx)
     double dp = f0;
@@ -199,12 +225,19 @@ template <typename T>
 hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
                            const cplx<double> *tw, double *sums, hipStream_t st) {
   const long ncl = (long)ny * nz / 2;
+  if (d.xwalls && !d.ctwx) return hipErrorInvalidValue;
   switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
     constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                             \
     dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                   \
-    if (d.stash)                                                                                 \
+    if (d.xwalls && d.stash)                                                                     \
+      hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, true, 1>), g, dim3(TPL * LPW), 0, st, d,    \
+                         out, tw, sums, ncl, ny, nz, sp);                                        \
+    else if (d.xwalls)                                                                           \
+      hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, false, 1>), g, dim3(TPL * LPW), 0, st, d,   \
+                         out, tw, sums, ncl, ny, nz, sp);                                        \
+    else if (d.stash)                                                                            \
       hipLaunchKernelGGL((k_xfwd_div<T, N, TPL, LPW, true>), g, dim3(TPL * LPW), 0, st, d, out,  \
                          tw, sums, ncl, ny, nz, sp);                                             \
     else                                                                                         \
@@ -226,15 +259,15 @@ template hipError_t launch_xfwd_div<float>(int, int, int, const DivArgs &, float
 hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
                           double *w, double *p, const double *zal, const double *zga,
                           const double *rdzc, double gx, double gy, double gdt, double c,
-                          bool ywalls, hipStream_t st) {
+                          bool ywalls, bool xwalls, hipStream_t st) {
   dim3 g((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4));
-  const int yw = ywalls ? 1 : 0;
+  const int yw = ywalls ? 1 : 0, xw = xwalls ? 1 : 0;
   if (c != 0.0)
     hipLaunchKernelGGL((k_project<true>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc, nx,
-                       ny, nz, gx, gy, gdt, c, yw);
+                       ny, nz, gx, gy, gdt, c, yw, xw);
   else
     hipLaunchKernelGGL((k_project<false>), g, dim3(256), 0, st, phi, u, v, w, p, zal, zga, rdzc,
-                       nx, ny, nz, gx, gy, gdt, c, yw);
+                       nx, ny, nz, gx, gy, gdt, c, yw, xw);
   return hipGetLastError();
 }
 

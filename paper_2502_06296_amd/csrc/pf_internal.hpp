@@ -228,6 +228,9 @@ struct DivArgs {
   double idx, idy, igdt;
   double *stash;
   int ywalls;  // 1: zero-gradient y walls, v[ny-1] is the top wall face (no flux)
+  int xwalls;  // 1: zero-gradient x walls, u[nx-1] is the east wall face (no flux);
+               // the cosine transform along x with ctwx = exp(-i pi q / 2 nx)
+  const cplx<double> *ctwx;
 };
 template <typename T>
 hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, size_t sp,
@@ -235,11 +238,11 @@ hipError_t launch_xfwd_div(int nx, int ny, int nz, const DivArgs &d, T *out, siz
 // u -= gx (phi[i+1] - phi[i]), v -= gy (phi[j+1] - phi[j]), w -= gdt rdzc[k]
 // (phi[k+1] - phi[k]) (gx = gdt/dx, gy = gdt/dy), p += phi - c L_z phi with
 // the Neumann rows zal, zga. ywalls: no v correction on the top wall face
-// j = ny-1.
+// j = ny-1; xwalls: no u correction on the east wall face i = nx-1.
 hipError_t launch_project(int nx, int ny, int nz, const double *phi, double *u, double *v,
                           double *w, double *p, const double *zal, const double *zga,
                           const double *rdzc, double gx, double gy, double gdt, double c,
-                          bool ywalls, hipStream_t st);
+                          bool ywalls, bool xwalls, hipStream_t st);
 
 // Poisson z solve on the doubly packed spectrum (in place), float64
 // elimination in registers; the (0,0) slot column is set to zero. `variant`

@@ -2,8 +2,8 @@
 along x) and value-zero (the sine transform) -- alone and with every y
 boundary, through the C ABI against the CPU oracle, element by element, in
 the three precisions: the Poisson solve and the 3-D Helmholtz. Also graph
-replays, the float64 7-point residual at a larger size, and the projection's
-refusal of x walls.
+replays, the float64 7-point residual at a larger size, and the projection
+with zero-gradient x walls (and its refusal of value-zero ones).
 
 Bars: float64 1e-12, float32 with one float64-residual correction 1e-10,
 plain float32 1e-5, each for the relative L2 error and for the largest
@@ -129,9 +129,46 @@ def test_xwalls_graph_replays_equal_eager(xbc):
         assert torch.equal(p, pe), rep
 
 
-def test_projection_rejects_x_walls():
+PROJ_CASES = [
+    (64, 64, 64, 1.5, 0.0, "periodic", 0),
+    (96, 128, 40, 2.0, 1e-3, "periodic", 1),   # radix-3 x, implicit z-diffusion pressure term
+    (128, 96, 9, 1.2, 0.0, "walls", 2),        # with zero-gradient y walls
+    (1024, 64, 6, 1.5, 0.0, "periodic", 3),    # the workloads' x length
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,beta,c,ybc,seed", PROJ_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine", "fp32"])
+def test_xwalls_projection_matches_oracle(nx, ny, nz, beta, c, ybc, seed, prec):
+    from oracle import projection as oproj
+    print(f"projection x walls, y {ybc}, {prec} {nx}x{ny}x{nz} c={c}", flush=True)
+    zf = synth.tanh_faces(nz, 2.0, beta)
+    u = synth.uniform_pm1(360 + seed, (nz, ny, nx))
+    v = synth.uniform_pm1(361 + seed, (nz, ny, nx))
+    w = synth.uniform_pm1(362 + seed, (nz - 1, ny, nx))
+    p = synth.uniform_pm1(363 + seed, (nz, ny, nx))
+    gdt = 0.37
+    yb = YBC[ybc]
+    ref = oproj.project(u, v, w, p, zf, LX, LY, gdt, c, ybc=yb, xbc=ogrid.X_WALLS)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, beta, zf=zf, precision=prec, ybc=ybc, xbc="walls")
+    t = [torch.from_numpy(a).to(_dev()) for a in (u, v, w, p)]
+    phi = torch.empty_like(t[0])
+    pf.poisson_project(plan, *t, phi, gdt, c)
+    torch.cuda.synchronize()
+    got = [a.cpu().numpy() for a in t] + [phi.cpu().numpy()]
+    for name, g, r in zip(("u", "v", "w", "p", "phi"), got, ref):
+        check(g, r, TOL[prec], name)
+    # the east wall face keeps its velocity
+    assert np.array_equal(got[0][:, :, nx - 1], u[:, :, nx - 1])
+    if prec != "fp32":
+        d1 = oproj.divergence(*got[:3], zf, LX, LY, yb, ogrid.X_WALLS)
+        d0 = oproj.divergence(u, v, w, zf, LX, LY, yb, ogrid.X_WALLS)
+        assert np.sqrt(np.sum(d1 ** 2)) <= TOL[prec] * np.sqrt(np.sum(d0 ** 2))
+
+
+def test_projection_rejects_value_zero_x_walls():
     nx, ny, nz = 64, 64, 16
-    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, xbc="walls")
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, xbc="dirichlet")
     t = [torch.zeros((nz if i != 2 else nz - 1, ny, nx), dtype=torch.float64, device=_dev())
          for i in range(5)]
     with pytest.raises(N.PfError) as e:
