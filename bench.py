@@ -42,8 +42,10 @@ HELM_C3 = (1024, 1024, 512)     # the three-component Helmholtz grid
 LX, LY, LZ = 2 * math.pi, math.pi, 2.0
 S_HELM = 0.5 * (1.0 / 5200.0) * 1e-4     # alpha * nu * dt, Re_tau = 5200
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
-KERNEL_SOURCES = ["paper_2502_06296_amd/csrc/kernels_fft.hip", "paper_2502_06296_amd/csrc/kernels_z.hip",
-                  "paper_2502_06296_amd/csrc/fft_lds.hpp", "paper_2502_06296_amd/csrc/pf_internal.hpp"]
+KERNEL_SOURCES = ["paper_2502_06296_amd/csrc/kernels_fft.hip", "paper_2502_06296_amd/csrc/kernels_fft_alt.hip",
+                  "paper_2502_06296_amd/csrc/kernels_fft_pf.hip", "paper_2502_06296_amd/csrc/kernels_z.hip",
+                  "paper_2502_06296_amd/csrc/fft_kernels.hpp", "paper_2502_06296_amd/csrc/fft_lds.hpp",
+                  "paper_2502_06296_amd/csrc/pf_internal.hpp"]
 
 # algorithmic HBM bytes per grid point of one launch of each stage (one read
 # and one write of what the stage must touch; stencil neighbours not counted)
