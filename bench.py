@@ -506,10 +506,11 @@ def per_gpu_share(args):
            "metric": "Gpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
     for prec in ("fp32_refine", "fp64"):
         log(f"{args.workload}: {prec}")
-        st = Step(pf, torch, dev, prec, f)
+        st = Step(pf, torch, dev, prec, f, tune=not args.no_tune)
         ms, _, stages = time_steps(st, args.steps, args.warmup)
         entry = {"value": round(npts / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
-                 "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in stages.items()}}
+                 "stages_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
+                 "autotuned": st.tuned}
         chunking = {}
         for rows in (32, 16, 8):
             if not autotune.set_pcr_shape(st.pcr, rows, 64):
