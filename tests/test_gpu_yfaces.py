@@ -69,3 +69,45 @@ def test_yfaces_with_x_walls_matches_oracle(xbc, prec):
 def test_yfaces_reject_the_poisson_plan():
     with pytest.raises(N.PfError):
         pf.poisson_plan(64, 32, 16, ybc="faces")
+
+
+def test_yfaces_substeps_captured_in_one_graph():
+    """Three Runge-Kutta substeps (a new s each, updated on the device) of the
+    face-located field's 3-D Helmholtz, captured in one graph and replayed
+    twice: every replay equals the eager run bitwise, and each substep the
+    oracle at its own s."""
+    nx, ny, nz = 128, 48, 24
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    svals = (2e-2, 5e-3, 1.2e-2)
+    plan = pf.helmholtz3d_plan(nx, ny, nz, "dirichlet_centre", svals[0], LX, LY, 2.0, 1.5, zf=zf,
+                               precision="fp32_refine", stream=stream, ybc="faces")
+    r = [torch.from_numpy(synth.normal01(520 + i, (nz, ny, nx))).to(dev) for i in range(3)]
+    ue = [torch.empty_like(x) for x in r]
+    ug = [torch.empty_like(x) for x in r]
+    torch.cuda.synchronize()
+
+    def substeps(out):
+        for i, s in enumerate(svals):
+            pf.helmholtz3d_update(plan, s)
+            pf.helmholtz3d_solve(plan, r[i], out[i])
+
+    with torch.cuda.stream(stream):
+        substeps(ue)
+    stream.synchronize()
+    for i, s in enumerate(svals):
+        ref = op.solve_helmholtz3d(r[i].cpu().numpy(), zf, s, ogrid.DIRICHLET_CENTRE, LX, LY,
+                                   ybc=ogrid.Y_FACES)
+        check(ue[i].cpu().numpy(), ref, TOL["fp32_refine"], f"substep {i}")
+    pf.pf_graph_begin(stream)
+    substeps(ug)
+    g = pf.pf_graph_end(stream)
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            for x in ug:
+                x.fill_(-1.0)
+        g.launch(stream)
+        stream.synchronize()
+        for i in range(3):
+            assert torch.equal(ug[i], ue[i]), (rep, i)
