@@ -144,23 +144,25 @@ def helmholtz3d_dense(r, zf, s, bc, lx, ly, ybc=0, xbc=0):
     zero-gradient (1) or value-zero (2) walls, plus L_z of family bc (C-order
     (n, ny, nx) flattening, n = nz or nz - 1). ybc = 3: a field on the y faces
     between value-zero walls (row j the face j + 1, row ny - 1 the top wall
-    face, zero in the result)."""
+    face, zero in the result); xbc = 3 the same along x."""
     n, ny, nx = r.shape
-    if ybc == 3:
-        # a field on the y faces: unknowns on the ny - 1 interior faces, the
-        # wall row (ny - 1) is zero
-        u = np.zeros(r.shape, dtype=np.result_type(r, np.float64))
-        u[:, : ny - 1, :] = _helm_dense(r[:, : ny - 1, :], zf, s, bc, lx, face_d2(ny, ly / ny), xbc)
-        return u
-    return _helm_dense(r, zf, s, bc, lx, _d2(ny, ly, ybc), xbc)
+    # a field on the y (x) faces: unknowns on the interior faces, the wall
+    # row (column) is zero
+    my = ny - 1 if ybc == 3 else ny
+    mx = nx - 1 if xbc == 3 else nx
+    Dy = face_d2(ny, ly / ny) if ybc == 3 else _d2(ny, ly, ybc)
+    Dx = face_d2(nx, lx / nx) if xbc == 3 else _d2(nx, lx, xbc)
+    u = np.zeros(r.shape, dtype=np.result_type(r, np.float64))
+    u[:, :my, :mx] = _helm_dense(r[:, :my, :mx], zf, s, bc, Dx, Dy)
+    return u
 
 
-def _helm_dense(r, zf, s, bc, lx, Dy, xbc):
-    n, my, nx = r.shape
-    Ix, Iy = np.eye(nx), np.eye(my)
+def _helm_dense(r, zf, s, bc, Dx, Dy):
+    n, my, mx = r.shape
+    Ix, Iy = np.eye(mx), np.eye(my)
     Dz = lz_dense(zf, bc)
     Iz = np.eye(Dz.shape[0])
-    L = (np.kron(Iz, np.kron(Iy, _d2(nx, lx, xbc))) + np.kron(Iz, np.kron(Dy, Ix))
+    L = (np.kron(Iz, np.kron(Iy, Dx)) + np.kron(Iz, np.kron(Dy, Ix))
          + np.kron(Dz, np.kron(Iy, Ix)))
     M = np.eye(L.shape[0]) - s * L
     return np.linalg.solve(M, r.reshape(-1)).reshape(r.shape)

@@ -30,6 +30,8 @@ Y_FACES = 3            # value-zero walls at both y ends, unknowns on the y face
 X_PERIODIC = 0         # x periodic (the channel)
 X_WALLS = 1            # zero-gradient walls at both x ends, cell centres
 X_DIRICHLET = 2        # value-zero walls at both x ends, cell centres
+X_FACES = 3            # value-zero walls at both x ends, unknowns on the x faces
+                       # (column i is face i + 1; column nx - 1 is the east wall face)
 
 
 def z_metrics(zf, dtype=np.float64):

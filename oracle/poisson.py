@@ -64,8 +64,8 @@ def _y_transform(ybc):
 def _x_transform(xbc):
     """(forward, inverse, wavenumbers) of the x direction for xbc: the same
     three members of the Fourier-based transforms as along y."""
-    return _y_transform({grid.X_WALLS: grid.Y_WALLS, grid.X_DIRICHLET: grid.Y_DIRICHLET}.get(
-        xbc, grid.Y_PERIODIC))
+    return _y_transform({grid.X_WALLS: grid.Y_WALLS, grid.X_DIRICHLET: grid.Y_DIRICHLET,
+                         grid.X_FACES: grid.Y_FACES}.get(xbc, grid.Y_PERIODIC))
 
 
 def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
@@ -77,8 +77,8 @@ def solve_poisson(f, zf, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERIODIC):
     where the value vanishes: the sine transform. xbc does the same for the x
     ends (grid.X_WALLS, grid.X_DIRICHLET). With value-zero walls in x or y, L7
     is nonsingular, so f is not projected and p carries no pin."""
-    if ybc == grid.Y_FACES:
-        raise ValueError("the pressure lives at cell centres: y faces are for the 3-D Helmholtz")
+    if ybc == grid.Y_FACES or xbc == grid.X_FACES:
+        raise ValueError("the pressure lives at cell centres: faces are for the 3-D Helmholtz")
     dt = f.dtype.type
     nz, ny, nx = f.shape
     singular = ybc != grid.Y_DIRICHLET and xbc != grid.X_DIRICHLET
@@ -157,9 +157,10 @@ def solve_helmholtz3d(r, zf, s, bc, lx, ly, ybc=grid.Y_PERIODIC, xbc=grid.X_PERI
     dt = r.dtype.type
     n, ny, nx = r.shape
     s = dt(s)
-    # ybc = grid.Y_FACES: a field on the y faces (the face-located velocity
-    # of a y-walled grid): the type-I sine transform over the ny - 1 interior
-    # faces; the wall row stays zero
+    # ybc = grid.Y_FACES (xbc = grid.X_FACES): a field on the y (x) faces, the
+    # face-located velocity of a y- (x-) walled grid: the type-I sine
+    # transform over the ny - 1 (nx - 1) interior faces; the wall row (column)
+    # stays zero
     xf, xi, xw = _x_transform(xbc)
     yf, yi, yw = _y_transform(ybc)
     R = yf(xf(r, axis=2), axis=1)

@@ -336,3 +336,33 @@ def _gradient_across_the_east_wall(orig):
 def test_planted_xwall_projection_mistake_is_caught(monkeypatch, attr, mut):
     monkeypatch.setattr(projection, attr, mut(getattr(projection, attr)))
     assert _xwall_projection_pin_errors() > 1e-6
+
+
+def _xface_pin_errors():
+    """The dense brute force of the 3-D Helmholtz on the x faces."""
+    errs = []
+    for bc, n in ((grid.DIRICHLET_CENTRE, 5), (grid.DIRICHLET_FACE, 4)):
+        zf = synth.tanh_faces(5, 2.0, 1.5)
+        r = synth.uniform_pm1(130 + bc, (n, 4, 6))
+        errs.append(poisson.rel_l2(poisson.solve_helmholtz3d(r, zf, 0.05, bc, LX, LY, xbc=grid.X_FACES),
+                                   dense.helmholtz3d_dense(r, zf, 0.05, bc, LX, LY, xbc=3)))
+    return max(errs)
+
+
+def test_unmutated_xface_oracle_passes():
+    assert _xface_pin_errors() < 1e-12
+
+
+def _x_faces_as_cell_centres(orig):
+    def f(xbc):
+        return orig(grid.X_DIRICHLET if xbc == grid.X_FACES else xbc)
+    return f
+
+
+@pytest.mark.parametrize("target,attr,mut", [
+    (grid, "face_wall_wavenumbers", _face_modes_from_zero),
+    (poisson, "_x_transform", _x_faces_as_cell_centres),
+])
+def test_planted_xface_mistake_is_caught(monkeypatch, target, attr, mut):
+    monkeypatch.setattr(target, attr, mut(getattr(target, attr)))
+    assert _xface_pin_errors() > 1e-6

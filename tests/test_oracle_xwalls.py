@@ -82,3 +82,43 @@ def test_planted_mistake_is_caught(monkeypatch):
         transforms.rfft_packed, transforms.irfft_packed, grid.wall_wavenumbers))
     got = poisson.solve_poisson(f, zf, LX, LY, xbc=grid.X_WALLS)
     assert np.max(np.abs(got - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
+# a field on the x faces between value-zero walls (the face-located u of an
+# x-walled grid): the type-I sine transform along x
+
+@pytest.mark.parametrize("bc", [grid.DIRICHLET_CENTRE, grid.DIRICHLET_FACE])
+@pytest.mark.parametrize("ybc,dense_ybc", [(grid.Y_PERIODIC, 0), (grid.Y_WALLS, 1), (grid.Y_FACES, 3)])
+def test_helmholtz3d_on_x_faces_matches_dense(bc, ybc, dense_ybc):
+    nx, ny, nz, s = 6, 4, 5, 0.05
+    zf = synth.tanh_faces(nz, 2.0, 1.5)
+    n = nz if bc == grid.DIRICHLET_CENTRE else nz - 1
+    r = synth.uniform_pm1(110 + bc + 3 * dense_ybc, (n, ny, nx))
+    got = poisson.solve_helmholtz3d(r, zf, s, bc, LX, LY, ybc=ybc, xbc=grid.X_FACES)
+    ref = dense.helmholtz3d_dense(r, zf, s, bc, LX, LY, ybc=dense_ybc, xbc=3)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.all(got[:, :, nx - 1] == 0)
+
+
+def test_helmholtz3d_on_x_faces_residual_from_face_fluxes():
+    nx, ny, nz, s = 10, 8, 6, 0.03
+    zf = synth.tanh_faces(nz, 2.0, 1.2)
+    r = synth.uniform_pm1(121, (nz, ny, nx))
+    u = poisson.solve_helmholtz3d(r, zf, s, grid.DIRICHLET_CENTRE, LX, LY, xbc=grid.X_FACES)
+    dx, dy = LX / nx, LY / ny
+    ui = u[:, :, : nx - 1]
+    pad = np.concatenate([np.zeros((nz, ny, 1)), ui, np.zeros((nz, ny, 1))], axis=2)
+    lxx = (pad[:, :, 2:] - 2 * ui + pad[:, :, :-2]) / dx ** 2
+    lyy = (np.roll(ui, -1, 1) - 2 * ui + np.roll(ui, 1, 1)) / dy ** 2
+    al, ga, ex = grid.zop(zf, grid.DIRICHLET_CENTRE)
+    lz = -(al + ga + ex)[:, None, None] * ui
+    lz[1:] += al[1:, None, None] * ui[:-1]
+    lz[:-1] += ga[:-1, None, None] * ui[1:]
+    res = r[:, :, : nx - 1] - (ui - s * (lxx + lyy + lz))
+    assert np.max(np.abs(res)) <= 1e-12 * np.max(np.abs(r))
+
+
+def test_poisson_rejects_x_faces():
+    zf = synth.tanh_faces(4, 2.0, 1.0)
+    with pytest.raises(ValueError):
+        poisson.solve_poisson(np.zeros((4, 4, 4)), zf, LX, LY, xbc=grid.X_FACES)
