@@ -109,9 +109,15 @@ typedef enum { PF_BC_NEUMANN = 0, PF_BC_DIRICHLET_CENTRE = 1, PF_BC_DIRICHLET_FA
  * poisson_solve and helmholtz3d_plan / helmholtz3d_solve; poisson_project
  * takes PF_X_WALLS (u[:, :, nx-1] is then the east wall face: no flux
  * through it or through the west wall face enters the divergence, and it is
- * left unchanged) and returns PF_ERR_UNSUPPORTED for PF_X_DIRICHLET. */
+ * left unchanged) and returns PF_ERR_UNSUPPORTED for PF_X_DIRICHLET.
+ * PF_X_FACES (helmholtz3d_plan only): PF_Y_FACES along x, a field on the x
+ * faces (the face-located velocity u of an x-walled grid): column i of each
+ * row holds the face i + 1 (i = 0..nx-2), column nx - 1 the east wall face
+ * (zero in the result up to rounding; r there is not read); the type-I sine
+ * transform along x, wavenumbers 4 sin^2(pi q / 2 nx) / dx^2, q = 1..nx-1;
+ * 2 nx must be a built length. */
 enum { PF_Y_PERIODIC = 0, PF_Y_WALLS = 1, PF_Y_DIRICHLET = 2, PF_Y_FACES = 3 };
-enum { PF_X_PERIODIC = 0, PF_X_WALLS = 1, PF_X_DIRICHLET = 2 };
+enum { PF_X_PERIODIC = 0, PF_X_WALLS = 1, PF_X_DIRICHLET = 2, PF_X_FACES = 3 };
 typedef struct pf_grid {
   int32_t nx, ny, nz;
   double lx, ly, lz;

@@ -48,15 +48,16 @@ pf_status check_grid(const pf_grid *g, bool need_fft) {
   if (g->ybc != PF_Y_PERIODIC && g->ybc != PF_Y_WALLS && g->ybc != PF_Y_DIRICHLET && g->ybc != PF_Y_FACES)
     return fail(PF_ERR_ARG, "ybc must be PF_Y_PERIODIC, PF_Y_WALLS, PF_Y_DIRICHLET or PF_Y_FACES (got %d)",
                 g->ybc);
-  if (g->xbc != PF_X_PERIODIC && g->xbc != PF_X_WALLS && g->xbc != PF_X_DIRICHLET)
-    return fail(PF_ERR_ARG, "xbc must be PF_X_PERIODIC, PF_X_WALLS or PF_X_DIRICHLET (got %d)", g->xbc);
+  if (g->xbc != PF_X_PERIODIC && g->xbc != PF_X_WALLS && g->xbc != PF_X_DIRICHLET && g->xbc != PF_X_FACES)
+    return fail(PF_ERR_ARG, "xbc must be PF_X_PERIODIC, PF_X_WALLS, PF_X_DIRICHLET or PF_X_FACES (got %d)",
+                g->xbc);
   if (need_fft) {
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PF_ERR_ARG, "lx, ly must be > 0");
 #define PF_LEN_STR(N) " " #N
-    if (!pf::fft_size_supported(g->nx))
-      return fail(PF_ERR_UNSUPPORTED, "x length %d not built (built:" PF_FOR_FFT_SIZES(PF_LEN_STR) ")",
-                  g->nx);
-    // a field on the y faces takes one transform of twice its rows
+    // a field on the x (y) faces takes one transform of twice its length
+    if (g->xbc == PF_X_FACES ? !pf::fft_size_supported(2 * g->nx) : !pf::fft_size_supported(g->nx))
+      return fail(PF_ERR_UNSUPPORTED, "x length %d%s not built (built:" PF_FOR_FFT_SIZES(PF_LEN_STR) ")",
+                  g->nx, g->xbc == PF_X_FACES ? " (faces: twice the length)" : "");
     if (g->ybc == PF_Y_FACES ? !pf::fft_size_supported_y(2 * g->ny) : !pf::fft_size_supported_y(g->ny))
       return fail(PF_ERR_UNSUPPORTED,
                   "y length %d%s not built (built:" PF_FOR_FFT_SIZES_Y(PF_LEN_STR) ")", g->ny,
@@ -400,9 +401,17 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   if (precision == PF_FP32_REFINE && (n_refine < 0 || n_refine > 1))
     return fail(PF_ERR_UNSUPPORTED, "n_refine must be 0 or 1 (got %d)", n_refine);
   if (g->nz > 1024) return fail(PF_ERR_UNSUPPORTED, "nz=%d too large for the z solve (max 1024)", g->nz);
-  if (g->ybc == PF_Y_FACES && bc == PF_BC_NEUMANN)
-    return fail(PF_ERR_UNSUPPORTED, "ybc PF_Y_FACES places a velocity component on the y faces: "
+  if ((g->ybc == PF_Y_FACES || g->xbc == PF_X_FACES) && bc == PF_BC_NEUMANN)
+    return fail(PF_ERR_UNSUPPORTED, "PF_Y_FACES / PF_X_FACES place a velocity component on the faces: "
                                     "helmholtz3d_plan only");
+  {
+    // a y workgroup takes 2*LPW adjacent x slots of every row
+    const int nyt = g->ybc == PF_Y_FACES ? 2 * g->ny : g->ny;
+    const int lpw = precision == PF_FP64 ? pf::y_lpw<double>(nyt) : pf::y_lpw<float>(nyt);
+    if (g->nx % (2 * lpw))
+      return fail(PF_ERR_UNSUPPORTED, "nx=%d must be a multiple of %d for the y transforms of this grid "
+                                      "and precision", g->nx, 2 * lpw);
+  }
   const int nzu = bc == PF_BC_DIRICHLET_FACE ? g->nz - 1 : g->nz;  // planes of the field
   int zc = pf::zsolve_default_variant(g->nx, nzu, precision == PF_FP64);
   if (const char *ev = std::getenv("PF_ZSOLVE_VARIANT")) {
@@ -444,7 +453,9 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
   std::vector<double2> ctwx;
   if (g->xbc != PF_X_PERIODIC) {
     const double dx = g->lx / g->nx;
-    const int q0 = g->xbc == PF_X_DIRICHLET ? 1 : 0;
+    // x faces: the type-I sine modes q = 1..nx-1 in slots 0..nx-2, the value-
+    // zero walls' formula (the last slot, the wall face, holds no mode)
+    const int q0 = g->xbc == PF_X_DIRICHLET || g->xbc == PF_X_FACES ? 1 : 0;
     for (int q = 0; q < g->nx; ++q) {
       const long double v = std::sin((long double)M_PI * (q + q0) / (2.0L * g->nx));
       sx[q] = (double)(4.0L * v * v / ((long double)dx * dx));
@@ -479,7 +490,8 @@ static pf_status channel_plan(pf_poisson_plan **out, const pf_grid *g, int32_t p
     if (!walls && g->xbc != PF_X_PERIODIC)
       for (int m = 0; m < g->ny; ++m) sy[g->ny + m] = sy[m];
   }
-  auto twxd = twiddles<double2>(g->nx), twyd = twiddles<double2>(g->ybc == PF_Y_FACES ? 2 * g->ny : g->ny);
+  auto twxd = twiddles<double2>(g->xbc == PF_X_FACES ? 2 * g->nx : g->nx),
+       twyd = twiddles<double2>(g->ybc == PF_Y_FACES ? 2 * g->ny : g->ny);
   DevArena &A = pl->ar;
   pl->o_zal = A.add(al.data(), al.size());
   pl->o_zga = A.add(ga.data(), ga.size());
@@ -599,9 +611,10 @@ static pf_status poisson_enqueue(pf_poisson_plan *pl, const double *rhs, double 
   // the 3-D Helmholtz: no singular mode (zm stays zero, added as a no-op),
   // and the chain solves (L - kappa) u' = r, so u = -kappa u'. Value-zero y
   // walls: no singular mode either (nothing projected, no pin)
-  // the y inverse leaves the factor ny (2 ny for the type-I sine transform
-  // of a field on the y faces)
-  const double scale = 1.0 / ((double)pl->nx * pl->ny * (pl->ybc == PF_Y_FACES ? 2 : 1));
+  // the y and x inverses leave the factors ny and nx (2 ny, 2 nx for the
+  // type-I sine transform of a field on the y, x faces)
+  const double scale = 1.0 / ((double)pl->nx * pl->ny * (pl->ybc == PF_Y_FACES ? 2 : 1) *
+                              (pl->xbc == PF_X_FACES ? 2 : 1));
   const bool helm = pl->bc != PF_BC_NEUMANN;
   const double oscale = helm ? -pl->kappa * scale : scale;
   const bool nozero = helm || pl->ybc == PF_Y_DIRICHLET || pl->xbc == PF_X_DIRICHLET;

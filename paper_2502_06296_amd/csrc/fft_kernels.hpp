@@ -34,6 +34,19 @@ __device__ __forceinline__ void st2(T *p, double x, double y) {
 // takes the cosine coefficient of index N-1-q as its mode q. Z_0 is the sum
 // of each line, as in the periodic case.
 __device__ __forceinline__ int xw_src(int n, int N) { return n < N / 2 ? 2 * n : 2 * N - 1 - 2 * n; }
+// XW = 3: a field on the x faces between value-zero walls (line positions
+// 0..NL-2 hold the faces 1..NL-1, position NL-1 the east wall face): the
+// type-I sine transform X_q = 2 sum_m x_m sin(pi q m / NL), q = 1..NL-1, of
+// both lines of a pair at once, as one complex FFT of length N = 2 NL of the
+// oddly extended pair (e_m = x_m, e_{N-m} = -x_m, e_0 = e_NL = 0): X_q = i E_q,
+// its real and imaginary parts the two lines' coefficients; slot q - 1 holds
+// mode q and the last slot is zero.
+template <int XW>
+__device__ __forceinline__ cplx<double> xface_src(int i, int NL, const double *a, const double *b) {
+  if (i == 0 || i == NL) return mkc<double>(0.0, 0.0);
+  if (i < NL) return mkc<double>(a[i - 1], b[i - 1]);
+  return mkc<double>(-a[2 * NL - 1 - i], -b[2 * NL - 1 - i]);
+}
 template <typename T, int N, int TPL, int LPW, bool SUMS, int XW, int RO = 0>
 __device__ __forceinline__ void xfwd_body(const double *__restrict__ in, T *__restrict__ out,
                                                    const cplx<double> *__restrict__ tw,
@@ -48,12 +61,15 @@ __device__ __forceinline__ void xfwd_body(const double *__restrict__ in, T *__re
   const long c = (long)bx_ * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
+  constexpr int NL = XW == 3 ? N / 2 : N;  // line length
   // the first pass reads the line pair straight from global memory
-  const double *a = in + (ok ? (size_t)(2 * c) * N : 0);
-  const double *b = a + N;
+  const double *a = in + (ok ? (size_t)(2 * c) * NL : 0);
+  const double *b = a + NL;
   auto src = [&](int i) {
     if constexpr (XW == 0) {
       return ok ? mkc<double>(a[i], b[i]) : mkc<double>(0.0, 0.0);
+    } else if constexpr (XW == 3) {
+      return ok ? xface_src<XW>(i, NL, a, b) : mkc<double>(0.0, 0.0);
     } else {
       const int x = xw_src(i, N);
       const double sg = (XW == 2 && (x & 1)) ? -1.0 : 1.0;
@@ -62,8 +78,26 @@ __device__ __forceinline__ void xfwd_body(const double *__restrict__ in, T *__re
   };
   fft_line_io<double, N, TPL, false, true, false, RO>(buf, tw, t, src, [](int, const C &) {});
   if (!ok) return;
-  T *oa = out + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
-  T *ob = oa + N;
+  T *oa = out + (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * NL;
+  T *ob = oa + NL;
+  if constexpr (XW == 3) {
+#pragma unroll
+    for (int q = t; q < N; q += TPL) {
+      if (q >= 1 && q < NL) {
+        const C v = buf[lds_idx(q)];
+        oa[q - 1] = (T)(-v.y);
+        ob[q - 1] = (T)v.x;
+      } else if (q == NL) {
+        oa[NL - 1] = (T)0.0;
+        ob[NL - 1] = (T)0.0;
+      }
+      if (SUMS && q == 0) {  // no zero mode: the faces field has no mean mode
+        sums[2 * c] = 0.0;
+        sums[2 * c + 1] = 0.0;
+      }
+    }
+    return;
+  }
   if constexpr (XW != 0) {
 #pragma unroll
     for (int q = t; q < N; q += TPL) {
@@ -155,13 +189,16 @@ __device__ __forceinline__ void resid_spec_body(
   const long rem = (long)b - (long)(k0 / kResidPlanes) * per;
   const int k = k0 + (int)(rem % sz), j = (int)(rem / sz) * 2 * LPW + 2 * l;  // lines j, j+1
   C *buf = lds + l * lds_len(N);
+  constexpr int NL = XW == 3 ? N / 2 : N;  // line length
   {
     // the first pass reads the line pair of f straight from global memory
-    const double *fa = f + ((size_t)k * ny + j) * N;
-    const double *fb = fa + N;
+    const double *fa = f + ((size_t)k * ny + j) * NL;
+    const double *fb = fa + NL;
     auto src = [&](int i) {
       if constexpr (XW == 0) {
         return mkc<double>(fa[i], fb[i]);
+      } else if constexpr (XW == 3) {
+        return xface_src<XW>(i, NL, fa, fb);
       } else {
         const int x = xw_src(i, N);
         const double sg = (XW == 2 && (x & 1)) ? -1.0 : 1.0;
@@ -184,14 +221,26 @@ __device__ __forceinline__ void resid_spec_body(
   const double gm = j == 0 ? (ywalls == 2 ? -1.0 : ywalls == 3 ? 0.0 : 1.0) : 1.0;
   const double gp = j + 2 == ny ? (ywalls == 2 ? -1.0 : ywalls == 3 ? 0.0 : 1.0) : 1.0;
   const float *Wk = W + (size_t)k * sp;
-  const float *w0 = Wk + (size_t)j * N, *w1 = w0 + N;          // lines j, j+1
-  const float *wm = Wk + (size_t)jm * N, *wp = Wk + (size_t)jp2 * N;
-  float *oa = out + (size_t)k * sp + (size_t)j * N;
-  float *ob = oa + N;
+  const float *w0 = Wk + (size_t)j * NL, *w1 = w0 + NL;        // lines j, j+1
+  const float *wm = Wk + (size_t)jm * NL, *wp = Wk + (size_t)jp2 * NL;
+  float *oa = out + (size_t)k * sp + (size_t)j * NL;
+  float *ob = oa + NL;
 #pragma unroll
   for (int q = t; q < N / 2; q += TPL) {
+    if (XW == 3 && q >= NL / 2) continue;  // slot pairs of a line of NL
     C A, B;
-    if constexpr (XW != 0) {
+    if constexpr (XW == 3) {
+      // slots 2q and 2q+1 (modes 2q+1, 2q+2; the last slot is the wall)
+      C v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int sl = 2 * q + h;
+        const C e = sl < NL - 1 ? buf[lds_idx(sl + 1)] : mkc<double>(0.0, 0.0);
+        v[h] = mkc<double>(-e.y, e.x);
+      }
+      A = mkc<double>(v[0].x, v[1].x);
+      B = mkc<double>(v[0].y, v[1].y);
+    } else if constexpr (XW != 0) {
       // slots 2q and 2q+1 of lines a (real parts) and b (imaginary parts)
       C v[2];
 #pragma unroll
@@ -625,8 +674,34 @@ __device__ __forceinline__ void xinv_body(const TS *in, TO *out,
   const long c = (long)bx_ * LPW + l;
   const bool ok = c < ncl;
   C *buf = lds + l * lds_len(N);
+  constexpr int NL = XW == 3 ? N / 2 : N;  // line length
   double m0 = 0.0, m1 = 0.0;  // largest |iterate| and |correction| seen (SUM2)
-  if (XW != 0 && ok) {
+  if (XW == 3 && ok) {
+    // the pair's slots oddly extended: mode q (slot q - 1) at positions q and
+    // N - q negated; positions 0 and NL zero (the wall slot is not read)
+    const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * NL;
+    const TS *a = in + o;
+    const TS *b = a + NL;
+#pragma unroll
+    for (int s = t; s < NL; s += TPL) {
+      if (s < NL - 1) {
+        double xa = (double)a[s], xb = (double)b[s];
+        if (SUM2) {
+          const double ya = (double)in2[o + s], yb = (double)in2[o + NL + s];
+          m0 = fmax(m0, fmax(fabs(xa), fabs(xb)));
+          m1 = fmax(m1, fmax(fabs(ya), fabs(yb)));
+          xa += ya;
+          xb += yb;
+        }
+        buf[lds_idx(s + 1)] = mkc<double>(xa, xb);
+        buf[lds_idx(N - 1 - s)] = mkc<double>(-xa, -xb);
+      } else {
+        buf[lds_idx(0)] = mkc<double>(0.0, 0.0);
+        buf[lds_idx(NL)] = mkc<double>(0.0, 0.0);
+      }
+    }
+  }
+  if (XW != 0 && XW != 3 && ok) {
     const size_t o = (size_t)(2 * c / ny) * sp + (size_t)(2 * c % ny) * N;
     const TS *a = in + o;
     const TS *b = a + N;
@@ -648,7 +723,7 @@ __device__ __forceinline__ void xinv_body(const TS *in, TO *out,
     __syncthreads();
     // one thread per index pair (q, N - q), q = 0..N/2: both read before
     // either is overwritten
-    if (ok) {
+    if (XW != 3 && ok) {
       for (int q = t; q <= N / 2; q += TPL) {
         const C xq = buf[lds_idx(q)];
         const C xn = q == 0 ? mkc<double>(0.0, 0.0) : buf[lds_idx(N - q)];
@@ -705,11 +780,21 @@ __device__ __forceinline__ void xinv_body(const TS *in, TO *out,
   __syncthreads();
   // the last pass writes both real lines straight to global memory
   const double add = ADDZ && ok ? zm[(2 * c) / ny] : 0.0;
-  TO *oa = out + (ok ? (size_t)(2 * c) * N : 0);
-  TO *ob = oa + N;
+  TO *oa = out + (ok ? (size_t)(2 * c) * NL : 0);
+  TO *ob = oa + NL;
   auto dst = [&](int pos, const C &z) {
     if (ok) {
-      if constexpr (XW == 0) {
+      if constexpr (XW == 3) {
+        // the inverse DFT of the odd extension is 2i sum_q X_q sin(pi q m / NL):
+        // face m = pos (position m - 1) takes -i z, times 1 / (2 NL) in scale
+        if (pos >= 1 && pos < NL) {
+          oa[pos - 1] = (TO)(z.y * scale + add);
+          ob[pos - 1] = (TO)(-z.x * scale + add);
+        } else if (pos == NL) {
+          oa[NL - 1] = (TO)add;
+          ob[NL - 1] = (TO)add;
+        }
+      } else if constexpr (XW == 0) {
         oa[pos] = (TO)(z.x * scale + add);
         ob[pos] = (TO)(z.y * scale + add);
       } else {

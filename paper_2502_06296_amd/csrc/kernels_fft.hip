@@ -322,6 +322,24 @@ hipError_t launch_xfwd(int nx, int ny, const double *in, T *out, size_t sp,
                        const cplx<double> *ctwx, int shape) {
   const long ncl = lines / 2;
   if (xw != 0 && (!sums || !ctwx)) return hipErrorInvalidValue;
+  if (xw == 3) {
+    // a field on the x faces: one transform of twice the line length
+    if (shape != 0) return hipErrorInvalidValue;
+    switch (2 * nx) {
+#define PF_CASE(N)                                                                              \
+  case N: {                                                                                     \
+    constexpr int TPL = xfwd_tpl(N), LPW = x_lpw(N);                                            \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW));                                                  \
+    hipLaunchKernelGGL((k_xfwd<T, N, TPL, LPW, true, 3>), g, dim3(TPL * LPW), 0, st, in, out,    \
+                       tw, ctwx, sums, ncl, ny, sp);                                            \
+    return hipGetLastError();                                                                   \
+  }
+      PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   if (shape != 0) {
     if (xw != 0 || !sums) return hipErrorInvalidValue;
     return launch_xfwd_alt<T>(shape, nx, ny, in, out, sp, tw, sums, lines, st);
@@ -363,11 +381,28 @@ hipError_t launch_resid_spec(int nx, int ny, int nz, const double *f, const doub
     return launch_resid_alt(shape, nx, ny, nz, f, fbar, W, out, sp, tw, sums_p, sx, zal, zga, zex, idy2,
                             ywalls, st);
   }
-  switch (nx) {
 #define PF_RESID(N, XW)                                                                          \
   hipLaunchKernelGGL((k_resid_spec<N, TPL, LPW, XW>), dim3((unsigned)nblk), dim3(TPL * LPW), 0,  \
                      st, f, fbar, W, out, tw, ctwx, sums_p, sx, zal, zga, zex, ny, nz, idy2,      \
                      ywalls == 3 ? 0.5 / ny : 1.0 / ny, ywalls, sp)
+  if (xw == 3) {
+    // a field on the x faces: one transform of twice the line length
+    switch (2 * nx) {
+#define PF_CASE(N)                                                                               \
+  case N: {                                                                                      \
+    constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                        \
+    if (ny % (2 * LPW)) return hipErrorInvalidValue;                                             \
+    const long nblk = (long)ny * nz / (2 * LPW);                                                 \
+    PF_RESID(N, 3);                                                                              \
+    return hipGetLastError();                                                                    \
+  }
+      PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  switch (nx) {
 #define PF_CASE(N)                                                                               \
   case N: {                                                                                      \
     constexpr int TPL = resid_tpl(N), LPW = resid_lpw(N);                                        \
@@ -514,10 +549,29 @@ hipError_t launch_xinv(int nx, int ny, const TS *in, size_t sp, TO *out, const c
     if (xw != 0 || !zm) return hipErrorInvalidValue;
     return launch_xinv_alt<TS, TO>(shape, nx, ny, in, sp, out, tw, zm, in2, scale, lines, st, stat);
   }
-  switch (nx) {
 #define PF_XINV(N, ADDZ, SUM2, XW, STAT)                                                         \
   hipLaunchKernelGGL((k_xinv<TS, TO, N, TPL, LPW, ADDZ, SUM2, XW>), g, b, 0, st, in, out, tw,    \
                      ctwx, zm, in2, scale, ny, ncl, sp, STAT)
+  if (xw == 3) {
+    // a field on the x faces: one transform of twice the line length
+    switch (2 * nx) {
+#define PF_CASE(N)                                                                              \
+  case N: {                                                                                     \
+    constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \
+    dim3 g((unsigned)((ncl + LPW - 1) / LPW)), b(TPL * LPW);                                    \
+    if (in2)                                                                                    \
+      PF_XINV(N, true, true, 3, stat);                                                          \
+    else                                                                                        \
+      PF_XINV(N, true, false, 3, nullptr);                                                      \
+    return hipGetLastError();                                                                   \
+  }
+      PF_FOR_FFT_SIZES(PF_CASE)
+#undef PF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  switch (nx) {
 #define PF_CASE(N)                                                                              \
   case N: {                                                                                     \
     constexpr int TPL = x_tpl(N), LPW = x_lpw(N);                                               \

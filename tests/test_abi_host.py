@@ -96,6 +96,22 @@ def test_y_faces_are_for_the_helmholtz_and_need_twice_the_rows_built():
         assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
             N.PF_ERR_UNSUPPORTED
         assert b"faces" in N.lib().pf_last_error()
+    # the same along x (xbc 3)
+    g, keep = N.make_grid(32, 64, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 3)
+    assert N.lib().poisson_plan(C.byref(h), C.byref(g), 0, 1, None, C.byref(ws)) == N.PF_ERR_UNSUPPORTED
+    assert b"helmholtz3d_plan only" in N.lib().pf_last_error()
+    for nx in (100, 2048):
+        g, keep = N.make_grid(nx, 64, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 3)
+        assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == \
+            N.PF_ERR_UNSUPPORTED
+        assert b"faces" in N.lib().pf_last_error()
+    g, keep = N.make_grid(64, 64, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 4)
+    assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 0, 1, None, C.byref(ws)) == N.PF_ERR_ARG
+    # 48 faces along x: a float32 y workgroup of 96-point columns takes 32 x slots
+    g, keep = N.make_grid(48, 96, 16, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 3)
+    assert N.lib().helmholtz3d_plan(C.byref(h), C.byref(g), 1, 1e-3, 2, 1, None, C.byref(ws)) == \
+        N.PF_ERR_UNSUPPORTED
+    assert b"multiple of 32" in N.lib().pf_last_error()
 
 
 def test_plan_rejects_bad_precision_and_refinement():
@@ -213,7 +229,7 @@ def test_pcr_prepare_rows_rejects_rows_outside_the_m_matrix_form():
 def test_plan_validates_the_x_boundary_before_any_device_call():
     L = N.lib()
     h = C.c_void_p()
-    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 3)
+    g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, 4)
     assert L.poisson_plan(C.byref(h), C.byref(g), 0, 1, None, None) == N.PF_ERR_ARG
     g, keep = N.make_grid(64, 64, 64, 2 * np.pi, np.pi, 2.0, 1.5, None, 0, -1)
     assert L.poisson_plan(C.byref(h), C.byref(g), 0, 1, None, None) == N.PF_ERR_ARG
