@@ -403,7 +403,12 @@ __global__ __launch_bounds__(512, WAVES) void k_zsolve2(TS *data, int nx, int ny
 // once every thread holds its rows. Only single-pass workgroups tile; the
 // two-pass ones (the pair of slots 0 and 1, x walls) read and write their
 // columns directly.
-template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1>
+// DB: the three reduced-row arrays are doubled, and the steps of the cyclic
+// reduction alternate between the two sets: a step writes one set while the
+// previous step's reads of the other may still be in flight, so a step
+// takes one barrier instead of two.
+template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1,
+          bool DB = false>
 __device__ __forceinline__ void zsolve3_body(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
@@ -426,9 +431,10 @@ __device__ __forceinline__ void zsolve3_body(TS *data, int nx, int ny, int nz, i
   }
   constexpr int TC = 2 * TP;  // columns of one round
   // one tile region: P*M rows of TC values, at least the three arrays
-  const size_t region = ((size_t)P * M * TC * sizeof(TS) > (size_t)3 * P * TP * sizeof(D2)
+  constexpr int NX = DB ? 6 : 3;  // reduced-row arrays
+  const size_t region = ((size_t)P * M * TC * sizeof(TS) > (size_t)NX * P * TP * sizeof(D2)
                              ? (size_t)P * M * TC * sizeof(TS)
-                             : (size_t)3 * P * TP * sizeof(D2)) / sizeof(double);
+                             : (size_t)NX * P * TP * sizeof(D2)) / sizeof(double);
   double *const reg0 = tex + P * M;
   D2 *X1 = reinterpret_cast<D2 *>(reg0);
   D2 *X2 = X1 + P * TP;
@@ -547,24 +553,47 @@ __device__ __forceinline__ void zsolve3_body(TS *data, int nx, int ny, int nz, i
     }
     __syncthreads();
     // cyclic reduction on the P separator rows (normalised, see k_zsolve2)
-    for (int s = 1; s < P; s *= 2) {
-      X1[me] = mkc<double>(A, E);
-      X2[me] = mkc<double>(S0, S1);
-      X3[me] = mkc<double>(G, E);
-      __syncthreads();
-      const int lo = (ch - s < 0 ? 0 : ch - s) * TP + pc;
-      const int hi = (ch + s >= P ? P - 1 : ch + s) * TP + pc;
-      const D2 ae = X1[lo], dl = X2[lo], ge = X3[hi], dh = X2[hi];
-      const double na = A * ae.x, ng = G * ge.x, ne = E + A * ae.y + G * ge.y;
-      const double n0 = S0 + A * dl.x + G * dh.x, n1 = S1 + A * dl.y + G * dh.y;
-      __syncthreads();
-      const double b = rcpn<NR>(na + ng + ne);
-      A = na * b; G = ng * b; E = ne * b; S0 = n0 * b; S1 = n1 * b;
+    D2 *F2 = X2;  // the set the separator values go to
+    if constexpr (DB) {
+      D2 *const Y1 = X3 + P * TP, *const Y2 = Y1 + P * TP, *const Y3 = Y2 + P * TP;
+      bool odd = false;
+      for (int s = 1; s < P; s *= 2) {
+        D2 *const Z1 = odd ? Y1 : X1, *const Z2 = odd ? Y2 : X2, *const Z3 = odd ? Y3 : X3;
+        Z1[me] = mkc<double>(A, E);
+        Z2[me] = mkc<double>(S0, S1);
+        Z3[me] = mkc<double>(G, E);
+        __syncthreads();
+        const int lo = (ch - s < 0 ? 0 : ch - s) * TP + pc;
+        const int hi = (ch + s >= P ? P - 1 : ch + s) * TP + pc;
+        const D2 ae = Z1[lo], dl = Z2[lo], ge = Z3[hi], dh = Z2[hi];
+        const double na = A * ae.x, ng = G * ge.x, ne = E + A * ae.y + G * ge.y;
+        const double n0 = S0 + A * dl.x + G * dh.x, n1 = S1 + A * dl.y + G * dh.y;
+        const double b = rcpn<NR>(na + ng + ne);
+        A = na * b; G = ng * b; E = ne * b; S0 = n0 * b; S1 = n1 * b;
+        odd = !odd;
+      }
+      // the set the last step did not read
+      F2 = odd ? Y2 : X2;
+    } else {
+      for (int s = 1; s < P; s *= 2) {
+        X1[me] = mkc<double>(A, E);
+        X2[me] = mkc<double>(S0, S1);
+        X3[me] = mkc<double>(G, E);
+        __syncthreads();
+        const int lo = (ch - s < 0 ? 0 : ch - s) * TP + pc;
+        const int hi = (ch + s >= P ? P - 1 : ch + s) * TP + pc;
+        const D2 ae = X1[lo], dl = X2[lo], ge = X3[hi], dh = X2[hi];
+        const double na = A * ae.x, ng = G * ge.x, ne = E + A * ae.y + G * ge.y;
+        const double n0 = S0 + A * dl.x + G * dh.x, n1 = S1 + A * dl.y + G * dh.y;
+        __syncthreads();
+        const double b = rcpn<NR>(na + ng + ne);
+        A = na * b; G = ng * b; E = ne * b; S0 = n0 * b; S1 = n1 * b;
+      }
     }
     // separator values: the own one and the previous chunk's
-    X2[me] = mkc<double>(S0, S1);
+    F2[me] = mkc<double>(S0, S1);
     __syncthreads();
-    const D2 xl = ch > 0 ? X2[me - TP] : mkc<double>(0.0, 0.0);
+    const D2 xl = ch > 0 ? F2[me - TP] : mkc<double>(0.0, 0.0);
     __syncthreads();
     // interior: forward y_q = (D_q + fa_q x_lo) / b_q, backward x_q = y_q + gamma_q x_{q+1} / b_q
     double a = al(0);
@@ -628,12 +657,14 @@ __device__ __forceinline__ void zsolve3_body(TS *data, int nx, int ny, int nz, i
   }
   if (tiled) tile_io(false);
 }
-template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1>
+template <typename TS, int M, int TP, int NR, int WAVES, int MAXT = 512, bool TILE = false, int R = 1,
+          bool DB = false>
 __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int ny, int nz, int P,
                                                       const double *zal, const double *zga,
                                                       const double *zex, const double *sx,
                                                       const double *sy, size_t sp, int xr) {
-  zsolve3_body<TS, M, TP, NR, WAVES, MAXT, TILE, R>(data, nx, ny, nz, P, zal, zga, zex, sx, sy, sp, xr, blockIdx.x, gridDim.x);
+  zsolve3_body<TS, M, TP, NR, WAVES, MAXT, TILE, R, DB>(data, nx, ny, nz, P, zal, zga, zex, sx, sy, sp, xr,
+                                                        blockIdx.x, gridDim.x);
 }
 
 // one z-solve shape for several problems with the same chunk count (see
@@ -662,6 +693,7 @@ struct ZVariant {
   int maxt = 512;    // threads per workgroup at most
   bool tile = false; // separator form with the column tile staged through LDS
   int rounds = 1;    // tiled: the threads take the TI columns in rounds of TI/rounds
+  bool dbl = false;  // separator form: double-buffered reduced rows, one barrier per reduction step
 };
 static const ZVariant kZVariants[] = {
     {16, 16, 0, false, false, 2}, {16, 16, 4, true, false, 2}, {16, 16, 0, true, false, 2},
@@ -687,6 +719,10 @@ static const ZVariant kZVariants[] = {
     {8, 16, 1, true, true, 1, false, true, 1024, true, 1},  {16, 16, 1, true, true, 1, false, true, 512, true, 1},
     {16, 32, 1, true, true, 1, false, true, 512, true, 1},  {8, 32, 1, true, true, 1, false, true, 1024, true, 1},
     {8, 16, 1, true, true, 1, false, true, 512, true, 1},   {8, 32, 1, true, true, 1, false, true, 512, true, 2},
+    // 1024-thread separator shapes with double-buffered reduced rows (LDS
+    // room for the second set): the 16-column float32 tile and the direct form
+    {8, 16, 1, true, true, 1, false, true, 1024, true, 1, true},
+    {8, 16, 1, true, true, 1, false, true, 1024, false, 1, true},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
@@ -699,12 +735,13 @@ int zsolve_variant_count() { return kZVariantCount; }
 static size_t zsolve_lds(const ZVariant &z, int P, int esize) {
   const int tp = z.TI / 2;
   const size_t tables = (size_t)3 * P * z.M * sizeof(double);
+  const size_t nxa = z.dbl ? 6 : 3;  // reduced-row arrays
   if (z.tile) {
     const int tpr = tp / z.rounds;  // thread pairs of a round
-    return tables + z.rounds * std::max((size_t)3 * P * tpr * 2 * sizeof(double),
+    return tables + z.rounds * std::max(nxa * P * tpr * 2 * sizeof(double),
                                         (size_t)P * z.M * 2 * tpr * esize);
   }
-  if (z.paired && z.sep) return tables + (size_t)3 * P * tp * 2 * sizeof(double);
+  if (z.paired && z.sep) return tables + nxa * P * tp * 2 * sizeof(double);
   return z.paired ? (size_t)3 * P * (2 * tp + zskew(tp, z.skew)) * 2 * sizeof(double) + tables
                   : (size_t)4 * 2 * P * z.TI * sizeof(double);
 }
@@ -727,14 +764,16 @@ int zsolve_default_variant(int nx, int nz, bool fp64) {
   // planes) 35 (0.71 ms: separator form, 8 rows, 16-column tiles through
   // LDS), 31 (0.72), 18 (0.84: 8 rows, 8 columns, direct); the unpaired 4
   // and 3 as fall-backs where the LDS or thread budget excludes the paired
-  // shapes. At 1024 rows float64 storage takes 20 (11.5 ms at
-  // 2048x1024x1024; 28 11.3, the tiled 31 12.8, 4 22.2) and float32 storage
-  // the tiled 29 (8.2 ms: 32-column tiles in two rounds; 18 8.9). Short
+  // shapes. At 1024 rows float64 storage takes 38 (11.06 ms at
+  // 2048x1024x1024: 28 with double-buffered reduced rows; 28 11.30, 20
+  // 11.52, the tiled 31 12.8, 4 22.2) and float32 storage the tiled 37 (8.01
+  // ms: 16-column tiles, double-buffered reduced rows; 29 8.20, 31 8.38, 18
+  // 8.9). Short
   // columns (few chunks) would leave those shapes with tiny workgroups, so
   // the first fitting shape with at least 128 threads wins, widened by the
   // 64- and 128-column shapes.
-  static const int f64[] = {21, 10, 19, 26, 25, 24, 23, 20, 8, 4, 3},
-                   f32[] = {35, 29, 31, 18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
+  static const int f64[] = {21, 10, 19, 38, 26, 25, 24, 23, 20, 8, 4, 3},
+                   f32[] = {35, 37, 29, 31, 18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
   const int *list = fp64 ? f64 : f32;
   const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
   auto threads = [&](int v) {
@@ -822,6 +861,14 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
     PF_ZT(34, 8, 32, 1024, 1)
     PF_ZT(35, 8, 16, 512, 1)
     PF_ZT(36, 8, 32, 512, 2)
+  case 37:
+    hipLaunchKernelGGL((k_zsolve3<TS, 8, 8, 1, 1, 1024, true, 1, true>), g, b, shm, st, data, nx, ny, nz, P,
+                       zal, zga, zex, sx, sy, sp, (int)xr);
+    break;
+  case 38:
+    hipLaunchKernelGGL((k_zsolve3<TS, 8, 8, 1, 1, 1024, false, 1, true>), g, b, shm, st, data, nx, ny, nz, P,
+                       zal, zga, zex, sx, sy, sp, (int)xr);
+    break;
 #undef PF_ZT
 #undef PF_ZW
 #undef PF_ZS
@@ -832,7 +879,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #undef PF_ZV
   return hipGetLastError();
 }
-bool zsolve_variant_groups(int variant) { return variant >= 18 && variant < kZVariantCount; }
+bool zsolve_variant_groups(int variant) { return variant >= 18 && variant <= 36; }
 int zsolve_chunks(int variant, int nz) { return (nz + kZVariants[variant].M - 1) / kZVariants[variant].M; }
 
 hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st) {
