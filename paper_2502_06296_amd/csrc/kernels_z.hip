@@ -669,13 +669,13 @@ __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3(TS *data, int nx, int n
 
 // one z-solve shape for several problems with the same chunk count (see
 // GJobs): float32 storage, periodic x
-template <int M, int TP, int NR, int WAVES, int MAXT, bool TILE, int R>
+template <int M, int TP, int NR, int WAVES, int MAXT, bool TILE, int R, bool DB = false>
 __global__ __launch_bounds__(MAXT, WAVES) void k_zsolve3_grp(const GJobs g) {
   const GJob &J = g.j[blockIdx.y];
   if (blockIdx.x >= J.nblk) return;  // uniform per block
-  zsolve3_body<float, M, TP, NR, WAVES, MAXT, TILE, R>(static_cast<float *>(J.out), J.nx, J.ny, J.nz, J.P,
-                                                       J.zal, J.zga, J.zex, J.sx, J.sy, J.sp, 0, blockIdx.x,
-                                                       J.nblk);
+  zsolve3_body<float, M, TP, NR, WAVES, MAXT, TILE, R, DB>(static_cast<float *>(J.out), J.nx, J.ny, J.nz,
+                                                           J.P, J.zal, J.zga, J.zex, J.sx, J.sy, J.sp, 0,
+                                                           blockIdx.x, J.nblk);
 }
 
 // Launch shapes of the z solve: rows per thread M, columns per workgroup
@@ -879,7 +879,7 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
 #undef PF_ZV
   return hipGetLastError();
 }
-bool zsolve_variant_groups(int variant) { return variant >= 18 && variant <= 36; }
+bool zsolve_variant_groups(int variant) { return variant >= 18 && variant < kZVariantCount; }
 int zsolve_chunks(int variant, int nz) { return (nz + kZVariants[variant].M - 1) / kZVariants[variant].M; }
 
 hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st) {
@@ -920,6 +920,12 @@ hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st) {
     PF_G(34, 8, 32, 1, 1024, true, 1)
     PF_G(35, 8, 16, 1, 512, true, 1)
     PF_G(36, 8, 32, 1, 512, true, 2)
+  case 37:
+    hipLaunchKernelGGL((k_zsolve3_grp<8, 8, 1, 1, 1024, true, 1, true>), gr, b, shm, st, g);
+    break;
+  case 38:
+    hipLaunchKernelGGL((k_zsolve3_grp<8, 8, 1, 1, 1024, false, 1, true>), gr, b, shm, st, g);
+    break;
 #undef PF_G
     default:
       return hipErrorInvalidValue;

@@ -92,6 +92,15 @@ def test_mixed_batch_groups_what_it_can():
     _run(specs, range(len(specs)))
 
 
+def test_grouped_batch_of_long_columns():
+    """Columns of more than 512 rows take the 1024-thread z-solve shapes
+    (double-buffered reduced rows): still grouped, bitwise equal to the single
+    solves, at the oracle."""
+    specs = [(64, 64, 600, 1.5), (128, 64, 600, 1.3), (64, 64, 600, 1.2, "fp32_refine", "helmholtz3d"),
+             (64, 64, 1000, 1.5)]
+    _run(specs, [0, 2, 3])
+
+
 def test_batch_larger_than_one_launch():
     """20 problems of one shape: two launches per stage (16 + 4 jobs)."""
     specs = [(64, 64, 24, 1.0 + 0.05 * t) for t in range(20)]
