@@ -723,6 +723,9 @@ static const ZVariant kZVariants[] = {
     // room for the second set): the 16-column float32 tile and the direct form
     {8, 16, 1, true, true, 1, false, true, 1024, true, 1, true},
     {8, 16, 1, true, true, 1, false, true, 1024, false, 1, true},
+    // the 512-thread defaults of 512-row columns with double-buffered reduced rows
+    {8, 16, 1, true, true, 1, false, true, 512, true, 1, true},
+    {16, 32, 0, true, true, 1, false, true, 512, false, 1, true},
 };
 constexpr int kZVariantCount = sizeof(kZVariants) / sizeof(kZVariants[0]);
 
@@ -759,10 +762,12 @@ bool zsolve_variant_fits(int v, int nx, int nz, int esize) {
 }
 
 int zsolve_default_variant(int nx, int nz, bool fp64) {
-  // fastest measured on MI355X at 1024x512x512: float64 storage 21 (1.06 ms:
-  // separator form, 16 rows, 32 columns), 10 (1.11); float32 storage (padded
-  // planes) 35 (0.71 ms: separator form, 8 rows, 16-column tiles through
-  // LDS), 31 (0.72), 18 (0.84: 8 rows, 8 columns, direct); the unpaired 4
+  // fastest measured on MI355X at 1024x512x512: float64 storage 40 (1.037
+  // ms: separator form, 16 rows, 32 columns, double-buffered reduced rows),
+  // 21 (1.050, the same with one set), 10 (1.11); float32 storage (padded
+  // planes) 39 (0.711 ms: separator form, 8 rows, 16-column tiles through
+  // LDS, double-buffered reduced rows), 35 (0.752, one set), 31, 18 (0.84:
+  // 8 rows, 8 columns, direct); the unpaired 4
   // and 3 as fall-backs where the LDS or thread budget excludes the paired
   // shapes. At 1024 rows float64 storage takes 38 (11.06 ms at
   // 2048x1024x1024: 28 with double-buffered reduced rows; 28 11.30, 20
@@ -772,8 +777,8 @@ int zsolve_default_variant(int nx, int nz, bool fp64) {
   // columns (few chunks) would leave those shapes with tiny workgroups, so
   // the first fitting shape with at least 128 threads wins, widened by the
   // 64- and 128-column shapes.
-  static const int f64[] = {21, 10, 19, 38, 26, 25, 24, 23, 20, 8, 4, 3},
-                   f32[] = {35, 37, 29, 31, 18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
+  static const int f64[] = {40, 21, 10, 19, 38, 26, 25, 24, 23, 20, 8, 4, 3},
+                   f32[] = {39, 35, 37, 29, 31, 18, 19, 16, 13, 24, 23, 26, 25, 8, 4, 3};
   const int *list = fp64 ? f64 : f32;
   const int len = fp64 ? (int)(sizeof(f64) / sizeof(int)) : (int)(sizeof(f32) / sizeof(int));
   auto threads = [&](int v) {
@@ -869,6 +874,14 @@ hipError_t launch_zsolve(int nx, int ny, int nz, TS *data, size_t sp, const doub
     hipLaunchKernelGGL((k_zsolve3<TS, 8, 8, 1, 1, 1024, false, 1, true>), g, b, shm, st, data, nx, ny, nz, P,
                        zal, zga, zex, sx, sy, sp, (int)xr);
     break;
+  case 39:
+    hipLaunchKernelGGL((k_zsolve3<TS, 8, 8, 1, 1, 512, true, 1, true>), g, b, shm, st, data, nx, ny, nz, P,
+                       zal, zga, zex, sx, sy, sp, (int)xr);
+    break;
+  case 40:
+    hipLaunchKernelGGL((k_zsolve3<TS, 16, 16, 1, 1, 512, false, 1, true>), g, b, shm, st, data, nx, ny, nz,
+                       P, zal, zga, zex, sx, sy, sp, (int)xr);
+    break;
 #undef PF_ZT
 #undef PF_ZW
 #undef PF_ZS
@@ -925,6 +938,12 @@ hipError_t launch_zsolve_grp(int variant, GJobs &g, hipStream_t st) {
     break;
   case 38:
     hipLaunchKernelGGL((k_zsolve3_grp<8, 8, 1, 1, 1024, false, 1, true>), gr, b, shm, st, g);
+    break;
+  case 39:
+    hipLaunchKernelGGL((k_zsolve3_grp<8, 8, 1, 1, 512, true, 1, true>), gr, b, shm, st, g);
+    break;
+  case 40:
+    hipLaunchKernelGGL((k_zsolve3_grp<16, 16, 1, 1, 512, false, 1, true>), gr, b, shm, st, g);
     break;
 #undef PF_G
     default:
