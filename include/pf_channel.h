@@ -378,7 +378,8 @@ pf_status pcr_timing_read(pf_pcr_plan *plan, double *ms, int32_t *count);
 /* ------------------------------------------------------------ tuning
  * Launch-shape variants that an autotuner may choose between. For
  * PF_STAGE_ZSOLVE the variants are table entries of (rows per thread,
- * columns per workgroup, occupancy bound, reciprocal flavour). For
+ * columns per workgroup, occupancy bound, reciprocal flavour, elimination
+ * form, column tile through LDS, single or double-buffered reduced rows). For
  * PF_STAGE_XFWD (the x forward, the x inverse and the refinement's residual)
  * and PF_STAGE_YFWD (both y transforms) of a direction without walls they
  * are 5 transform shapes: 0 the default, 1 half the threads per line, 2
