@@ -150,3 +150,39 @@ def test_transform_tuner_caches_and_plans_apply_the_cache(tmp_path, monkeypatch)
     pf.poisson_solve(d, rhs, r)
     torch.cuda.synchronize()
     assert op.rel_l2(q.cpu().numpy(), r.cpu().numpy()) < 1e-10
+
+
+@pytest.mark.parametrize("nx,ny,nz,yshape,zvar", [(256, 512, 24, 4, 39), (128, 3072, 4, 4, 38),
+                                                   (64, 256, 640, 3, 37)])
+def test_tuned_shapes_replay_in_a_graph(nx, ny, nz, yshape, zvar):
+    """A plan with non-default shapes (the persistent y transforms, whose
+    grid comes from an occupancy query; the double-buffered z solves)
+    captured in a graph: three replays, with eager work between them, equal
+    the eager solve bitwise."""
+    from paper_2502_06296_amd import solver
+    f, zf = synth.channel_rhs(48, nx, ny, nz, beta=1.5)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    plan = pf.poisson_plan(nx, ny, nz, LX, LY, 2.0, 1.5, zf=zf, precision="fp32_refine", tuned=False,
+                           stream=stream)
+    assert autotune.set_variant(plan, autotune.STAGE_YFWD, yshape)
+    if not autotune.set_zsolve_variant(plan, zvar):
+        pytest.skip(f"z-solve variant {zvar} does not fit {nx}x{ny}x{nz}")
+    rhs = torch.from_numpy(f).to(dev)
+    pe, pg = torch.empty_like(rhs), torch.empty_like(rhs)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        pf.poisson_solve(plan, rhs, pe)
+    stream.synchronize()
+    check_ref = op.solve_poisson(f, zf, LX, LY)
+    assert op.rel_l2(pe.cpu().numpy(), check_ref) < 1e-10
+    pf.pf_graph_begin(stream)
+    pf.poisson_solve(plan, rhs, pg)
+    g = pf.pf_graph_end(stream)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            pg.fill_(-1.0)
+            pf.poisson_solve(plan, rhs, torch.empty_like(rhs))  # eager work between the replays
+        g.launch(stream)
+        stream.synchronize()
+        assert torch.equal(pg, pe), rep
